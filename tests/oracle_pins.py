@@ -1,0 +1,229 @@
+"""Checks that pin the FP64 oracle to facts fixed by the paper and by mathematics.
+
+Each ``pin_*`` function raises AssertionError when the oracle disagrees with:
+  * hand derivations of Eq. 1 on one- and two-neuron networks,
+  * the exact linear program over a box when every ReLU is active (SLR is then exact),
+  * brute-force sampling (every sampled point lies inside every propagated bound),
+  * closed-form unsafe volumes (Irwin-Hall simplex, |x0 - 1/2| > 1/4),
+  * a dense grid of points on tiny random networks (every point in an unsafe leaf is unsafe),
+  * exact accounting invariants.
+They are plain functions so that the mutation tests can re-run them against an oracle with a
+planted mistake and require that at least one of them fails.
+"""
+from __future__ import annotations
+
+from fractions import Fraction
+
+import numpy as np
+
+import synth
+from oracle import count, slr
+
+
+def _f32(a):
+    return np.asarray(a, np.float32)
+
+
+def relu_identity_net():
+    """x in [-1, 1] -> z = x -> y = ReLU(z)."""
+    return [(_f32([[1.0]]), _f32([0.0])), (_f32([[1.0]]), _f32([0.0]))]
+
+
+def two_neuron_net(w_out):
+    """z1 = x1 + x2, z2 = x1 - x2 on [-1, 1]^2; y = w_out . ReLU(z)."""
+    return [(_f32([[1, 1], [1, -1]]), _f32([0, 0])), (_f32([w_out]), _f32([0.0]))]
+
+
+def pin_eq1_single_relu():
+    """Eq. 1 by hand: z = x on [-1,1] gives l=-1, u=1, lam=1/2, L = x/2, U = (x+1)/2."""
+    net = relu_identity_net()
+    g_lo, g_hi, tr = slr.propagate(net, [[1.0]], [0.0], [[-1.0]], [[1.0]], keep=True)
+    t = tr[0]
+    assert abs(t["lo"][0, 0] + 1.0) < 1e-12 and abs(t["hi"][0, 0] - 1.0) < 1e-12
+    assert np.allclose(t["Lr"][0, 0], [0.0, 0.5], atol=1e-12)
+    assert np.allclose(t["Ur"][0, 0], [0.5, 0.5], atol=1e-12)
+    assert abs(g_lo[0, 0] + 0.5) < 1e-12 and abs(g_hi[0, 0] - 1.0) < 1e-12
+    assert g_lo[0, 0] <= -0.5 and g_hi[0, 0] >= 1.0           # outward rounding only
+    # the same box with d = -1.5 is provably safe, with d = +0.6 provably unsafe
+    g_lo, g_hi = slr.propagate(net, [[1.0]], [-1.5], [[-1.0]], [[1.0]])
+    assert slr.classify(g_lo, g_hi)[0] == 2
+    g_lo, g_hi = slr.propagate(net, [[1.0]], [0.6], [[-1.0]], [[1.0]])
+    assert slr.classify(g_lo, g_hi)[0] == 1
+
+
+def pin_two_neurons():
+    """Hand derivation with both signs of output weight (exercises W+ and W-).
+
+    Each hidden neuron has l=-2, u=2, lam=1/2: L1=(x1+x2)/2, U1=(x1+x2+2)/2,
+    L2=(x1-x2)/2, U2=(x1-x2+2)/2.  For y = a1 + a2: [L1+L2, U1+U2] = [x1, x1+2] -> [-1, 3].
+    For y = a1 - a2: [L1-U2, U1-L2] = [x2-1, x2+1] -> [-2, 2].
+    """
+    box = ([[-1.0, -1.0]], [[1.0, 1.0]])
+    g_lo, g_hi = slr.propagate(two_neuron_net([1, 1]), [[1.0]], [0.0], *box)
+    assert abs(g_lo[0, 0] + 1.0) < 1e-12 and abs(g_hi[0, 0] - 3.0) < 1e-12
+    g_lo, g_hi = slr.propagate(two_neuron_net([1, -1]), [[1.0]], [0.0], *box)
+    assert abs(g_lo[0, 0] + 2.0) < 1e-12 and abs(g_hi[0, 0] - 2.0) < 1e-12
+    # on [0,1] x [-1,1] neuron 1 still crosses (l=-1, u=2, lam=2/3) while neuron 2 has
+    # l=-1, u=2 as well; y = a1 + a2 gives [L1+L2, U1+U2] = 2/3 [2 x1, 2 x1 + 2] -> [0, 8/3]
+    g_lo, g_hi = slr.propagate(two_neuron_net([1, 1]), [[1.0]], [0.0], [[0.0, -1.0]], [[1.0, 1.0]])
+    assert abs(g_lo[0, 0] - 0.0) < 1e-12 and abs(g_hi[0, 0] - 8.0 / 3.0) < 1e-12
+
+
+def pin_linear_regime(seed=0):
+    """All ReLUs active (identity first layer on a positive box): bounds equal the exact LP."""
+    rng = np.random.default_rng(seed)
+    for d in (2, 3, 4):
+        W2 = rng.normal(size=(2, d)).astype(np.float32)
+        b2 = rng.normal(size=2).astype(np.float32)
+        net = [(np.eye(d, dtype=np.float32), np.zeros(d, np.float32)), (W2, b2)]
+        C = np.array([[1.0, 0.0], [0.0, -1.0]], np.float32)
+        dv = np.zeros(2, np.float32)
+        blo, bhi = synth.random_boxes(np.zeros(d), np.ones(d), 20, seed + d, 8)
+        g_lo, g_hi = slr.propagate(net, C, dv, blo, bhi)
+        corners = np.array(np.meshgrid(*[[0, 1]] * d, indexing="ij")).reshape(d, -1).T
+        for i in range(blo.shape[0]):
+            v = blo[i].astype(np.float64) + (bhi[i] - blo[i]).astype(np.float64) * corners
+            gv = slr.property_values(net, C, dv, v)
+            assert np.allclose(g_lo[i], gv.min(axis=0), atol=1e-12, rtol=1e-12)
+            assert np.allclose(g_hi[i], gv.max(axis=0), atol=1e-12, rtol=1e-12)
+
+
+def _eval_eq(E, x):
+    return E[..., 0] + np.einsum("ni,pi->pn", E[..., 1:], x) if E.ndim == 2 else None
+
+
+def pin_soundness(seed=0, n_boxes=6, n_points=4000, alpha=False):
+    """Brute force: every sampled point (and every vertex) lies inside every bound."""
+    rng = np.random.default_rng(seed)
+    shapes = ([2, 16, 16, 1], [3, 8, 8, 2], [4, 10, 10, 10, 3])
+    for si, sizes in enumerate(shapes):
+        net = synth.make_net(sizes, seed * 10 + si)
+        n_out = sizes[-1]
+        C = rng.normal(size=(min(2, n_out), n_out)).astype(np.float32)
+        dv = rng.normal(scale=0.1, size=C.shape[0]).astype(np.float32)
+        d = sizes[0]
+        blo, bhi = synth.uniform_boxes(-np.ones(d), np.ones(d), n_boxes, seed * 7 + si, 0.6)
+        al = None
+        if alpha:
+            al = rng.uniform(0, 1, size=(n_boxes, sum(sizes[1:-1])))
+        g_lo, g_hi, tr = slr.propagate(net, C, dv, blo, bhi, alpha=al, keep=True)
+        for b in range(n_boxes):
+            x = slr.sample_points(blo[b], bhi[b], n_points, rng)
+            zs = slr.preactivations(net, x)
+            for li, z in enumerate(zs):
+                t = tr[li]
+                Lx = t["L"][b, :, 0] + x @ t["L"][b, :, 1:].T
+                Ux = t["U"][b, :, 0] + x @ t["U"][b, :, 1:].T
+                assert np.all(Lx <= z + 1e-12 * (1 + np.abs(z)))
+                assert np.all(z <= Ux + 1e-12 * (1 + np.abs(z)))
+                assert np.all(t["lo"][b] <= z.min(axis=0))
+                assert np.all(z.max(axis=0) <= t["hi"][b])
+                a = np.maximum(z, 0.0)
+                Lr = t["Lr"][b, :, 0] + x @ t["Lr"][b, :, 1:].T
+                Ur = t["Ur"][b, :, 0] + x @ t["Ur"][b, :, 1:].T
+                assert np.all(Lr <= a + 1e-12 * (1 + a))
+                assert np.all(a <= Ur + 1e-12 * (1 + a))
+            gv = slr.property_values(net, C, dv, x)
+            assert np.all(g_lo[b] <= gv.min(axis=0))
+            assert np.all(gv.max(axis=0) <= g_hi[b])
+
+
+def irwin_hall_net():
+    """y = x0 + x1 + x2 + b on [0,1]^3 through an identity hidden layer, b = float32(-2.98)."""
+    return [(np.eye(3, dtype=np.float32), np.zeros(3, np.float32)),
+            (_f32([[1, 1, 1]]), _f32([-2.98]))]
+
+
+def irwin_hall_volume():
+    """Exact volume of {x in [0,1]^3 : sum x > -b} = (3 + b)^3 / 6 for the float32 b."""
+    t = Fraction(3) + Fraction(float(np.float32(-2.98)))
+    return t ** 3 / 6
+
+
+def pin_irwin_hall():
+    net = irwin_hall_net()
+    V = irwin_hall_volume()
+    lo, hi = np.zeros(3), np.ones(3)
+    prev = None
+    for D in (18, 24, 30):
+        r = count.count_exact(net, [[1.0]], [0.0], lo, hi, D, 1 << 22)
+        assert r["unsafe_exact"] <= V <= r["unsafe_exact"] + r["undecided_exact"]
+        if prev is not None:
+            # six more levels halve every side twice: the undecided shell shrinks ~4x
+            assert r["undecided_exact"] <= prev / 2
+        prev = r["undecided_exact"]
+    # at depth 30 (sides 2^-10) most of the simplex (edge 0.02) is resolved unsafe
+    assert r["unsafe_exact"] > V / 2
+
+
+def abs_net():
+    """y = ReLU(x0 - 1/2) + ReLU(1/2 - x0) - 1/4 on [0,1]^2; unsafe (y > 0) volume = 1/2."""
+    return [(_f32([[1, 0], [-1, 0]]), _f32([-0.5, 0.5])), (_f32([[1, 1]]), _f32([-0.25]))]
+
+
+def pin_abs_closed_form():
+    net = abs_net()
+    r = count.count_exact(net, [[1.0]], [0.0], np.zeros(2), np.ones(2), 14, 1 << 22, trace=True)
+    assert r["unsafe_exact"] <= Fraction(1, 2) <= r["unsafe_exact"] + r["undecided_exact"]
+    # only the 4 columns of width 2^-7 touching x0 = 1/4 or 3/4 can stay undecided
+    assert r["undecided_exact"] <= Fraction(4, 2 ** 7)
+    for lev in r["levels"]:
+        for i, c in enumerate(lev["cls"]):
+            a, b = lev["lo"][i, 0], lev["hi"][i, 0]
+            if c == 1:
+                assert b <= 0.25 or a >= 0.75
+            elif c == 2:
+                assert a >= 0.25 and b <= 0.75
+
+
+def pin_dense_grid(seed=0, cells=1024):
+    """tiny2d: leaves classify every point of an aligned grid correctly (no tolerance)."""
+    inst = synth.tiny2d(seed)
+    r = count.count_exact(inst.net, inst.C, inst.dvec, inst.lo, inst.hi, inst.max_depth,
+                          inst.max_leaves, trace=True)
+    h = 2.0 / cells
+    centers = -1.0 + h * (np.arange(cells) + 0.5)
+    X, Y = np.meshgrid(centers, centers, indexing="ij")
+    pts = np.stack([X.ravel(), Y.ravel()], axis=1)
+    g = slr.property_values(inst.net, inst.C, inst.dvec, pts)[:, 0]
+    unsafe_pt = g > 0.0
+    grid_frac = Fraction(int(unsafe_pt.sum()), cells * cells)
+    assert r["unsafe_exact"] <= grid_frac <= r["unsafe_exact"] + r["undecided_exact"]
+    G = unsafe_pt.reshape(cells, cells)
+    for lev in r["levels"]:
+        for i, c in enumerate(lev["cls"]):
+            if c == 0:
+                continue
+            i0 = int(round((lev["lo"][i, 0] + 1.0) / h))
+            i1 = int(round((lev["hi"][i, 0] + 1.0) / h))
+            j0 = int(round((lev["lo"][i, 1] + 1.0) / h))
+            j1 = int(round((lev["hi"][i, 1] + 1.0) / h))
+            blockv = G[i0:i1, j0:j1]
+            assert blockv.size > 0
+            if c == 1:
+                assert blockv.all()
+            else:
+                assert not blockv.any()
+
+
+def pin_accounting(seed=1):
+    inst = synth.tiny2d(seed)
+    prev = None
+    for D in (6, 10, 14):
+        r = count.count_exact(inst.net, inst.C, inst.dvec, inst.lo, inst.hi, D, 1 << 22,
+                              trace=True)
+        assert r["unsafe_exact"] + r["safe_exact"] + r["undecided_exact"] == 1
+        if prev is not None:
+            assert prev["unsafe_exact"] <= r["unsafe_exact"]
+            assert prev["safe_exact"] <= r["safe_exact"]
+        prev = r
+        for lev in r["levels"]:
+            t = lev["depth"]
+            w = lev["hi"] - lev["lo"]
+            # on a cube every box of depth t is the cube halved t times, widest side first
+            assert np.all(w[:, t % 2] == 2.0 * 2.0 ** -(t // 2))
+            assert np.all(lev["path"] >> np.uint64(t) == 1)
+
+
+ALL_PINS = [pin_eq1_single_relu, pin_two_neurons, pin_linear_regime, pin_soundness,
+            pin_irwin_hall, pin_abs_closed_form, pin_dense_grid, pin_accounting]
