@@ -1,0 +1,172 @@
+#!/usr/bin/env python3
+"""Throughput of the exact #DNN-Verification count (Alg. 1 with SLR) on one MI355X.
+
+One step = one complete ``count_exact`` on the 5-input, 6x50 ReLU network (He-normal, seed 0)
+over [0,1]^5 with the unsafe property y0 - y1 > 0, max depth 40, a 2^20-leaf budget and
+65536-box bound launches: every level of the branch-and-bound tree is bounded, classified,
+compacted and bisected on the GPU, and the exact leaf volumes are summed.  The network, the
+property and the workspace are resident in HBM before the timed region starts.
+
+Prints one JSON line: ``value`` is boxes bounded per second (whole job), ``ms_per_step`` the
+time to the final bracket; ``roofline`` rates the bound kernel (the dominant kernel) against
+the FP32 MFMA peak from its HIP-event-timed launches; ``cpu_baseline`` times the FP64 oracle
+on a bounded sample of the same workload on the host cores.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "boxes bounded/s + time-to-exact unsafe volume, plain vs batched+α on 1 GPU"
+PEAK_FP32_MFMA = 157.3      # TFLOP/s, MI355X dense FP32 matrix
+PEAK_HBM = 8000.0           # GB/s
+
+
+def flops_per_box(sizes, rows):
+    """Algorithmic flops of the bound kernel per box (contractions only).
+
+    First layer: d multiply-adds for the center and d multiplies for the slopes per neuron
+    (3 d flops); each hidden-to-hidden layer: the center equation (d + 1 columns) times W and
+    the radius (1 column) times |W|, 2 n_in n_out (d + 2) flops; the folded output rows the same
+    with n_out = rows.
+    """
+    d = sizes[0]
+    f = 3 * d * sizes[1]
+    hidden = sizes[1:-1]
+    for a, b in zip(hidden[:-1], hidden[1:]):
+        f += 2 * a * b * (d + 2)
+    f += 2 * hidden[-1] * rows * (d + 2)
+    return f
+
+
+def bytes_per_box(d):
+    """Algorithmic HBM bytes of the bound kernel per box: corners in, class out."""
+    return 2 * d * 4 + 1
+
+
+def kernel_source_hash():
+    src = os.path.join(ROOT, "paper_2312_05890_amd", "csrc", "slr_kernels.hip")
+    return hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per bound launch from the committed rocprofv3 counter summary, if current."""
+    path = os.path.join(ROOT, "profiles", "bound_f32_acas_traffic.json")
+    try:
+        rec = json.load(open(path))
+    except (OSError, ValueError):
+        return None
+    if rec.get("kernel_source_sha256_16") != kernel_source_hash():
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def cpu_baseline(seed, leaves):
+    """The FP64 oracle, untuned, on the same network with a smaller leaf budget."""
+    from oracle import count
+    import synth
+    try:
+        from threadpoolctl import threadpool_info
+        cores = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+    except Exception:
+        cores = os.cpu_count()
+    inst = synth.acas(seed)
+    t0 = time.perf_counter()
+    r = count.count_exact(inst.net, inst.C, inst.dvec, inst.lo, inst.hi, inst.max_depth, leaves)
+    dt = time.perf_counter() - t0
+    return {"value": r["n_boxes_bounded"] / dt, "unit": "boxes/s", "cores": cores,
+            "kind": "oracle",
+            "sample": f"FP64 NumPy oracle count_exact on the same network and property with a "
+                      f"{leaves}-leaf budget ({r['n_boxes_bounded']} boxes, levels 0-"
+                      f"{r['depth_reached']}), {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--cpu-leaves", type=int, default=1 << 15)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on exactly one GPU (asked for {args.gpus}); the "
+              "multi-GPU split of the frontier is described but not built", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np  # noqa: F401
+    import torch
+    import synth
+    import paper_2312_05890_amd as E
+
+    inst = synth.acas(args.seed)
+    net = E.Net(inst.net)
+    prop = E.Property(net, inst.C, inst.dvec)
+    chunk = 65536
+    ws = torch.empty(E.workspace_size(net, prop, inst.max_leaves), dtype=torch.uint8,
+                     device="cuda")
+
+    def step(timing):
+        return E.count_exact(net, prop, inst.lo, inst.hi, inst.max_depth, inst.max_leaves,
+                             chunk=chunk, workspace=ws, timing=timing)
+
+    for _ in range(args.warmup):
+        step(False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    res = [step(True) for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+
+    boxes = sum(r["n_boxes_bounded"] for r in res)
+    fpb = flops_per_box(inst.sizes, inst.C.shape[0])
+    bound_s = sum(r["bound_ms"] for r in res) / 1e3
+    launches = sum(r["bound_launches"] for r in res)
+    achieved = boxes * fpb / bound_s / 1e12
+    traffic = measured_traffic()
+    r0 = res[-1]
+    line = {
+        "metric": METRIC,
+        "value": boxes / dt,
+        "unit": "boxes/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": dt / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "exact count, 5-50x6-5 ReLU MLP (He-normal seed %d), [0,1]^5, "
+                               "unsafe iff y0-y1>0, max depth 40, 2^20-leaf budget, 65536-box "
+                               "launches" % args.seed,
+                   "mode": "plain"},
+        "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_FP32_MFMA,
+                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_MFMA,
+                     "traffic": traffic},
+        "bound_kernel": {"flops_per_box": fpb, "bytes_per_box": bytes_per_box(inst.sizes[0]),
+                         "avg_launch_us": bound_s / launches * 1e6,
+                         "launches_per_step": launches // args.steps,
+                         "boxes_per_s": boxes / bound_s},
+        "time_to_bracket_ms": r0["seconds"] * 1e3,
+        "bracket": [r0["unsafe"], r0["unsafe"] + r0["undecided"]],
+        "boxes_per_step": r0["n_boxes_bounded"],
+        "depth_reached": r0["depth_reached"],
+        "recheck64_per_step": r0["n_recheck64"],
+    }
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(args.seed, args.cpu_leaves)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

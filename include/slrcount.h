@@ -1,0 +1,183 @@
+/*
+ * slrcount: #DNN-Verification counting with Symbolic Linear Relaxation on MI355X (gfx950).
+ *
+ * The engine answers the counting version of DNN verification (paper §2.3): for a ReLU
+ * network N, an input box P (the precondition, §2.1) and an unsafe output set given as linear
+ * rows (the negated postcondition, §3), it returns a sound bracket on the fraction of P whose
+ * outputs are unsafe (the violation rate, §2.3).  It follows Alg. 1 (§3): every box of one
+ * branch-and-bound level is bounded at once (§3), with a lower and an upper linear equation
+ * per neuron relaxed at crossing ReLUs by Eq. 1 (§2.2); boxes whose reachable set lies inside
+ * the unsafe set add their volume, boxes that cannot reach it are dropped, the rest are
+ * bisected (iterative refinement, §2.2).
+ *
+ * Conventions for every entry point:
+ *   - return value: SLR_OK (0) or SLR_BUDGET (1) on success, a negative SLR_E* code on error;
+ *     last_error() then holds a message (thread-local, owned by the library, valid until the
+ *     next call on the same thread);
+ *   - "host" pointers are read synchronously during the call and may be freed afterwards;
+ *     "device" pointers are HIP device memory owned by the caller;
+ *   - arrays are dense and row-major; all inputs are validated before any GPU work starts;
+ *   - a stream argument is a hipStream_t (NULL = the default stream).
+ */
+#ifndef SLRCOUNT_H
+#define SLRCOUNT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    SLR_OK = 0,           /* finished; for counts: nothing left undecided                    */
+    SLR_BUDGET = 1,       /* depth or leaf budget reached: the result is a valid bracket     */
+    SLR_EINVAL = -1,      /* bad argument: shape, NaN/Inf, lo > hi, non-float32 corner, ...   */
+    SLR_ENOMEM = -2,      /* workspace too small or device allocation failed                 */
+    SLR_EHIP = -3,        /* HIP runtime error                                                */
+    SLR_EINTERNAL = -4,   /* an internal consistency check failed                            */
+    SLR_EUNSUPPORTED = -5 /* valid input outside the sizes this build supports               */
+};
+
+/* Box classes written by bound_boxes and recorded in traces. */
+enum { SLR_UNDECIDED = 0, SLR_UNSAFE = 1, SLR_SAFE = 2 };
+
+typedef struct slr_net slr_net;            /* opaque; immutable after load_net            */
+typedef struct slr_property slr_property;  /* opaque; immutable after load_property       */
+
+/*
+ * load_net: copy a ReLU multilayer perceptron to the device.
+ *   n_affine  number of affine layers (>= 2: at least one hidden ReLU layer, at most 8);
+ *   sizes     host [n_affine + 1]: input dimension d (1..32), hidden widths (1..256), n_out
+ *             (1..64);
+ *   W         host [n_affine] pointers; W[l] is row-major [sizes[l+1], sizes[l]] float32;
+ *   b         host [n_affine] pointers; b[l] is [sizes[l+1]] float32.
+ * ReLU follows every affine layer but the last.  The float32 values are the network.
+ * *out receives a handle owned by the caller (release with free_net).  NaN/Inf weights give
+ * SLR_EINVAL.  The handle may be used concurrently from several threads and streams.
+ */
+int load_net(int32_t n_affine, const int32_t* sizes, const float* const* W,
+             const float* const* b, slr_net** out);
+void free_net(slr_net* net);
+
+/*
+ * load_property: the unsafe output set (the negated postcondition Q of §2.1 and §3).
+ * An output y is unsafe iff every row r of C y + d is strictly positive.  A single output box
+ * Y_l <= y <= Y_u is the special case with rows +e_i, -e_i (§3).
+ *   rows   1..16;  C host [rows, n_out] float32;  d host [rows] float32.
+ * The rows are folded into the last affine layer in FP64 (C W_L, C b_L + d) and kept on the
+ * device; the handle is immutable and must be released with free_property before its net.
+ */
+int load_property(const slr_net* net, int32_t rows, const float* C, const float* d,
+                  slr_property** out);
+void free_property(slr_property* prop);
+
+/*
+ * bound_boxes: one launch of the bound kernel over n boxes (the per-level step of Alg. 1).
+ *   lo, hi  device [n, d] float32 box corners (lo <= hi);
+ *   g_lo, g_hi  device [n, rows] float32: lower/upper bound of each property row over the box;
+ *   cls     device [n] int8 or NULL: SLR_UNSAFE if every row's lower bound is > 0, SLR_SAFE
+ *           if some row's upper bound is <= 0, SLR_UNDECIDED otherwise;
+ *   raw     0: bounds widened outward by the float32 rounding-error margin (sound), and boxes
+ *           whose class could change within that margin re-decided in FP64;
+ *           1: unwidened float32 bounds (for comparison with an FP64 reference), cls from them.
+ * Asynchronous on `stream`; no allocation; n = 0 is a no-op.  The caller keeps the buffers
+ * alive until the stream has passed the call.
+ */
+int bound_boxes(const slr_net* net, const slr_property* prop, int64_t n, const float* lo,
+                const float* hi, float* g_lo, float* g_hi, int8_t* cls, int32_t raw,
+                void* stream);
+
+/* Options of the exact count (Alg. 1). */
+typedef struct {
+    int32_t max_depth;      /* boxes still undecided at this depth are not split (0..62)   */
+    int64_t max_leaves;     /* leaf budget, applied at level boundaries (>= 1)              */
+    int32_t chunk;          /* boxes per bound launch (0 = 65536)                            */
+    void* workspace;        /* device memory of at least workspace_size() bytes             */
+    size_t workspace_bytes;
+    void* stream;           /* hipStream_t used for all work of the call                     */
+    /* optional per-box trace (host arrays, NULL to disable): for every bounded box, in level
+       order, its depth, path id (root 1, children 2p and 2p+1) and final class */
+    int64_t trace_capacity;
+    int32_t* trace_depth;
+    uint64_t* trace_path;
+    int8_t* trace_cls;
+    int32_t timing;         /* 1: time the bound-kernel launches with HIP events on `stream` */
+} slr_exact_opts;
+
+typedef struct {
+    double unsafe, safe, undecided;   /* volume fractions of the input box; they sum to 1   */
+    int64_t n_unsafe, n_safe, n_undecided;   /* leaf boxes per class                        */
+    int64_t n_boxes_bounded;          /* boxes evaluated by the bound kernel                 */
+    int64_t n_recheck64;              /* boxes re-decided in FP64                            */
+    int32_t depth_reached;            /* deepest level bounded                               */
+    int32_t status;                   /* SLR_OK or SLR_BUDGET                                */
+    double seconds;                   /* wall time of the call                               */
+    int64_t trace_count;              /* boxes written to the trace (<= trace_capacity)      */
+    double bound_ms;                  /* with timing: summed bound-kernel time per level (ms) */
+    int64_t bound_launches;           /* bound-kernel launches made by the call              */
+} slr_count_result;
+
+/*
+ * workspace_size: bytes of device workspace needed by count_exact / count_approx for a leaf
+ * budget `max_leaves` and up to `samples` sample points per split (0 for count_exact only).
+ */
+int workspace_size(const slr_net* net, const slr_property* prop, int64_t max_leaves,
+                   int32_t samples, size_t* bytes);
+
+/*
+ * count_exact: Alg. 1 level by level on the device.
+ *   lo, hi  host [d] float64 corners of the input box; each must be exactly representable
+ *           in float32 (SLR_EINVAL otherwise).
+ * Returns SLR_OK when nothing is left undecided, SLR_BUDGET when the depth or leaf budget
+ * stopped the search (out holds the sound bracket [unsafe, unsafe + undecided]).  Volumes are
+ * exact: every leaf of depth t holds 2^-t of the box.  Synchronizes `stream` before returning.
+ */
+int count_exact(const slr_net* net, const slr_property* prop, const double* lo, const double* hi,
+                const slr_exact_opts* opts, slr_count_result* out);
+
+/* Options of the approximate count (CountingProVe with count_exact as leaf backend, §2.3). */
+typedef struct {
+    int32_t trials;          /* independent trials T (1..64)                                */
+    int32_t samples;         /* uniform samples per split (1..65536)                        */
+    double confidence;       /* e.g. 0.99: bound <= violation rate with this probability    */
+    uint64_t seed;           /* Philox4x32-10 key                                          */
+    int32_t max_splits;      /* cap on splits per trial                                    */
+    int32_t grid_bits;       /* split points lie on the grid lo + k (hi - lo) 2^-grid_bits  */
+    double resolve_tol;      /* a subdomain is resolved when <= this fraction is undecided  */
+    slr_exact_opts leaf;     /* options (and workspace) of each leaf count                  */
+} slr_approx_opts;
+
+typedef struct {
+    double lower_bound;      /* 2^-beta min_i estimate[i], beta = log2(1/(1-confidence))/T  */
+    double estimate[64];     /* per-trial estimate 2^s v f                                  */
+    int32_t splits[64];      /* per-trial number of splits s                                */
+    int32_t trials;
+    double seconds;
+} slr_approx_result;
+
+/*
+ * count_approx: probabilistic lower bound on the violation rate.  Each trial halves the
+ * domain (at the lower median of the violating samples along a random dimension, keeping a
+ * random side) until count_exact resolves the subdomain; see the implementation file for the
+ * exact draw layout.  Synchronizes opts->leaf.stream.
+ */
+int count_approx(const slr_net* net, const slr_property* prop, const double* lo,
+                 const double* hi, const slr_approx_opts* opts, slr_approx_result* out);
+
+/*
+ * sample_violations: concrete float32 forward pass of n points (device [n, d]) writing
+ * viol[i] = 1 if every property row is > 0 at point i, else 0 (device int8 [n]).
+ * Asynchronous on `stream`.
+ */
+int sample_violations(const slr_net* net, const slr_property* prop, int64_t n, const float* x,
+                      int8_t* viol, void* stream);
+
+/* Message of the last failed call on this thread ("" if none). */
+const char* last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SLRCOUNT_H */

@@ -1,0 +1,9 @@
+"""MI355X-native #DNN-Verification counter with Symbolic Linear Relaxation.
+
+The engine is the C-ABI library ``libslrcount.so`` (hand-written HIP for gfx950, declared in
+``include/slrcount.h``); this package is its thin Python binding.  Build the library with
+``python -m paper_2312_05890_amd.build``.
+"""
+from .slrcount import (EXPORTS, SAFE, SLR_BUDGET, SLR_OK, UNDECIDED, UNSAFE, Net, Property,  # noqa: F401
+                       SlrError, bound_boxes, count_approx, count_exact, last_error, lib,
+                       load_net, load_property, sample_violations, workspace_size)

@@ -1,0 +1,732 @@
+// Host engine of the SLR counter: validation, device-resident networks and properties, the
+// level driver of the exact count (Alg. 1) and the approximate count built on it.
+#include "../../include/slrcount.h"
+#include "slr_internal.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+int hip_fail(hipError_t e, const char* what) {
+    return fail(SLR_EHIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+#define HIP_TRY(expr, what)                              \
+    do {                                                 \
+        hipError_t _e = (expr);                          \
+        if (_e != hipSuccess) return hip_fail(_e, what); \
+    } while (0)
+
+constexpr double kKappa = 2.0;   // safety factor on the rounding-error bounds
+
+double gamma_n(double n, double u) { return n * u / (1.0 - n * u); }
+
+// float32 value >= x
+float round_up_f32(double x) {
+    float f = (float)x;
+    if ((double)f < x) f = std::nextafter(f, INFINITY);
+    return f;
+}
+
+int ceil_div(int a, int b) { return (a + b - 1) / b; }
+
+// K-steps that carry at least one real input neuron (layout: neuron 16 (s/4) + 4 g + s%4).
+int k_steps(int n_in) {
+    const int mt = ceil_div(n_in, 16);
+    const int r = n_in - 16 * (mt - 1);
+    return 4 * (mt - 1) + std::min(4, r);
+}
+
+// MFMA A-operand fragments of W [n_out][n_in]: frag[mt][s][lane] = W[16 mt + lane % 16][k]
+// with k = 16 (s / 4) + 4 (lane / 16) + s % 4 (zero outside the matrix or beyond ks).
+std::vector<float> pack_fragments(const float* W, int n_out, int n_in, int ks, int ks_alloc) {
+    const int mt_out = ceil_div(n_out, 16);
+    std::vector<float> f((size_t)mt_out * ks_alloc * 64, 0.f);
+    for (int mt = 0; mt < mt_out; ++mt)
+        for (int s = 0; s < ks; ++s)
+            for (int lane = 0; lane < 64; ++lane) {
+                const int row = 16 * mt + lane % 16;
+                const int k = 16 * (s / 4) + 4 * (lane / 16) + s % 4;
+                if (row < n_out && k < n_in)
+                    f[((size_t)mt * ks_alloc + s) * 64 + lane] = W[(size_t)row * n_in + k];
+            }
+    return f;
+}
+
+bool all_finite(const float* p, size_t n) {
+    for (size_t i = 0; i < n; ++i)
+        if (!std::isfinite(p[i])) return false;
+    return true;
+}
+
+bool is_device_ptr(const void* p) {
+    if (!p) return false;
+    hipPointerAttribute_t a;
+    hipError_t e = hipPointerGetAttributes(&a, p);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return false;
+    }
+    return a.type == hipMemoryTypeDevice || a.type == hipMemoryTypeManaged ||
+           a.type == hipMemoryTypeUnified;
+}
+
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC 2011): ten rounds of multiply-xor on a
+// 128-bit counter under a 64-bit key bumped by the Weyl constants between rounds.
+struct Philox {
+    static void block(const uint32_t ctr_in[4], const uint32_t key_in[2], uint32_t out[4]) {
+        uint32_t c0 = ctr_in[0], c1 = ctr_in[1], c2 = ctr_in[2], c3 = ctr_in[3];
+        uint32_t k0 = key_in[0], k1 = key_in[1];
+        for (int r = 0; r < 10; ++r) {
+            if (r > 0) {
+                k0 += 0x9E3779B9u;
+                k1 += 0xBB67AE85u;
+            }
+            const uint64_t p0 = (uint64_t)0xD2511F53u * c0;
+            const uint64_t p1 = (uint64_t)0xCD9E8D57u * c2;
+            const uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+            const uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+            const uint32_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
+            c0 = n0;
+            c1 = lo1;
+            c2 = n2;
+            c3 = lo0;
+        }
+        out[0] = c0;
+        out[1] = c1;
+        out[2] = c2;
+        out[3] = c3;
+    }
+    static double u53(uint32_t a, uint32_t b) {
+        return ((double)(a >> 5) * 67108864.0 + (double)(b >> 6)) / 9007199254740992.0;
+    }
+};
+
+constexpr uint32_t kTagSample = 1, kTagSplit = 2;
+
+}  // namespace
+
+// ------------------------------------------------------------------------------------------
+// Network and property handles
+// ------------------------------------------------------------------------------------------
+struct slr_net {
+    NetDev dev{};
+    void* mem = nullptr;
+    int n_affine = 0;
+    std::vector<int> sizes;
+    std::vector<double> WL, bL;   // last affine layer in float64 (for property folding)
+};
+
+struct slr_property {
+    PropDev dev{};
+    void* mem = nullptr;
+    const slr_net* net = nullptr;
+    int rows = 0;
+};
+
+extern "C" const char* last_error(void) { return g_err.c_str(); }
+
+extern "C" int load_net(int32_t n_affine, const int32_t* sizes, const float* const* W,
+                        const float* const* b, slr_net** out) {
+    g_err.clear();
+    if (!out) return fail(SLR_EINVAL, "load_net: out is NULL");
+    *out = nullptr;
+    if (n_affine < 2 || n_affine > SLR_MAX_AFFINE)
+        return fail(SLR_EINVAL, "load_net: n_affine must be in [2, %d], got %d", SLR_MAX_AFFINE, n_affine);
+    if (!sizes || !W || !b) return fail(SLR_EINVAL, "load_net: NULL array");
+    const int d = sizes[0];
+    if (d < 1 || d > SLR_MAX_D) return fail(SLR_EINVAL, "load_net: input dimension %d not in [1, %d]", d, SLR_MAX_D);
+    for (int l = 1; l < n_affine; ++l)
+        if (sizes[l] < 1 || sizes[l] > SLR_MAX_WIDTH)
+            return fail(SLR_EINVAL, "load_net: hidden width %d not in [1, %d]", sizes[l], SLR_MAX_WIDTH);
+    if (sizes[n_affine] < 1 || sizes[n_affine] > SLR_MAX_OUT)
+        return fail(SLR_EINVAL, "load_net: output width %d not in [1, %d]", sizes[n_affine], SLR_MAX_OUT);
+    for (int l = 0; l < n_affine; ++l) {
+        if (!W[l] || !b[l]) return fail(SLR_EINVAL, "load_net: layer %d has a NULL array", l);
+        if (!all_finite(W[l], (size_t)sizes[l + 1] * sizes[l]) || !all_finite(b[l], sizes[l + 1]))
+            return fail(SLR_EINVAL, "load_net: layer %d has a NaN or Inf", l);
+    }
+
+    // host images of every device array, then one allocation
+    std::vector<std::vector<char>> blobs;
+    auto add = [&](const void* p, size_t bytes) {
+        blobs.emplace_back((const char*)p, (const char*)p + bytes);
+        return blobs.size() - 1;
+    };
+    NetDev nd{};
+    nd.d = d;
+    nd.n_affine = n_affine;
+    nd.n1 = sizes[1];
+    nd.mt1 = ceil_div(sizes[1], 16);
+    nd.n_last = sizes[n_affine - 1];
+    nd.mt_last = ceil_div(nd.n_last, 16);
+    nd.mt_max = 0;
+    nd.n_max = 0;
+    for (int l = 1; l < n_affine; ++l) {
+        nd.mt_max = std::max(nd.mt_max, ceil_div(sizes[l], 16));
+        nd.n_max = std::max(nd.n_max, sizes[l]);
+    }
+    const double u32 = std::ldexp(1.0, -24), u64 = std::ldexp(1.0, -53);
+    nd.kfirst = round_up_f32(kKappa * gamma_n(d + 2, u32));
+    nd.kconc = round_up_f32(kKappa * gamma_n(d + 3, u32));
+    nd.krelu = round_up_f32(kKappa * gamma_n(4, u32));
+    nd.kfirst64 = kKappa * gamma_n(d + 2, u64) * (1 + 1e-12);
+    nd.kconc64 = kKappa * gamma_n(d + 3, u64) * (1 + 1e-12);
+    nd.krelu64 = kKappa * gamma_n(4, u64) * (1 + 1e-12);
+
+    const size_t i_w1 = add(W[0], sizeof(float) * sizes[1] * d);
+    const size_t i_b1 = add(b[0], sizeof(float) * sizes[1]);
+    struct MidIdx { size_t frag, w, bias, absrow; };
+    std::vector<MidIdx> mids;
+    for (int l = 1; l <= n_affine - 2; ++l) {
+        const int n_in = sizes[l], n_out = sizes[l + 1];
+        MidLayer& L = nd.mid[l - 1];
+        L.n_in = n_in;
+        L.n_out = n_out;
+        L.mt_out = ceil_div(n_out, 16);
+        L.ks = k_steps(n_in);
+        L.ks_alloc = (L.ks + 3) / 4 * 4;
+        L.kgam = round_up_f32(kKappa * gamma_n(n_in + 2, u32));
+        L.kgam64 = kKappa * gamma_n(n_in + 2, u64) * (1 + 1e-12);
+        std::vector<float> frag = pack_fragments(W[l], n_out, n_in, L.ks, L.ks_alloc);
+        std::vector<float> bias(16 * L.mt_out, 0.f), absrow(16 * L.mt_out, 0.f);
+        for (int jrow = 0; jrow < n_out; ++jrow) {
+            bias[jrow] = b[l][jrow];
+            double s = 0;
+            for (int k = 0; k < n_in; ++k) s += std::fabs((double)W[l][(size_t)jrow * n_in + k]);
+            absrow[jrow] = round_up_f32(s * (1 + 1e-12));
+        }
+        MidIdx mi;
+        mi.frag = add(frag.data(), frag.size() * sizeof(float));
+        mi.w = add(W[l], sizeof(float) * n_out * n_in);
+        mi.bias = add(bias.data(), bias.size() * sizeof(float));
+        mi.absrow = add(absrow.data(), absrow.size() * sizeof(float));
+        mids.push_back(mi);
+    }
+    std::vector<size_t> offs(blobs.size());
+    size_t total = 0;
+    for (size_t i = 0; i < blobs.size(); ++i) {
+        offs[i] = total;
+        total += (blobs[i].size() + 255) / 256 * 256;
+    }
+    void* mem = nullptr;
+    hipError_t e = hipMalloc(&mem, total);
+    if (e != hipSuccess) return fail(SLR_ENOMEM, "load_net: hipMalloc(%zu): %s", total, hipGetErrorString(e));
+    std::vector<char> host(total, 0);
+    for (size_t i = 0; i < blobs.size(); ++i) memcpy(host.data() + offs[i], blobs[i].data(), blobs[i].size());
+    e = hipMemcpy(mem, host.data(), total, hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        (void)hipFree(mem);
+        return hip_fail(e, "load_net: upload");
+    }
+    char* base = (char*)mem;
+    nd.w1 = (const float*)(base + offs[i_w1]);
+    nd.b1 = (const float*)(base + offs[i_b1]);
+    for (int l = 0; l < n_affine - 2; ++l) {
+        nd.mid[l].wfrag = (const float*)(base + offs[mids[l].frag]);
+        nd.mid[l].w = (const float*)(base + offs[mids[l].w]);
+        nd.mid[l].bias = (const float*)(base + offs[mids[l].bias]);
+        nd.mid[l].absrow = (const float*)(base + offs[mids[l].absrow]);
+    }
+    slr_net* net = new slr_net;
+    net->dev = nd;
+    net->mem = mem;
+    net->n_affine = n_affine;
+    net->sizes.assign(sizes, sizes + n_affine + 1);
+    const int nL = sizes[n_affine], kL = sizes[n_affine - 1];
+    net->WL.resize((size_t)nL * kL);
+    net->bL.resize(nL);
+    for (size_t i = 0; i < net->WL.size(); ++i) net->WL[i] = W[n_affine - 1][i];
+    for (int i = 0; i < nL; ++i) net->bL[i] = b[n_affine - 1][i];
+    *out = net;
+    return SLR_OK;
+}
+
+extern "C" void free_net(slr_net* net) {
+    if (!net) return;
+    (void)hipFree(net->mem);
+    delete net;
+}
+
+extern "C" int load_property(const slr_net* net, int32_t rows, const float* C, const float* dv,
+                             slr_property** out) {
+    g_err.clear();
+    if (!out) return fail(SLR_EINVAL, "load_property: out is NULL");
+    *out = nullptr;
+    if (!net) return fail(SLR_EINVAL, "load_property: net is NULL");
+    if (rows < 1 || rows > SLR_MAX_ROWS) return fail(SLR_EINVAL, "load_property: rows %d not in [1, %d]", rows, SLR_MAX_ROWS);
+    if (!C || !dv) return fail(SLR_EINVAL, "load_property: NULL array");
+    const int n_out = net->sizes[net->n_affine];
+    const int K = net->sizes[net->n_affine - 1];
+    if (!all_finite(C, (size_t)rows * n_out) || !all_finite(dv, rows))
+        return fail(SLR_EINVAL, "load_property: NaN or Inf in C or d");
+    std::vector<double> wg64((size_t)rows * K), bg64(rows), ag64(rows);
+    std::vector<float> wg((size_t)rows * K), bg(rows), ag(rows);
+    for (int r = 0; r < rows; ++r) {
+        double bsum = dv[r];
+        double asum = 0;
+        for (int o = 0; o < n_out; ++o) bsum += (double)C[r * n_out + o] * net->bL[o];
+        for (int k = 0; k < K; ++k) {
+            double s = 0, sa = 0;
+            for (int o = 0; o < n_out; ++o) {
+                s += (double)C[r * n_out + o] * net->WL[(size_t)o * K + k];
+                sa += std::fabs((double)C[r * n_out + o]) * std::fabs(net->WL[(size_t)o * K + k]);
+            }
+            wg64[(size_t)r * K + k] = s;
+            wg[(size_t)r * K + k] = (float)s;
+            asum += sa;
+        }
+        bg64[r] = bsum;
+        bg[r] = (float)bsum;
+        ag64[r] = asum * (1 + 1e-12);
+        ag[r] = round_up_f32(asum * (1 + 1e-12));
+    }
+    const double u32 = std::ldexp(1.0, -24), u64 = std::ldexp(1.0, -53);
+    PropDev pd{};
+    pd.rows = rows;
+    pd.n_last = K;
+    pd.kout = round_up_f32(kKappa * gamma_n(K + 3, u32));
+    pd.kout64 = kKappa * gamma_n(K + n_out + 3, u64) * (1 + 1e-12);
+    const size_t s_wg = (wg.size() * 4 + 255) / 256 * 256, s_r = (rows * 4 + 255) / 256 * 256;
+    const size_t s_wg64 = (wg64.size() * 8 + 255) / 256 * 256, s_r64 = (rows * 8 + 255) / 256 * 256;
+    const size_t total = s_wg + 2 * s_r + s_wg64 + 2 * s_r64;
+    std::vector<char> host(total, 0);
+    size_t o = 0;
+    memcpy(host.data() + o, wg.data(), wg.size() * 4);
+    const size_t o_wg = o; o += s_wg;
+    memcpy(host.data() + o, bg.data(), rows * 4);
+    const size_t o_bg = o; o += s_r;
+    memcpy(host.data() + o, ag.data(), rows * 4);
+    const size_t o_ag = o; o += s_r;
+    memcpy(host.data() + o, wg64.data(), wg64.size() * 8);
+    const size_t o_wg64 = o; o += s_wg64;
+    memcpy(host.data() + o, bg64.data(), rows * 8);
+    const size_t o_bg64 = o; o += s_r64;
+    memcpy(host.data() + o, ag64.data(), rows * 8);
+    const size_t o_ag64 = o;
+    void* mem = nullptr;
+    hipError_t e = hipMalloc(&mem, total);
+    if (e != hipSuccess) return fail(SLR_ENOMEM, "load_property: hipMalloc: %s", hipGetErrorString(e));
+    e = hipMemcpy(mem, host.data(), total, hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        (void)hipFree(mem);
+        return hip_fail(e, "load_property: upload");
+    }
+    char* base = (char*)mem;
+    pd.wg = (const float*)(base + o_wg);
+    pd.bg = (const float*)(base + o_bg);
+    pd.ag = (const float*)(base + o_ag);
+    pd.wg64 = (const double*)(base + o_wg64);
+    pd.bg64 = (const double*)(base + o_bg64);
+    pd.ag64 = (const double*)(base + o_ag64);
+    slr_property* p = new slr_property;
+    p->dev = pd;
+    p->mem = mem;
+    p->net = net;
+    p->rows = rows;
+    *out = p;
+    return SLR_OK;
+}
+
+extern "C" void free_property(slr_property* prop) {
+    if (!prop) return;
+    (void)hipFree(prop->mem);
+    delete prop;
+}
+
+// ------------------------------------------------------------------------------------------
+// Workspace layout of the exact count (all regions 256-byte aligned)
+// ------------------------------------------------------------------------------------------
+namespace {
+
+constexpr int kMaxLevels = 63;
+
+struct Workspace {
+    float *lo[2], *hi[2];
+    unsigned long long* path[2];
+    int8_t* cls;
+    unsigned* tile_und;
+    LevelStats* stats;           // [kMaxLevels]
+    double* vol;                 // [3]
+    unsigned long long* counts;  // [3]
+    unsigned long long* rechecks;
+    unsigned* err;
+    float* samples;              // [samples][d]
+    int8_t* viol;                // [samples]
+    size_t bytes;
+};
+
+size_t align256(size_t x) { return (x + 255) / 256 * 256; }
+
+Workspace layout_ws(char* base, int d, int64_t cap, int samples) {
+    Workspace w{};
+    size_t o = 0;
+    auto take = [&](size_t bytes) {
+        char* p = base ? base + o : nullptr;
+        o += align256(bytes);
+        return p;
+    };
+    for (int s = 0; s < 2; ++s) {
+        w.lo[s] = (float*)take(sizeof(float) * d * cap);
+        w.hi[s] = (float*)take(sizeof(float) * d * cap);
+        w.path[s] = (unsigned long long*)take(sizeof(unsigned long long) * cap);
+    }
+    w.cls = (int8_t*)take(cap);
+    w.tile_und = (unsigned*)take(sizeof(unsigned) * level_tiles(cap));
+    w.stats = (LevelStats*)take(sizeof(LevelStats) * kMaxLevels);
+    w.vol = (double*)take(sizeof(double) * 3);
+    w.counts = (unsigned long long*)take(sizeof(unsigned long long) * 3);
+    w.rechecks = (unsigned long long*)take(sizeof(unsigned long long));
+    w.err = (unsigned*)take(sizeof(unsigned));
+    w.samples = (float*)take(sizeof(float) * (size_t)d * std::max(samples, 0));
+    w.viol = (int8_t*)take(std::max(samples, 0));
+    w.bytes = o;
+    return w;
+}
+
+int check_pair(const slr_net* net, const slr_property* prop, const char* who) {
+    if (!net) return fail(SLR_EINVAL, "%s: net is NULL", who);
+    if (!prop) return fail(SLR_EINVAL, "%s: property is NULL", who);
+    if (prop->net != net) return fail(SLR_EINVAL, "%s: property was loaded for another net", who);
+    if (!bound_f32_supported(net->dev, prop->dev))
+        return fail(SLR_EUNSUPPORTED, "%s: network shape (d=%d, widths up to %d) exceeds this build's LDS tiles", who, net->dev.d, net->dev.n_max);
+    return SLR_OK;
+}
+
+int check_box(const slr_net* net, const double* lo, const double* hi, const char* who) {
+    if (!lo || !hi) return fail(SLR_EINVAL, "%s: NULL box", who);
+    for (int k = 0; k < net->dev.d; ++k) {
+        if (!std::isfinite(lo[k]) || !std::isfinite(hi[k]))
+            return fail(SLR_EINVAL, "%s: non-finite box corner", who);
+        if ((double)(float)lo[k] != lo[k] || (double)(float)hi[k] != hi[k])
+            return fail(SLR_EINVAL, "%s: box corner %d is not exactly representable in float32", who, k);
+        if (lo[k] > hi[k]) return fail(SLR_EINVAL, "%s: lo > hi in dimension %d", who, k);
+    }
+    return SLR_OK;
+}
+
+}  // namespace
+
+extern "C" int workspace_size(const slr_net* net, const slr_property* prop, int64_t max_leaves,
+                              int32_t samples, size_t* bytes) {
+    g_err.clear();
+    if (!bytes) return fail(SLR_EINVAL, "workspace_size: bytes is NULL");
+    if (!net) return fail(SLR_EINVAL, "workspace_size: net is NULL");
+    (void)prop;
+    if (max_leaves < 1) return fail(SLR_EINVAL, "workspace_size: max_leaves must be >= 1");
+    if (samples < 0) return fail(SLR_EINVAL, "workspace_size: samples must be >= 0");
+    *bytes = layout_ws(nullptr, net->dev.d, max_leaves, samples).bytes;
+    return SLR_OK;
+}
+
+extern "C" int bound_boxes(const slr_net* net, const slr_property* prop, int64_t n,
+                           const float* lo, const float* hi, float* g_lo, float* g_hi,
+                           int8_t* cls, int32_t raw, void* stream) {
+    g_err.clear();
+    int rc = check_pair(net, prop, "bound_boxes");
+    if (rc) return rc;
+    if (n < 0) return fail(SLR_EINVAL, "bound_boxes: n < 0");
+    if (raw != 0 && raw != 1) return fail(SLR_EINVAL, "bound_boxes: raw must be 0 or 1");
+    if (n == 0) return SLR_OK;
+    if (!is_device_ptr(lo) || !is_device_ptr(hi) || !is_device_ptr(g_lo) || !is_device_ptr(g_hi))
+        return fail(SLR_EINVAL, "bound_boxes: lo, hi, g_lo and g_hi must be device memory");
+    if (cls && !is_device_ptr(cls)) return fail(SLR_EINVAL, "bound_boxes: cls must be device memory");
+    hipStream_t s = (hipStream_t)stream;
+    int unsup = 0;
+    HIP_TRY(launch_bound_f32(net->dev, prop->dev, n, lo, hi, g_lo, g_hi, cls, raw, s, &unsup),
+            "bound_boxes: bound kernel");
+    if (unsup) return fail(SLR_EUNSUPPORTED, "bound_boxes: shape not supported");
+    if (!raw && cls)
+        HIP_TRY(launch_recheck64(net->dev, prop->dev, n, lo, hi, g_lo, g_hi, cls, nullptr, s),
+                "bound_boxes: recheck kernel");
+    return SLR_OK;
+}
+
+extern "C" int sample_violations(const slr_net* net, const slr_property* prop, int64_t n,
+                                 const float* x, int8_t* viol, void* stream) {
+    g_err.clear();
+    int rc = check_pair(net, prop, "sample_violations");
+    if (rc) return rc;
+    if (n < 0) return fail(SLR_EINVAL, "sample_violations: n < 0");
+    if (n == 0) return SLR_OK;
+    if (!is_device_ptr(x) || !is_device_ptr(viol))
+        return fail(SLR_EINVAL, "sample_violations: x and viol must be device memory");
+    HIP_TRY(launch_sample_forward(net->dev, prop->dev, n, x, viol, (hipStream_t)stream),
+            "sample_violations: kernel");
+    return SLR_OK;
+}
+
+namespace {
+
+int count_exact_impl(const slr_net* net, const slr_property* prop, const double* lo,
+                     const double* hi, const slr_exact_opts* o, const Workspace& w,
+                     slr_count_result* out) {
+    const auto t0 = std::chrono::steady_clock::now();
+    hipStream_t s = (hipStream_t)o->stream;
+    const int d = net->dev.d;
+    const int D = o->max_depth;
+    const int64_t M = o->max_leaves;
+    const int64_t chunk = o->chunk > 0 ? o->chunk : 65536;
+
+    HIP_TRY(hipMemsetAsync(w.stats, 0, sizeof(LevelStats) * kMaxLevels, s), "count_exact: clear");
+    HIP_TRY(hipMemsetAsync(w.rechecks, 0, sizeof(unsigned long long), s), "count_exact: clear");
+    HIP_TRY(hipMemsetAsync(w.err, 0, sizeof(unsigned), s), "count_exact: clear");
+    std::vector<float> root(2 * d);
+    for (int k = 0; k < d; ++k) {
+        root[k] = (float)lo[k];
+        root[d + k] = (float)hi[k];
+    }
+    const unsigned long long one = 1;
+    HIP_TRY(hipMemcpyAsync(w.lo[0], root.data(), sizeof(float) * d, hipMemcpyHostToDevice, s), "count_exact: root");
+    HIP_TRY(hipMemcpyAsync(w.hi[0], root.data() + d, sizeof(float) * d, hipMemcpyHostToDevice, s), "count_exact: root");
+    HIP_TRY(hipMemcpyAsync(w.path[0], &one, sizeof one, hipMemcpyHostToDevice, s), "count_exact: root");
+
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    if (o->timing) {
+        HIP_TRY(hipEventCreate(&ev0), "count_exact: event");
+        HIP_TRY(hipEventCreate(&ev1), "count_exact: event");
+    }
+    struct EventGuard {
+        hipEvent_t a, b;
+        ~EventGuard() {
+            if (a) (void)hipEventDestroy(a);
+            if (b) (void)hipEventDestroy(b);
+        }
+    } guard{ev0, ev1};
+    double bound_ms = 0.0;
+    int64_t launches = 0;
+    int64_t n = 1, resolved = 0, bounded = 0, tcount = 0;
+    int cur = 0, levels = 0, stop_level = 0, stopped = 0, status = SLR_OK;
+    std::vector<unsigned long long> hpath;
+    std::vector<int8_t> hcls;
+    for (int t = 0; t <= D; ++t) {
+        int unsup = 0;
+        if (ev0) HIP_TRY(hipEventRecord(ev0, s), "count_exact: event");
+        for (int64_t off = 0; off < n; off += chunk) {
+            const int64_t m = std::min(chunk, n - off);
+            HIP_TRY(launch_bound_f32(net->dev, prop->dev, m, w.lo[cur] + off * d, w.hi[cur] + off * d,
+                                     nullptr, nullptr, w.cls + off, 0, s, &unsup),
+                    "count_exact: bound kernel");
+            if (unsup) return fail(SLR_EUNSUPPORTED, "count_exact: shape not supported");
+            ++launches;
+        }
+        if (ev1) HIP_TRY(hipEventRecord(ev1, s), "count_exact: event");
+        HIP_TRY(launch_recheck64(net->dev, prop->dev, n, w.lo[cur], w.hi[cur], nullptr, nullptr,
+                                 w.cls, w.rechecks, s), "count_exact: recheck kernel");
+        HIP_TRY(launch_level_count(n, w.cls, w.tile_und, w.stats + t, s), "count_exact: count kernel");
+        LevelStats hs;
+        HIP_TRY(hipMemcpyAsync(&hs, w.stats + t, sizeof hs, hipMemcpyDeviceToHost, s), "count_exact: readback");
+        if (o->trace_capacity > 0 && o->trace_path && o->trace_cls && o->trace_depth && tcount < o->trace_capacity) {
+            const int64_t m = std::min<int64_t>(n, o->trace_capacity - tcount);
+            hpath.resize(m);
+            hcls.resize(m);
+            HIP_TRY(hipMemcpyAsync(hpath.data(), w.path[cur], m * sizeof(unsigned long long), hipMemcpyDeviceToHost, s), "count_exact: trace");
+            HIP_TRY(hipMemcpyAsync(hcls.data(), w.cls, m, hipMemcpyDeviceToHost, s), "count_exact: trace");
+            HIP_TRY(hipStreamSynchronize(s), "count_exact: sync");
+            for (int64_t i = 0; i < m; ++i) {
+                o->trace_depth[tcount + i] = t;
+                o->trace_path[tcount + i] = hpath[i];
+                o->trace_cls[tcount + i] = hcls[i];
+            }
+            tcount += m;
+        }
+        HIP_TRY(hipStreamSynchronize(s), "count_exact: sync");
+        if (ev0) {
+            float ms = 0.f;
+            HIP_TRY(hipEventElapsedTime(&ms, ev0, ev1), "count_exact: event");
+            bound_ms += ms;
+        }
+        bounded += n;
+        levels = t + 1;
+        resolved += (int64_t)(hs.unsafe_cnt + hs.safe_cnt);
+        const int64_t und = (int64_t)hs.undecided_cnt;
+        if ((int64_t)(hs.unsafe_cnt + hs.safe_cnt) + und != n)
+            return fail(SLR_EINTERNAL, "count_exact: level %d counts %lld boxes of %lld", t,
+                        (long long)(hs.unsafe_cnt + hs.safe_cnt + und), (long long)n);
+        if (und == 0) break;
+        if (t == D || resolved + 2 * und > M) {
+            stopped = 1;
+            stop_level = t;
+            status = SLR_BUDGET;
+            break;
+        }
+        HIP_TRY(launch_split(n, d, w.cls, w.tile_und, w.lo[cur], w.hi[cur], w.path[cur],
+                             w.lo[cur ^ 1], w.hi[cur ^ 1], w.path[cur ^ 1], w.err, s),
+                "count_exact: split kernel");
+        n = 2 * und;
+        cur ^= 1;
+    }
+    HIP_TRY(launch_volume(w.stats, levels, stop_level, stopped, w.vol, w.counts, w.err, s), "count_exact: volume kernel");
+    double vol[3];
+    unsigned long long counts[3], rechecks = 0;
+    unsigned err = 0;
+    HIP_TRY(hipMemcpyAsync(vol, w.vol, sizeof vol, hipMemcpyDeviceToHost, s), "count_exact: readback");
+    HIP_TRY(hipMemcpyAsync(counts, w.counts, sizeof counts, hipMemcpyDeviceToHost, s), "count_exact: readback");
+    HIP_TRY(hipMemcpyAsync(&rechecks, w.rechecks, sizeof rechecks, hipMemcpyDeviceToHost, s), "count_exact: readback");
+    HIP_TRY(hipMemcpyAsync(&err, w.err, sizeof err, hipMemcpyDeviceToHost, s), "count_exact: readback");
+    HIP_TRY(hipStreamSynchronize(s), "count_exact: sync");
+    if (err & 1u) return fail(SLR_EINTERNAL, "count_exact: a bisection midpoint is not exact in float32 (box too deep for its coordinates)");
+    if (err & 2u) return fail(SLR_EINTERNAL, "count_exact: leaf volumes do not sum to the box volume");
+    out->unsafe = vol[0];
+    out->safe = vol[1];
+    out->undecided = vol[2];
+    out->n_unsafe = (int64_t)counts[0];
+    out->n_safe = (int64_t)counts[1];
+    out->n_undecided = (int64_t)counts[2];
+    out->n_boxes_bounded = bounded;
+    out->n_recheck64 = (int64_t)rechecks;
+    out->depth_reached = levels - 1;
+    out->status = status;
+    out->trace_count = tcount;
+    out->bound_ms = bound_ms;
+    out->bound_launches = launches;
+    out->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    return status;
+}
+
+int check_exact_opts(const slr_net* net, const slr_exact_opts* o, int samples, Workspace* w, const char* who) {
+    if (!o) return fail(SLR_EINVAL, "%s: opts is NULL", who);
+    if (o->max_depth < 0 || o->max_depth > kMaxLevels - 1)
+        return fail(SLR_EINVAL, "%s: max_depth must be in [0, %d]", who, kMaxLevels - 1);
+    if (o->max_leaves < 1) return fail(SLR_EINVAL, "%s: max_leaves must be >= 1", who);
+    if (o->chunk < 0) return fail(SLR_EINVAL, "%s: chunk must be >= 0", who);
+    if (o->trace_capacity < 0) return fail(SLR_EINVAL, "%s: trace_capacity must be >= 0", who);
+    const size_t need = layout_ws(nullptr, net->dev.d, o->max_leaves, samples).bytes;
+    if (!o->workspace || o->workspace_bytes < need)
+        return fail(SLR_ENOMEM, "%s: workspace of %zu bytes is smaller than the %zu required", who,
+                    o->workspace_bytes, need);
+    if (!is_device_ptr(o->workspace)) return fail(SLR_EINVAL, "%s: workspace must be device memory", who);
+    *w = layout_ws((char*)o->workspace, net->dev.d, o->max_leaves, samples);
+    return SLR_OK;
+}
+
+}  // namespace
+
+extern "C" int count_exact(const slr_net* net, const slr_property* prop, const double* lo,
+                           const double* hi, const slr_exact_opts* opts, slr_count_result* out) {
+    g_err.clear();
+    int rc = check_pair(net, prop, "count_exact");
+    if (rc) return rc;
+    if (!out) return fail(SLR_EINVAL, "count_exact: out is NULL");
+    if ((rc = check_box(net, lo, hi, "count_exact"))) return rc;
+    Workspace w;
+    if ((rc = check_exact_opts(net, opts, 0, &w, "count_exact"))) return rc;
+    memset(out, 0, sizeof *out);
+    return count_exact_impl(net, prop, lo, hi, opts, w, out);
+}
+
+// Split point for [a, b] near med on the grid A + k (B - A) 2^-bits, kept one step inside (a, b);
+// intervals narrower than two steps are bisected at the midpoint.
+static double snap_split(double med, double a, double b, double A, double B, int bits) {
+    const double h = (B - A) * std::ldexp(1.0, -bits);
+    if (b - a < 2.0 * h) return 0.5 * (a + b);
+    double k = std::floor((med - A) / h + 0.5);
+    const double k_lo = std::floor((a - A) / h + 0.5) + 1;
+    const double k_hi = std::floor((b - A) / h + 0.5) - 1;
+    k = std::min(std::max(k, k_lo), k_hi);
+    return A + k * h;
+}
+
+extern "C" int count_approx(const slr_net* net, const slr_property* prop, const double* lo,
+                            const double* hi, const slr_approx_opts* opts, slr_approx_result* out) {
+    g_err.clear();
+    int rc = check_pair(net, prop, "count_approx");
+    if (rc) return rc;
+    if (!out || !opts) return fail(SLR_EINVAL, "count_approx: NULL argument");
+    if ((rc = check_box(net, lo, hi, "count_approx"))) return rc;
+    const slr_approx_opts& o = *opts;
+    if (o.trials < 1 || o.trials > 64) return fail(SLR_EINVAL, "count_approx: trials must be in [1, 64]");
+    if (o.samples < 1 || o.samples > 65536) return fail(SLR_EINVAL, "count_approx: samples must be in [1, 65536]");
+    if (!(o.confidence > 0.0 && o.confidence < 1.0)) return fail(SLR_EINVAL, "count_approx: confidence must be in (0, 1)");
+    if (o.max_splits < 0 || o.max_splits > 1000) return fail(SLR_EINVAL, "count_approx: max_splits must be in [0, 1000]");
+    if (o.grid_bits < 1 || o.grid_bits > 20) return fail(SLR_EINVAL, "count_approx: grid_bits must be in [1, 20]");
+    if (!(o.resolve_tol >= 0.0)) return fail(SLR_EINVAL, "count_approx: resolve_tol must be >= 0");
+    Workspace w;
+    if ((rc = check_exact_opts(net, &o.leaf, o.samples, &w, "count_approx"))) return rc;
+    memset(out, 0, sizeof *out);
+    const auto t0 = std::chrono::steady_clock::now();
+    const int d = net->dev.d;
+    const double beta = std::log2(1.0 / (1.0 - o.confidence)) / o.trials;
+    const uint32_t key[2] = {(uint32_t)(o.seed & 0xFFFFFFFFu), (uint32_t)(o.seed >> 32)};
+    hipStream_t s = (hipStream_t)o.leaf.stream;
+    std::vector<double> slo(d), shi(d), coords;
+    std::vector<float> pts((size_t)o.samples * d);
+    std::vector<int8_t> viol(o.samples);
+    double best = INFINITY;
+    for (int t = 0; t < o.trials; ++t) {
+        for (int k = 0; k < d; ++k) {
+            slo[k] = lo[k];
+            shi[k] = hi[k];
+        }
+        int splits = 0;
+        slr_count_result r;
+        while (true) {
+            memset(&r, 0, sizeof r);
+            rc = count_exact_impl(net, prop, slo.data(), shi.data(), &o.leaf, w, &r);
+            if (rc < 0) return rc;
+            if (r.undecided <= o.resolve_tol || splits >= o.max_splits) break;
+            // uniform samples of the subdomain (float64 arithmetic, rounded to float32)
+            for (int p = 0; p < o.samples; ++p)
+                for (int k = 0; k < d; ++k) {
+                    const uint64_t q = (uint64_t)p * d + k;
+                    const uint32_t ctr[4] = {(uint32_t)(q >> 1), (uint32_t)splits, (uint32_t)t, kTagSample};
+                    uint32_t wv[4];
+                    Philox::block(ctr, key, wv);
+                    const double u = (q & 1) ? Philox::u53(wv[2], wv[3]) : Philox::u53(wv[0], wv[1]);
+                    pts[(size_t)p * d + k] = (float)(slo[k] + u * (shi[k] - slo[k]));
+                }
+            HIP_TRY(hipMemcpyAsync(w.samples, pts.data(), pts.size() * sizeof(float), hipMemcpyHostToDevice, s), "count_approx: samples");
+            HIP_TRY(launch_sample_forward(net->dev, prop->dev, o.samples, w.samples, w.viol, s), "count_approx: sample kernel");
+            HIP_TRY(hipMemcpyAsync(viol.data(), w.viol, o.samples, hipMemcpyDeviceToHost, s), "count_approx: readback");
+            HIP_TRY(hipStreamSynchronize(s), "count_approx: sync");
+            const uint32_t sctr[4] = {0u, (uint32_t)splits, (uint32_t)t, kTagSplit};
+            uint32_t sw[4];
+            Philox::block(sctr, key, sw);
+            const int dim = (int)(((uint64_t)sw[0] * (uint64_t)d) >> 32);
+            const int side = (int)(sw[1] & 1u);
+            coords.clear();
+            for (int p = 0; p < o.samples; ++p)
+                if (viol[p]) coords.push_back(pts[(size_t)p * d + dim]);
+            if (coords.empty())
+                for (int p = 0; p < o.samples; ++p) coords.push_back(pts[(size_t)p * d + dim]);
+            std::sort(coords.begin(), coords.end());
+            const double med = coords[(coords.size() - 1) / 2];
+            const double m = snap_split(med, slo[dim], shi[dim], lo[dim], hi[dim], o.grid_bits);
+            if ((double)(float)m != m) return fail(SLR_EINTERNAL, "count_approx: split point not exact in float32");
+            if (side == 0) shi[dim] = m; else slo[dim] = m;
+            ++splits;
+        }
+        double v = 1.0;
+        for (int k = 0; k < d; ++k)
+            if (hi[k] > lo[k]) v *= (shi[k] - slo[k]) / (hi[k] - lo[k]);
+        const double E = std::ldexp(v * r.unsafe, splits);
+        out->estimate[t] = E;
+        out->splits[t] = splits;
+        best = std::min(best, E);
+    }
+    out->trials = o.trials;
+    out->lower_bound = std::exp2(-beta) * best;
+    out->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    return SLR_OK;
+}

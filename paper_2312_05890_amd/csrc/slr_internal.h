@@ -1,0 +1,86 @@
+// Internal descriptors shared by the host engine and the gfx950 kernels.
+//
+// Device representation of one box's symbolic state (the center/radius form of the lower and
+// upper equations of §3): in box-local coordinates t in [-1, 1]^d (x = mid + rad * t) every
+// neuron keeps a center equation c(t) = c_0 + sum_i c_i t_i and a radius r >= 0 with
+// L = c - r and U = c + r.  Eq. 1 scales both equations by the same ratio, so L and U keep
+// equal slopes and the radius stays a constant; the W+/W- rule of symbolic propagation then
+// becomes C' = W C + b and r' = |W| r.  A third quantity q <= r tracks how much of r is
+// rounding margin (propagated like r), which tells boxes whose class could differ in exact
+// arithmetic from the rest.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#define SLR_MAX_AFFINE 8
+#define SLR_MAX_D 32
+#define SLR_MAX_WIDTH 256
+#define SLR_MAX_ROWS 16
+#define SLR_MAX_OUT 64
+
+// One hidden-to-hidden affine layer (its input is a hidden ReLU layer).
+struct MidLayer {
+    const float* wfrag;   // [mt_out][ks_alloc][64] MFMA A-operand fragments (see pack_fragments)
+    const float* w;       // row-major [n_out][n_in] float32 (FP64 recheck path)
+    const float* bias;    // [16 * mt_out], zero padded
+    const float* absrow;  // [16 * mt_out]: sum_k |W_jk|, rounded up to float32
+    int n_in, n_out, mt_out, ks, ks_alloc;
+    float kgam;           // kappa * gamma_{n_in + 2} for float32, rounded up
+    double kgam64;        // the same for float64
+};
+
+struct NetDev {
+    int d;                // input dimension
+    int n_affine;         // affine layers (>= 2)
+    int n1, mt1;          // first hidden width and its 16-row tiles
+    int mt_max;           // max 16-row tiles over hidden layers
+    int n_last, mt_last;  // width (and tiles) of the last hidden layer
+    int n_max;            // max hidden width
+    const float* w1;      // [n1][d] row-major
+    const float* b1;      // [n1]
+    MidLayer mid[SLR_MAX_AFFINE];   // affine layers 1 .. n_affine-2
+    float kfirst, kconc, krelu;     // kappa*gamma_{d+2}, kappa*gamma_{d+3}, kappa*gamma_4
+    double kfirst64, kconc64, krelu64;
+};
+
+struct PropDev {
+    int rows, n_last;
+    const float* wg;      // [rows][n_last] folded last layer C W_L, float32
+    const float* bg;      // [rows] C b_L + d
+    const float* ag;      // [rows] row sums of |C| |W_L| (bounds sum_k |wg_rk|), rounded up
+    const double* wg64;   // the folded layer in float64
+    const double* bg64;
+    const double* ag64;
+    float kout;           // kappa * gamma_{n_last + 3}, float32
+    double kout64;        // kappa * gamma_{n_last + n_out + 3}, float64
+};
+
+// Per-level counters of the exact count (device, 64-bit).
+struct LevelStats {
+    unsigned long long unsafe_cnt;
+    unsigned long long safe_cnt;
+    unsigned long long undecided_cnt;
+    unsigned long long pad;
+};
+
+// Kernel launchers (slr_kernels.hip).  All are asynchronous on `stream`.
+hipError_t launch_bound_f32(const NetDev& net, const PropDev& prop, int64_t n, const float* lo,
+                            const float* hi, float* g_lo, float* g_hi, int8_t* cls, int raw,
+                            hipStream_t stream, int* unsupported);
+hipError_t launch_recheck64(const NetDev& net, const PropDev& prop, int64_t n, const float* lo,
+                            const float* hi, float* g_lo, float* g_hi, int8_t* cls,
+                            unsigned long long* counter, hipStream_t stream);
+hipError_t launch_level_count(int64_t n, const int8_t* cls, unsigned int* tile_und,
+                              LevelStats* stats, hipStream_t stream);
+hipError_t launch_split(int64_t n, int d, const int8_t* cls, const unsigned int* tile_und,
+                        const float* lo, const float* hi, const unsigned long long* path,
+                        float* lo2, float* hi2, unsigned long long* path2, unsigned int* err,
+                        hipStream_t stream);
+hipError_t launch_volume(const LevelStats* stats, int levels, int stop_level, int stopped,
+                         double* out3, unsigned long long* out_counts, unsigned int* err,
+                         hipStream_t stream);
+hipError_t launch_sample_forward(const NetDev& net, const PropDev& prop, int64_t n,
+                                 const float* x, int8_t* viol, hipStream_t stream);
+int bound_f32_supported(const NetDev& net, const PropDev& prop);
+size_t level_tiles(int64_t n);

@@ -1,0 +1,817 @@
+// gfx950 kernels of the SLR counter: bound (FP32 MFMA), FP64 recheck, level bookkeeping.
+//
+// Bound kernel (one branch-and-bound level at a time, §3): a workgroup of four wavefronts takes
+// 16*NT boxes.  For box b and neuron m the state is the center equation c_0..c_d, the radius r
+// (see slr_internal.h) and q, the part of r that comes from rounding margins (it decides which
+// boxes need the FP64 re-decision), NCOL = d + 3 floats, kept in LDS in the layout
+//     S[nt][c][g][j][s]     (j = box within the 16-box N tile, (g, s) = neuron)
+// where neuron k of the layer input sits at g = (k % 16) / 4, s = 4 (k / 16) + k % 4.  That is
+// exactly the B-operand layout of v_mfma_f32_16x16x4f32 (lane 16 g + j supplies B[g][j] of
+// K-step s) and also exactly where the same lane finds output rows 16 mt + 4 g + v of the
+// accumulator D[4 g + v][j] of M tile mt.  So every hidden layer is
+//     MFMA:      acc[c] += W_frag(mt, s) * S[c][s]        (c <= d, A = W)
+//                acc[c] += |W_frag(mt, s)| * S[c][s]       (r and q columns, A = |W|)
+//     epilogue:  lane-local on its 4 neurons x NCOL columns: bias, rounding margin,
+//                concretization, Eq. 1, then one 16-byte LDS store per column.
+// The first affine layer (box -> hidden) is exact and done on the VALU; the output layer with
+// the folded property rows is a short VALU contraction over the LDS state.
+#include "slr_internal.h"
+
+#include <hip/hip_runtime.h>
+
+#include <float.h>
+#include <math.h>
+
+namespace {
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+constexpr float kU32 = 0x1p-24f;     // unit roundoff of float32
+constexpr float kEta = 0x1p-96f;     // absolute floor: covers flushed subnormal products
+constexpr double kEta64 = 0x1p-960;
+constexpr double kU64 = 0x1p-53;
+constexpr int kNW = 4;               // wavefronts per bound workgroup
+
+__device__ __forceinline__ f32x4 mfma16(float a, float b, f32x4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+// Concretization, rounding margin and ReLU relaxation (Eq. 1) of four neurons of one box.
+// In: a[c][v] = pre-activation center coefficients (c = 0..d, bias included), the unwidened
+// radius a[d+1][v] and margin part a[d+2][v]; eps[v] = rounding margin of the affine step.
+// Out: post-activation state in place; emax = max_v bound on |value| over the box.
+template <int NCOL>
+__device__ __forceinline__ void relu_epilogue(float (&a)[NCOL][4], const float (&eps)[4],
+                                              const bool (&valid)[4], int raw, float kconc,
+                                              float krelu, float& emax) {
+    constexpr int D = NCOL - 3;
+    constexpr int R = NCOL - 2, Q = NCOL - 1;
+    emax = 0.f;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        float c0 = a[0][v];
+        float S = 0.f;
+#pragma unroll
+        for (int c = 1; c <= D; ++c) S += fabsf(a[c][v]);
+        float r = a[R][v] + eps[v];
+        float q = a[Q][v] + eps[v];
+        const float delta = raw ? 0.f : kconc * (fabsf(c0) + r + S);
+        const float lo = (c0 - (r + S)) - delta;
+        const float hi = (c0 + (r + S)) + delta;
+        float e = 0.f;
+        if (!valid[v] || hi <= 0.f) {
+#pragma unroll
+            for (int c = 0; c < NCOL; ++c) a[c][v] = 0.f;
+        } else if (lo >= 0.f) {
+            a[R][v] = r;
+            a[Q][v] = q;
+            e = fabsf(c0) + S + r;
+        } else {
+            float lam = hi / (hi - lo);
+            if (!raw) lam = fminf(1.f, lam * (1.f + 4.f * kU32));
+            const float sh = -0.5f * lam * lo;
+            const float er = raw ? 0.f : krelu * lam * ((fabsf(c0) + S + r) - lo);
+#pragma unroll
+            for (int c = 1; c <= D; ++c) a[c][v] *= lam;
+            c0 = fmaf(lam, c0, sh);
+            r = fmaf(lam, r, sh) + er;
+            a[0][v] = c0;
+            a[R][v] = r;
+            // moving l and u by at most q + delta moves both relaxation lines by at most that
+            a[Q][v] = fmaf(1.f + lam, q, delta + er);
+            e = (fabsf(c0) + lam * S + r) * (1.f + 4.f * kU32);
+        }
+        emax = fmaxf(emax, e);
+    }
+}
+
+template <int NCOL, int NT, int UW>
+__global__ __launch_bounds__(kNW * 64) void bound_f32_kernel(
+    NetDev net, PropDev prop, int64_t n, const float* __restrict__ blo,
+    const float* __restrict__ bhi, float* __restrict__ g_lo, float* __restrict__ g_hi,
+    int8_t* __restrict__ cls, int raw, int SP) {
+    extern __shared__ float lds[];
+    constexpr int T = NT * 16;
+    constexpr int D = NCOL - 3;
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6, g = lane >> 4, j = lane & 15;
+    const int64_t box0 = (int64_t)blockIdx.x * T;
+    const int d = net.d;
+
+    float* S = lds;                                   // [NT][NCOL][4][16][SP]
+    float* part = S + NT * NCOL * 64 * SP;            // [2 parity][mt_max][T] bound on |value|
+    float* OUT = part + 2 * net.mt_max * T;           // [rows][T][NCOL]
+    const int colstride = 64 * SP;
+    auto part_at = [&](int par, int mt, int bj) -> float& {
+        return part[(par * net.mt_max + mt) * T + bj];
+    };
+
+    // ---------------- first affine layer: exact on the VALU, then the ReLU epilogue
+    {
+        const int units = net.mt1 * NT;
+#pragma unroll
+        for (int i = 0; i < UW; ++i) {
+            const int u = wave + kNW * i;
+            if (u < units) {
+                const int mt = u / NT, nt = u - (u / NT) * NT;
+                const int64_t b = box0 + nt * 16 + j;
+                const bool bval = b < n;
+                float mid[D], rad[D];
+#pragma unroll
+                for (int k = 0; k < D; ++k) {
+                    float l = 0.f, h = 0.f;
+                    if (bval && k < d) {
+                        l = blo[b * d + k];
+                        h = bhi[b * d + k];
+                    }
+                    const float m = 0.5f * (l + h);
+                    mid[k] = m;
+                    rad[k] = raw ? 0.5f * (h - l) : fmaxf(h - m, m - l) * (1.f + 0x1p-22f);
+                }
+                float a[NCOL][4], eps[4];
+                bool valid[4];
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int m = 16 * mt + 4 * g + v;
+                    valid[v] = m < net.n1;
+                    float c0 = 0.f, s = 0.f;
+                    if (valid[v]) {
+                        const float bb = net.b1[m];
+                        c0 = bb;
+                        s = fabsf(bb);
+#pragma unroll
+                        for (int k = 0; k < D; ++k) {
+                            const float w = k < d ? net.w1[m * d + k] : 0.f;
+                            c0 = fmaf(w, mid[k], c0);
+                            a[k + 1][v] = w * rad[k];
+                            s += fabsf(w) * (fabsf(mid[k]) + rad[k]);
+                        }
+                    } else {
+#pragma unroll
+                        for (int k = 0; k < D; ++k) a[k + 1][v] = 0.f;
+                    }
+                    a[0][v] = c0;
+                    a[NCOL - 2][v] = 0.f;
+                    a[NCOL - 1][v] = 0.f;
+                    eps[v] = raw ? 0.f : net.kfirst * s + kEta;
+                }
+                float emax;
+                relu_epilogue<NCOL>(a, eps, valid, raw, net.kconc, net.krelu, emax);
+                float* sb = S + ((nt * NCOL * 4 + g) * 16 + j) * SP + 4 * mt;
+#pragma unroll
+                for (int c = 0; c < NCOL; ++c) {
+                    f32x4 o = {a[c][0], a[c][1], a[c][2], a[c][3]};
+                    *reinterpret_cast<f32x4*>(sb + c * colstride) = o;
+                }
+                emax = fmaxf(emax, __shfl_xor(emax, 16));
+                emax = fmaxf(emax, __shfl_xor(emax, 32));
+                if (g == 0) part_at(0, mt, nt * 16 + j) = emax;
+            }
+        }
+    }
+    __syncthreads();
+
+    // ---------------- hidden-to-hidden layers on MFMA with fused epilogues
+    int rp = 0;
+    int mt_prev = net.mt1;
+    for (int l = 0; l < net.n_affine - 2; ++l) {
+        const MidLayer* L = &net.mid[l];
+        const int units = L->mt_out * NT;
+        const int ks = L->ks;
+        f32x4 res[UW][NCOL];
+#pragma unroll
+        for (int i = 0; i < UW; ++i) {
+            const int u = wave + kNW * i;
+            if (u < units) {
+                const int mt = u / NT, nt = u - (u / NT) * NT;
+                f32x4 acc[NCOL];
+#pragma unroll
+                for (int c = 0; c < NCOL; ++c) acc[c] = f32x4{0.f, 0.f, 0.f, 0.f};
+                const float* wf = L->wfrag + (size_t)mt * L->ks_alloc * 64 + lane;
+                const float* sb = S + ((nt * NCOL * 4 + g) * 16 + j) * SP;
+                for (int q = 0; q < ks; q += 4) {
+                    f32x4 bq[NCOL];
+#pragma unroll
+                    for (int c = 0; c < NCOL; ++c)
+                        bq[c] = *reinterpret_cast<const f32x4*>(sb + c * colstride + q);
+                    float af[4];
+#pragma unroll
+                    for (int ss = 0; ss < 4; ++ss) af[ss] = wf[(q + ss) * 64];
+#pragma unroll
+                    for (int ss = 0; ss < 4; ++ss) {
+                        if (q + ss < ks) {
+                            const float aw = af[ss];
+                            const float aa = fabsf(aw);
+#pragma unroll
+                            for (int c = 0; c < NCOL - 2; ++c) acc[c] = mfma16(aw, bq[c][ss], acc[c]);
+                            acc[NCOL - 2] = mfma16(aa, bq[NCOL - 2][ss], acc[NCOL - 2]);
+                            acc[NCOL - 1] = mfma16(aa, bq[NCOL - 1][ss], acc[NCOL - 1]);
+                        }
+                    }
+                }
+#pragma unroll
+                for (int c = 0; c < NCOL; ++c) res[i][c] = acc[c];
+            }
+        }
+        __syncthreads();   // every wave has read the layer input
+#pragma unroll
+        for (int i = 0; i < UW; ++i) {
+            const int u = wave + kNW * i;
+            if (u < units) {
+                const int mt = u / NT, nt = u - (u / NT) * NT;
+                const int bj = nt * 16 + j;
+                float emax_in = 0.f;
+                for (int q = 0; q < mt_prev; ++q) emax_in = fmaxf(emax_in, part_at(rp, q, bj));
+                float a[NCOL][4], eps[4];
+                bool valid[4];
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int m = 16 * mt + 4 * g + v;
+                    valid[v] = m < L->n_out;
+                    const float bb = L->bias[m];
+                    const float A = L->absrow[m];
+#pragma unroll
+                    for (int c = 0; c < NCOL; ++c) a[c][v] = res[i][c][v];
+                    a[0][v] += bb;
+                    eps[v] = raw ? 0.f : L->kgam * (A * emax_in + fabsf(bb)) + kEta;
+                }
+                float emax;
+                relu_epilogue<NCOL>(a, eps, valid, raw, net.kconc, net.krelu, emax);
+                float* sb = S + ((nt * NCOL * 4 + g) * 16 + j) * SP + 4 * mt;
+#pragma unroll
+                for (int c = 0; c < NCOL; ++c) {
+                    f32x4 o = {a[c][0], a[c][1], a[c][2], a[c][3]};
+                    *reinterpret_cast<f32x4*>(sb + c * colstride) = o;
+                }
+                emax = fmaxf(emax, __shfl_xor(emax, 16));
+                emax = fmaxf(emax, __shfl_xor(emax, 32));
+                if (g == 0) part_at(rp ^ 1, mt, bj) = emax;
+            }
+        }
+        rp ^= 1;
+        mt_prev = L->mt_out;
+        __syncthreads();   // the layer output is complete
+    }
+
+    // ---------------- output layer: folded property rows, VALU contraction over the state
+    const int rows = prop.rows;
+    const int K = prop.n_last;
+    const int items = rows * T * NCOL;
+    for (int it = tid; it < items; it += kNW * 64) {
+        const int c = it % NCOL;
+        const int bj = (it / NCOL) % T;
+        const int r = it / (NCOL * T);
+        const int nt = bj >> 4, jj = bj & 15;
+        const float* wr = prop.wg + r * K;
+        const float* col = S + (nt * NCOL + c) * colstride + jj * SP;
+        float s = 0.f;
+        for (int k = 0; k < K; ++k) {
+            const int gg = (k >> 2) & 3;
+            const int sidx = 4 * (k >> 4) + (k & 3);
+            float w = wr[k];
+            if (c >= NCOL - 2) w = fabsf(w);
+            s = fmaf(w, col[gg * 16 * SP + sidx], s);
+        }
+        OUT[(r * T + bj) * NCOL + c] = s;
+    }
+    __syncthreads();
+    for (int bj = tid; bj < T; bj += kNW * 64) {
+        const int64_t b = box0 + bj;
+        if (b >= n) continue;
+        float emax = 0.f;
+        for (int q = 0; q < net.mt_last; ++q) emax = fmaxf(emax, part_at(rp, q, bj));
+        bool unsafe = true, safe = false, amb_unsafe = true, amb_safe = false;
+        for (int r = 0; r < rows; ++r) {
+            const float* o = OUT + (r * T + bj) * NCOL;
+            const float bg = prop.bg[r];
+            const float G0 = o[0] + bg;
+            float Sg = 0.f;
+            for (int c = 1; c <= D; ++c) Sg += fabsf(o[c]);
+            const float eps = raw ? 0.f : prop.kout * (prop.ag[r] * emax + fabsf(bg)) + kEta;
+            const float R = o[NCOL - 2] + eps;
+            const float delta = raw ? 0.f : net.kconc * (fabsf(G0) + R + Sg);
+            const float glo = (G0 - (R + Sg)) - delta;
+            const float ghi = (G0 + (R + Sg)) + delta;
+            // distance within which the exact-arithmetic decision may differ from this one:
+            // twice the propagated margins plus 2^-14 of the row's magnitude
+            const float tau = 2.f * (o[NCOL - 1] + eps + delta) +
+                              0x1p-14f * fmaxf(fabsf(glo), fabsf(ghi));
+            if (g_lo) g_lo[b * rows + r] = glo;
+            if (g_hi) g_hi[b * rows + r] = ghi;
+            unsafe = unsafe && (glo > 0.f);
+            safe = safe || (ghi <= 0.f);
+            amb_unsafe = amb_unsafe && (glo + tau > 0.f);
+            amb_safe = amb_safe || (ghi - tau <= 0.f);
+        }
+        int8_t k = unsafe ? 1 : (safe ? 2 : 0);
+        if (k == 0 && !raw && (amb_unsafe || amb_safe)) k = 3;
+        if (cls) cls[b] = k;
+    }
+}
+
+// ------------------------------------------------------------------------------------------
+// FP64 re-decision of boxes the float32 pass marked ambiguous (class 3): the same center/radius
+// propagation on the VALU in double precision, one box per workgroup, one thread per neuron.
+// ------------------------------------------------------------------------------------------
+
+__device__ __forceinline__ double block_max256(double v, double* red) {
+    const int tid = threadIdx.x;
+    red[tid] = v;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (tid < s) red[tid] = fmax(red[tid], red[tid + s]);
+        __syncthreads();
+    }
+    const double r = red[0];
+    __syncthreads();
+    return r;
+}
+
+__device__ __forceinline__ double relu64(double* st, int ncol, double eps, double kconc,
+                                         double krelu) {
+    // st: one neuron's row (ncol entries, radius last, unwidened); returns |value| bound
+    const int D = ncol - 2;
+    double c0 = st[0];
+    double S = 0.0;
+    for (int c = 1; c <= D; ++c) S += fabs(st[c]);
+    double r = st[ncol - 1] + eps;
+    const double delta = kconc * (fabs(c0) + r + S);
+    const double lo = (c0 - (r + S)) - delta;
+    const double hi = (c0 + (r + S)) + delta;
+    if (hi <= 0.0) {
+        for (int c = 0; c < ncol; ++c) st[c] = 0.0;
+        return 0.0;
+    }
+    if (lo >= 0.0) {
+        st[ncol - 1] = r;
+        return fabs(c0) + S + r;
+    }
+    const double lam = fmin(1.0, (hi / (hi - lo)) * (1.0 + 4.0 * kU64));
+    const double sh = -0.5 * lam * lo;
+    const double er = krelu * lam * ((fabs(c0) + S + r) - lo);
+    for (int c = 1; c <= D; ++c) st[c] *= lam;
+    c0 = fma(lam, c0, sh);
+    r = fma(lam, r, sh) + er;
+    st[0] = c0;
+    st[ncol - 1] = r;
+    return (fabs(c0) + lam * S + r) * (1.0 + 4.0 * kU64);
+}
+
+__global__ __launch_bounds__(256) void recheck64_kernel(NetDev net, PropDev prop, int64_t n,
+                                                        const float* __restrict__ blo,
+                                                        const float* __restrict__ bhi,
+                                                        float* __restrict__ g_lo,
+                                                        float* __restrict__ g_hi,
+                                                        int8_t* __restrict__ cls,
+                                                        unsigned long long* counter) {
+    extern __shared__ double sm[];
+    __shared__ int list[256];
+    __shared__ int cnt;
+    const int tid = threadIdx.x;
+    const int d = net.d, ncol = d + 2;
+    const int nrow = net.n_max > prop.rows * ncol ? net.n_max : prop.rows * ncol;
+    double* A = sm;                    // [nrow][ncol]
+    double* B = A + nrow * ncol;       // [nrow][ncol]
+    double* red = B + nrow * ncol;     // [256]
+    double* mid = red + 256;           // [32]
+    double* rad = mid + SLR_MAX_D;     // [32]
+
+    for (int64_t base = (int64_t)blockIdx.x * 256; base < n; base += (int64_t)gridDim.x * 256) {
+        if (tid == 0) cnt = 0;
+        __syncthreads();
+        const int64_t i = base + tid;
+        if (i < n && cls[i] == 3) list[atomicAdd(&cnt, 1)] = tid;
+        __syncthreads();
+        const int m_list = cnt;
+        for (int q = 0; q < m_list; ++q) {
+            const int64_t b = base + list[q];
+            if (tid < d) {
+                const double l = blo[b * d + tid], h = bhi[b * d + tid];
+                const double m = 0.5 * (l + h);
+                mid[tid] = m;
+                rad[tid] = fmax(h - m, m - l) * (1.0 + 0x1p-50);
+            }
+            __syncthreads();
+            // first affine layer
+            double e = 0.0;
+            if (tid < net.n1) {
+                double* st = A + tid * ncol;
+                const double bb = net.b1[tid];
+                double c0 = bb, s = fabs(bb);
+                for (int k = 0; k < d; ++k) {
+                    const double w = net.w1[tid * d + k];
+                    c0 = fma(w, mid[k], c0);
+                    st[k + 1] = w * rad[k];
+                    s += fabs(w) * (fabs(mid[k]) + rad[k]);
+                }
+                st[0] = c0;
+                st[ncol - 1] = 0.0;
+                e = relu64(st, ncol, net.kfirst64 * s + kEta64, net.kconc64, net.krelu64);
+            }
+            double emax = block_max256(e, red);
+            double* in = A;
+            double* out = B;
+            for (int l = 0; l < net.n_affine - 2; ++l) {
+                const MidLayer* L = &net.mid[l];
+                e = 0.0;
+                if (tid < L->n_out) {
+                    double* st = out + tid * ncol;
+                    const float* wr = L->w + (size_t)tid * L->n_in;
+                    for (int c = 0; c < ncol; ++c) st[c] = 0.0;
+                    double A_row = 0.0;
+                    for (int k = 0; k < L->n_in; ++k) {
+                        const double w = wr[k];
+                        const double* x = in + k * ncol;
+                        for (int c = 0; c < ncol - 1; ++c) st[c] = fma(w, x[c], st[c]);
+                        st[ncol - 1] = fma(fabs(w), x[ncol - 1], st[ncol - 1]);
+                        A_row += fabs(w);
+                    }
+                    const double bb = L->bias[tid];
+                    st[0] += bb;
+                    const double eps = L->kgam64 * (A_row * (1.0 + 0x1p-40) * emax + fabs(bb)) + kEta64;
+                    e = relu64(st, ncol, eps, net.kconc64, net.krelu64);
+                }
+                emax = block_max256(e, red);
+                double* t = in;
+                in = out;
+                out = t;
+            }
+            // output rows: one (row, column) item per thread
+            const int rows = prop.rows;
+            const int K = prop.n_last;
+            for (int it = tid; it < rows * ncol; it += 256) {
+                const int r = it / ncol, c = it % ncol;
+                double s = 0.0;
+                for (int k = 0; k < K; ++k) {
+                    double w = prop.wg64[r * K + k];
+                    if (c == ncol - 1) w = fabs(w);
+                    s = fma(w, in[k * ncol + c], s);
+                }
+                out[it] = s;
+            }
+            __syncthreads();
+            if (tid == 0) {
+                bool unsafe = true, safe = false;
+                for (int r = 0; r < rows; ++r) {
+                    const double* o = out + r * ncol;
+                    const double bg = prop.bg64[r];
+                    const double G0 = o[0] + bg;
+                    double Sg = 0.0;
+                    for (int c = 1; c <= d; ++c) Sg += fabs(o[c]);
+                    const double eps = prop.kout64 * (prop.ag64[r] * emax + fabs(bg)) + kEta64;
+                    const double R = o[ncol - 1] + eps;
+                    const double delta = net.kconc64 * (fabs(G0) + R + Sg);
+                    const double glo = (G0 - (R + Sg)) - delta;
+                    const double ghi = (G0 + (R + Sg)) + delta;
+                    // float32 copies rounded outward
+                    float flo = (float)glo;
+                    if ((double)flo > glo) flo = nextafterf(flo, -INFINITY);
+                    float fhi = (float)ghi;
+                    if ((double)fhi < ghi) fhi = nextafterf(fhi, INFINITY);
+                    if (g_lo) g_lo[b * rows + r] = flo;
+                    if (g_hi) g_hi[b * rows + r] = fhi;
+                    unsafe = unsafe && (glo > 0.0);
+                    safe = safe || (ghi <= 0.0);
+                }
+                cls[b] = unsafe ? 1 : (safe ? 2 : 0);
+                if (counter) atomicAdd(counter, 1ull);
+            }
+            __syncthreads();
+        }
+        __syncthreads();
+    }
+}
+
+// ------------------------------------------------------------------------------------------
+// Level bookkeeping: per-tile undecided counts, class histograms, compaction + bisection.
+// ------------------------------------------------------------------------------------------
+constexpr int kTile = 1024;   // boxes per bookkeeping workgroup (256 threads x 4)
+
+__device__ __forceinline__ unsigned block_sum256(unsigned v, unsigned* red) {
+    // returns the total; red holds 4 wave partials
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    if (lane == 0) red[wave] = v;
+    __syncthreads();
+    const unsigned t = red[0] + red[1] + red[2] + red[3];
+    __syncthreads();
+    return t;
+}
+
+__global__ __launch_bounds__(256) void level_count_kernel(int64_t n, const int8_t* __restrict__ cls,
+                                                          unsigned* __restrict__ tile_und,
+                                                          LevelStats* stats) {
+    __shared__ unsigned red[4];
+    const int64_t base = (int64_t)blockIdx.x * kTile + threadIdx.x * 4;
+    unsigned nu = 0, ns = 0, nd = 0;
+    for (int q = 0; q < 4; ++q) {
+        const int64_t i = base + q;
+        if (i < n) {
+            const int8_t c = cls[i];
+            nu += c == 1;
+            ns += c == 2;
+            nd += c == 0;
+        }
+    }
+    nu = block_sum256(nu, red);
+    ns = block_sum256(ns, red);
+    nd = block_sum256(nd, red);
+    if (threadIdx.x == 0) {
+        tile_und[blockIdx.x] = nd;
+        if (nu) atomicAdd(&stats->unsafe_cnt, (unsigned long long)nu);
+        if (ns) atomicAdd(&stats->safe_cnt, (unsigned long long)ns);
+        if (nd) atomicAdd(&stats->undecided_cnt, (unsigned long long)nd);
+    }
+}
+
+__global__ __launch_bounds__(256) void split_kernel(int64_t n, int d, const int8_t* __restrict__ cls,
+                                                    const unsigned* __restrict__ tile_und,
+                                                    const float* __restrict__ lo,
+                                                    const float* __restrict__ hi,
+                                                    const unsigned long long* __restrict__ path,
+                                                    float* __restrict__ lo2, float* __restrict__ hi2,
+                                                    unsigned long long* __restrict__ path2,
+                                                    unsigned* err) {
+    __shared__ unsigned red[4];
+    __shared__ unsigned wpre[4];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    // offset of this tile: undecided boxes of all earlier tiles
+    unsigned pre = 0;
+    for (unsigned k = tid; k < blockIdx.x; k += 256) pre += tile_und[k];
+    const unsigned base_out = block_sum256(pre, red);
+    if (tile_und[blockIdx.x] == 0) return;
+    const int64_t base = (int64_t)blockIdx.x * kTile + tid * 4;
+    unsigned flags = 0, cnt = 0;
+    for (int q = 0; q < 4; ++q) {
+        const int64_t i = base + q;
+        if (i < n && cls[i] == 0) {
+            flags |= 1u << q;
+            ++cnt;
+        }
+    }
+    // exclusive scan of cnt over the workgroup (thread order = box order)
+    unsigned incl = cnt;
+    for (int o = 1; o < 64; o <<= 1) {
+        const unsigned t = __shfl_up(incl, o);
+        if (lane >= o) incl += t;
+    }
+    if (lane == 63) wpre[wave] = incl;
+    __syncthreads();
+    unsigned woff = 0;
+    for (int w = 0; w < wave; ++w) woff += wpre[w];
+    unsigned rank = base_out + woff + incl - cnt;
+    for (int q = 0; q < 4; ++q) {
+        if (!(flags & (1u << q))) continue;
+        const int64_t i = base + q;
+        const float* l = lo + i * d;
+        const float* h = hi + i * d;
+        int js = 0;
+        float wbest = h[0] - l[0];
+        for (int k = 1; k < d; ++k) {
+            const float w = h[k] - l[k];
+            if (w > wbest) {
+                wbest = w;
+                js = k;
+            }
+        }
+        const float m = 0.5f * (l[js] + h[js]);
+        if (!(m - l[js] == h[js] - m && l[js] < m && m < h[js])) atomicOr(err, 1u);
+        const int64_t o0 = 2 * (int64_t)rank, o1 = o0 + 1;
+        for (int k = 0; k < d; ++k) {
+            lo2[o0 * d + k] = l[k];
+            hi2[o0 * d + k] = k == js ? m : h[k];
+            lo2[o1 * d + k] = k == js ? m : l[k];
+            hi2[o1 * d + k] = h[k];
+        }
+        const unsigned long long p = path[i];
+        path2[o0] = 2ull * p;
+        path2[o1] = 2ull * p + 1ull;
+        ++rank;
+    }
+}
+
+// Exact leaf-volume sums: sum_t count_t 2^(Dm - t) in 64-bit integers (the totals partition
+// 2^Dm exactly), converted to float64 fractions with a single rounding.
+__global__ void volume_kernel(const LevelStats* stats, int levels, int stop_level, int stopped,
+                              double* out3, unsigned long long* out_counts, unsigned* err) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    const int Dm = levels - 1;
+    unsigned long long su = 0, ss = 0, sd = 0, nu = 0, ns = 0, nd = 0;
+    for (int t = 0; t < levels; ++t) {
+        su += stats[t].unsafe_cnt << (Dm - t);
+        ss += stats[t].safe_cnt << (Dm - t);
+        nu += stats[t].unsafe_cnt;
+        ns += stats[t].safe_cnt;
+    }
+    if (stopped) {
+        sd = stats[stop_level].undecided_cnt << (Dm - stop_level);
+        nd = stats[stop_level].undecided_cnt;
+    }
+    if (su + ss + sd != (1ull << Dm)) atomicOr(err, 2u);
+    out3[0] = ldexp((double)su, -Dm);
+    out3[1] = ldexp((double)ss, -Dm);
+    out3[2] = ldexp((double)sd, -Dm);
+    out_counts[0] = nu;
+    out_counts[1] = ns;
+    out_counts[2] = nd;
+}
+
+// Concrete float32 forward pass of sample points (used to place the approximate count's splits).
+__global__ __launch_bounds__(256) void sample_forward_kernel(NetDev net, PropDev prop, int64_t n,
+                                                             const float* __restrict__ x,
+                                                             int8_t* __restrict__ viol) {
+    __shared__ float h0[SLR_MAX_WIDTH], h1[SLR_MAX_WIDTH];
+    __shared__ int ok;
+    const int tid = threadIdx.x;
+    const int d = net.d;
+    for (int64_t p = blockIdx.x; p < n; p += gridDim.x) {
+        if (tid < d) h1[tid] = x[p * d + tid];
+        if (tid == 0) ok = 1;
+        __syncthreads();
+        if (tid < net.n1) {
+            float s = net.b1[tid];
+            for (int k = 0; k < d; ++k) s = fmaf(net.w1[tid * d + k], h1[k], s);
+            h0[tid] = fmaxf(s, 0.f);
+        }
+        __syncthreads();
+        float* in = h0;
+        float* out = h1;
+        for (int l = 0; l < net.n_affine - 2; ++l) {
+            const MidLayer* L = &net.mid[l];
+            if (tid < L->n_out) {
+                float s = L->bias[tid];
+                const float* wr = L->w + (size_t)tid * L->n_in;
+                for (int k = 0; k < L->n_in; ++k) s = fmaf(wr[k], in[k], s);
+                out[tid] = fmaxf(s, 0.f);
+            }
+            __syncthreads();
+            float* t = in;
+            in = out;
+            out = t;
+        }
+        if (tid < prop.rows) {
+            float s = prop.bg[tid];
+            for (int k = 0; k < prop.n_last; ++k) s = fmaf(prop.wg[tid * prop.n_last + k], in[k], s);
+            if (!(s > 0.f)) atomicAnd(&ok, 0);
+        }
+        __syncthreads();
+        if (tid == 0) viol[p] = (int8_t)ok;
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------------------------
+// Bound-kernel shape classes: NCOL (state columns) and (NT boxes/16, UW units per wave).
+// ---------------------------------------------------------------------------------------------
+// Dynamic LDS above the default 64 KiB must be allowed per kernel (gfx950 has 160 KiB per
+// workgroup, static LDS included).  A failed request is cleared so it cannot leak into later
+// error checks.
+hipError_t allow_lds(const void* kern, size_t bytes) {
+    if (bytes <= 64 * 1024) return hipSuccess;
+    hipError_t e = hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    if (e != hipSuccess) (void)hipGetLastError();
+    return e;
+}
+
+int ncol_class(int d) {
+    const int c = d + 3;
+    if (c <= 12) return c;
+    if (c <= 14) return 14;
+    if (c <= 18) return 18;
+    if (c <= 26) return 26;
+    return 35;
+}
+
+void tile_class(int mt_max, int* NT, int* UW) {
+    if (mt_max <= 1) { *NT = 4; *UW = 1; }
+    else if (mt_max == 2) { *NT = 2; *UW = 1; }
+    else if (mt_max <= 4) { *NT = 1; *UW = 1; }
+    else if (mt_max <= 8) { *NT = 1; *UW = 2; }
+    else { *NT = 1; *UW = 4; }
+}
+
+int state_stride(int mt_max) { return 4 * mt_max + ((mt_max & 1) ? 0 : 4); }
+
+size_t bound_lds_bytes(int NCOL, int NT, int mt_max, int rows) {
+    const int T = NT * 16;
+    const int SP = state_stride(mt_max);
+    return sizeof(float) * ((size_t)NT * NCOL * 64 * SP + 2 * (size_t)mt_max * T + (size_t)rows * T * NCOL);
+}
+
+template <int NCOL, int NT, int UW>
+hipError_t launch_inst(const NetDev& net, const PropDev& prop, int64_t n, const float* lo,
+                       const float* hi, float* g_lo, float* g_hi, int8_t* cls, int raw,
+                       hipStream_t stream) {
+    const size_t lds = bound_lds_bytes(NCOL, NT, net.mt_max, prop.rows);
+    auto kern = bound_f32_kernel<NCOL, NT, UW>;
+    hipError_t e = allow_lds((const void*)kern, lds);
+    if (e != hipSuccess) return e;
+    const int64_t blocks = (n + NT * 16 - 1) / (NT * 16);
+    (void)hipGetLastError();
+    hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(kNW * 64), lds, stream, net, prop, n,
+                       lo, hi, g_lo, g_hi, cls, raw, state_stride(net.mt_max));
+    return hipGetLastError();
+}
+
+template <int NCOL>
+hipError_t launch_ncol(int NT, int UW, const NetDev& net, const PropDev& prop, int64_t n,
+                       const float* lo, const float* hi, float* g_lo, float* g_hi, int8_t* cls,
+                       int raw, hipStream_t stream) {
+    if (NT == 4) return launch_inst<NCOL, 4, 1>(net, prop, n, lo, hi, g_lo, g_hi, cls, raw, stream);
+    if (NT == 2) return launch_inst<NCOL, 2, 1>(net, prop, n, lo, hi, g_lo, g_hi, cls, raw, stream);
+    if (UW == 1) return launch_inst<NCOL, 1, 1>(net, prop, n, lo, hi, g_lo, g_hi, cls, raw, stream);
+    if (UW == 2) return launch_inst<NCOL, 1, 2>(net, prop, n, lo, hi, g_lo, g_hi, cls, raw, stream);
+    if constexpr (NCOL <= 18)
+        return launch_inst<NCOL, 1, 4>(net, prop, n, lo, hi, g_lo, g_hi, cls, raw, stream);
+    return hipErrorInvalidValue;
+}
+
+}  // namespace
+
+int bound_f32_supported(const NetDev& net, const PropDev& prop) {
+    const int NCOL = ncol_class(net.d);
+    int NT, UW;
+    tile_class(net.mt_max, &NT, &UW);
+    if (UW == 4 && NCOL > 18) return 0;
+    if (bound_lds_bytes(NCOL, NT, net.mt_max, prop.rows) > 160 * 1024) return 0;
+    return 1;
+}
+
+hipError_t launch_bound_f32(const NetDev& net, const PropDev& prop, int64_t n, const float* lo,
+                            const float* hi, float* g_lo, float* g_hi, int8_t* cls, int raw,
+                            hipStream_t stream, int* unsupported) {
+    *unsupported = 0;
+    if (n <= 0) return hipSuccess;
+    if (!bound_f32_supported(net, prop)) {
+        *unsupported = 1;
+        return hipSuccess;
+    }
+    int NT, UW;
+    tile_class(net.mt_max, &NT, &UW);
+    switch (ncol_class(net.d)) {
+#define SLR_CASE(C) \
+    case C: return launch_ncol<C>(NT, UW, net, prop, n, lo, hi, g_lo, g_hi, cls, raw, stream);
+        SLR_CASE(4) SLR_CASE(5) SLR_CASE(6) SLR_CASE(7) SLR_CASE(8) SLR_CASE(9)
+        SLR_CASE(10) SLR_CASE(11) SLR_CASE(12) SLR_CASE(14) SLR_CASE(18) SLR_CASE(26) SLR_CASE(35)
+#undef SLR_CASE
+        default: *unsupported = 1; return hipSuccess;
+    }
+}
+
+hipError_t launch_recheck64(const NetDev& net, const PropDev& prop, int64_t n, const float* lo,
+                            const float* hi, float* g_lo, float* g_hi, int8_t* cls,
+                            unsigned long long* counter, hipStream_t stream) {
+    if (n <= 0) return hipSuccess;
+    const int ncol = net.d + 2;
+    const int nrow = net.n_max > prop.rows * ncol ? net.n_max : prop.rows * ncol;
+    const size_t lds = sizeof(double) * (2 * (size_t)nrow * ncol + 256 + 2 * SLR_MAX_D);
+    hipError_t e = allow_lds((const void*)recheck64_kernel, lds);
+    if (e != hipSuccess) return e;
+    int64_t blocks = (n + 255) / 256;
+    (void)hipGetLastError();
+    if (blocks > 65535) blocks = 65535;
+    hipLaunchKernelGGL(recheck64_kernel, dim3((unsigned)blocks), dim3(256), lds, stream, net, prop,
+                       n, lo, hi, g_lo, g_hi, cls, counter);
+    return hipGetLastError();
+}
+
+size_t level_tiles(int64_t n) { return (size_t)((n + kTile - 1) / kTile); }
+
+hipError_t launch_level_count(int64_t n, const int8_t* cls, unsigned* tile_und, LevelStats* stats,
+                              hipStream_t stream) {
+    if (n <= 0) return hipSuccess;
+    (void)hipGetLastError();
+    hipLaunchKernelGGL(level_count_kernel, dim3((unsigned)level_tiles(n)), dim3(256), 0, stream, n,
+                       cls, tile_und, stats);
+    return hipGetLastError();
+}
+
+hipError_t launch_split(int64_t n, int d, const int8_t* cls, const unsigned* tile_und,
+                        const float* lo, const float* hi, const unsigned long long* path,
+                        float* lo2, float* hi2, unsigned long long* path2, unsigned* err,
+                        hipStream_t stream) {
+    if (n <= 0) return hipSuccess;
+    (void)hipGetLastError();
+    hipLaunchKernelGGL(split_kernel, dim3((unsigned)level_tiles(n)), dim3(256), 0, stream, n, d,
+                       cls, tile_und, lo, hi, path, lo2, hi2, path2, err);
+    return hipGetLastError();
+}
+
+hipError_t launch_volume(const LevelStats* stats, int levels, int stop_level, int stopped,
+                         double* out3, unsigned long long* out_counts, unsigned* err,
+                         hipStream_t stream) {
+    (void)hipGetLastError();
+    hipLaunchKernelGGL(volume_kernel, dim3(1), dim3(64), 0, stream, stats, levels, stop_level,
+                       stopped, out3, out_counts, err);
+    return hipGetLastError();
+}
+
+hipError_t launch_sample_forward(const NetDev& net, const PropDev& prop, int64_t n, const float* x,
+                                 int8_t* viol, hipStream_t stream) {
+    if (n <= 0) return hipSuccess;
+    int64_t blocks = n < 4096 ? n : 4096;
+    (void)hipGetLastError();
+    hipLaunchKernelGGL(sample_forward_kernel, dim3((unsigned)blocks), dim3(256), 0, stream, net,
+                       prop, n, x, viol);
+    return hipGetLastError();
+}

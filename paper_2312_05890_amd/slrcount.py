@@ -1,0 +1,283 @@
+"""ctypes binding of ``libslrcount.so`` (declared in ``include/slrcount.h``).
+
+Argument marshalling only: every step of the computation runs in the library's HIP kernels.
+PyTorch provides device memory and the current stream.  The library is loaded on first use;
+if it is missing or cannot be loaded the call raises, there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional, Sequence, Tuple
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libslrcount.so")
+
+SLR_OK, SLR_BUDGET = 0, 1
+UNDECIDED, UNSAFE, SAFE = 0, 1, 2
+
+# every entry point declared in include/slrcount.h
+EXPORTS = ("load_net", "free_net", "load_property", "free_property", "bound_boxes",
+           "workspace_size", "count_exact", "count_approx", "sample_violations", "last_error")
+
+
+class SlrError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"slrcount error {code}: {msg}")
+        self.code = code
+
+
+class ExactOpts(C.Structure):
+    _fields_ = [("max_depth", C.c_int32), ("max_leaves", C.c_int64), ("chunk", C.c_int32),
+                ("workspace", C.c_void_p), ("workspace_bytes", C.c_size_t),
+                ("stream", C.c_void_p), ("trace_capacity", C.c_int64),
+                ("trace_depth", C.POINTER(C.c_int32)), ("trace_path", C.POINTER(C.c_uint64)),
+                ("trace_cls", C.POINTER(C.c_int8)), ("timing", C.c_int32)]
+
+
+class CountResult(C.Structure):
+    _fields_ = [("unsafe", C.c_double), ("safe", C.c_double), ("undecided", C.c_double),
+                ("n_unsafe", C.c_int64), ("n_safe", C.c_int64), ("n_undecided", C.c_int64),
+                ("n_boxes_bounded", C.c_int64), ("n_recheck64", C.c_int64),
+                ("depth_reached", C.c_int32), ("status", C.c_int32), ("seconds", C.c_double),
+                ("trace_count", C.c_int64), ("bound_ms", C.c_double),
+                ("bound_launches", C.c_int64)]
+
+
+class ApproxOpts(C.Structure):
+    _fields_ = [("trials", C.c_int32), ("samples", C.c_int32), ("confidence", C.c_double),
+                ("seed", C.c_uint64), ("max_splits", C.c_int32), ("grid_bits", C.c_int32),
+                ("resolve_tol", C.c_double), ("leaf", ExactOpts)]
+
+
+class ApproxResult(C.Structure):
+    _fields_ = [("lower_bound", C.c_double), ("estimate", C.c_double * 64),
+                ("splits", C.c_int32 * 64), ("trials", C.c_int32), ("seconds", C.c_double)]
+
+
+_LIB = None
+
+
+def lib() -> C.CDLL:
+    """Load the HIP library (once).  Raises if it has not been built."""
+    global _LIB
+    if _LIB is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with "
+                              "`python -m paper_2312_05890_amd.build`")
+        L = C.CDLL(LIB_PATH)
+        vp, i32, i64 = C.c_void_p, C.c_int32, C.c_int64
+        L.load_net.argtypes = [i32, C.POINTER(C.c_int32), C.POINTER(vp), C.POINTER(vp), C.POINTER(vp)]
+        L.load_net.restype = C.c_int
+        L.free_net.argtypes = [vp]
+        L.free_net.restype = None
+        L.load_property.argtypes = [vp, i32, vp, vp, C.POINTER(vp)]
+        L.load_property.restype = C.c_int
+        L.free_property.argtypes = [vp]
+        L.free_property.restype = None
+        L.bound_boxes.argtypes = [vp, vp, i64, vp, vp, vp, vp, vp, i32, vp]
+        L.bound_boxes.restype = C.c_int
+        L.workspace_size.argtypes = [vp, vp, i64, i32, C.POINTER(C.c_size_t)]
+        L.workspace_size.restype = C.c_int
+        L.count_exact.argtypes = [vp, vp, C.POINTER(C.c_double), C.POINTER(C.c_double),
+                                  C.POINTER(ExactOpts), C.POINTER(CountResult)]
+        L.count_exact.restype = C.c_int
+        L.count_approx.argtypes = [vp, vp, C.POINTER(C.c_double), C.POINTER(C.c_double),
+                                   C.POINTER(ApproxOpts), C.POINTER(ApproxResult)]
+        L.count_approx.restype = C.c_int
+        L.sample_violations.argtypes = [vp, vp, i64, vp, vp, vp]
+        L.sample_violations.restype = C.c_int
+        L.last_error.argtypes = []
+        L.last_error.restype = C.c_char_p
+        _LIB = L
+    return _LIB
+
+
+def last_error() -> str:
+    return lib().last_error().decode()
+
+
+def _check(rc: int) -> int:
+    if rc < 0:
+        raise SlrError(rc, last_error())
+    return rc
+
+
+def _stream(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return C.c_void_p(stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream))
+
+
+class Net:
+    """A ReLU network resident on the device (``load_net``)."""
+
+    def __init__(self, layers: Sequence[Tuple[np.ndarray, np.ndarray]]):
+        L = lib()
+        self._keep = [(np.ascontiguousarray(W, np.float32), np.ascontiguousarray(b, np.float32))
+                      for W, b in layers]
+        sizes = [self._keep[0][0].shape[1]] + [W.shape[0] for W, _ in self._keep]
+        for (W, b), n_in, n_out in zip(self._keep, sizes[:-1], sizes[1:]):
+            if W.shape != (n_out, n_in) or b.shape != (n_out,):
+                raise ValueError("layer shapes do not chain")
+        self.sizes = sizes
+        self.d = sizes[0]
+        n = len(self._keep)
+        arr_s = (C.c_int32 * (n + 1))(*sizes)
+        arr_w = (C.c_void_p * n)(*[W.ctypes.data for W, _ in self._keep])
+        arr_b = (C.c_void_p * n)(*[b.ctypes.data for _, b in self._keep])
+        h = C.c_void_p()
+        _check(L.load_net(n, arr_s, arr_w, arr_b, C.byref(h)))
+        self.handle = h
+
+    def __del__(self):
+        if getattr(self, "handle", None) and _LIB is not None:
+            _LIB.free_net(self.handle)
+            self.handle = None
+
+
+class Property:
+    """Unsafe set {y : C y + d > 0 on every row} bound to a network (``load_property``)."""
+
+    def __init__(self, net: Net, Cm, dv):
+        self.net = net
+        self.C = np.ascontiguousarray(np.atleast_2d(Cm), np.float32)
+        self.dv = np.ascontiguousarray(np.ravel(dv), np.float32)
+        self.rows = self.C.shape[0]
+        if self.C.shape[1] != net.sizes[-1] or self.dv.shape[0] != self.rows:
+            raise ValueError("property shape does not match the network output")
+        h = C.c_void_p()
+        _check(lib().load_property(net.handle, self.rows, self.C.ctypes.data,
+                                   self.dv.ctypes.data, C.byref(h)))
+        self.handle = h
+
+    def __del__(self):
+        if getattr(self, "handle", None) and _LIB is not None:
+            _LIB.free_property(self.handle)
+            self.handle = None
+
+
+def load_net(layers) -> Net:
+    return Net(layers)
+
+
+def load_property(net: Net, Cm, dv) -> Property:
+    return Property(net, Cm, dv)
+
+
+def bound_boxes(net: Net, prop: Property, lo, hi, g_lo=None, g_hi=None, cls=None,
+                raw: bool = False, stream=None, want_cls: bool = True):
+    """Bounds of every property row over each box; ``lo``/``hi`` are device float32 [n, d]."""
+    import torch
+    n = lo.shape[0]
+    assert lo.is_cuda and hi.is_cuda and lo.dtype == torch.float32 and hi.dtype == torch.float32
+    assert lo.is_contiguous() and hi.is_contiguous() and tuple(lo.shape) == (n, net.d)
+    assert tuple(hi.shape) == (n, net.d)
+    if g_lo is None:
+        g_lo = torch.empty((n, prop.rows), dtype=torch.float32, device=lo.device)
+    if g_hi is None:
+        g_hi = torch.empty((n, prop.rows), dtype=torch.float32, device=lo.device)
+    if cls is None and want_cls:
+        cls = torch.empty((n,), dtype=torch.int8, device=lo.device)
+    _check(lib().bound_boxes(net.handle, prop.handle, n, lo.data_ptr(), hi.data_ptr(),
+                             g_lo.data_ptr(), g_hi.data_ptr(),
+                             cls.data_ptr() if cls is not None else None, int(bool(raw)),
+                             _stream(stream)))
+    return g_lo, g_hi, cls
+
+
+def workspace_size(net: Net, prop: Property, max_leaves: int, samples: int = 0) -> int:
+    out = C.c_size_t()
+    _check(lib().workspace_size(net.handle, prop.handle, int(max_leaves), int(samples),
+                                C.byref(out)))
+    return out.value
+
+
+def _exact_opts(net, prop, max_depth, max_leaves, chunk, workspace, stream, samples,
+                trace_capacity=0, timing=False):
+    import torch
+    need = workspace_size(net, prop, max_leaves, samples)
+    if workspace is None:
+        workspace = torch.empty(need, dtype=torch.uint8, device="cuda")
+    assert workspace.is_cuda
+    o = ExactOpts()
+    o.max_depth = int(max_depth)
+    o.max_leaves = int(max_leaves)
+    o.chunk = int(chunk)
+    o.workspace = workspace.data_ptr()
+    o.workspace_bytes = workspace.numel() * workspace.element_size()
+    o.stream = _stream(stream)
+    o.trace_capacity = int(trace_capacity)
+    o.timing = int(bool(timing))
+    return o, workspace
+
+
+def count_exact(net: Net, prop: Property, lo, hi, max_depth: int, max_leaves: int,
+                chunk: int = 0, workspace=None, stream=None, trace: bool = False,
+                trace_capacity: Optional[int] = None, timing: bool = False) -> dict:
+    """Alg. 1 on the device; returns the bracket, counts and (optionally) a per-box trace."""
+    lo = np.ascontiguousarray(lo, np.float64)
+    hi = np.ascontiguousarray(hi, np.float64)
+    cap = 0
+    if trace:
+        cap = int(trace_capacity if trace_capacity is not None else 4 * max_leaves + 64)
+    o, ws = _exact_opts(net, prop, max_depth, max_leaves, chunk, workspace, stream, 0, cap, timing)
+    if trace:
+        t_depth = np.zeros(cap, np.int32)
+        t_path = np.zeros(cap, np.uint64)
+        t_cls = np.zeros(cap, np.int8)
+        o.trace_depth = t_depth.ctypes.data_as(C.POINTER(C.c_int32))
+        o.trace_path = t_path.ctypes.data_as(C.POINTER(C.c_uint64))
+        o.trace_cls = t_cls.ctypes.data_as(C.POINTER(C.c_int8))
+    r = CountResult()
+    rc = _check(lib().count_exact(net.handle, prop.handle,
+                                  lo.ctypes.data_as(C.POINTER(C.c_double)),
+                                  hi.ctypes.data_as(C.POINTER(C.c_double)), C.byref(o),
+                                  C.byref(r)))
+    out = {f: getattr(r, f) for f, _ in CountResult._fields_}
+    out["rc"] = rc
+    if trace:
+        k = r.trace_count
+        out["trace_depth"] = t_depth[:k].copy()
+        out["trace_path"] = t_path[:k].copy()
+        out["trace_cls"] = t_cls[:k].copy()
+    return out
+
+
+def count_approx(net: Net, prop: Property, lo, hi, trials: int = 20, samples: int = 1000,
+                 confidence: float = 0.99, seed: int = 0, max_splits: int = 60,
+                 grid_bits: int = 16, resolve_tol: float = 0.01, leaf_depth: int = 48,
+                 leaf_leaves: int = 1 << 16, chunk: int = 0, workspace=None,
+                 stream=None) -> dict:
+    lo = np.ascontiguousarray(lo, np.float64)
+    hi = np.ascontiguousarray(hi, np.float64)
+    leaf, ws = _exact_opts(net, prop, leaf_depth, leaf_leaves, chunk, workspace, stream, samples)
+    o = ApproxOpts()
+    o.trials = int(trials)
+    o.samples = int(samples)
+    o.confidence = float(confidence)
+    o.seed = int(seed)
+    o.max_splits = int(max_splits)
+    o.grid_bits = int(grid_bits)
+    o.resolve_tol = float(resolve_tol)
+    o.leaf = leaf
+    r = ApproxResult()
+    _check(lib().count_approx(net.handle, prop.handle, lo.ctypes.data_as(C.POINTER(C.c_double)),
+                              hi.ctypes.data_as(C.POINTER(C.c_double)), C.byref(o), C.byref(r)))
+    t = r.trials
+    return dict(lower_bound=r.lower_bound, estimates=list(r.estimate[:t]),
+                splits=list(r.splits[:t]), seconds=r.seconds)
+
+
+def sample_violations(net: Net, prop: Property, x, viol=None, stream=None):
+    import torch
+    assert x.is_cuda and x.dtype == torch.float32 and x.is_contiguous()
+    n = x.shape[0]
+    if viol is None:
+        viol = torch.empty((n,), dtype=torch.int8, device=x.device)
+    _check(lib().sample_violations(net.handle, prop.handle, n, x.data_ptr(), viol.data_ptr(),
+                                   _stream(stream)))
+    return viol

@@ -1,0 +1,302 @@
+"""HIP path against the FP64 oracle, through the C ABI (needs an MI355X).
+
+Parity protocol:
+  * raw (unwidened) float32 bounds agree with the oracle within 1e-5 relative to the row's
+    interval magnitude max(1, |g_lo|, |g_hi|) (each endpoint is c0 -+ (r + S), a sum whose terms
+    can be far larger than the endpoint itself);
+  * widened bounds contain every sampled point's exact value;
+  * classes agree wherever the oracle's margin min_r(|g_lo_r|, |g_hi_r|) exceeds 1e-5;
+  * exact counts visit the same boxes (matched by depth and path id), with identical classes,
+    leaf counts and volumes, unless a box with margin <= 1e-5 explains the difference.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import count, slr
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-5
+
+
+def E():
+    import paper_2312_05890_amd as eng
+    return eng
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, np.float32)).cuda()
+
+
+def load(inst):
+    eng = E()
+    net = eng.Net(inst.net)
+    return net, eng.Property(net, inst.C, inst.dvec)
+
+
+def margin(g_lo, g_hi):
+    return np.minimum(np.abs(g_lo), np.abs(g_hi)).min(axis=1)
+
+
+def gpu_bounds(inst, blo, bhi, raw):
+    net, prop = load(inst)
+    g_lo, g_hi, cls = E().bound_boxes(net, prop, dev(blo), dev(bhi), raw=raw)
+    torch.cuda.synchronize()
+    return g_lo.cpu().numpy().astype(np.float64), g_hi.cpu().numpy().astype(np.float64), \
+        cls.cpu().numpy()
+
+
+CASES = [("tiny2d", 0, 10), ("tiny2d", 3, 16), ("acas", 0, 12), ("acas", 1, 33),
+         ("acas", 2, 38), ("nav22", 0, 30), ("nav22", 1, 60)]
+
+
+def make(name, seed):
+    return getattr(synth, name)(seed)
+
+
+@pytest.mark.parametrize("name,seed,depth", CASES)
+def test_bound_raw_parity(name, seed, depth):
+    inst = make(name, seed)
+    blo, bhi = synth.random_boxes(inst.lo, inst.hi, 1000, seed + 17, depth)
+    o_lo, o_hi = slr.propagate(inst.net, inst.C, inst.dvec, blo, bhi)
+    g_lo, g_hi, _ = gpu_bounds(inst, blo, bhi, raw=True)
+    scale = TOL * np.maximum(1.0, np.maximum(np.abs(o_lo), np.abs(o_hi)))
+    err_lo = np.abs(g_lo - o_lo) / scale
+    err_hi = np.abs(g_hi - o_hi) / scale
+    assert err_lo.max() <= 1.0, f"worst lower-bound error {err_lo.max():.3g} x tolerance"
+    assert err_hi.max() <= 1.0, f"worst upper-bound error {err_hi.max():.3g} x tolerance"
+
+
+@pytest.mark.parametrize("name,seed,depth", CASES)
+def test_widened_bounds_sound_and_classes(name, seed, depth):
+    inst = make(name, seed)
+    blo, bhi = synth.random_boxes(inst.lo, inst.hi, 600, seed + 5, depth)
+    g_lo, g_hi, cls = gpu_bounds(inst, blo, bhi, raw=False)
+    rng = np.random.default_rng(seed)
+    for i in range(0, blo.shape[0], 37):
+        x = slr.sample_points(blo[i].astype(np.float64), bhi[i].astype(np.float64), 300, rng)
+        gv = slr.property_values(inst.net, inst.C, inst.dvec, x)
+        assert np.all(g_lo[i] <= gv.min(axis=0)) and np.all(gv.max(axis=0) <= g_hi[i])
+    o_lo, o_hi = slr.propagate(inst.net, inst.C, inst.dvec, blo, bhi)
+    o_cls = slr.classify(o_lo, o_hi)
+    big = margin(o_lo, o_hi) > TOL
+    assert np.array_equal(cls[big], o_cls[big])
+    assert set(np.unique(cls)) <= {0, 1, 2}
+
+
+def test_bound_ragged_and_empty():
+    inst = synth.acas(4)
+    net, prop = load(inst)
+    for n in (0, 1, 15, 16, 17, 63, 65, 257):
+        blo, bhi = synth.random_boxes(inst.lo, inst.hi, n, n, 25)
+        if n == 0:
+            blo = np.zeros((0, 5), np.float32)
+            bhi = np.zeros((0, 5), np.float32)
+        g_lo, g_hi, cls = E().bound_boxes(net, prop, dev(blo), dev(bhi), raw=True)
+        torch.cuda.synchronize()
+        if n == 0:
+            continue
+        o_lo, o_hi = slr.propagate(inst.net, inst.C, inst.dvec, blo, bhi)
+        assert np.allclose(g_lo.cpu().numpy(), o_lo, rtol=TOL, atol=TOL)
+        assert np.allclose(g_hi.cpu().numpy(), o_hi, rtol=TOL, atol=TOL)
+
+
+def test_degenerate_boxes_contain_point_value():
+    inst = synth.acas(5)
+    rng = np.random.default_rng(1)
+    x = rng.uniform(0, 1, size=(40, 5)).astype(np.float32)
+    g_lo, g_hi, _ = gpu_bounds(inst, x, x, raw=False)
+    gv = slr.property_values(inst.net, inst.C, inst.dvec, x.astype(np.float64))
+    assert np.all(g_lo <= gv) and np.all(gv <= g_hi)
+    # unwidened bounds of a point are the forward pass up to float32 rounding
+    r_lo, r_hi, _ = gpu_bounds(inst, x, x, raw=True)
+    assert np.all(np.abs(r_lo - gv) <= 1e-5 * np.maximum(1.0, np.abs(gv)))
+    assert np.all(np.abs(r_hi - gv) <= 1e-5 * np.maximum(1.0, np.abs(gv)))
+
+
+def _index(levels_or_trace, oracle: bool):
+    out = {}
+    if oracle:
+        for lev in levels_or_trace:
+            mg = margin(lev["g_lo"], lev["g_hi"])
+            for p, c, m in zip(lev["path"], lev["cls"], mg):
+                out[(lev["depth"], int(p))] = (int(c), float(m))
+    else:
+        d, p, c = levels_or_trace
+        for a, b, k in zip(d, p, c):
+            out[(int(a), int(b))] = (int(k), None)
+    return out
+
+
+def _ancestor_in(key, keys):
+    t, p = key
+    while t > 0:
+        t -= 1
+        p >>= 1
+        if (t, p) in keys:
+            return True
+    return False
+
+
+def compare_counts(inst, D, M, chunk=0):
+    net, prop = load(inst)
+    g = E().count_exact(net, prop, inst.lo, inst.hi, D, M, chunk=chunk, trace=True)
+    o = count.count_exact(inst.net, inst.C, inst.dvec, inst.lo, inst.hi, D, M, trace=True)
+    oi = _index(o["levels"], True)
+    gi = _index((g["trace_depth"], g["trace_path"], g["trace_cls"]), False)
+    small = {k for k, (c, m) in oi.items() if m <= TOL}
+    diverge = set()
+    for k in oi.keys() & gi.keys():
+        if oi[k][0] != gi[k][0]:
+            assert k in small, f"class mismatch at {k} with margin {oi[k][1]}"
+            diverge.add(k)
+    for k in oi.keys() ^ gi.keys():
+        assert _ancestor_in(k, diverge), f"box {k} visited by one side only"
+    if not diverge:
+        assert g["n_unsafe"] == o["n_unsafe"] and g["n_safe"] == o["n_safe"]
+        assert g["n_undecided"] == o["n_undecided"]
+        assert g["unsafe"] == o["unsafe"] and g["safe"] == o["safe"]
+        assert g["undecided"] == o["undecided"]
+        assert g["n_boxes_bounded"] == o["n_boxes_bounded"]
+        assert g["depth_reached"] == o["depth_reached"]
+        assert g["status"] == o["status"]
+    else:
+        assert abs(g["unsafe"] - o["unsafe"]) <= sum(2.0 ** -k[0] for k in diverge)
+    assert g["unsafe"] + g["safe"] + g["undecided"] == 1.0
+    return g, o, diverge
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_count_exact_tiny2d(seed):
+    inst = synth.tiny2d(seed)
+    g, o, div = compare_counts(inst, inst.max_depth, inst.max_leaves)
+    assert g["status"] in (0, 1)
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_count_exact_acas_small_budget(seed):
+    inst = synth.acas(seed)
+    compare_counts(inst, 40, 1 << 12, chunk=1000)
+
+
+def test_count_exact_closed_forms():
+    from tests import oracle_pins as P
+    for net, lo, hi, D in ((P.abs_net(), np.zeros(2), np.ones(2), 14),
+                           (P.irwin_hall_net(), np.zeros(3), np.ones(3), 24)):
+        inst = synth.Instance("cf", net, lo, hi, np.array([[1.0]], np.float32),
+                              np.zeros(1, np.float32), D, 1 << 20)
+        g, o, div = compare_counts(inst, D, 1 << 20)
+        assert not div
+
+
+def test_count_exact_nav22():
+    inst = synth.nav22(0)
+    compare_counts(inst, 40, 1 << 11)
+
+
+def test_count_exact_deterministic_and_budget():
+    inst = synth.tiny2d(7)
+    net, prop = load(inst)
+    a = E().count_exact(net, prop, inst.lo, inst.hi, 16, 1 << 20)
+    b = E().count_exact(net, prop, inst.lo, inst.hi, 16, 1 << 20)
+    for k in ("unsafe", "safe", "undecided", "n_unsafe", "n_safe", "n_undecided"):
+        assert a[k] == b[k]
+    c = E().count_exact(net, prop, inst.lo, inst.hi, 30, 100)
+    assert c["status"] == 1 and c["n_unsafe"] + c["n_safe"] + c["n_undecided"] <= 100
+    z = E().count_exact(net, prop, inst.lo, inst.hi, 0, 10)
+    assert z["n_boxes_bounded"] == 1 and z["depth_reached"] == 0
+
+
+def test_count_exact_rejects_bad_input():
+    inst = synth.tiny2d(0)
+    net, prop = load(inst)
+    eng = E()
+    with pytest.raises(eng.SlrError) as e:
+        eng.count_exact(net, prop, np.array([0.5, 0.0]), np.array([0.0, 1.0]), 5, 10)
+    assert e.value.code == -1
+    with pytest.raises(eng.SlrError) as e:
+        eng.count_exact(net, prop, np.array([0.1, 0.0]), np.array([1.0, 1.0]), 5, 10)
+    assert e.value.code == -1                      # 0.1 is not a float32 value
+    small = torch.empty(16, dtype=torch.uint8, device="cuda")
+    with pytest.raises(eng.SlrError) as e:
+        eng.count_exact(net, prop, inst.lo, inst.hi, 5, 10, workspace=small)
+    assert e.value.code == -2
+    other = eng.Net(synth.tiny2d(1).net)
+    p_other = eng.Property(other, inst.C, inst.dvec)
+    with pytest.raises(eng.SlrError):
+        eng.count_exact(net, p_other, inst.lo, inst.hi, 5, 10)
+
+
+def reconstruct(lo, hi, depth, path):
+    """Box of a path id under widest-side bisection (lowest index on ties)."""
+    lo = np.array(lo, np.float64)
+    hi = np.array(hi, np.float64)
+    for t in range(depth - 1, -1, -1):
+        j = int(np.argmax(hi - lo))
+        m = 0.5 * (lo[j] + hi[j])
+        if (int(path) >> t) & 1:
+            lo[j] = m
+        else:
+            hi[j] = m
+    return lo, hi
+
+
+def test_count_exact_acas_full_size_sampled():
+    """The benchmark workload (2^20-leaf budget, 65536-box launches), checked on samples."""
+    inst = synth.acas(0)
+    net, prop = load(inst)
+    g = E().count_exact(net, prop, inst.lo, inst.hi, inst.max_depth, inst.max_leaves,
+                        chunk=65536, trace=True, trace_capacity=1 << 22)
+    assert g["unsafe"] + g["safe"] + g["undecided"] == 1.0
+    assert g["n_unsafe"] + g["n_safe"] + g["n_undecided"] <= inst.max_leaves
+    n = g["trace_count"]
+    assert n == g["n_boxes_bounded"]
+    rng = np.random.default_rng(0)
+    idx = rng.choice(n, size=300, replace=False)
+    blo, bhi = [], []
+    for i in idx:
+        a, b = reconstruct(inst.lo, inst.hi, int(g["trace_depth"][i]), int(g["trace_path"][i]))
+        blo.append(a)
+        bhi.append(b)
+    blo = np.array(blo)
+    bhi = np.array(bhi)
+    o_lo, o_hi = slr.propagate(inst.net, inst.C, inst.dvec, blo, bhi)
+    oc = slr.classify(o_lo, o_hi)
+    big = margin(o_lo, o_hi) > TOL
+    assert np.array_equal(g["trace_cls"][idx][big], oc[big])
+
+
+def test_sample_violations_matches_forward():
+    inst = synth.nav22(2)
+    net, prop = load(inst)
+    rng = np.random.default_rng(3)
+    x = rng.uniform(0, 1, size=(3000, 22)).astype(np.float32)
+    v = E().sample_violations(net, prop, dev(x)).cpu().numpy()
+    gv = slr.property_values(inst.net, inst.C, inst.dvec, x.astype(np.float64))
+    o = np.all(gv > 0, axis=1)
+    mg = np.abs(gv).min(axis=1)
+    sure = mg > 1e-4
+    assert np.array_equal(v[sure].astype(bool), o[sure])
+
+
+def test_count_approx_matches_oracle_draws():
+    """Same Philox draws on both sides: identical split counts and estimates up to rounding."""
+    from tests import oracle_pins as P
+    net_l = [(np.eye(3, dtype=np.float32), np.zeros(3, np.float32)),
+             (np.array([[1, 1, 1]], np.float32), np.array([-2.0], np.float32))]
+    eng = E()
+    net = eng.Net(net_l)
+    prop = eng.Property(net, [[1.0]], [0.0])
+    kw = dict(trials=4, samples=200, seed=11, max_splits=8, grid_bits=16, resolve_tol=0.02)
+    g = eng.count_approx(net, prop, np.zeros(3), np.ones(3), leaf_depth=18, leaf_leaves=1 << 12, **kw)
+    o = count.count_approx(net_l, [[1.0]], [0.0], np.zeros(3), np.ones(3), leaf_depth=18,
+                           leaf_leaves=1 << 12, **kw)
+    assert g["splits"] == o["splits"]
+    assert np.allclose(g["estimates"], o["estimates"], rtol=1e-12, atol=0)
+    assert g["lower_bound"] <= 1.0 / 6.0       # true volume of {sum x > 2} is 1/6

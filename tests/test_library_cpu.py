@@ -1,0 +1,80 @@
+"""Host-side checks of the C-ABI library that need no GPU: it loads, exports every declared
+entry point, and rejects invalid arguments before touching the device."""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "slrcount.h")
+
+
+@pytest.fixture(scope="module")
+def eng():
+    import paper_2312_05890_amd as eng
+    if not os.path.exists(eng.slrcount.LIB_PATH):
+        from paper_2312_05890_amd import build
+        build.build()
+    eng.lib()
+    return eng
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?(?:int|void|char)\s*\*?\s*(\w+)\s*\(", text, flags=re.M)
+    return sorted(set(names))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for n in ("load_net", "count_exact", "count_approx", "bound_boxes"):
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol(eng):
+    lib = C.CDLL(eng.slrcount.LIB_PATH)
+    missing = [n for n in declared_functions() if not hasattr(lib, n)]
+    assert not missing, missing
+    assert set(eng.EXPORTS) == set(declared_functions())
+
+
+def _load(eng, sizes, W, b):
+    L = eng.lib()
+    n = len(W)
+    h = C.c_void_p()
+    rc = L.load_net(n, (C.c_int32 * (n + 1))(*sizes),
+                    (C.c_void_p * n)(*[w.ctypes.data for w in W]),
+                    (C.c_void_p * n)(*[x.ctypes.data for x in b]), C.byref(h))
+    return rc, h
+
+
+def test_load_net_rejects_bad_shapes_and_values(eng):
+    W = [np.ones((4, 3), np.float32), np.ones((2, 4), np.float32)]
+    b = [np.zeros(4, np.float32), np.zeros(2, np.float32)]
+    rc, _ = _load(eng, [3, 4], W[:1], b[:1])              # n_affine = 1
+    assert rc == -1 and "n_affine" in eng.last_error()
+    rc, _ = _load(eng, [0, 4, 2], W, b)
+    assert rc == -1 and "input dimension" in eng.last_error()
+    rc, _ = _load(eng, [3, 300, 2], W, b)
+    assert rc == -1 and "hidden width" in eng.last_error()
+    Wn = [W[0].copy(), W[1]]
+    Wn[0][1, 2] = np.nan
+    rc, _ = _load(eng, [3, 4, 2], Wn, b)
+    assert rc == -1 and "NaN" in eng.last_error()
+
+
+def test_calls_reject_null_handles(eng):
+    L = eng.lib()
+    lo = (C.c_double * 2)(0.0, 0.0)
+    hi = (C.c_double * 2)(1.0, 1.0)
+    assert L.count_exact(None, None, lo, hi, None, None) == -1
+    assert L.bound_boxes(None, None, 0, None, None, None, None, None, 0, None) == -1
+    assert L.count_approx(None, None, lo, hi, None, None) == -1
+    out = C.c_size_t()
+    assert L.workspace_size(None, None, 10, 0, C.byref(out)) == -1
+    assert "net is NULL" in eng.last_error()
