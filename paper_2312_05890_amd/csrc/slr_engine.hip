@@ -197,7 +197,7 @@ extern "C" int load_net(int32_t n_affine, const int32_t* sizes, const float* con
 
     const size_t i_w1 = add(W[0], sizeof(float) * sizes[1] * d);
     const size_t i_b1 = add(b[0], sizeof(float) * sizes[1]);
-    struct MidIdx { size_t frag, w, bias, absrow; };
+    struct MidIdx { size_t frag, w, wt, bias, absrow; };
     std::vector<MidIdx> mids;
     for (int l = 1; l <= n_affine - 2; ++l) {
         const int n_in = sizes[l], n_out = sizes[l + 1];
@@ -220,6 +220,10 @@ extern "C" int load_net(int32_t n_affine, const int32_t* sizes, const float* con
         MidIdx mi;
         mi.frag = add(frag.data(), frag.size() * sizeof(float));
         mi.w = add(W[l], sizeof(float) * n_out * n_in);
+        std::vector<float> wt((size_t)n_in * n_out);
+        for (int jrow = 0; jrow < n_out; ++jrow)
+            for (int k = 0; k < n_in; ++k) wt[(size_t)k * n_out + jrow] = W[l][(size_t)jrow * n_in + k];
+        mi.wt = add(wt.data(), wt.size() * sizeof(float));
         mi.bias = add(bias.data(), bias.size() * sizeof(float));
         mi.absrow = add(absrow.data(), absrow.size() * sizeof(float));
         mids.push_back(mi);
@@ -246,6 +250,7 @@ extern "C" int load_net(int32_t n_affine, const int32_t* sizes, const float* con
     for (int l = 0; l < n_affine - 2; ++l) {
         nd.mid[l].wfrag = (const float*)(base + offs[mids[l].frag]);
         nd.mid[l].w = (const float*)(base + offs[mids[l].w]);
+        nd.mid[l].wt = (const float*)(base + offs[mids[l].wt]);
         nd.mid[l].bias = (const float*)(base + offs[mids[l].bias]);
         nd.mid[l].absrow = (const float*)(base + offs[mids[l].absrow]);
     }
@@ -366,6 +371,8 @@ struct Workspace {
     float *lo[2], *hi[2];
     unsigned long long* path[2];
     int8_t* cls;
+    unsigned* amb_list;          // [cap] boxes of the level that need the FP64 re-decision
+    unsigned* amb_count;
     unsigned* tile_und;
     LevelStats* stats;           // [kMaxLevels]
     double* vol;                 // [3]
@@ -393,6 +400,8 @@ Workspace layout_ws(char* base, int d, int64_t cap, int samples) {
         w.path[s] = (unsigned long long*)take(sizeof(unsigned long long) * cap);
     }
     w.cls = (int8_t*)take(cap);
+    w.amb_list = (unsigned*)take(sizeof(unsigned) * cap);
+    w.amb_count = (unsigned*)take(sizeof(unsigned));
     w.tile_und = (unsigned*)take(sizeof(unsigned) * level_tiles(cap));
     w.stats = (LevelStats*)take(sizeof(LevelStats) * kMaxLevels);
     w.vol = (double*)take(sizeof(double) * 3);
@@ -454,11 +463,13 @@ extern "C" int bound_boxes(const slr_net* net, const slr_property* prop, int64_t
     if (cls && !is_device_ptr(cls)) return fail(SLR_EINVAL, "bound_boxes: cls must be device memory");
     hipStream_t s = (hipStream_t)stream;
     int unsup = 0;
-    HIP_TRY(launch_bound_f32(net->dev, prop->dev, n, lo, hi, g_lo, g_hi, cls, raw, s, &unsup),
+    HIP_TRY(launch_bound_f32(net->dev, prop->dev, n, lo, hi, g_lo, g_hi, cls, raw, s, &unsup,
+                             nullptr, nullptr, 0),
             "bound_boxes: bound kernel");
     if (unsup) return fail(SLR_EUNSUPPORTED, "bound_boxes: shape not supported");
     if (!raw && cls)
-        HIP_TRY(launch_recheck64(net->dev, prop->dev, n, lo, hi, g_lo, g_hi, cls, nullptr, s),
+        HIP_TRY(launch_recheck64(net->dev, prop->dev, n, lo, hi, g_lo, g_hi, cls, nullptr, nullptr,
+                                 nullptr, s),
                 "bound_boxes: recheck kernel");
     return SLR_OK;
 }
@@ -522,18 +533,21 @@ int count_exact_impl(const slr_net* net, const slr_property* prop, const double*
     std::vector<int8_t> hcls;
     for (int t = 0; t <= D; ++t) {
         int unsup = 0;
+        HIP_TRY(hipMemsetAsync(w.amb_count, 0, sizeof(unsigned), s), "count_exact: clear");
         if (ev0) HIP_TRY(hipEventRecord(ev0, s), "count_exact: event");
         for (int64_t off = 0; off < n; off += chunk) {
             const int64_t m = std::min(chunk, n - off);
             HIP_TRY(launch_bound_f32(net->dev, prop->dev, m, w.lo[cur] + off * d, w.hi[cur] + off * d,
-                                     nullptr, nullptr, w.cls + off, 0, s, &unsup),
+                                     nullptr, nullptr, w.cls + off, 0, s, &unsup, w.amb_list,
+                                     w.amb_count, (unsigned)off),
                     "count_exact: bound kernel");
             if (unsup) return fail(SLR_EUNSUPPORTED, "count_exact: shape not supported");
             ++launches;
         }
         if (ev1) HIP_TRY(hipEventRecord(ev1, s), "count_exact: event");
         HIP_TRY(launch_recheck64(net->dev, prop->dev, n, w.lo[cur], w.hi[cur], nullptr, nullptr,
-                                 w.cls, w.rechecks, s), "count_exact: recheck kernel");
+                                 w.cls, w.rechecks, w.amb_list, w.amb_count, s),
+                "count_exact: recheck kernel");
         HIP_TRY(launch_level_count(n, w.cls, w.tile_und, w.stats + t, s), "count_exact: count kernel");
         LevelStats hs;
         HIP_TRY(hipMemcpyAsync(&hs, w.stats + t, sizeof hs, hipMemcpyDeviceToHost, s), "count_exact: readback");

@@ -22,7 +22,8 @@
 // One hidden-to-hidden affine layer (its input is a hidden ReLU layer).
 struct MidLayer {
     const float* wfrag;   // [mt_out][ks_alloc][64] MFMA A-operand fragments (see pack_fragments)
-    const float* w;       // row-major [n_out][n_in] float32 (FP64 recheck path)
+    const float* w;       // row-major [n_out][n_in] float32 (sample forward pass)
+    const float* wt;      // transposed [n_in][n_out] (FP64 recheck: coalesced across neurons)
     const float* bias;    // [16 * mt_out], zero padded
     const float* absrow;  // [16 * mt_out]: sum_k |W_jk|, rounded up to float32
     int n_in, n_out, mt_out, ks, ks_alloc;
@@ -65,12 +66,17 @@ struct LevelStats {
 };
 
 // Kernel launchers (slr_kernels.hip).  All are asynchronous on `stream`.
+// The bound kernel writes class 3 for boxes whose class could differ in exact arithmetic and,
+// if amb_list is given, appends list_base + (box index) to amb_list[atomicAdd(amb_count)].
 hipError_t launch_bound_f32(const NetDev& net, const PropDev& prop, int64_t n, const float* lo,
                             const float* hi, float* g_lo, float* g_hi, int8_t* cls, int raw,
-                            hipStream_t stream, int* unsupported);
+                            hipStream_t stream, int* unsupported, unsigned* amb_list,
+                            unsigned* amb_count, unsigned list_base);
+// FP64 re-decision of the boxes list[0 .. *list_count), or of every class-3 box if list is NULL.
 hipError_t launch_recheck64(const NetDev& net, const PropDev& prop, int64_t n, const float* lo,
                             const float* hi, float* g_lo, float* g_hi, int8_t* cls,
-                            unsigned long long* counter, hipStream_t stream);
+                            unsigned long long* counter, const unsigned* list,
+                            const unsigned* list_count, hipStream_t stream);
 hipError_t launch_level_count(int64_t n, const int8_t* cls, unsigned int* tile_und,
                               LevelStats* stats, hipStream_t stream);
 hipError_t launch_split(int64_t n, int d, const int8_t* cls, const unsigned int* tile_und,

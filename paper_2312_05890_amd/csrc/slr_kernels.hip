@@ -89,7 +89,8 @@ template <int NCOL, int NT, int UW>
 __global__ __launch_bounds__(kNW * 64) void bound_f32_kernel(
     NetDev net, PropDev prop, int64_t n, const float* __restrict__ blo,
     const float* __restrict__ bhi, float* __restrict__ g_lo, float* __restrict__ g_hi,
-    int8_t* __restrict__ cls, int raw, int SP) {
+    int8_t* __restrict__ cls, int raw, int SP, unsigned* __restrict__ amb_list,
+    unsigned* __restrict__ amb_count, unsigned list_base) {
     extern __shared__ float lds[];
     constexpr int T = NT * 16;
     constexpr int D = NCOL - 3;
@@ -304,32 +305,34 @@ __global__ __launch_bounds__(kNW * 64) void bound_f32_kernel(
             amb_safe = amb_safe || (ghi - tau <= 0.f);
         }
         int8_t k = unsafe ? 1 : (safe ? 2 : 0);
-        if (k == 0 && !raw && (amb_unsafe || amb_safe)) k = 3;
+        if (k == 0 && !raw && (amb_unsafe || amb_safe)) {
+            k = 3;
+            if (amb_list) amb_list[atomicAdd(amb_count, 1u)] = list_base + (unsigned)b;
+        }
         if (cls) cls[b] = k;
     }
 }
 
 // ------------------------------------------------------------------------------------------
 // FP64 re-decision of boxes the float32 pass marked ambiguous (class 3): the same center/radius
-// propagation on the VALU in double precision, one box per workgroup, one thread per neuron.
+// propagation on the VALU in double precision, one box per wavefront, neurons across lanes.
 // ------------------------------------------------------------------------------------------
 
-__device__ __forceinline__ double block_max256(double v, double* red) {
-    const int tid = threadIdx.x;
-    red[tid] = v;
-    __syncthreads();
-    for (int s = 128; s > 0; s >>= 1) {
-        if (tid < s) red[tid] = fmax(red[tid], red[tid + s]);
-        __syncthreads();
-    }
-    const double r = red[0];
-    __syncthreads();
-    return r;
+// LDS ordering between lanes of one wavefront.
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ __forceinline__ double wave_max(double v) {
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
+    return v;
 }
 
 __device__ __forceinline__ double relu64(double* st, int ncol, double eps, double kconc,
                                          double krelu) {
-    // st: one neuron's row (ncol entries, radius last, unwidened); returns |value| bound
+    // st: one neuron's row (center c_0..c_d, then the unwidened radius); returns |value| bound
     const int D = ncol - 2;
     double c0 = st[0];
     double S = 0.0;
@@ -357,127 +360,146 @@ __device__ __forceinline__ double relu64(double* st, int ncol, double eps, doubl
     return (fabs(c0) + lam * S + r) * (1.0 + 4.0 * kU64);
 }
 
+// One box on one wavefront.  ws: this wave's LDS (2 * nrow * ncol + 2 * 32 doubles).
+__device__ void recheck_box(const NetDev& net, const PropDev& prop, int64_t b,
+                            const float* __restrict__ blo, const float* __restrict__ bhi,
+                            float* __restrict__ g_lo, float* __restrict__ g_hi,
+                            int8_t* __restrict__ cls, unsigned long long* counter, double* ws,
+                            int nrow) {
+    const int lane = threadIdx.x & 63;
+    const int d = net.d, ncol = d + 2;
+    double* A = ws;
+    double* B = A + nrow * ncol;
+    double* mid = B + nrow * ncol;
+    double* rad = mid + SLR_MAX_D;
+    if (lane < d) {
+        const double l = blo[b * d + lane], h = bhi[b * d + lane];
+        const double m = 0.5 * (l + h);
+        mid[lane] = m;
+        rad[lane] = fmax(h - m, m - l) * (1.0 + 0x1p-50);
+    }
+    wave_sync();
+    double e = 0.0;
+    for (int j = lane; j < net.n1; j += 64) {
+        double* st = A + j * ncol;
+        const double bb = net.b1[j];
+        double c0 = bb, s = fabs(bb);
+        for (int k = 0; k < d; ++k) {
+            const double w = net.w1[j * d + k];
+            c0 = fma(w, mid[k], c0);
+            st[k + 1] = w * rad[k];
+            s += fabs(w) * (fabs(mid[k]) + rad[k]);
+        }
+        st[0] = c0;
+        st[ncol - 1] = 0.0;
+        e = fmax(e, relu64(st, ncol, net.kfirst64 * s + kEta64, net.kconc64, net.krelu64));
+    }
+    double emax = wave_max(e);
+    wave_sync();
+    double* in = A;
+    double* out = B;
+    for (int l = 0; l < net.n_affine - 2; ++l) {
+        const MidLayer* L = &net.mid[l];
+        e = 0.0;
+        for (int j = lane; j < L->n_out; j += 64) {
+            double* st = out + j * ncol;
+            for (int c = 0; c < ncol; ++c) st[c] = 0.0;
+            double A_row = 0.0;
+            for (int k = 0; k < L->n_in; ++k) {
+                const double w = L->wt[(size_t)k * L->n_out + j];
+                const double* x = in + k * ncol;
+                for (int c = 0; c < ncol - 1; ++c) st[c] = fma(w, x[c], st[c]);
+                st[ncol - 1] = fma(fabs(w), x[ncol - 1], st[ncol - 1]);
+                A_row += fabs(w);
+            }
+            const double bb = L->bias[j];
+            st[0] += bb;
+            const double eps = L->kgam64 * (A_row * (1.0 + 0x1p-40) * emax + fabs(bb)) + kEta64;
+            e = fmax(e, relu64(st, ncol, eps, net.kconc64, net.krelu64));
+        }
+        emax = wave_max(e);
+        wave_sync();
+        double* t = in;
+        in = out;
+        out = t;
+    }
+    // output rows: one (row, column) item per lane
+    const int rows = prop.rows;
+    const int K = prop.n_last;
+    for (int it = lane; it < rows * ncol; it += 64) {
+        const int r = it / ncol, c = it % ncol;
+        double s = 0.0;
+        for (int k = 0; k < K; ++k) {
+            double w = prop.wg64[r * K + k];
+            if (c == ncol - 1) w = fabs(w);
+            s = fma(w, in[k * ncol + c], s);
+        }
+        out[it] = s;
+    }
+    wave_sync();
+    if (lane == 0) {
+        bool unsafe = true, safe = false;
+        for (int r = 0; r < rows; ++r) {
+            const double* o = out + r * ncol;
+            const double bg = prop.bg64[r];
+            const double G0 = o[0] + bg;
+            double Sg = 0.0;
+            for (int c = 1; c <= d; ++c) Sg += fabs(o[c]);
+            const double eps = prop.kout64 * (prop.ag64[r] * emax + fabs(bg)) + kEta64;
+            const double R = o[ncol - 1] + eps;
+            const double delta = net.kconc64 * (fabs(G0) + R + Sg);
+            const double glo = (G0 - (R + Sg)) - delta;
+            const double ghi = (G0 + (R + Sg)) + delta;
+            // float32 copies rounded outward
+            float flo = (float)glo;
+            if ((double)flo > glo) flo = nextafterf(flo, -INFINITY);
+            float fhi = (float)ghi;
+            if ((double)fhi < ghi) fhi = nextafterf(fhi, INFINITY);
+            if (g_lo) g_lo[b * rows + r] = flo;
+            if (g_hi) g_hi[b * rows + r] = fhi;
+            unsafe = unsafe && (glo > 0.0);
+            safe = safe || (ghi <= 0.0);
+        }
+        cls[b] = unsafe ? 1 : (safe ? 2 : 0);
+        if (counter) atomicAdd(counter, 1ull);
+    }
+    wave_sync();
+}
+
+// List mode (list != NULL): boxes list[0 .. *list_count) (indices into lo/hi/cls), one per wave.
+// Scan mode: every box with cls == 3 among the n boxes.
 __global__ __launch_bounds__(256) void recheck64_kernel(NetDev net, PropDev prop, int64_t n,
                                                         const float* __restrict__ blo,
                                                         const float* __restrict__ bhi,
                                                         float* __restrict__ g_lo,
                                                         float* __restrict__ g_hi,
                                                         int8_t* __restrict__ cls,
-                                                        unsigned long long* counter) {
+                                                        unsigned long long* counter,
+                                                        const unsigned* __restrict__ list,
+                                                        const unsigned* __restrict__ list_count,
+                                                        int nrow) {
     extern __shared__ double sm[];
-    __shared__ int list[256];
+    __shared__ int llist[256];
     __shared__ int cnt;
-    const int tid = threadIdx.x;
-    const int d = net.d, ncol = d + 2;
-    const int nrow = net.n_max > prop.rows * ncol ? net.n_max : prop.rows * ncol;
-    double* A = sm;                    // [nrow][ncol]
-    double* B = A + nrow * ncol;       // [nrow][ncol]
-    double* red = B + nrow * ncol;     // [256]
-    double* mid = red + 256;           // [32]
-    double* rad = mid + SLR_MAX_D;     // [32]
-
+    const int tid = threadIdx.x, wave = tid >> 6;
+    const int waves = blockDim.x >> 6;
+    const int ncol = net.d + 2;
+    double* ws = sm + (size_t)wave * (2 * nrow * ncol + 2 * SLR_MAX_D);
+    if (list) {
+        const int64_t total = min((int64_t)*list_count, n);
+        for (int64_t i = (int64_t)blockIdx.x * waves + wave; i < total; i += (int64_t)gridDim.x * waves)
+            recheck_box(net, prop, list[i], blo, bhi, g_lo, g_hi, cls, counter, ws, nrow);
+        return;
+    }
     for (int64_t base = (int64_t)blockIdx.x * 256; base < n; base += (int64_t)gridDim.x * 256) {
         if (tid == 0) cnt = 0;
         __syncthreads();
         const int64_t i = base + tid;
-        if (i < n && cls[i] == 3) list[atomicAdd(&cnt, 1)] = tid;
+        if (i < n && cls[i] == 3) llist[atomicAdd(&cnt, 1)] = tid;
         __syncthreads();
-        const int m_list = cnt;
-        for (int q = 0; q < m_list; ++q) {
-            const int64_t b = base + list[q];
-            if (tid < d) {
-                const double l = blo[b * d + tid], h = bhi[b * d + tid];
-                const double m = 0.5 * (l + h);
-                mid[tid] = m;
-                rad[tid] = fmax(h - m, m - l) * (1.0 + 0x1p-50);
-            }
-            __syncthreads();
-            // first affine layer
-            double e = 0.0;
-            if (tid < net.n1) {
-                double* st = A + tid * ncol;
-                const double bb = net.b1[tid];
-                double c0 = bb, s = fabs(bb);
-                for (int k = 0; k < d; ++k) {
-                    const double w = net.w1[tid * d + k];
-                    c0 = fma(w, mid[k], c0);
-                    st[k + 1] = w * rad[k];
-                    s += fabs(w) * (fabs(mid[k]) + rad[k]);
-                }
-                st[0] = c0;
-                st[ncol - 1] = 0.0;
-                e = relu64(st, ncol, net.kfirst64 * s + kEta64, net.kconc64, net.krelu64);
-            }
-            double emax = block_max256(e, red);
-            double* in = A;
-            double* out = B;
-            for (int l = 0; l < net.n_affine - 2; ++l) {
-                const MidLayer* L = &net.mid[l];
-                e = 0.0;
-                if (tid < L->n_out) {
-                    double* st = out + tid * ncol;
-                    const float* wr = L->w + (size_t)tid * L->n_in;
-                    for (int c = 0; c < ncol; ++c) st[c] = 0.0;
-                    double A_row = 0.0;
-                    for (int k = 0; k < L->n_in; ++k) {
-                        const double w = wr[k];
-                        const double* x = in + k * ncol;
-                        for (int c = 0; c < ncol - 1; ++c) st[c] = fma(w, x[c], st[c]);
-                        st[ncol - 1] = fma(fabs(w), x[ncol - 1], st[ncol - 1]);
-                        A_row += fabs(w);
-                    }
-                    const double bb = L->bias[tid];
-                    st[0] += bb;
-                    const double eps = L->kgam64 * (A_row * (1.0 + 0x1p-40) * emax + fabs(bb)) + kEta64;
-                    e = relu64(st, ncol, eps, net.kconc64, net.krelu64);
-                }
-                emax = block_max256(e, red);
-                double* t = in;
-                in = out;
-                out = t;
-            }
-            // output rows: one (row, column) item per thread
-            const int rows = prop.rows;
-            const int K = prop.n_last;
-            for (int it = tid; it < rows * ncol; it += 256) {
-                const int r = it / ncol, c = it % ncol;
-                double s = 0.0;
-                for (int k = 0; k < K; ++k) {
-                    double w = prop.wg64[r * K + k];
-                    if (c == ncol - 1) w = fabs(w);
-                    s = fma(w, in[k * ncol + c], s);
-                }
-                out[it] = s;
-            }
-            __syncthreads();
-            if (tid == 0) {
-                bool unsafe = true, safe = false;
-                for (int r = 0; r < rows; ++r) {
-                    const double* o = out + r * ncol;
-                    const double bg = prop.bg64[r];
-                    const double G0 = o[0] + bg;
-                    double Sg = 0.0;
-                    for (int c = 1; c <= d; ++c) Sg += fabs(o[c]);
-                    const double eps = prop.kout64 * (prop.ag64[r] * emax + fabs(bg)) + kEta64;
-                    const double R = o[ncol - 1] + eps;
-                    const double delta = net.kconc64 * (fabs(G0) + R + Sg);
-                    const double glo = (G0 - (R + Sg)) - delta;
-                    const double ghi = (G0 + (R + Sg)) + delta;
-                    // float32 copies rounded outward
-                    float flo = (float)glo;
-                    if ((double)flo > glo) flo = nextafterf(flo, -INFINITY);
-                    float fhi = (float)ghi;
-                    if ((double)fhi < ghi) fhi = nextafterf(fhi, INFINITY);
-                    if (g_lo) g_lo[b * rows + r] = flo;
-                    if (g_hi) g_hi[b * rows + r] = fhi;
-                    unsafe = unsafe && (glo > 0.0);
-                    safe = safe || (ghi <= 0.0);
-                }
-                cls[b] = unsafe ? 1 : (safe ? 2 : 0);
-                if (counter) atomicAdd(counter, 1ull);
-            }
-            __syncthreads();
-        }
+        const int m = cnt;
+        for (int q = wave; q < m; q += waves)
+            recheck_box(net, prop, base + llist[q], blo, bhi, g_lo, g_hi, cls, counter, ws, nrow);
         __syncthreads();
     }
 }
@@ -701,7 +723,8 @@ size_t bound_lds_bytes(int NCOL, int NT, int mt_max, int rows) {
 template <int NCOL, int NT, int UW>
 hipError_t launch_inst(const NetDev& net, const PropDev& prop, int64_t n, const float* lo,
                        const float* hi, float* g_lo, float* g_hi, int8_t* cls, int raw,
-                       hipStream_t stream) {
+                       hipStream_t stream, unsigned* amb_list, unsigned* amb_count,
+                       unsigned list_base) {
     const size_t lds = bound_lds_bytes(NCOL, NT, net.mt_max, prop.rows);
     auto kern = bound_f32_kernel<NCOL, NT, UW>;
     hipError_t e = allow_lds((const void*)kern, lds);
@@ -709,20 +732,21 @@ hipError_t launch_inst(const NetDev& net, const PropDev& prop, int64_t n, const 
     const int64_t blocks = (n + NT * 16 - 1) / (NT * 16);
     (void)hipGetLastError();
     hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(kNW * 64), lds, stream, net, prop, n,
-                       lo, hi, g_lo, g_hi, cls, raw, state_stride(net.mt_max));
+                       lo, hi, g_lo, g_hi, cls, raw, state_stride(net.mt_max), amb_list,
+                       amb_count, list_base);
     return hipGetLastError();
 }
 
 template <int NCOL>
 hipError_t launch_ncol(int NT, int UW, const NetDev& net, const PropDev& prop, int64_t n,
                        const float* lo, const float* hi, float* g_lo, float* g_hi, int8_t* cls,
-                       int raw, hipStream_t stream) {
-    if (NT == 4) return launch_inst<NCOL, 4, 1>(net, prop, n, lo, hi, g_lo, g_hi, cls, raw, stream);
-    if (NT == 2) return launch_inst<NCOL, 2, 1>(net, prop, n, lo, hi, g_lo, g_hi, cls, raw, stream);
-    if (UW == 1) return launch_inst<NCOL, 1, 1>(net, prop, n, lo, hi, g_lo, g_hi, cls, raw, stream);
-    if (UW == 2) return launch_inst<NCOL, 1, 2>(net, prop, n, lo, hi, g_lo, g_hi, cls, raw, stream);
+                       int raw, hipStream_t stream, unsigned* al, unsigned* ac, unsigned lb) {
+    if (NT == 4) return launch_inst<NCOL, 4, 1>(net, prop, n, lo, hi, g_lo, g_hi, cls, raw, stream, al, ac, lb);
+    if (NT == 2) return launch_inst<NCOL, 2, 1>(net, prop, n, lo, hi, g_lo, g_hi, cls, raw, stream, al, ac, lb);
+    if (UW == 1) return launch_inst<NCOL, 1, 1>(net, prop, n, lo, hi, g_lo, g_hi, cls, raw, stream, al, ac, lb);
+    if (UW == 2) return launch_inst<NCOL, 1, 2>(net, prop, n, lo, hi, g_lo, g_hi, cls, raw, stream, al, ac, lb);
     if constexpr (NCOL <= 18)
-        return launch_inst<NCOL, 1, 4>(net, prop, n, lo, hi, g_lo, g_hi, cls, raw, stream);
+        return launch_inst<NCOL, 1, 4>(net, prop, n, lo, hi, g_lo, g_hi, cls, raw, stream, al, ac, lb);
     return hipErrorInvalidValue;
 }
 
@@ -739,7 +763,8 @@ int bound_f32_supported(const NetDev& net, const PropDev& prop) {
 
 hipError_t launch_bound_f32(const NetDev& net, const PropDev& prop, int64_t n, const float* lo,
                             const float* hi, float* g_lo, float* g_hi, int8_t* cls, int raw,
-                            hipStream_t stream, int* unsupported) {
+                            hipStream_t stream, int* unsupported, unsigned* amb_list,
+                            unsigned* amb_count, unsigned list_base) {
     *unsupported = 0;
     if (n <= 0) return hipSuccess;
     if (!bound_f32_supported(net, prop)) {
@@ -750,7 +775,8 @@ hipError_t launch_bound_f32(const NetDev& net, const PropDev& prop, int64_t n, c
     tile_class(net.mt_max, &NT, &UW);
     switch (ncol_class(net.d)) {
 #define SLR_CASE(C) \
-    case C: return launch_ncol<C>(NT, UW, net, prop, n, lo, hi, g_lo, g_hi, cls, raw, stream);
+    case C: return launch_ncol<C>(NT, UW, net, prop, n, lo, hi, g_lo, g_hi, cls, raw, stream, \
+                                  amb_list, amb_count, list_base);
         SLR_CASE(4) SLR_CASE(5) SLR_CASE(6) SLR_CASE(7) SLR_CASE(8) SLR_CASE(9)
         SLR_CASE(10) SLR_CASE(11) SLR_CASE(12) SLR_CASE(14) SLR_CASE(18) SLR_CASE(26) SLR_CASE(35)
 #undef SLR_CASE
@@ -760,18 +786,22 @@ hipError_t launch_bound_f32(const NetDev& net, const PropDev& prop, int64_t n, c
 
 hipError_t launch_recheck64(const NetDev& net, const PropDev& prop, int64_t n, const float* lo,
                             const float* hi, float* g_lo, float* g_hi, int8_t* cls,
-                            unsigned long long* counter, hipStream_t stream) {
+                            unsigned long long* counter, const unsigned* list,
+                            const unsigned* list_count, hipStream_t stream) {
     if (n <= 0) return hipSuccess;
     const int ncol = net.d + 2;
     const int nrow = net.n_max > prop.rows * ncol ? net.n_max : prop.rows * ncol;
-    const size_t lds = sizeof(double) * (2 * (size_t)nrow * ncol + 256 + 2 * SLR_MAX_D);
+    const size_t per_wave = sizeof(double) * (2 * (size_t)nrow * ncol + 2 * SLR_MAX_D);
+    int waves = 4;
+    while (waves > 1 && per_wave * waves > 150 * 1024) --waves;
+    const size_t lds = per_wave * waves;
     hipError_t e = allow_lds((const void*)recheck64_kernel, lds);
     if (e != hipSuccess) return e;
-    int64_t blocks = (n + 255) / 256;
-    (void)hipGetLastError();
+    int64_t blocks = list ? 2048 : (n + 255) / 256;
     if (blocks > 65535) blocks = 65535;
-    hipLaunchKernelGGL(recheck64_kernel, dim3((unsigned)blocks), dim3(256), lds, stream, net, prop,
-                       n, lo, hi, g_lo, g_hi, cls, counter);
+    (void)hipGetLastError();
+    hipLaunchKernelGGL(recheck64_kernel, dim3((unsigned)blocks), dim3(64 * waves), lds, stream, net,
+                       prop, n, lo, hi, g_lo, g_hi, cls, counter, list, list_count, nrow);
     return hipGetLastError();
 }
 
