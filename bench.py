@@ -96,6 +96,11 @@ def main():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--cpu-leaves", type=int, default=1 << 15)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--variant", type=int, default=0,
+                    help="bound kernel: 0 automatic, 1 LDS-staged, 2 register-resident")
+    ap.add_argument("--calibrate-copy-mib", type=int, default=0,
+                    help="first copy a tensor of this many MiB once (a plain copy kernel of "
+                         "known size, for scaling hardware byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on exactly one GPU (asked for {args.gpus}); the "
@@ -107,6 +112,7 @@ def main():
     import synth
     import paper_2312_05890_amd as E
 
+    E.bound_kernel_variant(args.variant)
     inst = synth.acas(args.seed)
     net = E.Net(inst.net)
     prop = E.Property(net, inst.C, inst.dvec)
@@ -118,6 +124,14 @@ def main():
         return E.count_exact(net, prop, inst.lo, inst.hi, inst.max_depth, inst.max_leaves,
                              chunk=chunk, workspace=ws, timing=timing)
 
+    if args.calibrate_copy_mib > 0:
+        n = args.calibrate_copy_mib << 18
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     for _ in range(args.warmup):
         step(False)
     torch.cuda.synchronize()
@@ -149,7 +163,7 @@ def main():
         "config": {"workload": "exact count, 5-50x6-5 ReLU MLP (He-normal seed %d), [0,1]^5, "
                                "unsafe iff y0-y1>0, max depth 40, 2^20-leaf budget, 65536-box "
                                "launches" % args.seed,
-                   "mode": "plain"},
+                   "mode": "plain", "kernel_variant": args.variant},
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_FP32_MFMA,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_MFMA,
                      "traffic": traffic},

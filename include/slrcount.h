@@ -88,6 +88,15 @@ int bound_boxes(const slr_net* net, const slr_property* prop, int64_t n, const f
                 const float* hi, float* g_lo, float* g_hi, int8_t* cls, int32_t raw,
                 void* stream);
 
+/*
+ * bound_kernel_variant: process-wide choice of the bound kernel.
+ *   0  automatic (default): currently the LDS-staged kernel, which measured faster;
+ *   1  always the LDS-staged kernel;
+ *   2  the register-resident kernel (shapes it cannot take then fail with SLR_EUNSUPPORTED).
+ * Both kernels compute the same bounds.  Not synchronized with calls in flight on other threads.
+ */
+int bound_kernel_variant(int32_t variant);
+
 /* Options of the exact count (Alg. 1). */
 typedef struct {
     int32_t max_depth;      /* boxes still undecided at this depth are not split (0..62)   */

@@ -51,24 +51,46 @@ float round_up_f32(double x) {
 
 int ceil_div(int a, int b) { return (a + b - 1) / b; }
 
-// K-steps that carry at least one real input neuron (layout: neuron 16 (s/4) + 4 g + s%4).
+// Relabeling of one hidden layer of n neurons: row (padded index 16 mt + 4 g + v) of neuron i.
+// Full tiles keep the order; the last tile (r neurons) fills rows v-major: t = 4 v + g.
+std::vector<int> rows_to_neurons(int n) {
+    const int mt = ceil_div(n, 16);
+    const int r = n - 16 * (mt - 1);
+    std::vector<int> at(16 * mt, -1);
+    for (int i = 0; i < n; ++i) {
+        if (i < 16 * (mt - 1)) {
+            at[i] = i;
+        } else {
+            const int t = i - 16 * (mt - 1);
+            const int v = t / 4, g = t % 4;
+            at[16 * (mt - 1) + 4 * g + v] = i;
+        }
+    }
+    (void)r;
+    return at;
+}
+
+// K-steps that carry at least one real input neuron: 4 (tiles - 1) + ceil(r / 4).
 int k_steps(int n_in) {
     const int mt = ceil_div(n_in, 16);
     const int r = n_in - 16 * (mt - 1);
-    return 4 * (mt - 1) + std::min(4, r);
+    return 4 * (mt - 1) + (r + 3) / 4;
 }
 
-// MFMA A-operand fragments of W [n_out][n_in]: frag[mt][s][lane] = W[16 mt + lane % 16][k]
-// with k = 16 (s / 4) + 4 (lane / 16) + s % 4 (zero outside the matrix or beyond ks).
-std::vector<float> pack_fragments(const float* W, int n_out, int n_in, int ks, int ks_alloc) {
-    const int mt_out = ceil_div(n_out, 16);
+// MFMA A-operand fragments: frag[mt][s][lane] = W[out_at[16 mt + lane % 16]][in_at[k]] with
+// k = 16 (s / 4) + 4 (lane / 16) + s % 4 the padded input row (zero where either is padding).
+// out_at / in_at map padded rows to neurons (-1 = padding); W is row-major [n_out][n_in].
+std::vector<float> pack_fragments(const float* W, int n_in, const std::vector<int>& out_at,
+                                  const std::vector<int>& in_at, int ks, int ks_alloc) {
+    const int mt_out = (int)out_at.size() / 16;
     std::vector<float> f((size_t)mt_out * ks_alloc * 64, 0.f);
     for (int mt = 0; mt < mt_out; ++mt)
         for (int s = 0; s < ks; ++s)
             for (int lane = 0; lane < 64; ++lane) {
-                const int row = 16 * mt + lane % 16;
-                const int k = 16 * (s / 4) + 4 * (lane / 16) + s % 4;
-                if (row < n_out && k < n_in)
+                const int row = out_at[16 * mt + lane % 16];
+                const int kk = 16 * (s / 4) + 4 * (lane / 16) + s % 4;
+                const int k = kk < (int)in_at.size() ? in_at[kk] : -1;
+                if (row >= 0 && k >= 0)
                     f[((size_t)mt * ks_alloc + s) * 64 + lane] = W[(size_t)row * n_in + k];
             }
     return f;
@@ -136,6 +158,7 @@ struct slr_net {
     int n_affine = 0;
     std::vector<int> sizes;
     std::vector<double> WL, bL;   // last affine layer in float64 (for property folding)
+    std::vector<int> last_at;     // relabeling of the last hidden layer (padded row -> neuron)
 };
 
 struct slr_property {
@@ -183,6 +206,7 @@ extern "C" int load_net(int32_t n_affine, const int32_t* sizes, const float* con
     nd.mt_last = ceil_div(nd.n_last, 16);
     nd.mt_max = 0;
     nd.n_max = 0;
+    nd.frag_total = 0;
     for (int l = 1; l < n_affine; ++l) {
         nd.mt_max = std::max(nd.mt_max, ceil_div(sizes[l], 16));
         nd.n_max = std::max(nd.n_max, sizes[l]);
@@ -197,7 +221,19 @@ extern "C" int load_net(int32_t n_affine, const int32_t* sizes, const float* con
 
     const size_t i_w1 = add(W[0], sizeof(float) * sizes[1] * d);
     const size_t i_b1 = add(b[0], sizeof(float) * sizes[1]);
-    struct MidIdx { size_t frag, w, wt, bias, absrow; };
+    std::vector<std::vector<int>> at(n_affine - 1);
+    for (int h = 0; h < n_affine - 1; ++h) at[h] = rows_to_neurons(sizes[h + 1]);
+    nd.r1 = sizes[1] - 16 * (nd.mt1 - 1);
+    std::vector<float> w1p((size_t)16 * nd.mt1 * d, 0.f), b1p(16 * nd.mt1, 0.f);
+    for (int row = 0; row < 16 * nd.mt1; ++row) {
+        const int i = at[0][row];
+        if (i < 0) continue;
+        b1p[row] = b[0][i];
+        for (int k = 0; k < d; ++k) w1p[(size_t)row * d + k] = W[0][(size_t)i * d + k];
+    }
+    const size_t i_w1p = add(w1p.data(), w1p.size() * sizeof(float));
+    const size_t i_b1p = add(b1p.data(), b1p.size() * sizeof(float));
+    struct MidIdx { size_t frag, w, wt, bias, absrow, b; };
     std::vector<MidIdx> mids;
     for (int l = 1; l <= n_affine - 2; ++l) {
         const int n_in = sizes[l], n_out = sizes[l + 1];
@@ -206,16 +242,21 @@ extern "C" int load_net(int32_t n_affine, const int32_t* sizes, const float* con
         L.n_out = n_out;
         L.mt_out = ceil_div(n_out, 16);
         L.ks = k_steps(n_in);
+        L.r_out = n_out - 16 * (L.mt_out - 1);
         L.ks_alloc = (L.ks + 3) / 4 * 4;
+        L.frag_off = nd.frag_total;
+        nd.frag_total += L.mt_out * L.ks_alloc * 64;
         L.kgam = round_up_f32(kKappa * gamma_n(n_in + 2, u32));
         L.kgam64 = kKappa * gamma_n(n_in + 2, u64) * (1 + 1e-12);
-        std::vector<float> frag = pack_fragments(W[l], n_out, n_in, L.ks, L.ks_alloc);
+        std::vector<float> frag = pack_fragments(W[l], n_in, at[l], at[l - 1], L.ks, L.ks_alloc);
         std::vector<float> bias(16 * L.mt_out, 0.f), absrow(16 * L.mt_out, 0.f);
-        for (int jrow = 0; jrow < n_out; ++jrow) {
-            bias[jrow] = b[l][jrow];
+        for (int row = 0; row < 16 * L.mt_out; ++row) {
+            const int jrow = at[l][row];
+            if (jrow < 0) continue;
+            bias[row] = b[l][jrow];
             double s = 0;
             for (int k = 0; k < n_in; ++k) s += std::fabs((double)W[l][(size_t)jrow * n_in + k]);
-            absrow[jrow] = round_up_f32(s * (1 + 1e-12));
+            absrow[row] = round_up_f32(s * (1 + 1e-12));
         }
         MidIdx mi;
         mi.frag = add(frag.data(), frag.size() * sizeof(float));
@@ -226,6 +267,7 @@ extern "C" int load_net(int32_t n_affine, const int32_t* sizes, const float* con
         mi.wt = add(wt.data(), wt.size() * sizeof(float));
         mi.bias = add(bias.data(), bias.size() * sizeof(float));
         mi.absrow = add(absrow.data(), absrow.size() * sizeof(float));
+        mi.b = add(b[l], sizeof(float) * n_out);
         mids.push_back(mi);
     }
     std::vector<size_t> offs(blobs.size());
@@ -247,12 +289,15 @@ extern "C" int load_net(int32_t n_affine, const int32_t* sizes, const float* con
     char* base = (char*)mem;
     nd.w1 = (const float*)(base + offs[i_w1]);
     nd.b1 = (const float*)(base + offs[i_b1]);
+    nd.w1p = (const float*)(base + offs[i_w1p]);
+    nd.b1p = (const float*)(base + offs[i_b1p]);
     for (int l = 0; l < n_affine - 2; ++l) {
         nd.mid[l].wfrag = (const float*)(base + offs[mids[l].frag]);
         nd.mid[l].w = (const float*)(base + offs[mids[l].w]);
         nd.mid[l].wt = (const float*)(base + offs[mids[l].wt]);
         nd.mid[l].bias = (const float*)(base + offs[mids[l].bias]);
         nd.mid[l].absrow = (const float*)(base + offs[mids[l].absrow]);
+        nd.mid[l].b = (const float*)(base + offs[mids[l].b]);
     }
     slr_net* net = new slr_net;
     net->dev = nd;
@@ -264,6 +309,7 @@ extern "C" int load_net(int32_t n_affine, const int32_t* sizes, const float* con
     net->bL.resize(nL);
     for (size_t i = 0; i < net->WL.size(); ++i) net->WL[i] = W[n_affine - 1][i];
     for (int i = 0; i < nL; ++i) net->bL[i] = b[n_affine - 1][i];
+    net->last_at = at[n_affine - 2];
     *out = net;
     return SLR_OK;
 }
@@ -313,9 +359,21 @@ extern "C" int load_property(const slr_net* net, int32_t rows, const float* C, c
     pd.n_last = K;
     pd.kout = round_up_f32(kKappa * gamma_n(K + 3, u32));
     pd.kout64 = kKappa * gamma_n(K + n_out + 3, u64) * (1 + 1e-12);
+    pd.ks_out = k_steps(K);
+    pd.ks_out_alloc = (pd.ks_out + 3) / 4 * 4;
+    std::vector<int> row_at(16, -1);
+    for (int r = 0; r < rows; ++r) row_at[r] = r;
+    std::vector<float> wgfrag = pack_fragments(wg.data(), K, row_at, net->last_at, pd.ks_out, pd.ks_out_alloc);
+    pd.kpad = (int)net->last_at.size();
+    std::vector<float> wgp((size_t)rows * pd.kpad, 0.f);
+    for (int r = 0; r < rows; ++r)
+        for (int kk = 0; kk < pd.kpad; ++kk)
+            if (net->last_at[kk] >= 0) wgp[(size_t)r * pd.kpad + kk] = wg[(size_t)r * K + net->last_at[kk]];
+    const size_t s_wgp = (wgp.size() * 4 + 255) / 256 * 256;
     const size_t s_wg = (wg.size() * 4 + 255) / 256 * 256, s_r = (rows * 4 + 255) / 256 * 256;
+    const size_t s_frag = (wgfrag.size() * 4 + 255) / 256 * 256;
     const size_t s_wg64 = (wg64.size() * 8 + 255) / 256 * 256, s_r64 = (rows * 8 + 255) / 256 * 256;
-    const size_t total = s_wg + 2 * s_r + s_wg64 + 2 * s_r64;
+    const size_t total = s_wg + 2 * s_r + s_wg64 + 2 * s_r64 + s_frag + s_wgp;
     std::vector<char> host(total, 0);
     size_t o = 0;
     memcpy(host.data() + o, wg.data(), wg.size() * 4);
@@ -329,7 +387,11 @@ extern "C" int load_property(const slr_net* net, int32_t rows, const float* C, c
     memcpy(host.data() + o, bg64.data(), rows * 8);
     const size_t o_bg64 = o; o += s_r64;
     memcpy(host.data() + o, ag64.data(), rows * 8);
-    const size_t o_ag64 = o;
+    const size_t o_ag64 = o; o += s_r64;
+    memcpy(host.data() + o, wgfrag.data(), wgfrag.size() * 4);
+    const size_t o_frag = o; o += s_frag;
+    memcpy(host.data() + o, wgp.data(), wgp.size() * 4);
+    const size_t o_wgp = o;
     void* mem = nullptr;
     hipError_t e = hipMalloc(&mem, total);
     if (e != hipSuccess) return fail(SLR_ENOMEM, "load_property: hipMalloc: %s", hipGetErrorString(e));
@@ -345,6 +407,8 @@ extern "C" int load_property(const slr_net* net, int32_t rows, const float* C, c
     pd.wg64 = (const double*)(base + o_wg64);
     pd.bg64 = (const double*)(base + o_bg64);
     pd.ag64 = (const double*)(base + o_ag64);
+    pd.wgfrag = (const float*)(base + o_frag);
+    pd.wgp = (const float*)(base + o_wgp);
     slr_property* p = new slr_property;
     p->dev = pd;
     p->mem = mem;
@@ -446,6 +510,13 @@ extern "C" int workspace_size(const slr_net* net, const slr_property* prop, int6
     if (max_leaves < 1) return fail(SLR_EINVAL, "workspace_size: max_leaves must be >= 1");
     if (samples < 0) return fail(SLR_EINVAL, "workspace_size: samples must be >= 0");
     *bytes = layout_ws(nullptr, net->dev.d, max_leaves, samples).bytes;
+    return SLR_OK;
+}
+
+extern "C" int bound_kernel_variant(int32_t variant) {
+    g_err.clear();
+    if (set_bound_variant(variant) != 0)
+        return fail(SLR_EINVAL, "bound_kernel_variant: %d is not 0, 1 or 2", variant);
     return SLR_OK;
 }
 

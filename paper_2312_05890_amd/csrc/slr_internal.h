@@ -8,6 +8,12 @@
 // becomes C' = W C + b and r' = |W| r.  A third quantity q <= r tracks how much of r is
 // rounding margin (propagated like r), which tells boxes whose class could differ in exact
 // arithmetic from the rest.
+//
+// Hidden neurons are relabeled on the device (a permutation, which leaves the network's function
+// and its bounds unchanged): a layer of n neurons occupies 16-row tiles; the last tile holds
+// r = n - 16 (tiles - 1) neurons, placed at rows 4 g + v in the order v-major (all g for v = 0
+// first).  Row 16 mt + 4 g + v is then valid iff mt < tiles - 1 or 4 v + g < r, and the next
+// layer needs only 4 (tiles - 1) + ceil(r / 4) MFMA K-steps.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -24,9 +30,12 @@ struct MidLayer {
     const float* wfrag;   // [mt_out][ks_alloc][64] MFMA A-operand fragments (see pack_fragments)
     const float* w;       // row-major [n_out][n_in] float32 (sample forward pass)
     const float* wt;      // transposed [n_in][n_out] (FP64 recheck: coalesced across neurons)
-    const float* bias;    // [16 * mt_out], zero padded
+    const float* bias;    // [16 * mt_out] by relabeled row, zero padded
+    const float* b;       // [n_out] in the original neuron order (FP64 recheck, forward pass)
     const float* absrow;  // [16 * mt_out]: sum_k |W_jk|, rounded up to float32
     int n_in, n_out, mt_out, ks, ks_alloc;
+    int r_out;            // neurons in the last 16-row output tile
+    int frag_off;         // offset (floats) of this layer's fragments in the staged copy
     float kgam;           // kappa * gamma_{n_in + 2} for float32, rounded up
     double kgam64;        // the same for float64
 };
@@ -38,8 +47,12 @@ struct NetDev {
     int mt_max;           // max 16-row tiles over hidden layers
     int n_last, mt_last;  // width (and tiles) of the last hidden layer
     int n_max;            // max hidden width
-    const float* w1;      // [n1][d] row-major
+    int frag_total;       // floats of all hidden-to-hidden fragments (staged into LDS)
+    const float* w1;      // [n1][d] row-major, original neuron order
     const float* b1;      // [n1]
+    const float* w1p;     // [16 mt1][d], relabeled rows (zero padding)
+    const float* b1p;     // [16 mt1]
+    int r1;               // neurons in the last 16-row tile of the first hidden layer
     MidLayer mid[SLR_MAX_AFFINE];   // affine layers 1 .. n_affine-2
     float kfirst, kconc, krelu;     // kappa*gamma_{d+2}, kappa*gamma_{d+3}, kappa*gamma_4
     double kfirst64, kconc64, krelu64;
@@ -48,6 +61,10 @@ struct NetDev {
 struct PropDev {
     int rows, n_last;
     const float* wg;      // [rows][n_last] folded last layer C W_L, float32
+    const float* wgfrag;  // [ks_out_alloc][64] MFMA A fragments of wg (rows padded to 16)
+    int ks_out, ks_out_alloc;
+    const float* wgp;     // [rows][kpad] wg with relabeled, zero-padded columns
+    int kpad;             // 16 * tiles of the last hidden layer
     const float* bg;      // [rows] C b_L + d
     const float* ag;      // [rows] row sums of |C| |W_L| (bounds sum_k |wg_rk|), rounded up
     const double* wg64;   // the folded layer in float64
@@ -89,4 +106,8 @@ hipError_t launch_volume(const LevelStats* stats, int levels, int stop_level, in
 hipError_t launch_sample_forward(const NetDev& net, const PropDev& prop, int64_t n,
                                  const float* x, int8_t* viol, hipStream_t stream);
 int bound_f32_supported(const NetDev& net, const PropDev& prop);
+// Bound-kernel variant: 0 automatic (register-resident where it fits), 1 LDS-staged,
+// 2 register-resident only.  Returns -1 for an unknown value.
+int set_bound_variant(int v);
+int bound_variant_for(const NetDev& net, const PropDev& prop);
 size_t level_tiles(int64_t n);

@@ -32,57 +32,73 @@ constexpr double kEta64 = 0x1p-960;
 constexpr double kU64 = 0x1p-53;
 constexpr int kNW = 4;               // wavefronts per bound workgroup
 
+// Row 16 mt + 4 g + v of a layer with `tiles` 16-row tiles whose last tile holds r neurons.
+__device__ __forceinline__ bool row_valid(int mt, int g, int v, int tiles, int r) {
+    return mt < tiles - 1 || 4 * v + g < r;
+}
+
 __device__ __forceinline__ f32x4 mfma16(float a, float b, f32x4 c) {
     return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
 
-// Concretization, rounding margin and ReLU relaxation (Eq. 1) of four neurons of one box.
-// In: a[c][v] = pre-activation center coefficients (c = 0..d, bias included), the unwidened
-// radius a[d+1][v] and margin part a[d+2][v]; eps[v] = rounding margin of the affine step.
-// Out: post-activation state in place; emax = max_v bound on |value| over the box.
+// Scalars of the epilogue: zero margins and no rounding-up in the unwidened mode.
+struct EpiConst {
+    float kconc, krelu, lamfac;
+};
+
+__device__ __forceinline__ EpiConst epi_const(const NetDev& net, int raw) {
+    EpiConst k;
+    k.kconc = raw ? 0.f : net.kconc;
+    k.krelu = raw ? 0.f : net.krelu;
+    // lam = hi * rcp(hi - lo): v_rcp_f32 is within 1 ulp, the product within 1/2 ulp, so a
+    // factor 1 + 2^-20 keeps the computed ratio >= the chord slope (any slope in [chord, 1] is a
+    // valid upper line and a valid lower slope)
+    k.lamfac = raw ? 1.f : 1.f + 0x1p-20f;
+    return k;
+}
+
+// Concretization, rounding margin and ReLU relaxation (Eq. 1) of four neurons of one box,
+// without branches.  In: a[c][v] = pre-activation center coefficients (c = 0..d, bias included),
+// the unwidened radius a[d+1][v] and margin part a[d+2][v]; eps[v] = rounding margin of the
+// affine step.  Out: post-activation state in place; returns max_v bound on |value| over the box.
 template <int NCOL>
-__device__ __forceinline__ void relu_epilogue(float (&a)[NCOL][4], const float (&eps)[4],
-                                              const bool (&valid)[4], int raw, float kconc,
-                                              float krelu, float& emax) {
+__device__ __forceinline__ float relu_epilogue(float (&a)[NCOL][4], const float (&eps)[4],
+                                               const bool (&valid)[4], const EpiConst& k) {
     constexpr int D = NCOL - 3;
     constexpr int R = NCOL - 2, Q = NCOL - 1;
-    emax = 0.f;
+    float emax = 0.f;
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
-        float c0 = a[0][v];
+        const float c0 = a[0][v];
         float S = 0.f;
 #pragma unroll
         for (int c = 1; c <= D; ++c) S += fabsf(a[c][v]);
-        float r = a[R][v] + eps[v];
-        float q = a[Q][v] + eps[v];
-        const float delta = raw ? 0.f : kconc * (fabsf(c0) + r + S);
+        const float r = a[R][v] + eps[v];
+        const float q = a[Q][v] + eps[v];
+        const float delta = k.kconc * (fabsf(c0) + r + S);
         const float lo = (c0 - (r + S)) - delta;
         const float hi = (c0 + (r + S)) + delta;
-        float e = 0.f;
-        if (!valid[v] || hi <= 0.f) {
+        const bool dead = !valid[v] || !(hi > 0.f);
+        const bool act = !dead && lo >= 0.f;
+        const bool cross = !dead && !act;
+        const float den = cross ? hi - lo : 1.f;
+        const float lamc = fminf(1.f, hi * __builtin_amdgcn_rcpf(den) * k.lamfac);
+        const float lam = dead ? 0.f : (act ? 1.f : lamc);
+        const float sh = cross ? -0.5f * lamc * lo : 0.f;
+        const float er = cross ? k.krelu * lamc * ((fabsf(c0) + S + r) - lo) : 0.f;
+        // dead: lam = sh = er = 0 zeroes every (finite) entry; active: lam = 1, sh = er = 0
 #pragma unroll
-            for (int c = 0; c < NCOL; ++c) a[c][v] = 0.f;
-        } else if (lo >= 0.f) {
-            a[R][v] = r;
-            a[Q][v] = q;
-            e = fabsf(c0) + S + r;
-        } else {
-            float lam = hi / (hi - lo);
-            if (!raw) lam = fminf(1.f, lam * (1.f + 4.f * kU32));
-            const float sh = -0.5f * lam * lo;
-            const float er = raw ? 0.f : krelu * lam * ((fabsf(c0) + S + r) - lo);
-#pragma unroll
-            for (int c = 1; c <= D; ++c) a[c][v] *= lam;
-            c0 = fmaf(lam, c0, sh);
-            r = fmaf(lam, r, sh) + er;
-            a[0][v] = c0;
-            a[R][v] = r;
-            // moving l and u by at most q + delta moves both relaxation lines by at most that
-            a[Q][v] = fmaf(1.f + lam, q, delta + er);
-            e = (fabsf(c0) + lam * S + r) * (1.f + 4.f * kU32);
-        }
-        emax = fmaxf(emax, e);
+        for (int c = 1; c <= D; ++c) a[c][v] *= lam;
+        const float c0n = fmaf(lam, c0, sh);
+        const float rn = fmaf(lam, r, sh) + er;
+        const float qf = cross ? 1.f + lamc : lam;
+        const float qa = cross ? delta + er : 0.f;
+        a[0][v] = c0n;
+        a[R][v] = rn;
+        a[Q][v] = fmaf(qf, q, qa);
+        emax = fmaxf(emax, (fabsf(c0n) + lam * S + rn) * (1.f + 4.f * kU32));
     }
+    return emax;
 }
 
 template <int NCOL, int NT, int UW>
@@ -99,6 +115,7 @@ __global__ __launch_bounds__(kNW * 64) void bound_f32_kernel(
     const int64_t box0 = (int64_t)blockIdx.x * T;
     const int d = net.d;
 
+    const EpiConst ek = epi_const(net, raw);
     float* S = lds;                                   // [NT][NCOL][4][16][SP]
     float* part = S + NT * NCOL * 64 * SP;            // [2 parity][mt_max][T] bound on |value|
     float* OUT = part + 2 * net.mt_max * T;           // [rows][T][NCOL]
@@ -134,15 +151,15 @@ __global__ __launch_bounds__(kNW * 64) void bound_f32_kernel(
 #pragma unroll
                 for (int v = 0; v < 4; ++v) {
                     const int m = 16 * mt + 4 * g + v;
-                    valid[v] = m < net.n1;
+                    valid[v] = row_valid(mt, g, v, net.mt1, net.r1);
                     float c0 = 0.f, s = 0.f;
                     if (valid[v]) {
-                        const float bb = net.b1[m];
+                        const float bb = net.b1p[m];
                         c0 = bb;
                         s = fabsf(bb);
 #pragma unroll
                         for (int k = 0; k < D; ++k) {
-                            const float w = k < d ? net.w1[m * d + k] : 0.f;
+                            const float w = k < d ? net.w1p[m * d + k] : 0.f;
                             c0 = fmaf(w, mid[k], c0);
                             a[k + 1][v] = w * rad[k];
                             s += fabsf(w) * (fabsf(mid[k]) + rad[k]);
@@ -156,8 +173,7 @@ __global__ __launch_bounds__(kNW * 64) void bound_f32_kernel(
                     a[NCOL - 1][v] = 0.f;
                     eps[v] = raw ? 0.f : net.kfirst * s + kEta;
                 }
-                float emax;
-                relu_epilogue<NCOL>(a, eps, valid, raw, net.kconc, net.krelu, emax);
+                float emax = relu_epilogue<NCOL>(a, eps, valid, ek);
                 float* sb = S + ((nt * NCOL * 4 + g) * 16 + j) * SP + 4 * mt;
 #pragma unroll
                 for (int c = 0; c < NCOL; ++c) {
@@ -190,24 +206,50 @@ __global__ __launch_bounds__(kNW * 64) void bound_f32_kernel(
                 for (int c = 0; c < NCOL; ++c) acc[c] = f32x4{0.f, 0.f, 0.f, 0.f};
                 const float* wf = L->wfrag + (size_t)mt * L->ks_alloc * 64 + lane;
                 const float* sb = S + ((nt * NCOL * 4 + g) * 16 + j) * SP;
-                for (int q = 0; q < ks; q += 4) {
-                    f32x4 bq[NCOL];
+                // full quads of K-steps, software-pipelined one quad ahead (A from global/L2,
+                // B from LDS), then the tail quad with per-step guards
+                const int nq = ks >> 2;
+                const int nqa = L->ks_alloc >> 2;
+                float af[4];
+                f32x4 bq[NCOL];
+#pragma unroll
+                for (int ss = 0; ss < 4; ++ss) af[ss] = wf[ss * 64];
+#pragma unroll
+                for (int c = 0; c < NCOL; ++c)
+                    bq[c] = *reinterpret_cast<const f32x4*>(sb + c * colstride);
+                for (int qi = 0; qi < nq; ++qi) {
+                    const int nx = min(qi + 1, nqa - 1) * 4;
+                    float an[4];
+                    f32x4 bn[NCOL];
+#pragma unroll
+                    for (int ss = 0; ss < 4; ++ss) an[ss] = wf[(nx + ss) * 64];
 #pragma unroll
                     for (int c = 0; c < NCOL; ++c)
-                        bq[c] = *reinterpret_cast<const f32x4*>(sb + c * colstride + q);
-                    float af[4];
-#pragma unroll
-                    for (int ss = 0; ss < 4; ++ss) af[ss] = wf[(q + ss) * 64];
+                        bn[c] = *reinterpret_cast<const f32x4*>(sb + c * colstride + nx);
 #pragma unroll
                     for (int ss = 0; ss < 4; ++ss) {
-                        if (q + ss < ks) {
-                            const float aw = af[ss];
-                            const float aa = fabsf(aw);
+                        const float aw = af[ss];
+                        const float aa = fabsf(aw);
 #pragma unroll
-                            for (int c = 0; c < NCOL - 2; ++c) acc[c] = mfma16(aw, bq[c][ss], acc[c]);
-                            acc[NCOL - 2] = mfma16(aa, bq[NCOL - 2][ss], acc[NCOL - 2]);
-                            acc[NCOL - 1] = mfma16(aa, bq[NCOL - 1][ss], acc[NCOL - 1]);
-                        }
+                        for (int c = 0; c < NCOL - 2; ++c) acc[c] = mfma16(aw, bq[c][ss], acc[c]);
+                        acc[NCOL - 2] = mfma16(aa, bq[NCOL - 2][ss], acc[NCOL - 2]);
+                        acc[NCOL - 1] = mfma16(aa, bq[NCOL - 1][ss], acc[NCOL - 1]);
+                    }
+#pragma unroll
+                    for (int ss = 0; ss < 4; ++ss) af[ss] = an[ss];
+#pragma unroll
+                    for (int c = 0; c < NCOL; ++c) bq[c] = bn[c];
+                }
+                const int tail = ks & 3;   // af/bq now hold quad nq (valid when tail > 0)
+#pragma unroll
+                for (int ss = 0; ss < 3; ++ss) {
+                    if (ss < tail) {
+                        const float aw = af[ss];
+                        const float aa = fabsf(aw);
+#pragma unroll
+                        for (int c = 0; c < NCOL - 2; ++c) acc[c] = mfma16(aw, bq[c][ss], acc[c]);
+                        acc[NCOL - 2] = mfma16(aa, bq[NCOL - 2][ss], acc[NCOL - 2]);
+                        acc[NCOL - 1] = mfma16(aa, bq[NCOL - 1][ss], acc[NCOL - 1]);
                     }
                 }
 #pragma unroll
@@ -228,7 +270,7 @@ __global__ __launch_bounds__(kNW * 64) void bound_f32_kernel(
 #pragma unroll
                 for (int v = 0; v < 4; ++v) {
                     const int m = 16 * mt + 4 * g + v;
-                    valid[v] = m < L->n_out;
+                    valid[v] = row_valid(mt, g, v, L->mt_out, L->r_out);
                     const float bb = L->bias[m];
                     const float A = L->absrow[m];
 #pragma unroll
@@ -236,8 +278,7 @@ __global__ __launch_bounds__(kNW * 64) void bound_f32_kernel(
                     a[0][v] += bb;
                     eps[v] = raw ? 0.f : L->kgam * (A * emax_in + fabsf(bb)) + kEta;
                 }
-                float emax;
-                relu_epilogue<NCOL>(a, eps, valid, raw, net.kconc, net.krelu, emax);
+                float emax = relu_epilogue<NCOL>(a, eps, valid, ek);
                 float* sb = S + ((nt * NCOL * 4 + g) * 16 + j) * SP + 4 * mt;
 #pragma unroll
                 for (int c = 0; c < NCOL; ++c) {
@@ -254,28 +295,77 @@ __global__ __launch_bounds__(kNW * 64) void bound_f32_kernel(
         __syncthreads();   // the layer output is complete
     }
 
-    // ---------------- output layer: folded property rows, VALU contraction over the state
+    // ---------------- output layer: folded property rows
     const int rows = prop.rows;
-    const int K = prop.n_last;
-    const int items = rows * T * NCOL;
-    for (int it = tid; it < items; it += kNW * 64) {
-        const int c = it % NCOL;
-        const int bj = (it / NCOL) % T;
-        const int r = it / (NCOL * T);
-        const int nt = bj >> 4, jj = bj & 15;
-        const float* wr = prop.wg + r * K;
-        const float* col = S + (nt * NCOL + c) * colstride + jj * SP;
-        float s = 0.f;
-        for (int k = 0; k < K; ++k) {
-            const int gg = (k >> 2) & 3;
-            const int sidx = 4 * (k >> 4) + (k & 3);
-            float w = wr[k];
-            if (c >= NCOL - 2) w = fabsf(w);
-            s = fmaf(w, col[gg * 16 * SP + sidx], s);
+    const bool mfma_out = rows * NT * NCOL <= 64;
+    if (mfma_out) {
+        // split-K on MFMA: wave w takes K-quads w, w + 4, ...; partial sums of the valid rows go
+        // to OUT as [wave][nt][c][row][box] and are added in the final loop
+        const int ksq = (prop.ks_out + 3) >> 2;
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) {
+            f32x4 G[NCOL];
+#pragma unroll
+            for (int c = 0; c < NCOL; ++c) G[c] = f32x4{0.f, 0.f, 0.f, 0.f};
+            const float* sb = S + ((nt * NCOL * 4 + g) * 16 + j) * SP;
+            for (int q = wave; q < ksq; q += kNW) {
+                f32x4 bq[NCOL];
+#pragma unroll
+                for (int c = 0; c < NCOL; ++c)
+                    bq[c] = *reinterpret_cast<const f32x4*>(sb + c * colstride + 4 * q);
+#pragma unroll
+                for (int ss = 0; ss < 4; ++ss) {
+                    if (4 * q + ss < prop.ks_out) {
+                        const float aw = prop.wgfrag[(4 * q + ss) * 64 + lane];
+                        const float aa = fabsf(aw);
+#pragma unroll
+                        for (int c = 0; c < NCOL - 2; ++c) G[c] = mfma16(aw, bq[c][ss], G[c]);
+                        G[NCOL - 2] = mfma16(aa, bq[NCOL - 2][ss], G[NCOL - 2]);
+                        G[NCOL - 1] = mfma16(aa, bq[NCOL - 1][ss], G[NCOL - 1]);
+                    }
+                }
+            }
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int row = 4 * g + v;
+                if (row < rows) {
+#pragma unroll
+                    for (int c = 0; c < NCOL; ++c)
+                        OUT[(((wave * NT + nt) * NCOL + c) * rows + row) * 16 + j] = G[c][v];
+                }
+            }
         }
-        OUT[(r * T + bj) * NCOL + c] = s;
+    } else {
+        // VALU contraction over the state
+        const int K = prop.kpad;
+        const int items = rows * T * NCOL;
+        for (int it = tid; it < items; it += kNW * 64) {
+            const int c = it % NCOL;
+            const int bj = (it / NCOL) % T;
+            const int r = it / (NCOL * T);
+            const int nt = bj >> 4, jj = bj & 15;
+            const float* wr = prop.wgp + r * K;
+            const float* col = S + (nt * NCOL + c) * colstride + jj * SP;
+            float sacc = 0.f;
+            for (int k = 0; k < K; ++k) {
+                const int gg = (k >> 2) & 3;
+                const int sidx = 4 * (k >> 4) + (k & 3);
+                float w = wr[k];
+                if (c >= NCOL - 2) w = fabsf(w);
+                sacc = fmaf(w, col[gg * 16 * SP + sidx], sacc);
+            }
+            OUT[(r * T + bj) * NCOL + c] = sacc;
+        }
     }
     __syncthreads();
+    auto outv = [&](int r, int bj, int c) -> float {
+        if (!mfma_out) return OUT[(r * T + bj) * NCOL + c];
+        const int nt = bj >> 4, jj = bj & 15;
+        float acc = 0.f;
+#pragma unroll
+        for (int w = 0; w < kNW; ++w) acc += OUT[(((w * NT + nt) * NCOL + c) * rows + r) * 16 + jj];
+        return acc;
+    };
     for (int bj = tid; bj < T; bj += kNW * 64) {
         const int64_t b = box0 + bj;
         if (b >= n) continue;
@@ -283,19 +373,18 @@ __global__ __launch_bounds__(kNW * 64) void bound_f32_kernel(
         for (int q = 0; q < net.mt_last; ++q) emax = fmaxf(emax, part_at(rp, q, bj));
         bool unsafe = true, safe = false, amb_unsafe = true, amb_safe = false;
         for (int r = 0; r < rows; ++r) {
-            const float* o = OUT + (r * T + bj) * NCOL;
             const float bg = prop.bg[r];
-            const float G0 = o[0] + bg;
+            const float G0 = outv(r, bj, 0) + bg;
             float Sg = 0.f;
-            for (int c = 1; c <= D; ++c) Sg += fabsf(o[c]);
+            for (int c = 1; c <= D; ++c) Sg += fabsf(outv(r, bj, c));
             const float eps = raw ? 0.f : prop.kout * (prop.ag[r] * emax + fabsf(bg)) + kEta;
-            const float R = o[NCOL - 2] + eps;
+            const float R = outv(r, bj, NCOL - 2) + eps;
             const float delta = raw ? 0.f : net.kconc * (fabsf(G0) + R + Sg);
             const float glo = (G0 - (R + Sg)) - delta;
             const float ghi = (G0 + (R + Sg)) + delta;
             // distance within which the exact-arithmetic decision may differ from this one:
             // twice the propagated margins plus 2^-14 of the row's magnitude
-            const float tau = 2.f * (o[NCOL - 1] + eps + delta) +
+            const float tau = 2.f * (outv(r, bj, NCOL - 1) + eps + delta) +
                               0x1p-14f * fmaxf(fabsf(glo), fabsf(ghi));
             if (g_lo) g_lo[b * rows + r] = glo;
             if (g_hi) g_hi[b * rows + r] = ghi;
@@ -412,7 +501,7 @@ __device__ void recheck_box(const NetDev& net, const PropDev& prop, int64_t b,
                 st[ncol - 1] = fma(fabs(w), x[ncol - 1], st[ncol - 1]);
                 A_row += fabs(w);
             }
-            const double bb = L->bias[j];
+            const double bb = L->b[j];
             st[0] += bb;
             const double eps = L->kgam64 * (A_row * (1.0 + 0x1p-40) * emax + fabs(bb)) + kEta64;
             e = fmax(e, relu64(st, ncol, eps, net.kconc64, net.krelu64));
@@ -638,6 +727,239 @@ __global__ void volume_kernel(const LevelStats* stats, int levels, int stop_leve
     out_counts[2] = nd;
 }
 
+// ------------------------------------------------------------------------------------------
+// Register-resident bound kernel for narrow networks (every hidden width <= 16 MT, d + 3 <=
+// NCOL).  One wavefront owns 16 boxes through the whole network: because the accumulator
+// layout of the 16x16x4 MFMA equals its B-operand layout (lane 16 g + j holds neurons
+// 16 mt + 4 g + v of box j), the post-activation state of M tile mt is directly the B operand
+// of K-steps 4 mt .. 4 mt + 3 of the next layer.  No LDS round trips and no workgroup barriers;
+// the per-box bound on |value| is a lane-local max plus two cross-lane shuffles.
+// ------------------------------------------------------------------------------------------
+// Accumulate K-steps s0 .. s0+nst-1 of one 16-row tile group: Z[mo] += A(mo, s) X[s % 4].
+template <int NCOL, int MO>
+__device__ __forceinline__ void mfma_steps(f32x4 (&Z)[MO][NCOL], const f32x4 (&X)[NCOL],
+                                           const float* __restrict__ wf, int ksa, int s0, int nst) {
+#pragma unroll
+    for (int ss = 0; ss < 4; ++ss) {
+        if (ss < nst) {
+#pragma unroll
+            for (int mo = 0; mo < MO; ++mo) {
+                const float aw = wf[(mo * ksa + s0 + ss) * 64];
+                const float aa = fabsf(aw);
+#pragma unroll
+                for (int c = 0; c < NCOL - 2; ++c) Z[mo][c] = mfma16(aw, X[c][ss], Z[mo][c]);
+                Z[mo][NCOL - 2] = mfma16(aa, X[NCOL - 2][ss], Z[mo][NCOL - 2]);
+                Z[mo][NCOL - 1] = mfma16(aa, X[NCOL - 1][ss], Z[mo][NCOL - 1]);
+            }
+        }
+    }
+}
+
+// Epilogue of tile mt of a hidden layer held in Y (pre-activations, bias included).
+template <int NCOL, int MT>
+__device__ __forceinline__ float tile_epilogue(const f32x4 (&Y)[MT][NCOL], const float (&epsv)[MT][4],
+                                               int mt, int tiles, int r_last, int g,
+                                               const EpiConst& ek, f32x4 (&X)[NCOL]) {
+    float a[NCOL][4], eps[4];
+    bool valid[4];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        valid[v] = mt < tiles && row_valid(mt, g, v, tiles, r_last);
+        eps[v] = epsv[mt][v];
+#pragma unroll
+        for (int c = 0; c < NCOL; ++c) a[c][v] = Y[mt][c][v];
+    }
+    const float e = relu_epilogue<NCOL>(a, eps, valid, ek);
+#pragma unroll
+    for (int c = 0; c < NCOL; ++c) X[c] = f32x4{a[c][0], a[c][1], a[c][2], a[c][3]};
+    return e;
+}
+
+// One stage: the epilogue of hidden layer Y, tile by tile, interleaved with the next affine
+// layer's MFMAs (MO output tiles, fragments wf [MO][ksa][64], ksn K-steps) into Z: the VALU work
+// of tile mt + 1 sits in the same basic block as the MFMAs of tile mt.
+template <int NCOL, int MT, int MO>
+__device__ __forceinline__ float stage(const f32x4 (&Y)[MT][NCOL], const float (&epsv)[MT][4],
+                                       int tiles, int r_last, int g, const EpiConst& ek,
+                                       const float* __restrict__ wf, int ksa, int ksn,
+                                       f32x4 (&Z)[MO][NCOL]) {
+#pragma unroll
+    for (int mo = 0; mo < MO; ++mo)
+#pragma unroll
+        for (int c = 0; c < NCOL; ++c) Z[mo][c] = f32x4{0.f, 0.f, 0.f, 0.f};
+    f32x4 Xc[NCOL];
+    float en = tile_epilogue<NCOL, MT>(Y, epsv, 0, tiles, r_last, g, ek, Xc);
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt) {
+        f32x4 Xn[NCOL];
+        const int nst = ksn - 4 * mt;
+        if (nst >= 4) {
+            mfma_steps<NCOL, MO>(Z, Xc, wf, ksa, 4 * mt, 4);
+            if (mt + 1 < MT) en = fmaxf(en, tile_epilogue<NCOL, MT>(Y, epsv, mt + 1, tiles, r_last, g, ek, Xn));
+        } else {
+            mfma_steps<NCOL, MO>(Z, Xc, wf, ksa, 4 * mt, nst);
+            if (mt + 1 < MT) en = fmaxf(en, tile_epilogue<NCOL, MT>(Y, epsv, mt + 1, tiles, r_last, g, ek, Xn));
+        }
+        if (mt + 1 < MT) {
+#pragma unroll
+            for (int c = 0; c < NCOL; ++c) Xc[c] = Xn[c];
+        }
+    }
+    en = fmaxf(en, __shfl_xor(en, 16));
+    return fmaxf(en, __shfl_xor(en, 32));
+}
+
+template <int NCOL, int MT>
+__global__ __launch_bounds__(256) void bound_reg_kernel(
+    NetDev net, PropDev prop, int64_t n, const float* __restrict__ blo,
+    const float* __restrict__ bhi, float* __restrict__ g_lo, float* __restrict__ g_hi,
+    int8_t* __restrict__ cls, int raw, unsigned* __restrict__ amb_list,
+    unsigned* __restrict__ amb_count, unsigned list_base) {
+    constexpr int D = NCOL - 3;
+    constexpr int KS = 4 * MT;
+    extern __shared__ float lds[];
+    const int nmid = net.n_affine - 2;
+    const int d = net.d;
+    // [mid fragments nmid][MT][KS][64] | output fragments [KS][64] | bias, |W| row sums
+    // [nmid][2][16 MT] | first layer [16 MT][d] + [16 MT] | per-wave output tile
+    float* frag = lds;
+    float* ofr = frag + nmid * MT * KS * 64;
+    float* aux = ofr + KS * 64;
+    float* w1s = aux + nmid * 32 * MT;
+    float* b1s = w1s + 16 * MT * d;
+    float* obuf_all = b1s + 16 * MT;
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6, g = lane >> 4, j = lane & 15;
+
+    for (int l = 0; l < nmid; ++l) {
+        const MidLayer* L = &net.mid[l];
+        for (int i = tid; i < MT * KS * 64; i += 256) {
+            const int mo = i / (KS * 64), st = (i / 64) % KS, ln = i % 64;
+            frag[l * MT * KS * 64 + i] = (mo < L->mt_out && st < L->ks_alloc)
+                                             ? L->wfrag[(mo * L->ks_alloc + st) * 64 + ln] : 0.f;
+        }
+        for (int i = tid; i < 16 * MT; i += 256) {
+            const bool in = i < 16 * L->mt_out;
+            aux[(l * 2 + 0) * 16 * MT + i] = in ? L->bias[i] : 0.f;
+            aux[(l * 2 + 1) * 16 * MT + i] = in ? L->absrow[i] : 0.f;
+        }
+    }
+    for (int i = tid; i < KS * 64; i += 256)
+        ofr[i] = (i / 64) < prop.ks_out_alloc ? prop.wgfrag[i] : 0.f;
+    for (int i = tid; i < 16 * MT * d; i += 256) w1s[i] = i < 16 * net.mt1 * d ? net.w1p[i] : 0.f;
+    for (int i = tid; i < 16 * MT; i += 256) b1s[i] = i < 16 * net.mt1 ? net.b1p[i] : 0.f;
+    __syncthreads();
+    float* obuf = obuf_all + wave * (NCOL * 256);   // [column][row 16][box 16]
+    const EpiConst ek = epi_const(net, raw);
+    const float eta = raw ? 0.f : kEta;
+
+    const int64_t tiles = (n + 15) / 16;
+    for (int64_t tile = (int64_t)blockIdx.x * 4 + wave; tile < tiles; tile += (int64_t)gridDim.x * 4) {
+        const int64_t b = tile * 16 + j;
+        const bool bval = b < n;
+        f32x4 Y[MT][NCOL];
+        float epsv[MT][4];
+        // ---- first affine layer (exact, VALU): pre-activations of hidden layer 0
+        {
+            float mid[D], rad[D];
+#pragma unroll
+            for (int k = 0; k < D; ++k) {
+                float l = 0.f, h = 0.f;
+                if (bval && k < d) {
+                    l = blo[b * d + k];
+                    h = bhi[b * d + k];
+                }
+                const float m = 0.5f * (l + h);
+                mid[k] = m;
+                rad[k] = raw ? 0.5f * (h - l) : fmaxf(h - m, m - l) * (1.f + 0x1p-22f);
+            }
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt) {
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int m = 16 * mt + 4 * g + v;
+                    const float bb = b1s[m];
+                    float c0 = bb, sm = fabsf(bb);
+#pragma unroll
+                    for (int k = 0; k < D; ++k) {
+                        const float w = k < d ? w1s[m * d + k] : 0.f;
+                        c0 = fmaf(w, mid[k], c0);
+                        Y[mt][k + 1][v] = w * rad[k];
+                        sm += fabsf(w) * (fabsf(mid[k]) + rad[k]);
+                    }
+                    Y[mt][0][v] = c0;
+                    Y[mt][NCOL - 2][v] = 0.f;
+                    Y[mt][NCOL - 1][v] = 0.f;
+                    epsv[mt][v] = raw ? 0.f : net.kfirst * sm + eta;
+                }
+            }
+        }
+        int tiles_l = net.mt1, r_l = net.r1;
+        float emax = 0.f;
+        // ---- hidden-to-hidden layers
+        for (int l = 0; l < nmid; ++l) {
+            const MidLayer* L = &net.mid[l];
+            f32x4 Z[MT][NCOL];
+            emax = stage<NCOL, MT, MT>(Y, epsv, tiles_l, r_l, g, ek, frag + l * MT * KS * 64 + lane,
+                                       KS, L->ks, Z);
+            const float* bias = aux + (l * 2 + 0) * 16 * MT;
+            const float* absr = aux + (l * 2 + 1) * 16 * MT;
+#pragma unroll
+            for (int mo = 0; mo < MT; ++mo)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int m = 16 * mo + 4 * g + v;
+                    const float bb = bias[m];
+#pragma unroll
+                    for (int c = 0; c < NCOL; ++c) Y[mo][c][v] = Z[mo][c][v];
+                    Y[mo][0][v] += bb;
+                    epsv[mo][v] = raw ? 0.f : L->kgam * (absr[m] * emax + fabsf(bb)) + eta;
+                }
+            tiles_l = L->mt_out;
+            r_l = L->r_out;
+        }
+        // ---- last hidden layer's epilogue interleaved with the output-row MFMAs
+        f32x4 G[1][NCOL];
+        emax = stage<NCOL, MT, 1>(Y, epsv, tiles_l, r_l, g, ek, ofr + lane, KS, prop.ks_out, G);
+        wave_sync();   // the previous tile's reads of obuf are done
+#pragma unroll
+        for (int c = 0; c < NCOL; ++c)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) obuf[(c * 16 + 4 * g + v) * 16 + j] = G[0][c][v];
+        wave_sync();
+        if (g == 0 && bval) {
+            const int rows = prop.rows;
+            bool unsafe = true, safe = false, amb_unsafe = true, amb_safe = false;
+            for (int r = 0; r < rows; ++r) {
+                const float bg = prop.bg[r];
+                const float G0 = obuf[(0 * 16 + r) * 16 + j] + bg;
+                float Sg = 0.f;
+#pragma unroll
+                for (int c = 1; c <= D; ++c) Sg += fabsf(obuf[(c * 16 + r) * 16 + j]);
+                const float eps = raw ? 0.f : prop.kout * (prop.ag[r] * emax + fabsf(bg)) + kEta;
+                const float Rg = obuf[((NCOL - 2) * 16 + r) * 16 + j] + eps;
+                const float delta = raw ? 0.f : net.kconc * (fabsf(G0) + Rg + Sg);
+                const float glo = (G0 - (Rg + Sg)) - delta;
+                const float ghi = (G0 + (Rg + Sg)) + delta;
+                const float tau = 2.f * (obuf[((NCOL - 1) * 16 + r) * 16 + j] + eps + delta) +
+                                  0x1p-14f * fmaxf(fabsf(glo), fabsf(ghi));
+                if (g_lo) g_lo[b * rows + r] = glo;
+                if (g_hi) g_hi[b * rows + r] = ghi;
+                unsafe = unsafe && (glo > 0.f);
+                safe = safe || (ghi <= 0.f);
+                amb_unsafe = amb_unsafe && (glo + tau > 0.f);
+                amb_safe = amb_safe || (ghi - tau <= 0.f);
+            }
+            int8_t kc = unsafe ? 1 : (safe ? 2 : 0);
+            if (kc == 0 && !raw && (amb_unsafe || amb_safe)) {
+                kc = 3;
+                if (amb_list) amb_list[atomicAdd(amb_count, 1u)] = list_base + (unsigned)b;
+            }
+            if (cls) cls[b] = kc;
+        }
+    }
+}
+
 // Concrete float32 forward pass of sample points (used to place the approximate count's splits).
 __global__ __launch_bounds__(256) void sample_forward_kernel(NetDev net, PropDev prop, int64_t n,
                                                              const float* __restrict__ x,
@@ -661,7 +983,7 @@ __global__ __launch_bounds__(256) void sample_forward_kernel(NetDev net, PropDev
         for (int l = 0; l < net.n_affine - 2; ++l) {
             const MidLayer* L = &net.mid[l];
             if (tid < L->n_out) {
-                float s = L->bias[tid];
+                float s = L->b[tid];
                 const float* wr = L->w + (size_t)tid * L->n_in;
                 for (int k = 0; k < L->n_in; ++k) s = fmaf(wr[k], in[k], s);
                 out[tid] = fmaxf(s, 0.f);
@@ -717,7 +1039,7 @@ int state_stride(int mt_max) { return 4 * mt_max + ((mt_max & 1) ? 0 : 4); }
 size_t bound_lds_bytes(int NCOL, int NT, int mt_max, int rows) {
     const int T = NT * 16;
     const int SP = state_stride(mt_max);
-    return sizeof(float) * ((size_t)NT * NCOL * 64 * SP + 2 * (size_t)mt_max * T + (size_t)rows * T * NCOL);
+    return sizeof(float) * ((size_t)NT * NCOL * 64 * SP + 2 * (size_t)mt_max * T + 4 * (size_t)rows * T * NCOL);
 }
 
 template <int NCOL, int NT, int UW>
@@ -750,9 +1072,94 @@ hipError_t launch_ncol(int NT, int UW, const NetDev& net, const PropDev& prop, i
     return hipErrorInvalidValue;
 }
 
+
+int g_num_cu = 0;
+
+int num_cu() {
+    if (g_num_cu == 0) {
+        int dev = 0, cu = 0;
+        if (hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && cu > 0)
+            g_num_cu = cu;
+        else
+            g_num_cu = 256;
+        (void)hipGetLastError();
+    }
+    return g_num_cu;
+}
+
+size_t reg_lds_bytes(const NetDev& net, const PropDev& prop, int ncol) {
+    (void)prop;
+    const size_t mt = net.mt_max, ks = 4 * mt, nmid = net.n_affine - 2;
+    return sizeof(float) * (nmid * mt * ks * 64 + ks * 64 + nmid * 32 * mt + 16 * mt * net.d +
+                            16 * mt + 4 * (size_t)ncol * 256);
+}
+
+template <int NCOL, int MT>
+hipError_t launch_reg(const NetDev& net, const PropDev& prop, int64_t n, const float* lo,
+                      const float* hi, float* g_lo, float* g_hi, int8_t* cls, int raw,
+                      hipStream_t stream, unsigned* al, unsigned* ac, unsigned lb) {
+    const int64_t waves_needed = (n + 15) / 16;
+    int64_t blocks = (waves_needed + 3) / 4;
+    const size_t lds = reg_lds_bytes(net, prop, NCOL);
+    auto kern = bound_reg_kernel<NCOL, MT>;
+    hipError_t e = allow_lds((const void*)kern, lds);
+    if (e != hipSuccess) return e;
+    // persistent grid: as many workgroups as can be resident at once
+    static int per_cu = 0;
+    if (per_cu == 0) {
+        int nb = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, (const void*)kern, 256, lds) != hipSuccess || nb < 1)
+            nb = 1;
+        (void)hipGetLastError();
+        per_cu = nb;
+    }
+    const int64_t cap = (int64_t)num_cu() * per_cu;
+    if (blocks > cap) blocks = cap;
+    (void)hipGetLastError();
+    hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(256), lds, stream, net, prop, n, lo, hi,
+                       g_lo, g_hi, cls, raw, al, ac, lb);
+    return hipGetLastError();
+}
+
+template <int NCOL>
+hipError_t launch_reg_mt(const NetDev& net, const PropDev& prop, int64_t n, const float* lo,
+                         const float* hi, float* g_lo, float* g_hi, int8_t* cls, int raw,
+                         hipStream_t stream, unsigned* al, unsigned* ac, unsigned lb) {
+    switch (net.mt_max) {
+        case 1: return launch_reg<NCOL, 1>(net, prop, n, lo, hi, g_lo, g_hi, cls, raw, stream, al, ac, lb);
+        case 2: return launch_reg<NCOL, 2>(net, prop, n, lo, hi, g_lo, g_hi, cls, raw, stream, al, ac, lb);
+        case 3: return launch_reg<NCOL, 3>(net, prop, n, lo, hi, g_lo, g_hi, cls, raw, stream, al, ac, lb);
+        case 4: return launch_reg<NCOL, 4>(net, prop, n, lo, hi, g_lo, g_hi, cls, raw, stream, al, ac, lb);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+int g_variant = 0;   // 0 auto, 1 LDS-staged, 2 register-resident
+
+bool reg_fits(const NetDev& net, const PropDev& prop) {
+    return net.mt_max <= 4 && net.d + 3 <= 10 && prop.rows <= 16 &&
+           reg_lds_bytes(net, prop, net.d + 3) <= 160 * 1024;
+}
+
 }  // namespace
 
+int set_bound_variant(int v) {
+    if (v < 0 || v > 2) return -1;
+    g_variant = v;
+    return 0;
+}
+
+int bound_variant_for(const NetDev& net, const PropDev& prop) {
+    if (g_variant == 2) return reg_fits(net, prop) ? 2 : -1;
+    return 1;
+}
+
+
 int bound_f32_supported(const NetDev& net, const PropDev& prop) {
+    const int v = bound_variant_for(net, prop);
+    if (v == 2) return 1;
+    if (v < 0) return 0;
     const int NCOL = ncol_class(net.d);
     int NT, UW;
     tile_class(net.mt_max, &NT, &UW);
@@ -770,6 +1177,16 @@ hipError_t launch_bound_f32(const NetDev& net, const PropDev& prop, int64_t n, c
     if (!bound_f32_supported(net, prop)) {
         *unsupported = 1;
         return hipSuccess;
+    }
+    if (bound_variant_for(net, prop) == 2) {
+        switch (net.d + 3) {
+#define SLR_RCASE(C) \
+    case C: return launch_reg_mt<C>(net, prop, n, lo, hi, g_lo, g_hi, cls, raw, stream, amb_list, \
+                                    amb_count, list_base);
+            SLR_RCASE(4) SLR_RCASE(5) SLR_RCASE(6) SLR_RCASE(7) SLR_RCASE(8) SLR_RCASE(9) SLR_RCASE(10)
+#undef SLR_RCASE
+            default: break;
+        }
     }
     int NT, UW;
     tile_class(net.mt_max, &NT, &UW);

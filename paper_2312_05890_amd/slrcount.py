@@ -20,7 +20,8 @@ UNDECIDED, UNSAFE, SAFE = 0, 1, 2
 
 # every entry point declared in include/slrcount.h
 EXPORTS = ("load_net", "free_net", "load_property", "free_property", "bound_boxes",
-           "workspace_size", "count_exact", "count_approx", "sample_violations", "last_error")
+           "workspace_size", "count_exact", "count_approx", "sample_violations", "last_error",
+           "bound_kernel_variant")
 
 
 class SlrError(RuntimeError):
@@ -89,6 +90,8 @@ def lib() -> C.CDLL:
         L.count_approx.restype = C.c_int
         L.sample_violations.argtypes = [vp, vp, i64, vp, vp, vp]
         L.sample_violations.restype = C.c_int
+        L.bound_kernel_variant.argtypes = [i32]
+        L.bound_kernel_variant.restype = C.c_int
         L.last_error.argtypes = []
         L.last_error.restype = C.c_char_p
         _LIB = L
@@ -187,6 +190,11 @@ def bound_boxes(net: Net, prop: Property, lo, hi, g_lo=None, g_hi=None, cls=None
                              cls.data_ptr() if cls is not None else None, int(bool(raw)),
                              _stream(stream)))
     return g_lo, g_hi, cls
+
+
+def bound_kernel_variant(variant: int) -> None:
+    """0 automatic, 1 LDS-staged, 2 register-resident (see include/slrcount.h)."""
+    _check(lib().bound_kernel_variant(int(variant)))
 
 
 def workspace_size(net: Net, prop: Property, max_leaves: int, samples: int = 0) -> int:

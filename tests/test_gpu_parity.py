@@ -30,6 +30,22 @@ def E():
     return eng
 
 
+@pytest.fixture(params=[1, 2], ids=["lds", "reg"])
+def variant(request):
+    """Run a test with the LDS-staged and with the register-resident bound kernel; restore the
+    automatic choice afterwards."""
+    E().bound_kernel_variant(request.param)
+    yield request.param
+    E().bound_kernel_variant(0)
+
+
+def need(variant, inst):
+    """Skip register-kernel runs on shapes that kernel does not take (d > 7 or width > 64)."""
+    widths = inst.sizes[1:-1]
+    if variant == 2 and (inst.sizes[0] + 3 > 10 or max(widths) > 64):
+        pytest.skip("shape outside the register-resident kernel")
+
+
 def dev(a):
     return torch.from_numpy(np.ascontiguousarray(a, np.float32)).cuda()
 
@@ -61,8 +77,9 @@ def make(name, seed):
 
 
 @pytest.mark.parametrize("name,seed,depth", CASES)
-def test_bound_raw_parity(name, seed, depth):
+def test_bound_raw_parity(name, seed, depth, variant):
     inst = make(name, seed)
+    need(variant, inst)
     blo, bhi = synth.random_boxes(inst.lo, inst.hi, 1000, seed + 17, depth)
     o_lo, o_hi = slr.propagate(inst.net, inst.C, inst.dvec, blo, bhi)
     g_lo, g_hi, _ = gpu_bounds(inst, blo, bhi, raw=True)
@@ -74,8 +91,9 @@ def test_bound_raw_parity(name, seed, depth):
 
 
 @pytest.mark.parametrize("name,seed,depth", CASES)
-def test_widened_bounds_sound_and_classes(name, seed, depth):
+def test_widened_bounds_sound_and_classes(name, seed, depth, variant):
     inst = make(name, seed)
+    need(variant, inst)
     blo, bhi = synth.random_boxes(inst.lo, inst.hi, 600, seed + 5, depth)
     g_lo, g_hi, cls = gpu_bounds(inst, blo, bhi, raw=False)
     rng = np.random.default_rng(seed)
@@ -90,7 +108,7 @@ def test_widened_bounds_sound_and_classes(name, seed, depth):
     assert set(np.unique(cls)) <= {0, 1, 2}
 
 
-def test_bound_ragged_and_empty():
+def test_bound_ragged_and_empty(variant):
     inst = synth.acas(4)
     net, prop = load(inst)
     for n in (0, 1, 15, 16, 17, 63, 65, 257):
@@ -107,7 +125,7 @@ def test_bound_ragged_and_empty():
         assert np.allclose(g_hi.cpu().numpy(), o_hi, rtol=TOL, atol=TOL)
 
 
-def test_degenerate_boxes_contain_point_value():
+def test_degenerate_boxes_contain_point_value(variant):
     inst = synth.acas(5)
     rng = np.random.default_rng(1)
     x = rng.uniform(0, 1, size=(40, 5)).astype(np.float32)
@@ -173,19 +191,19 @@ def compare_counts(inst, D, M, chunk=0):
 
 
 @pytest.mark.parametrize("seed", range(12))
-def test_count_exact_tiny2d(seed):
+def test_count_exact_tiny2d(seed, variant):
     inst = synth.tiny2d(seed)
     g, o, div = compare_counts(inst, inst.max_depth, inst.max_leaves)
     assert g["status"] in (0, 1)
 
 
 @pytest.mark.parametrize("seed", [0, 1])
-def test_count_exact_acas_small_budget(seed):
+def test_count_exact_acas_small_budget(seed, variant):
     inst = synth.acas(seed)
     compare_counts(inst, 40, 1 << 12, chunk=1000)
 
 
-def test_count_exact_closed_forms():
+def test_count_exact_closed_forms(variant):
     from tests import oracle_pins as P
     for net, lo, hi, D in ((P.abs_net(), np.zeros(2), np.ones(2), 14),
                            (P.irwin_hall_net(), np.zeros(3), np.ones(3), 24)):
@@ -247,7 +265,7 @@ def reconstruct(lo, hi, depth, path):
     return lo, hi
 
 
-def test_count_exact_acas_full_size_sampled():
+def test_count_exact_acas_full_size_sampled(variant):
     """The benchmark workload (2^20-leaf budget, 65536-box launches), checked on samples."""
     inst = synth.acas(0)
     net, prop = load(inst)
@@ -272,11 +290,13 @@ def test_count_exact_acas_full_size_sampled():
     assert np.array_equal(g["trace_cls"][idx][big], oc[big])
 
 
-def test_sample_violations_matches_forward():
-    inst = synth.nav22(2)
+@pytest.mark.parametrize("name", ["nav22", "acas", "tiny2d"])
+def test_sample_violations_matches_forward(name):
+    inst = getattr(synth, name)(2)
     net, prop = load(inst)
     rng = np.random.default_rng(3)
-    x = rng.uniform(0, 1, size=(3000, 22)).astype(np.float32)
+    d = inst.lo.shape[0]
+    x = (inst.lo + (inst.hi - inst.lo) * rng.uniform(0, 1, size=(3000, d))).astype(np.float32)
     v = E().sample_violations(net, prop, dev(x)).cpu().numpy()
     gv = slr.property_values(inst.net, inst.C, inst.dvec, x.astype(np.float64))
     o = np.all(gv > 0, axis=1)
@@ -300,3 +320,35 @@ def test_count_approx_matches_oracle_draws():
     assert g["splits"] == o["splits"]
     assert np.allclose(g["estimates"], o["estimates"], rtol=1e-12, atol=0)
     assert g["lower_bound"] <= 1.0 / 6.0       # true volume of {sum x > 2} is 1/6
+
+
+def test_variants_agree_bitwise_on_classes():
+    """Both kernels on the same boxes: identical classes, bounds within float32 rounding."""
+    inst = synth.acas(3)
+    blo, bhi = synth.random_boxes(inst.lo, inst.hi, 2000, 8, 34)
+    eng = E()
+    out = []
+    for v in (1, 2):
+        eng.bound_kernel_variant(v)
+        out.append(gpu_bounds(inst, blo, bhi, raw=False))
+    eng.bound_kernel_variant(0)
+    (a_lo, a_hi, a_c), (b_lo, b_hi, b_c) = out
+    assert np.array_equal(a_c, b_c)
+    sc = 1e-5 * np.maximum(1.0, np.maximum(np.abs(a_lo), np.abs(a_hi)))
+    assert np.all(np.abs(a_lo - b_lo) <= sc) and np.all(np.abs(a_hi - b_hi) <= sc)
+
+
+def test_variant_rejects_unknown_and_unfit():
+    eng = E()
+    with pytest.raises(eng.SlrError):
+        eng.bound_kernel_variant(7)
+    eng.bound_kernel_variant(2)
+    try:
+        inst = synth.nav22(0)           # d = 22 does not fit the register-resident kernel
+        net, prop = load(inst)
+        blo, bhi = synth.random_boxes(inst.lo, inst.hi, 4, 0, 3)
+        with pytest.raises(eng.SlrError) as e:
+            eng.bound_boxes(net, prop, dev(blo), dev(bhi))
+        assert e.value.code == -5
+    finally:
+        eng.bound_kernel_variant(0)
