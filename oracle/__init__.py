@@ -31,4 +31,4 @@ Where the paper is silent or garbled the readings are:
 Every bound carries an FP64 rounding margin (Higham's gamma_n = n u / (1 - n u), u = 2^-53),
 so the computed bounds are sound for the exact network; the margin is ~1e-13 relative.
 """
-from . import slr, count, philox  # noqa: F401
+from . import slr, count, philox, alpha  # noqa: F401
