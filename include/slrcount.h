@@ -112,6 +112,13 @@ typedef struct {
     uint64_t* trace_path;
     int8_t* trace_cls;
     int32_t timing;         /* 1: time the bound-kernel launches with HIP events on `stream` */
+    /* alpha mode: boxes that the plain bounds leave undecided at depth >= alpha_min_depth get
+       alpha_steps projected-Adam steps of optimized lower slopes (0 = plain only), in batches
+       of alpha_chunk boxes (the workspace must be sized for it) */
+    int32_t alpha_steps;
+    float alpha_lr;         /* Adam step size (0 = 0.1) */
+    int32_t alpha_min_depth;
+    int32_t alpha_chunk;
 } slr_exact_opts;
 
 typedef struct {
@@ -125,14 +132,18 @@ typedef struct {
     int64_t trace_count;              /* boxes written to the trace (<= trace_capacity)      */
     double bound_ms;                  /* with timing: summed bound-kernel time per level (ms) */
     int64_t bound_launches;           /* bound-kernel launches made by the call              */
+    int64_t n_alpha_boxes;            /* boxes given the alpha optimization                  */
+    int64_t n_alpha_decided;          /* of those, boxes the optimized bounds decided        */
+    double alpha_ms;                  /* with timing: time of the alpha passes (ms)          */
 } slr_count_result;
 
 /*
  * workspace_size: bytes of device workspace needed by count_exact / count_approx for a leaf
- * budget `max_leaves` and up to `samples` sample points per split (0 for count_exact only).
+ * budget `max_leaves`, up to `samples` sample points per split (0 for count_exact only) and
+ * alpha batches of `alpha_chunk` boxes (0 without alpha mode).
  */
 int workspace_size(const slr_net* net, const slr_property* prop, int64_t max_leaves,
-                   int32_t samples, size_t* bytes);
+                   int32_t samples, int32_t alpha_chunk, size_t* bytes);
 
 /*
  * count_exact: Alg. 1 level by level on the device.
@@ -181,6 +192,73 @@ int count_approx(const slr_net* net, const slr_property* prop, const double* lo,
  */
 int sample_violations(const slr_net* net, const slr_property* prop, int64_t n, const float* x,
                       int8_t* viol, void* stream);
+
+/* ------------------------------------------------------------------------------------------
+ * Alpha mode: optimized lower slopes.
+ *
+ * Eq. 1 replaces a crossing neuron (l < 0 < u) by the lines lam z (lower) and lam (z - l)
+ * (upper), lam = u / (u - l).  Any slope alpha in [0, 1] also gives a valid lower line alpha z,
+ * so each box may carry its own slope per hidden neuron, tuned by gradient to tighten the bound
+ * that decides the box; the upper line stays the chord of Eq. 1.  Slopes are device float32
+ * arrays [n][nh], nh = the sum of the hidden widths, neurons in their original order, the first
+ * hidden layer first.  Only the slopes of crossing neurons are used; values are clamped to [0, 1].
+ * ------------------------------------------------------------------------------------------ */
+
+/* alpha_size: nh, the slopes per box. */
+int alpha_size(const slr_net* net, int64_t* nh);
+
+/* alpha_tape_size: bytes of the tape bound_boxes_alpha writes for n boxes (per 16-box tile:
+   every layer's pre-activation equations and concrete bounds). */
+int alpha_tape_size(const slr_net* net, const slr_property* prop, int64_t n, size_t* bytes);
+
+/*
+ * bound_boxes_alpha: bounds of n boxes with per-box slopes, on `stream`, asynchronous.
+ *   lo, hi       device float32 [n, d]
+ *   alpha        device [n, nh]: the slopes (init = 0), or written with the plain ratios lam of
+ *                every crossing neuron and 1 elsewhere (init = 1); NULL = the plain relaxation
+ *   g_lo, g_hi   device float32 [n, rows] output bounds of the property rows
+ *   cls          device int8 [n] (optional): 1 unsafe, 2 safe, 0 undecided (no FP64 recheck)
+ *   raw          1 = no rounding margins (for gradient and parity tests), 0 = sound bounds
+ *   tape         device memory of at least alpha_tape_size(n) bytes, read by the adjoint
+ */
+int bound_boxes_alpha(const slr_net* net, const slr_property* prop, int64_t n, const float* lo,
+                      const float* hi, float* alpha, int32_t init, float* g_lo, float* g_hi,
+                      int8_t* cls, int32_t raw, void* tape, size_t tape_bytes, void* stream);
+
+/*
+ * bound_boxes_backward: the hand-written adjoint of bound_boxes_alpha.  Given seeds
+ * dg_lo = dJ/dg_lo and dg_hi = dJ/dg_hi (device [n, rows]; NULL = zero), writes
+ * dalpha = dJ/dalpha (device [n, nh]; 0 for neurons that are not crossing).  `tape` must hold
+ * what bound_boxes_alpha wrote for the same boxes, slopes and `raw`; the rounding margins are
+ * treated as constants.  Asynchronous on `stream`.
+ */
+int bound_boxes_backward(const slr_net* net, const slr_property* prop, int64_t n,
+                         const float* alpha, const void* tape, size_t tape_bytes,
+                         const float* dg_lo, const float* dg_hi, float* dalpha, int32_t raw,
+                         void* stream);
+
+typedef struct {
+    int32_t steps;           /* projected Adam steps (e.g. 20)                               */
+    float lr, beta1, beta2, eps;   /* Adam (e.g. 0.1, 0.9, 0.999, 1e-8)                      */
+    int32_t raw;             /* 1 = bounds without rounding margins                          */
+} slr_alpha_opts;
+
+/* alpha_workspace_size: device workspace of alpha_optimize for n boxes. */
+int alpha_workspace_size(const slr_net* net, const slr_property* prop, int64_t n, size_t* bytes);
+
+/*
+ * alpha_optimize: per box, starts from the plain ratios and takes `steps` projected Adam steps
+ * on the objective: if every property row is > 0 at the box center (float32 forward pass),
+ * maximize min_r g_lo[r]; otherwise minimize g_hi[r*], r* = the row with the smallest value at
+ * the center.  Every step's bounds are valid, so best_lo / best_hi (device [n, rows]) receive
+ * their running intersection (max of the lower, min of the upper bounds) and cls (device int8
+ * [n], optional) the class they decide.  alpha (device [n, nh], optional) receives the last
+ * slopes.  Synchronous only through `stream` (asynchronous to the host).
+ */
+int alpha_optimize(const slr_net* net, const slr_property* prop, int64_t n, const float* lo,
+                   const float* hi, const slr_alpha_opts* opts, float* alpha, float* best_lo,
+                   float* best_hi, int8_t* cls, void* workspace, size_t workspace_bytes,
+                   void* stream);
 
 /* Message of the last failed call on this thread ("" if none). */
 const char* last_error(void);

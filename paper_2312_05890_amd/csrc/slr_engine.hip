@@ -233,7 +233,15 @@ extern "C" int load_net(int32_t n_affine, const int32_t* sizes, const float* con
     }
     const size_t i_w1p = add(w1p.data(), w1p.size() * sizeof(float));
     const size_t i_b1p = add(b1p.data(), b1p.size() * sizeof(float));
-    struct MidIdx { size_t frag, w, wt, bias, absrow, b; };
+    // alpha mode: row -> neuron maps and slope offsets of the hidden layers
+    std::vector<size_t> i_rowmap(n_affine - 1);
+    nd.nh = 0;
+    for (int h = 0; h < n_affine - 1; ++h) {
+        i_rowmap[h] = add(at[h].data(), at[h].size() * sizeof(int));
+        nd.hoff[h] = nd.nh;
+        nd.nh += sizes[h + 1];
+    }
+    struct MidIdx { size_t frag, w, wt, bias, absrow, b, wtfrag; };
     std::vector<MidIdx> mids;
     for (int l = 1; l <= n_affine - 2; ++l) {
         const int n_in = sizes[l], n_out = sizes[l + 1];
@@ -268,6 +276,12 @@ extern "C" int load_net(int32_t n_affine, const int32_t* sizes, const float* con
         mi.bias = add(bias.data(), bias.size() * sizeof(float));
         mi.absrow = add(absrow.data(), absrow.size() * sizeof(float));
         mi.b = add(b[l], sizeof(float) * n_out);
+        // W^T fragments for the alpha adjoint: output rows = this layer's inputs
+        L.mt_in = ceil_div(n_in, 16);
+        L.kst = k_steps(n_out);
+        L.kst_alloc = (L.kst + 3) / 4 * 4;
+        std::vector<float> tfrag = pack_fragments(wt.data(), n_out, at[l - 1], at[l], L.kst, L.kst_alloc);
+        mi.wtfrag = add(tfrag.data(), tfrag.size() * sizeof(float));
         mids.push_back(mi);
     }
     std::vector<size_t> offs(blobs.size());
@@ -298,7 +312,9 @@ extern "C" int load_net(int32_t n_affine, const int32_t* sizes, const float* con
         nd.mid[l].bias = (const float*)(base + offs[mids[l].bias]);
         nd.mid[l].absrow = (const float*)(base + offs[mids[l].absrow]);
         nd.mid[l].b = (const float*)(base + offs[mids[l].b]);
+        nd.mid[l].wtfrag = (const float*)(base + offs[mids[l].wtfrag]);
     }
+    for (int h = 0; h < n_affine - 1; ++h) nd.rowmap[h] = (const int*)(base + offs[i_rowmap[h]]);
     slr_net* net = new slr_net;
     net->dev = nd;
     net->mem = mem;
@@ -369,11 +385,31 @@ extern "C" int load_property(const slr_net* net, int32_t rows, const float* C, c
     for (int r = 0; r < rows; ++r)
         for (int kk = 0; kk < pd.kpad; ++kk)
             if (net->last_at[kk] >= 0) wgp[(size_t)r * pd.kpad + kk] = wg[(size_t)r * K + net->last_at[kk]];
+    // alpha mode: relabeled property rows (tile row 4 g + v = property row 4 v + g) and W_g^T
+    const std::vector<int> rat = rows_to_neurons(rows);
+    std::vector<int> rat16(16, -1);
+    for (size_t i = 0; i < rat.size() && i < 16; ++i) rat16[i] = rat[i];
+    std::vector<float> wgfrag_a = pack_fragments(wg.data(), K, rat16, net->last_at, pd.ks_out, pd.ks_out_alloc);
+    std::vector<float> wgT((size_t)K * rows);
+    for (int r = 0; r < rows; ++r)
+        for (int k = 0; k < K; ++k) wgT[(size_t)k * rows + r] = wg[(size_t)r * K + k];
+    pd.ks_rows = k_steps(rows);
+    pd.ks_rows_alloc = (pd.ks_rows + 3) / 4 * 4;
+    std::vector<float> wgtfrag = pack_fragments(wgT.data(), rows, net->last_at, rat16, pd.ks_rows, pd.ks_rows_alloc);
+    std::vector<float> bga(16, 0.f), aga(16, 0.f);
+    for (int i = 0; i < 16; ++i)
+        if (rat16[i] >= 0) {
+            bga[i] = bg[rat16[i]];
+            aga[i] = ag[rat16[i]];
+        }
+    const size_t s_fa = (wgfrag_a.size() * 4 + 255) / 256 * 256;
+    const size_t s_ft = (wgtfrag.size() * 4 + 255) / 256 * 256;
+    const size_t s_16 = 256;
     const size_t s_wgp = (wgp.size() * 4 + 255) / 256 * 256;
     const size_t s_wg = (wg.size() * 4 + 255) / 256 * 256, s_r = (rows * 4 + 255) / 256 * 256;
     const size_t s_frag = (wgfrag.size() * 4 + 255) / 256 * 256;
     const size_t s_wg64 = (wg64.size() * 8 + 255) / 256 * 256, s_r64 = (rows * 8 + 255) / 256 * 256;
-    const size_t total = s_wg + 2 * s_r + s_wg64 + 2 * s_r64 + s_frag + s_wgp;
+    const size_t total = s_wg + 2 * s_r + s_wg64 + 2 * s_r64 + s_frag + s_wgp + s_fa + s_ft + 2 * s_16;
     std::vector<char> host(total, 0);
     size_t o = 0;
     memcpy(host.data() + o, wg.data(), wg.size() * 4);
@@ -391,7 +427,15 @@ extern "C" int load_property(const slr_net* net, int32_t rows, const float* C, c
     memcpy(host.data() + o, wgfrag.data(), wgfrag.size() * 4);
     const size_t o_frag = o; o += s_frag;
     memcpy(host.data() + o, wgp.data(), wgp.size() * 4);
-    const size_t o_wgp = o;
+    const size_t o_wgp = o; o += s_wgp;
+    memcpy(host.data() + o, wgfrag_a.data(), wgfrag_a.size() * 4);
+    const size_t o_fa = o; o += s_fa;
+    memcpy(host.data() + o, wgtfrag.data(), wgtfrag.size() * 4);
+    const size_t o_ft = o; o += s_ft;
+    memcpy(host.data() + o, bga.data(), 64);
+    const size_t o_bga = o; o += s_16;
+    memcpy(host.data() + o, aga.data(), 64);
+    const size_t o_aga = o;
     void* mem = nullptr;
     hipError_t e = hipMalloc(&mem, total);
     if (e != hipSuccess) return fail(SLR_ENOMEM, "load_property: hipMalloc: %s", hipGetErrorString(e));
@@ -409,6 +453,10 @@ extern "C" int load_property(const slr_net* net, int32_t rows, const float* C, c
     pd.ag64 = (const double*)(base + o_ag64);
     pd.wgfrag = (const float*)(base + o_frag);
     pd.wgp = (const float*)(base + o_wgp);
+    pd.wgfrag_a = (const float*)(base + o_fa);
+    pd.wgtfrag = (const float*)(base + o_ft);
+    pd.bga = (const float*)(base + o_bga);
+    pd.aga = (const float*)(base + o_aga);
     slr_property* p = new slr_property;
     p->dev = pd;
     p->mem = mem;
@@ -445,12 +493,50 @@ struct Workspace {
     unsigned* err;
     float* samples;              // [samples][d]
     int8_t* viol;                // [samples]
+    // alpha batches of up to achunk boxes
+    int64_t achunk;
+    float *alo, *ahi;            // [achunk][d] gathered undecided boxes
+    float *best_lo, *best_hi;    // [achunk][rows]
+    int8_t* acls;                // [achunk]
+    char* aws;                   // alpha_optimize workspace for achunk boxes
+    size_t aws_bytes;
     size_t bytes;
 };
 
 size_t align256(size_t x) { return (x + 255) / 256 * 256; }
 
-Workspace layout_ws(char* base, int d, int64_t cap, int samples) {
+// Workspace of alpha_optimize for n boxes.
+struct AlphaWs {
+    float* tape;
+    float *m, *v, *alpha;        // [n][nh]
+    float *g_lo, *g_hi;          // [n][rows]
+    int8_t* obj;                 // [n][2]
+    size_t tape_bytes, bytes;
+};
+
+AlphaWs layout_alpha(char* base, const NetDev& nd, const PropDev& pd, int64_t n) {
+    AlphaWs w{};
+    size_t o = 0;
+    auto take = [&](size_t bytes) {
+        char* p = base ? base + o : nullptr;
+        o += align256(bytes);
+        return p;
+    };
+    w.tape_bytes = alpha_tape_bytes(nd, pd, n);
+    w.tape = (float*)take(w.tape_bytes);
+    w.m = (float*)take(sizeof(float) * (size_t)n * nd.nh);
+    w.v = (float*)take(sizeof(float) * (size_t)n * nd.nh);
+    w.alpha = (float*)take(sizeof(float) * (size_t)n * nd.nh);
+    w.g_lo = (float*)take(sizeof(float) * (size_t)n * pd.rows);
+    w.g_hi = (float*)take(sizeof(float) * (size_t)n * pd.rows);
+    w.obj = (int8_t*)take((size_t)2 * n);
+    w.bytes = o;
+    return w;
+}
+
+Workspace layout_ws(char* base, const NetDev& nd, const PropDev& pd, int64_t cap, int samples,
+                    int64_t achunk) {
+    const int d = nd.d;
     Workspace w{};
     size_t o = 0;
     auto take = [&](size_t bytes) {
@@ -474,6 +560,16 @@ Workspace layout_ws(char* base, int d, int64_t cap, int samples) {
     w.err = (unsigned*)take(sizeof(unsigned));
     w.samples = (float*)take(sizeof(float) * (size_t)d * std::max(samples, 0));
     w.viol = (int8_t*)take(std::max(samples, 0));
+    w.achunk = achunk;
+    if (achunk > 0) {
+        w.alo = (float*)take(sizeof(float) * d * achunk);
+        w.ahi = (float*)take(sizeof(float) * d * achunk);
+        w.best_lo = (float*)take(sizeof(float) * pd.rows * achunk);
+        w.best_hi = (float*)take(sizeof(float) * pd.rows * achunk);
+        w.acls = (int8_t*)take(achunk);
+        w.aws_bytes = layout_alpha(nullptr, nd, pd, achunk).bytes;
+        w.aws = take(w.aws_bytes);
+    }
     w.bytes = o;
     return w;
 }
@@ -502,14 +598,17 @@ int check_box(const slr_net* net, const double* lo, const double* hi, const char
 }  // namespace
 
 extern "C" int workspace_size(const slr_net* net, const slr_property* prop, int64_t max_leaves,
-                              int32_t samples, size_t* bytes) {
+                              int32_t samples, int32_t alpha_chunk, size_t* bytes) {
     g_err.clear();
     if (!bytes) return fail(SLR_EINVAL, "workspace_size: bytes is NULL");
     if (!net) return fail(SLR_EINVAL, "workspace_size: net is NULL");
-    (void)prop;
     if (max_leaves < 1) return fail(SLR_EINVAL, "workspace_size: max_leaves must be >= 1");
     if (samples < 0) return fail(SLR_EINVAL, "workspace_size: samples must be >= 0");
-    *bytes = layout_ws(nullptr, net->dev.d, max_leaves, samples).bytes;
+    if (alpha_chunk < 0) return fail(SLR_EINVAL, "workspace_size: alpha_chunk must be >= 0");
+    if (alpha_chunk > 0 && !prop) return fail(SLR_EINVAL, "workspace_size: alpha mode needs the property");
+    PropDev pd{};
+    if (prop) pd = prop->dev;
+    *bytes = layout_ws(nullptr, net->dev, pd, max_leaves, samples, alpha_chunk).bytes;
     return SLR_OK;
 }
 
@@ -559,6 +658,179 @@ extern "C" int sample_violations(const slr_net* net, const slr_property* prop, i
     return SLR_OK;
 }
 
+// ------------------------------------------------------------------------------------------
+// Alpha mode
+// ------------------------------------------------------------------------------------------
+namespace {
+
+int check_alpha_pair(const slr_net* net, const slr_property* prop, const char* who) {
+    if (!net) return fail(SLR_EINVAL, "%s: net is NULL", who);
+    if (!prop) return fail(SLR_EINVAL, "%s: property is NULL", who);
+    if (prop->net != net) return fail(SLR_EINVAL, "%s: property was loaded for another net", who);
+    if (alpha_shape(net->dev, prop->dev).nc < 0) return fail(SLR_EUNSUPPORTED, "%s: input dimension too large", who);
+    return SLR_OK;
+}
+
+// Projected Adam on the slopes of n boxes (init pass + steps x (adjoint with fused update,
+// forward)); every forward pass folds its bounds into best_lo / best_hi and classifies.
+int alpha_run(const slr_net* net, const slr_property* prop, int64_t n, const float* lo,
+              const float* hi, const slr_alpha_opts& o, float* alpha, float* best_lo,
+              float* best_hi, int8_t* cls, const AlphaWs& w, hipStream_t s) {
+    if (n <= 0) return SLR_OK;
+    const NetDev& nd = net->dev;
+    const PropDev& pd = prop->dev;
+    HIP_TRY(launch_center_objective(nd, pd, n, lo, hi, w.obj, s), "alpha: center kernel");
+    HIP_TRY(hipMemsetAsync(w.m, 0, sizeof(float) * (size_t)n * nd.nh, s), "alpha: clear");
+    HIP_TRY(hipMemsetAsync(w.v, 0, sizeof(float) * (size_t)n * nd.nh, s), "alpha: clear");
+    AlphaArgs a{};
+    a.n = n;
+    a.lo = lo;
+    a.hi = hi;
+    a.alpha = alpha ? alpha : w.alpha;
+    a.g_lo = w.g_lo;
+    a.g_hi = w.g_hi;
+    a.best_lo = best_lo;
+    a.best_hi = best_hi;
+    a.cls = cls;
+    a.tape = w.tape;
+    a.raw = o.raw;
+    a.init = 1;
+    HIP_TRY(launch_alpha_forward(nd, pd, a, s), "alpha: forward kernel");
+    a.init = 0;
+    a.obj = w.obj;
+    a.adam_m = w.m;
+    a.adam_v = w.v;
+    a.lr = o.lr;
+    a.beta1 = o.beta1;
+    a.beta2 = o.beta2;
+    a.eps = o.eps;
+    double p1 = 1.0, p2 = 1.0;
+    for (int t = 1; t <= o.steps; ++t) {
+        p1 *= o.beta1;
+        p2 *= o.beta2;
+        a.c1 = (float)(1.0 / (1.0 - p1));
+        a.c2 = (float)(1.0 / (1.0 - p2));
+        HIP_TRY(launch_alpha_backward(nd, pd, a, s), "alpha: adjoint kernel");
+        HIP_TRY(launch_alpha_forward(nd, pd, a, s), "alpha: forward kernel");
+    }
+    return SLR_OK;
+}
+
+}  // namespace
+
+extern "C" int alpha_size(const slr_net* net, int64_t* nh) {
+    g_err.clear();
+    if (!net || !nh) return fail(SLR_EINVAL, "alpha_size: NULL argument");
+    *nh = net->dev.nh;
+    return SLR_OK;
+}
+
+extern "C" int alpha_tape_size(const slr_net* net, const slr_property* prop, int64_t n, size_t* bytes) {
+    g_err.clear();
+    int rc = check_alpha_pair(net, prop, "alpha_tape_size");
+    if (rc) return rc;
+    if (!bytes || n < 0) return fail(SLR_EINVAL, "alpha_tape_size: bad argument");
+    *bytes = alpha_tape_bytes(net->dev, prop->dev, n);
+    return SLR_OK;
+}
+
+extern "C" int alpha_workspace_size(const slr_net* net, const slr_property* prop, int64_t n, size_t* bytes) {
+    g_err.clear();
+    int rc = check_alpha_pair(net, prop, "alpha_workspace_size");
+    if (rc) return rc;
+    if (!bytes || n < 0) return fail(SLR_EINVAL, "alpha_workspace_size: bad argument");
+    *bytes = layout_alpha(nullptr, net->dev, prop->dev, n).bytes;
+    return SLR_OK;
+}
+
+extern "C" int bound_boxes_alpha(const slr_net* net, const slr_property* prop, int64_t n,
+                                 const float* lo, const float* hi, float* alpha, int32_t init,
+                                 float* g_lo, float* g_hi, int8_t* cls, int32_t raw, void* tape,
+                                 size_t tape_bytes, void* stream) {
+    g_err.clear();
+    int rc = check_alpha_pair(net, prop, "bound_boxes_alpha");
+    if (rc) return rc;
+    if (n < 0) return fail(SLR_EINVAL, "bound_boxes_alpha: n < 0");
+    if ((raw != 0 && raw != 1) || (init != 0 && init != 1))
+        return fail(SLR_EINVAL, "bound_boxes_alpha: raw and init must be 0 or 1");
+    if (n == 0) return SLR_OK;
+    if (!is_device_ptr(lo) || !is_device_ptr(hi) || !is_device_ptr(g_lo) || !is_device_ptr(g_hi))
+        return fail(SLR_EINVAL, "bound_boxes_alpha: lo, hi, g_lo and g_hi must be device memory");
+    if ((alpha && !is_device_ptr(alpha)) || (cls && !is_device_ptr(cls)))
+        return fail(SLR_EINVAL, "bound_boxes_alpha: alpha and cls must be device memory");
+    const size_t need = alpha_tape_bytes(net->dev, prop->dev, n);
+    if (!tape || tape_bytes < need)
+        return fail(SLR_ENOMEM, "bound_boxes_alpha: tape of %zu bytes is smaller than the %zu required", tape_bytes, need);
+    if (!is_device_ptr(tape)) return fail(SLR_EINVAL, "bound_boxes_alpha: tape must be device memory");
+    AlphaArgs a{};
+    a.n = n;
+    a.lo = lo;
+    a.hi = hi;
+    a.alpha = alpha;
+    a.init = init;
+    a.g_lo = g_lo;
+    a.g_hi = g_hi;
+    a.cls = cls;
+    a.raw = raw;
+    a.tape = (float*)tape;
+    HIP_TRY(launch_alpha_forward(net->dev, prop->dev, a, (hipStream_t)stream), "bound_boxes_alpha: kernel");
+    return SLR_OK;
+}
+
+extern "C" int bound_boxes_backward(const slr_net* net, const slr_property* prop, int64_t n,
+                                    const float* alpha, const void* tape, size_t tape_bytes,
+                                    const float* dg_lo, const float* dg_hi, float* dalpha,
+                                    int32_t raw, void* stream) {
+    g_err.clear();
+    int rc = check_alpha_pair(net, prop, "bound_boxes_backward");
+    if (rc) return rc;
+    if (n < 0) return fail(SLR_EINVAL, "bound_boxes_backward: n < 0");
+    if (raw != 0 && raw != 1) return fail(SLR_EINVAL, "bound_boxes_backward: raw must be 0 or 1");
+    if (n == 0) return SLR_OK;
+    if (!is_device_ptr(dalpha)) return fail(SLR_EINVAL, "bound_boxes_backward: dalpha must be device memory");
+    if ((alpha && !is_device_ptr(alpha)) || (dg_lo && !is_device_ptr(dg_lo)) || (dg_hi && !is_device_ptr(dg_hi)))
+        return fail(SLR_EINVAL, "bound_boxes_backward: alpha, dg_lo and dg_hi must be device memory");
+    const size_t need = alpha_tape_bytes(net->dev, prop->dev, n);
+    if (!tape || tape_bytes < need)
+        return fail(SLR_ENOMEM, "bound_boxes_backward: tape of %zu bytes is smaller than the %zu required", tape_bytes, need);
+    if (!is_device_ptr(tape)) return fail(SLR_EINVAL, "bound_boxes_backward: tape must be device memory");
+    AlphaArgs a{};
+    a.n = n;
+    a.alpha = const_cast<float*>(alpha);   // read only: no Adam state is given
+    a.tape = (float*)tape;
+    a.raw = raw;
+    a.dg_lo = dg_lo;
+    a.dg_hi = dg_hi;
+    a.dalpha = dalpha;
+    HIP_TRY(launch_alpha_backward(net->dev, prop->dev, a, (hipStream_t)stream), "bound_boxes_backward: kernel");
+    return SLR_OK;
+}
+
+extern "C" int alpha_optimize(const slr_net* net, const slr_property* prop, int64_t n,
+                              const float* lo, const float* hi, const slr_alpha_opts* opts,
+                              float* alpha, float* best_lo, float* best_hi, int8_t* cls,
+                              void* workspace, size_t workspace_bytes, void* stream) {
+    g_err.clear();
+    int rc = check_alpha_pair(net, prop, "alpha_optimize");
+    if (rc) return rc;
+    if (!opts) return fail(SLR_EINVAL, "alpha_optimize: opts is NULL");
+    if (n < 0) return fail(SLR_EINVAL, "alpha_optimize: n < 0");
+    if (opts->steps < 0 || opts->steps > 1000 || !(opts->lr >= 0.f) || !(opts->beta1 >= 0.f && opts->beta1 < 1.f) ||
+        !(opts->beta2 >= 0.f && opts->beta2 < 1.f) || !(opts->eps > 0.f) || (opts->raw != 0 && opts->raw != 1))
+        return fail(SLR_EINVAL, "alpha_optimize: bad options");
+    if (n == 0) return SLR_OK;
+    if (!is_device_ptr(lo) || !is_device_ptr(hi) || !is_device_ptr(best_lo) || !is_device_ptr(best_hi))
+        return fail(SLR_EINVAL, "alpha_optimize: lo, hi, best_lo and best_hi must be device memory");
+    if ((alpha && !is_device_ptr(alpha)) || (cls && !is_device_ptr(cls)))
+        return fail(SLR_EINVAL, "alpha_optimize: alpha and cls must be device memory");
+    const AlphaWs probe = layout_alpha(nullptr, net->dev, prop->dev, n);
+    if (!workspace || workspace_bytes < probe.bytes)
+        return fail(SLR_ENOMEM, "alpha_optimize: workspace of %zu bytes is smaller than the %zu required", workspace_bytes, probe.bytes);
+    if (!is_device_ptr(workspace)) return fail(SLR_EINVAL, "alpha_optimize: workspace must be device memory");
+    const AlphaWs w = layout_alpha((char*)workspace, net->dev, prop->dev, n);
+    return alpha_run(net, prop, n, lo, hi, *opts, alpha, best_lo, best_hi, cls, w, (hipStream_t)stream);
+}
+
 namespace {
 
 int count_exact_impl(const slr_net* net, const slr_property* prop, const double* lo,
@@ -596,8 +868,8 @@ int count_exact_impl(const slr_net* net, const slr_property* prop, const double*
             if (b) (void)hipEventDestroy(b);
         }
     } guard{ev0, ev1};
-    double bound_ms = 0.0;
-    int64_t launches = 0;
+    double bound_ms = 0.0, alpha_ms = 0.0;
+    int64_t launches = 0, alpha_boxes = 0, alpha_decided = 0, alpha_und_before = 0;
     int64_t n = 1, resolved = 0, bounded = 0, tcount = 0;
     int cur = 0, levels = 0, stop_level = 0, stopped = 0, status = SLR_OK;
     std::vector<unsigned long long> hpath;
@@ -615,10 +887,50 @@ int count_exact_impl(const slr_net* net, const slr_property* prop, const double*
             if (unsup) return fail(SLR_EUNSUPPORTED, "count_exact: shape not supported");
             ++launches;
         }
-        if (ev1) HIP_TRY(hipEventRecord(ev1, s), "count_exact: event");
+        if (ev1) {
+            HIP_TRY(hipEventRecord(ev1, s), "count_exact: event");
+            if (o->alpha_steps > 0) {
+                HIP_TRY(hipEventSynchronize(ev1), "count_exact: event");
+                float ms = 0.f;
+                HIP_TRY(hipEventElapsedTime(&ms, ev0, ev1), "count_exact: event");
+                bound_ms += ms;
+            }
+        }
         HIP_TRY(launch_recheck64(net->dev, prop->dev, n, w.lo[cur], w.hi[cur], nullptr, nullptr,
                                  w.cls, w.rechecks, w.amb_list, w.amb_count, s),
                 "count_exact: recheck kernel");
+        if (o->alpha_steps > 0 && t >= o->alpha_min_depth) {
+            if (ev0) HIP_TRY(hipEventRecord(ev0, s), "count_exact: event");
+            HIP_TRY(hipMemsetAsync(w.amb_count, 0, sizeof(unsigned), s), "count_exact: clear");
+            HIP_TRY(launch_collect_undecided(n, w.cls, w.amb_list, w.amb_count, s), "count_exact: collect kernel");
+            unsigned und_cnt = 0;
+            HIP_TRY(hipMemcpyAsync(&und_cnt, w.amb_count, sizeof und_cnt, hipMemcpyDeviceToHost, s), "count_exact: readback");
+            HIP_TRY(hipStreamSynchronize(s), "count_exact: sync");
+            slr_alpha_opts ao{};
+            ao.steps = o->alpha_steps;
+            ao.lr = o->alpha_lr > 0.f ? o->alpha_lr : 0.1f;
+            ao.beta1 = 0.9f;
+            ao.beta2 = 0.999f;
+            ao.eps = 1e-8f;
+            ao.raw = 0;
+            const AlphaWs aw = layout_alpha(w.aws, net->dev, prop->dev, w.achunk);
+            for (int64_t off = 0; off < (int64_t)und_cnt; off += w.achunk) {
+                const int64_t m = std::min<int64_t>(w.achunk, (int64_t)und_cnt - off);
+                HIP_TRY(launch_gather_boxes(m, d, w.amb_list + off, w.lo[cur], w.hi[cur], w.alo, w.ahi, s), "count_exact: gather kernel");
+                int arc = alpha_run(net, prop, m, w.alo, w.ahi, ao, nullptr, w.best_lo, w.best_hi, w.acls, aw, s);
+                if (arc) return arc;
+                HIP_TRY(launch_scatter_classes(m, w.amb_list + off, w.acls, w.cls, s), "count_exact: scatter kernel");
+            }
+            alpha_boxes += und_cnt;
+            alpha_und_before += und_cnt;
+            if (ev1) {
+                HIP_TRY(hipEventRecord(ev1, s), "count_exact: event");
+                HIP_TRY(hipEventSynchronize(ev1), "count_exact: event");
+                float ms = 0.f;
+                HIP_TRY(hipEventElapsedTime(&ms, ev0, ev1), "count_exact: event");
+                alpha_ms += ms;
+            }
+        }
         HIP_TRY(launch_level_count(n, w.cls, w.tile_und, w.stats + t, s), "count_exact: count kernel");
         LevelStats hs;
         HIP_TRY(hipMemcpyAsync(&hs, w.stats + t, sizeof hs, hipMemcpyDeviceToHost, s), "count_exact: readback");
@@ -637,7 +949,7 @@ int count_exact_impl(const slr_net* net, const slr_property* prop, const double*
             tcount += m;
         }
         HIP_TRY(hipStreamSynchronize(s), "count_exact: sync");
-        if (ev0) {
+        if (ev0 && o->alpha_steps <= 0) {
             float ms = 0.f;
             HIP_TRY(hipEventElapsedTime(&ms, ev0, ev1), "count_exact: event");
             bound_ms += ms;
@@ -646,6 +958,10 @@ int count_exact_impl(const slr_net* net, const slr_property* prop, const double*
         levels = t + 1;
         resolved += (int64_t)(hs.unsafe_cnt + hs.safe_cnt);
         const int64_t und = (int64_t)hs.undecided_cnt;
+        if (alpha_und_before > 0) {
+            alpha_decided += alpha_und_before - und;
+            alpha_und_before = 0;
+        }
         if ((int64_t)(hs.unsafe_cnt + hs.safe_cnt) + und != n)
             return fail(SLR_EINTERNAL, "count_exact: level %d counts %lld boxes of %lld", t,
                         (long long)(hs.unsafe_cnt + hs.safe_cnt + und), (long long)n);
@@ -686,23 +1002,34 @@ int count_exact_impl(const slr_net* net, const slr_property* prop, const double*
     out->trace_count = tcount;
     out->bound_ms = bound_ms;
     out->bound_launches = launches;
+    out->n_alpha_boxes = alpha_boxes;
+    out->n_alpha_decided = alpha_decided;
+    out->alpha_ms = alpha_ms;
     out->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     return status;
 }
 
-int check_exact_opts(const slr_net* net, const slr_exact_opts* o, int samples, Workspace* w, const char* who) {
+int check_exact_opts(const slr_net* net, const slr_property* prop, const slr_exact_opts* o,
+                     int samples, Workspace* w, const char* who) {
     if (!o) return fail(SLR_EINVAL, "%s: opts is NULL", who);
     if (o->max_depth < 0 || o->max_depth > kMaxLevels - 1)
         return fail(SLR_EINVAL, "%s: max_depth must be in [0, %d]", who, kMaxLevels - 1);
     if (o->max_leaves < 1) return fail(SLR_EINVAL, "%s: max_leaves must be >= 1", who);
     if (o->chunk < 0) return fail(SLR_EINVAL, "%s: chunk must be >= 0", who);
     if (o->trace_capacity < 0) return fail(SLR_EINVAL, "%s: trace_capacity must be >= 0", who);
-    const size_t need = layout_ws(nullptr, net->dev.d, o->max_leaves, samples).bytes;
+    if (o->alpha_steps < 0 || o->alpha_steps > 1000) return fail(SLR_EINVAL, "%s: alpha_steps must be in [0, 1000]", who);
+    if (o->alpha_chunk < 0) return fail(SLR_EINVAL, "%s: alpha_chunk must be >= 0", who);
+    if (o->alpha_steps > 0 && o->alpha_chunk < 1)
+        return fail(SLR_EINVAL, "%s: alpha mode needs alpha_chunk >= 1 (and a workspace sized for it)", who);
+    if (!(o->alpha_lr >= 0.f) || o->alpha_min_depth < 0)
+        return fail(SLR_EINVAL, "%s: alpha_lr and alpha_min_depth must be >= 0", who);
+    const int64_t achunk = o->alpha_steps > 0 ? o->alpha_chunk : 0;
+    const size_t need = layout_ws(nullptr, net->dev, prop->dev, o->max_leaves, samples, achunk).bytes;
     if (!o->workspace || o->workspace_bytes < need)
         return fail(SLR_ENOMEM, "%s: workspace of %zu bytes is smaller than the %zu required", who,
                     o->workspace_bytes, need);
     if (!is_device_ptr(o->workspace)) return fail(SLR_EINVAL, "%s: workspace must be device memory", who);
-    *w = layout_ws((char*)o->workspace, net->dev.d, o->max_leaves, samples);
+    *w = layout_ws((char*)o->workspace, net->dev, prop->dev, o->max_leaves, samples, achunk);
     return SLR_OK;
 }
 
@@ -716,7 +1043,7 @@ extern "C" int count_exact(const slr_net* net, const slr_property* prop, const d
     if (!out) return fail(SLR_EINVAL, "count_exact: out is NULL");
     if ((rc = check_box(net, lo, hi, "count_exact"))) return rc;
     Workspace w;
-    if ((rc = check_exact_opts(net, opts, 0, &w, "count_exact"))) return rc;
+    if ((rc = check_exact_opts(net, prop, opts, 0, &w, "count_exact"))) return rc;
     memset(out, 0, sizeof *out);
     return count_exact_impl(net, prop, lo, hi, opts, w, out);
 }
@@ -748,7 +1075,7 @@ extern "C" int count_approx(const slr_net* net, const slr_property* prop, const 
     if (o.grid_bits < 1 || o.grid_bits > 20) return fail(SLR_EINVAL, "count_approx: grid_bits must be in [1, 20]");
     if (!(o.resolve_tol >= 0.0)) return fail(SLR_EINVAL, "count_approx: resolve_tol must be >= 0");
     Workspace w;
-    if ((rc = check_exact_opts(net, &o.leaf, o.samples, &w, "count_approx"))) return rc;
+    if ((rc = check_exact_opts(net, prop, &o.leaf, o.samples, &w, "count_approx"))) return rc;
     memset(out, 0, sizeof *out);
     const auto t0 = std::chrono::steady_clock::now();
     const int d = net->dev.d;

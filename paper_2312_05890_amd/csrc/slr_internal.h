@@ -36,6 +36,9 @@ struct MidLayer {
     int n_in, n_out, mt_out, ks, ks_alloc;
     int r_out;            // neurons in the last 16-row output tile
     int frag_off;         // offset (floats) of this layer's fragments in the staged copy
+    const float* wtfrag;  // [mt_in][kst_alloc][64] fragments of W^T (alpha adjoint): rows are the
+                          // layer's input neurons, K runs over its output neurons
+    int mt_in, kst, kst_alloc;
     float kgam;           // kappa * gamma_{n_in + 2} for float32, rounded up
     double kgam64;        // the same for float64
 };
@@ -54,6 +57,11 @@ struct NetDev {
     const float* b1p;     // [16 mt1]
     int r1;               // neurons in the last 16-row tile of the first hidden layer
     MidLayer mid[SLR_MAX_AFFINE];   // affine layers 1 .. n_affine-2
+    // alpha mode: per hidden layer h, relabeled row -> neuron (-1 = padding) and the offset of
+    // the layer's slopes in a box's alpha vector (original neuron order, layer after layer)
+    const int* rowmap[SLR_MAX_AFFINE];
+    int hoff[SLR_MAX_AFFINE];
+    int nh;               // hidden neurons in total = alpha floats per box
     float kfirst, kconc, krelu;     // kappa*gamma_{d+2}, kappa*gamma_{d+3}, kappa*gamma_4
     double kfirst64, kconc64, krelu64;
 };
@@ -70,6 +78,13 @@ struct PropDev {
     const double* wg64;   // the folded layer in float64
     const double* bg64;
     const double* ag64;
+    // alpha mode: the property rows are relabeled like the last tile of a hidden layer (tile row
+    // 4 g + v holds property row 4 v + g), so that the adjoint needs only ceil(rows / 4) K-steps
+    const float* wgfrag_a;   // [ks_out_alloc][64] A fragments of wg with relabeled rows
+    const float* wgtfrag;    // [mt_last][ks_rows_alloc][64] fragments of wg^T
+    int ks_rows, ks_rows_alloc;
+    const float* bga;        // [16] bg by relabeled row (zero padded)
+    const float* aga;        // [16] ag by relabeled row
     float kout;           // kappa * gamma_{n_last + 3}, float32
     double kout64;        // kappa * gamma_{n_last + n_out + 3}, float64
 };
@@ -111,3 +126,52 @@ int bound_f32_supported(const NetDev& net, const PropDev& prop);
 int set_bound_variant(int v);
 int bound_variant_for(const NetDev& net, const PropDev& prop);
 size_t level_tiles(int64_t n);
+
+// ---------------------------------------------------------------------------------------------
+// Alpha mode (slr_alpha.hip): every box has its own lower slope per crossing hidden neuron.
+// ---------------------------------------------------------------------------------------------
+struct AlphaArgs {
+    int64_t n;
+    const float* lo;
+    const float* hi;
+    float* alpha;          // [n][nh]: read, or written with the plain ratios when init
+    float* g_lo;           // [n][rows] bounds of this pass (forward) / used for seeds (backward)
+    float* g_hi;
+    float* best_lo;        // optional running intersection of all passes' bounds
+    float* best_hi;
+    int8_t* cls;           // optional class from the (best) bounds
+    float* tape;           // per 16-box tile: pre-activation slots (+ 2 state slots if global)
+    int raw, init;
+    const float* dg_lo;    // backward seeds [n][rows], or NULL with obj
+    const float* dg_hi;
+    const int8_t* obj;     // [n][2] objective (mode, row) for seeds computed on the device
+    float* dalpha;         // optional [n][nh]
+    float* adam_m;         // optional fused projected Adam state [n][nh]
+    float* adam_v;
+    float lr, beta1, beta2, eps, c1, c2;
+};
+
+struct AlphaShape {
+    int nc;                // center columns per neuron (class >= d + 1)
+    int global_state;      // 1: the tile state lives in the tape's extra slots, not in LDS
+    int slots;             // tape slots per tile
+    size_t slot_floats;    // floats per slot
+    size_t lds_fwd, lds_bwd;
+};
+AlphaShape alpha_shape(const NetDev& net, const PropDev& prop);
+size_t alpha_tape_bytes(const NetDev& net, const PropDev& prop, int64_t n);
+hipError_t launch_alpha_forward(const NetDev& net, const PropDev& prop, const AlphaArgs& a,
+                                hipStream_t stream);
+hipError_t launch_alpha_backward(const NetDev& net, const PropDev& prop, const AlphaArgs& a,
+                                 hipStream_t stream);
+// obj[b][0] = 1 if every property row is > 0 at the box center, obj[b][1] = argmin row there
+// Level helpers of the alpha pass inside the exact count.
+hipError_t launch_collect_undecided(int64_t n, const int8_t* cls, unsigned* list, unsigned* count,
+                                    hipStream_t stream);
+hipError_t launch_gather_boxes(int64_t m, int d, const unsigned* list, const float* lo,
+                               const float* hi, float* lo2, float* hi2, hipStream_t stream);
+hipError_t launch_scatter_classes(int64_t m, const unsigned* list, const int8_t* cls2, int8_t* cls,
+                                  hipStream_t stream);
+hipError_t launch_center_objective(const NetDev& net, const PropDev& prop, int64_t n,
+                                   const float* lo, const float* hi, int8_t* obj,
+                                   hipStream_t stream);

@@ -21,7 +21,8 @@ UNDECIDED, UNSAFE, SAFE = 0, 1, 2
 # every entry point declared in include/slrcount.h
 EXPORTS = ("load_net", "free_net", "load_property", "free_property", "bound_boxes",
            "workspace_size", "count_exact", "count_approx", "sample_violations", "last_error",
-           "bound_kernel_variant")
+           "bound_kernel_variant", "alpha_size", "alpha_tape_size", "bound_boxes_alpha",
+           "bound_boxes_backward", "alpha_workspace_size", "alpha_optimize")
 
 
 class SlrError(RuntimeError):
@@ -35,7 +36,9 @@ class ExactOpts(C.Structure):
                 ("workspace", C.c_void_p), ("workspace_bytes", C.c_size_t),
                 ("stream", C.c_void_p), ("trace_capacity", C.c_int64),
                 ("trace_depth", C.POINTER(C.c_int32)), ("trace_path", C.POINTER(C.c_uint64)),
-                ("trace_cls", C.POINTER(C.c_int8)), ("timing", C.c_int32)]
+                ("trace_cls", C.POINTER(C.c_int8)), ("timing", C.c_int32),
+                ("alpha_steps", C.c_int32), ("alpha_lr", C.c_float),
+                ("alpha_min_depth", C.c_int32), ("alpha_chunk", C.c_int32)]
 
 
 class CountResult(C.Structure):
@@ -44,7 +47,13 @@ class CountResult(C.Structure):
                 ("n_boxes_bounded", C.c_int64), ("n_recheck64", C.c_int64),
                 ("depth_reached", C.c_int32), ("status", C.c_int32), ("seconds", C.c_double),
                 ("trace_count", C.c_int64), ("bound_ms", C.c_double),
-                ("bound_launches", C.c_int64)]
+                ("bound_launches", C.c_int64), ("n_alpha_boxes", C.c_int64),
+                ("n_alpha_decided", C.c_int64), ("alpha_ms", C.c_double)]
+
+
+class AlphaOpts(C.Structure):
+    _fields_ = [("steps", C.c_int32), ("lr", C.c_float), ("beta1", C.c_float),
+                ("beta2", C.c_float), ("eps", C.c_float), ("raw", C.c_int32)]
 
 
 class ApproxOpts(C.Structure):
@@ -80,7 +89,7 @@ def lib() -> C.CDLL:
         L.free_property.restype = None
         L.bound_boxes.argtypes = [vp, vp, i64, vp, vp, vp, vp, vp, i32, vp]
         L.bound_boxes.restype = C.c_int
-        L.workspace_size.argtypes = [vp, vp, i64, i32, C.POINTER(C.c_size_t)]
+        L.workspace_size.argtypes = [vp, vp, i64, i32, i32, C.POINTER(C.c_size_t)]
         L.workspace_size.restype = C.c_int
         L.count_exact.argtypes = [vp, vp, C.POINTER(C.c_double), C.POINTER(C.c_double),
                                   C.POINTER(ExactOpts), C.POINTER(CountResult)]
@@ -92,6 +101,21 @@ def lib() -> C.CDLL:
         L.sample_violations.restype = C.c_int
         L.bound_kernel_variant.argtypes = [i32]
         L.bound_kernel_variant.restype = C.c_int
+        sz = C.POINTER(C.c_size_t)
+        L.alpha_size.argtypes = [vp, C.POINTER(C.c_int64)]
+        L.alpha_size.restype = C.c_int
+        L.alpha_tape_size.argtypes = [vp, vp, i64, sz]
+        L.alpha_tape_size.restype = C.c_int
+        L.alpha_workspace_size.argtypes = [vp, vp, i64, sz]
+        L.alpha_workspace_size.restype = C.c_int
+        L.bound_boxes_alpha.argtypes = [vp, vp, i64, vp, vp, vp, i32, vp, vp, vp, i32, vp,
+                                        C.c_size_t, vp]
+        L.bound_boxes_alpha.restype = C.c_int
+        L.bound_boxes_backward.argtypes = [vp, vp, i64, vp, vp, C.c_size_t, vp, vp, vp, i32, vp]
+        L.bound_boxes_backward.restype = C.c_int
+        L.alpha_optimize.argtypes = [vp, vp, i64, vp, vp, C.POINTER(AlphaOpts), vp, vp, vp, vp,
+                                     vp, C.c_size_t, vp]
+        L.alpha_optimize.restype = C.c_int
         L.last_error.argtypes = []
         L.last_error.restype = C.c_char_p
         _LIB = L
@@ -197,17 +221,21 @@ def bound_kernel_variant(variant: int) -> None:
     _check(lib().bound_kernel_variant(int(variant)))
 
 
-def workspace_size(net: Net, prop: Property, max_leaves: int, samples: int = 0) -> int:
+def workspace_size(net: Net, prop: Property, max_leaves: int, samples: int = 0,
+                   alpha_chunk: int = 0) -> int:
     out = C.c_size_t()
     _check(lib().workspace_size(net.handle, prop.handle, int(max_leaves), int(samples),
-                                C.byref(out)))
+                                int(alpha_chunk), C.byref(out)))
     return out.value
 
 
 def _exact_opts(net, prop, max_depth, max_leaves, chunk, workspace, stream, samples,
-                trace_capacity=0, timing=False):
+                trace_capacity=0, timing=False, alpha_steps=0, alpha_lr=0.0, alpha_min_depth=0,
+                alpha_chunk=0):
     import torch
-    need = workspace_size(net, prop, max_leaves, samples)
+    if alpha_steps > 0 and alpha_chunk <= 0:
+        alpha_chunk = 16384
+    need = workspace_size(net, prop, max_leaves, samples, alpha_chunk if alpha_steps > 0 else 0)
     if workspace is None:
         workspace = torch.empty(need, dtype=torch.uint8, device="cuda")
     assert workspace.is_cuda
@@ -220,19 +248,29 @@ def _exact_opts(net, prop, max_depth, max_leaves, chunk, workspace, stream, samp
     o.stream = _stream(stream)
     o.trace_capacity = int(trace_capacity)
     o.timing = int(bool(timing))
+    o.alpha_steps = int(alpha_steps)
+    o.alpha_lr = float(alpha_lr)
+    o.alpha_min_depth = int(alpha_min_depth)
+    o.alpha_chunk = int(alpha_chunk)
     return o, workspace
 
 
 def count_exact(net: Net, prop: Property, lo, hi, max_depth: int, max_leaves: int,
                 chunk: int = 0, workspace=None, stream=None, trace: bool = False,
-                trace_capacity: Optional[int] = None, timing: bool = False) -> dict:
-    """Alg. 1 on the device; returns the bracket, counts and (optionally) a per-box trace."""
+                trace_capacity: Optional[int] = None, timing: bool = False,
+                alpha_steps: int = 0, alpha_lr: float = 0.1, alpha_min_depth: int = 0,
+                alpha_chunk: int = 0) -> dict:
+    """Alg. 1 on the device; returns the bracket, counts and (optionally) a per-box trace.
+
+    With ``alpha_steps`` > 0 the boxes the plain bounds leave undecided (from depth
+    ``alpha_min_depth`` on) are re-bounded with optimized lower slopes before they are split."""
     lo = np.ascontiguousarray(lo, np.float64)
     hi = np.ascontiguousarray(hi, np.float64)
     cap = 0
     if trace:
         cap = int(trace_capacity if trace_capacity is not None else 4 * max_leaves + 64)
-    o, ws = _exact_opts(net, prop, max_depth, max_leaves, chunk, workspace, stream, 0, cap, timing)
+    o, ws = _exact_opts(net, prop, max_depth, max_leaves, chunk, workspace, stream, 0, cap, timing,
+                        alpha_steps, alpha_lr, alpha_min_depth, alpha_chunk)
     if trace:
         t_depth = np.zeros(cap, np.int32)
         t_path = np.zeros(cap, np.uint64)
@@ -289,3 +327,138 @@ def sample_violations(net: Net, prop: Property, x, viol=None, stream=None):
     _check(lib().sample_violations(net.handle, prop.handle, n, x.data_ptr(), viol.data_ptr(),
                                    _stream(stream)))
     return viol
+
+
+# ---------------------------------------------------------------------------------------------
+# alpha mode
+# ---------------------------------------------------------------------------------------------
+def alpha_size(net: Net) -> int:
+    """Slopes per box: the sum of the hidden widths."""
+    out = C.c_int64()
+    _check(lib().alpha_size(net.handle, C.byref(out)))
+    return out.value
+
+
+def alpha_tape_size(net: Net, prop: Property, n: int) -> int:
+    out = C.c_size_t()
+    _check(lib().alpha_tape_size(net.handle, prop.handle, int(n), C.byref(out)))
+    return out.value
+
+
+def alpha_workspace_size(net: Net, prop: Property, n: int) -> int:
+    out = C.c_size_t()
+    _check(lib().alpha_workspace_size(net.handle, prop.handle, int(n), C.byref(out)))
+    return out.value
+
+
+def _check_boxes(net, lo, hi):
+    import torch
+    n = lo.shape[0]
+    assert lo.is_cuda and hi.is_cuda and lo.dtype == torch.float32 and hi.dtype == torch.float32
+    assert lo.is_contiguous() and hi.is_contiguous() and tuple(lo.shape) == (n, net.d)
+    assert tuple(hi.shape) == (n, net.d)
+    return n
+
+
+def _ptr(t):
+    return t.data_ptr() if t is not None else None
+
+
+def bound_boxes_alpha(net: Net, prop: Property, lo, hi, alpha=None, init: bool = False,
+                      raw: bool = False, tape=None, want_cls: bool = False, stream=None):
+    """Bounds with per-box slopes ``alpha`` (device [n, nh]); returns (g_lo, g_hi, cls, tape)."""
+    import torch
+    n = _check_boxes(net, lo, hi)
+    if alpha is not None:
+        assert alpha.is_cuda and alpha.dtype == torch.float32 and alpha.is_contiguous()
+        assert tuple(alpha.shape) == (n, alpha_size(net))
+    need = alpha_tape_size(net, prop, n)
+    if tape is None:
+        tape = torch.empty(max(need, 1), dtype=torch.uint8, device=lo.device)
+    g_lo = torch.empty((n, prop.rows), dtype=torch.float32, device=lo.device)
+    g_hi = torch.empty((n, prop.rows), dtype=torch.float32, device=lo.device)
+    cls = torch.empty((n,), dtype=torch.int8, device=lo.device) if want_cls else None
+    _check(lib().bound_boxes_alpha(net.handle, prop.handle, n, lo.data_ptr(), hi.data_ptr(),
+                                   _ptr(alpha), int(bool(init)), g_lo.data_ptr(), g_hi.data_ptr(),
+                                   _ptr(cls), int(bool(raw)), tape.data_ptr(),
+                                   tape.numel() * tape.element_size(), _stream(stream)))
+    return g_lo, g_hi, cls, tape
+
+
+def bound_boxes_backward(net: Net, prop: Property, tape, alpha, dg_lo=None, dg_hi=None,
+                         raw: bool = False, stream=None):
+    """dJ/dalpha from seeds dJ/dg_lo and dJ/dg_hi (device [n, rows]) and a forward tape."""
+    import torch
+    n = alpha.shape[0]
+    dalpha = torch.empty_like(alpha)
+    for t in (dg_lo, dg_hi):
+        if t is not None:
+            assert t.is_cuda and t.dtype == torch.float32 and t.is_contiguous()
+            assert tuple(t.shape) == (n, prop.rows)
+    _check(lib().bound_boxes_backward(net.handle, prop.handle, n, alpha.data_ptr(),
+                                      tape.data_ptr(), tape.numel() * tape.element_size(),
+                                      _ptr(dg_lo), _ptr(dg_hi), dalpha.data_ptr(),
+                                      int(bool(raw)), _stream(stream)))
+    return dalpha
+
+
+def alpha_optimize(net: Net, prop: Property, lo, hi, steps: int = 20, lr: float = 0.1,
+                   betas=(0.9, 0.999), eps: float = 1e-8, raw: bool = False, workspace=None,
+                   stream=None) -> dict:
+    """Projected Adam on per-box slopes; returns the last slopes, the intersected bounds and
+    their classes (device tensors)."""
+    import torch
+    n = _check_boxes(net, lo, hi)
+    need = alpha_workspace_size(net, prop, n)
+    if workspace is None:
+        workspace = torch.empty(max(need, 1), dtype=torch.uint8, device=lo.device)
+    alpha = torch.empty((n, alpha_size(net)), dtype=torch.float32, device=lo.device)
+    best_lo = torch.empty((n, prop.rows), dtype=torch.float32, device=lo.device)
+    best_hi = torch.empty((n, prop.rows), dtype=torch.float32, device=lo.device)
+    cls = torch.empty((n,), dtype=torch.int8, device=lo.device)
+    o = AlphaOpts(int(steps), float(lr), float(betas[0]), float(betas[1]), float(eps),
+                  int(bool(raw)))
+    _check(lib().alpha_optimize(net.handle, prop.handle, n, lo.data_ptr(), hi.data_ptr(),
+                                C.byref(o), alpha.data_ptr(), best_lo.data_ptr(),
+                                best_hi.data_ptr(), cls.data_ptr(), workspace.data_ptr(),
+                                workspace.numel() * workspace.element_size(), _stream(stream)))
+    return dict(alpha=alpha, best_lo=best_lo, best_hi=best_hi, cls=cls)
+
+
+def _make_slr_bound():
+    import torch
+
+    class SLRBound(torch.autograd.Function):
+        """(g_lo, g_hi) = SLRBound.apply(alpha, lo, hi, net, prop, raw): the bounds of every
+        property row over each box with per-box slopes; the backward pass is the library's
+        hand-written adjoint kernel (bound_boxes_backward)."""
+
+        @staticmethod
+        def forward(ctx, alpha, lo, hi, net, prop, raw=False):
+            a = alpha.detach().contiguous()
+            g_lo, g_hi, _, tape = bound_boxes_alpha(net, prop, lo, hi, a, raw=raw)
+            ctx.net, ctx.prop, ctx.raw = net, prop, raw
+            ctx.save_for_backward(a, tape)
+            return g_lo, g_hi
+
+        @staticmethod
+        def backward(ctx, dg_lo, dg_hi):
+            a, tape = ctx.saved_tensors
+            dlo = dg_lo.contiguous() if dg_lo is not None else None
+            dhi = dg_hi.contiguous() if dg_hi is not None else None
+            da = bound_boxes_backward(ctx.net, ctx.prop, tape, a, dlo, dhi, raw=ctx.raw)
+            return da, None, None, None, None, None
+
+    return SLRBound
+
+
+_SLRBOUND = None
+
+
+def __getattr__(name):
+    global _SLRBOUND
+    if name == "SLRBound":
+        if _SLRBOUND is None:
+            _SLRBOUND = _make_slr_bound()
+        return _SLRBOUND
+    raise AttributeError(name)

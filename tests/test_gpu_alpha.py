@@ -1,0 +1,282 @@
+"""Alpha mode (optimized lower slopes) on the GPU against the FP64 oracle, through the C ABI.
+
+* raw (unwidened) bounds with the same slopes agree with the oracle within 1e-5 of the row's
+  interval magnitude; with init the slopes written are the plain ratios and the bounds the plain
+  relaxation;
+* widened bounds with fixed slopes contain the oracle's bounds: with equal lower slopes every
+  widened concrete bound only widens the chord and the equations, so the float32 result must be
+  looser than the exact relaxation, which the oracle brackets within ~1e-13;
+* the hand-written adjoint agrees with autograd of the oracle's float64 torch forward (itself
+  pinned to central differences) on boxes away from phase switches and sign changes;
+* projected Adam never ends looser than the plain relaxation and its bounds stay sound;
+* the exact count with alpha returns a bracket inside the plain oracle bracket at the same depth.
+"""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import alpha as oalpha
+from oracle import count, slr
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-5
+
+
+def E():
+    import paper_2312_05890_amd as eng
+    return eng
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a, np.float32)).cuda()
+
+
+def load(inst):
+    eng = E()
+    net = eng.Net(inst.net)
+    return net, eng.Property(net, inst.C, inst.dvec)
+
+
+# (instance, number of boxes, box width scale): d = 2, 5, 22 (state in the tape) and the
+# 20-input 4 x 256 network (state in the tape, 16 tiles per layer)
+CASES = [("tiny2d", 40, 0.5), ("acas", 64, 0.2), ("nav22", 24, 0.05), ("wide20", 12, 0.02)]
+
+
+def make(name, n, scale, seed=0):
+    inst = getattr(synth, name)(seed)
+    lo, hi = synth.uniform_boxes(inst.lo, inst.hi, n, seed + 7, scale)
+    return inst, lo, hi
+
+
+def scale_of(g_lo, g_hi):
+    return np.maximum(1.0, np.maximum(np.abs(g_lo), np.abs(g_hi)))
+
+
+def rand_alpha(net, n, seed, a=0.0, b=1.0):
+    nh = E().alpha_size(net)
+    return np.random.default_rng(seed).uniform(a, b, size=(n, nh)).astype(np.float32)
+
+
+@pytest.mark.parametrize("name,n,scale", CASES, ids=[c[0] for c in CASES])
+def test_raw_bounds_match_oracle(name, n, scale):
+    inst, lo, hi = make(name, n, scale)
+    net, prop = load(inst)
+    al = rand_alpha(net, n, 1)
+    g_lo, g_hi, _, _ = E().bound_boxes_alpha(net, prop, dev(lo), dev(hi), dev(al), raw=True)
+    o_lo, o_hi = slr.propagate(inst.net, inst.C, inst.dvec, lo, hi, alpha=al)
+    s = scale_of(o_lo, o_hi)
+    assert np.all(np.abs(g_lo.cpu().numpy() - o_lo) <= TOL * s)
+    assert np.all(np.abs(g_hi.cpu().numpy() - o_hi) <= TOL * s)
+
+
+@pytest.mark.parametrize("name,n,scale", CASES, ids=[c[0] for c in CASES])
+def test_init_is_plain_relaxation(name, n, scale):
+    inst, lo, hi = make(name, n, scale, seed=2)
+    net, prop = load(inst)
+    al = torch.zeros((n, E().alpha_size(net)), dtype=torch.float32, device="cuda")
+    g_lo, g_hi, _, _ = E().bound_boxes_alpha(net, prop, dev(lo), dev(hi), al, init=True, raw=True)
+    o_lo, o_hi = slr.propagate(inst.net, inst.C, inst.dvec, lo, hi)
+    s = scale_of(o_lo, o_hi)
+    assert np.all(np.abs(g_lo.cpu().numpy() - o_lo) <= TOL * s)
+    assert np.all(np.abs(g_hi.cpu().numpy() - o_hi) <= TOL * s)
+    # the slopes written are the plain ratios wherever the phase is not borderline
+    lam = oalpha.plain_lambda(inst.net, inst.C, inst.dvec, lo, hi)
+    _, _, tr = slr.propagate(inst.net, inst.C, inst.dvec, lo, hi, keep=True)
+    robust = np.hstack([np.minimum(np.abs(t["lo"]), np.abs(t["hi"])) >
+                        1e-4 * np.maximum(1.0, np.abs(t["lo"]) + np.abs(t["hi"])) for t in tr])
+    a = al.cpu().numpy()
+    assert np.all(np.abs(a - lam)[robust] <= 1e-4)
+    # the same boxes without slopes (plain relaxation)
+    p_lo, p_hi, _, _ = E().bound_boxes_alpha(net, prop, dev(lo), dev(hi), None, raw=True)
+    assert np.all(np.abs(p_lo.cpu().numpy() - o_lo) <= TOL * s)
+    assert np.all(np.abs(p_hi.cpu().numpy() - o_hi) <= TOL * s)
+
+
+@pytest.mark.parametrize("name,n,scale", CASES, ids=[c[0] for c in CASES])
+def test_widened_bounds_contain_oracle(name, n, scale):
+    inst, lo, hi = make(name, n, scale, seed=3)
+    net, prop = load(inst)
+    al = rand_alpha(net, n, 4)
+    g_lo, g_hi, cls, _ = E().bound_boxes_alpha(net, prop, dev(lo), dev(hi), dev(al), want_cls=True)
+    g_lo, g_hi, cls = g_lo.cpu().numpy(), g_hi.cpu().numpy(), cls.cpu().numpy()
+    o_lo, o_hi = slr.propagate(inst.net, inst.C, inst.dvec, lo, hi, alpha=al)
+    slack = 1e-9 * scale_of(o_lo, o_hi)
+    assert np.all(g_lo <= o_lo + slack)
+    assert np.all(g_hi >= o_hi - slack)
+    # classes follow the widened bounds and agree with sampled values
+    expect = np.where(np.all(g_lo > 0, 1), 1, np.where(np.any(g_hi <= 0, 1), 2, 0))
+    assert np.array_equal(cls, expect)
+    rng = np.random.default_rng(5)
+    for b in range(min(n, 8)):
+        x = slr.sample_points(lo[b], hi[b], 500, rng, include_vertices=inst.sizes[0] <= 8)
+        gv = slr.property_values(inst.net, inst.C, inst.dvec, x)
+        assert np.all(g_lo[b] <= gv.min(0)) and np.all(gv.max(0) <= g_hi[b])
+
+
+def robust_boxes(inst, lo, hi, al, tol=1e-4):
+    """Boxes whose oracle propagation has no neuron near a phase switch and no coefficient of a
+    crossing neuron's equations near a sign change (the adjoint is piecewise)."""
+    _, _, tr = slr.propagate(inst.net, inst.C, inst.dvec, lo, hi, alpha=al, keep=True)
+    ok = np.ones(lo.shape[0], bool)
+    for t in tr:
+        mag = np.maximum(1.0, np.abs(t["lo"]) + np.abs(t["hi"]))
+        ok &= np.all(np.minimum(np.abs(t["lo"]), np.abs(t["hi"])) > tol * mag, axis=1)
+        cross = (t["lo"] < 0) & (t["hi"] > 0)
+        for E_ in (t["L"], t["U"]):
+            c = np.abs(E_[..., 1:])
+            near = (c > 0) & (c < tol * c.max(axis=2, keepdims=True))
+            ok &= ~np.any(near & cross[..., None], axis=(1, 2))
+    return ok
+
+
+@pytest.mark.parametrize("name,n,scale", CASES, ids=[c[0] for c in CASES])
+def test_adjoint_matches_oracle_autograd(name, n, scale):
+    inst, lo, hi = make(name, n, scale, seed=6)
+    net, prop = load(inst)
+    al = rand_alpha(net, n, 7, 0.05, 0.95)
+    mode, row = oalpha.objective_weights(inst.net, inst.C, inst.dvec, lo, hi)
+    o_lo, o_hi = slr.propagate(inst.net, inst.C, inst.dvec, lo, hi, alpha=al)
+    rows = inst.C.shape[0]
+    dlo = np.zeros((n, rows), np.float32)
+    dhi = np.zeros((n, rows), np.float32)
+    rstar = np.argmin(o_lo, axis=1)
+    for b in range(n):
+        if mode[b] == 1:
+            dlo[b, rstar[b]] = -1.0
+        else:
+            dhi[b, row[b]] = 1.0
+    eng = E()
+    a = dev(al)
+    _, _, _, tape = eng.bound_boxes_alpha(net, prop, dev(lo), dev(hi), a, raw=True)
+    ga = eng.bound_boxes_backward(net, prop, tape, a, dev(dlo), dev(dhi), raw=True).cpu().numpy()
+    go = oalpha.gradient(inst.net, inst.C, inst.dvec, lo, hi, al)
+    ok = robust_boxes(inst, lo, hi, al)
+    # the oracle's seeds use its own argmin of g_lo: ties between rows are not robust either
+    if rows > 1:
+        srt = np.sort(o_lo, axis=1)
+        ok &= (mode == 0) | (srt[:, 1] - srt[:, 0] > 1e-4 * scale_of(o_lo, o_hi).max(1))
+    assert ok.sum() >= max(2, n // 4), f"only {ok.sum()} robust boxes"
+    s = np.maximum(1e-3, np.abs(go).max(axis=1, keepdims=True))
+    err = np.abs(ga - go) / s
+    assert np.all(err[ok] <= 2e-3), f"max scaled error {err[ok].max():.3g}"
+
+
+def test_slrbound_autograd_function():
+    inst, lo, hi = make("acas", 32, 0.2, seed=8)
+    net, prop = load(inst)
+    eng = E()
+    al = dev(rand_alpha(net, 32, 9)).requires_grad_(True)
+    g_lo, g_hi = eng.SLRBound.apply(al, dev(lo), dev(hi), net, prop, True)
+    w_lo = torch.randn_like(g_lo)
+    w_hi = torch.randn_like(g_hi)
+    ((g_lo * w_lo).sum() + (g_hi * w_hi).sum()).backward()
+    _, _, _, tape = eng.bound_boxes_alpha(net, prop, dev(lo), dev(hi), al.detach(), raw=True)
+    ref = eng.bound_boxes_backward(net, prop, tape, al.detach(), w_lo.contiguous(),
+                                   w_hi.contiguous(), raw=True)
+    assert torch.equal(al.grad, ref)
+
+
+@pytest.mark.parametrize("name,n,scale", [("acas", 64, 0.2), ("wide20", 12, 0.02)],
+                         ids=["acas", "wide20"])
+def test_optimize_tightens_and_stays_sound(name, n, scale):
+    inst, lo, hi = make(name, n, scale, seed=10)
+    net, prop = load(inst)
+    eng = E()
+    r = eng.alpha_optimize(net, prop, dev(lo), dev(hi), steps=20)
+    b_lo, b_hi = r["best_lo"].cpu().numpy(), r["best_hi"].cpu().numpy()
+    cls = r["cls"].cpu().numpy()
+    p_lo, p_hi, _, _ = eng.bound_boxes_alpha(net, prop, dev(lo), dev(hi), None)
+    p_lo, p_hi = p_lo.cpu().numpy(), p_hi.cpu().numpy()
+    assert np.all(b_lo >= p_lo) and np.all(b_hi <= p_hi)
+    mode, row = oalpha.objective_weights(inst.net, inst.C, inst.dvec, lo, hi)
+    j_plain = np.where(mode == 1, -p_lo.min(1), p_hi[np.arange(n), row])
+    j_best = np.where(mode == 1, -b_lo.min(1), b_hi[np.arange(n), row])
+    assert np.mean(j_best < j_plain - 1e-6 * np.abs(j_plain)) > 0.2
+    expect = np.where(np.all(b_lo > 0, 1), 1, np.where(np.any(b_hi <= 0, 1), 2, 0))
+    assert np.array_equal(cls, expect)
+    rng = np.random.default_rng(11)
+    for b in range(min(n, 8)):
+        x = slr.sample_points(lo[b], hi[b], 500, rng, include_vertices=inst.sizes[0] <= 8)
+        gv = slr.property_values(inst.net, inst.C, inst.dvec, x)
+        assert np.all(b_lo[b] <= gv.min(0)) and np.all(gv.max(0) <= b_hi[b])
+    a = r["alpha"].cpu().numpy()
+    assert np.all((a >= 0) & (a <= 1))
+
+
+def test_optimize_close_to_oracle_adam():
+    """Same objective and optimizer as the float64 reference: the optimized objective values
+    land close to the reference's (trajectories are not expected to match bit for bit)."""
+    inst, lo, hi = make("acas", 16, 0.2, seed=12)
+    net, prop = load(inst)
+    r = E().alpha_optimize(net, prop, dev(lo), dev(hi), steps=20, raw=True)
+    mode, row = oalpha.objective_weights(inst.net, inst.C, inst.dvec, lo, hi)
+    b_lo, b_hi = r["best_lo"].cpu().numpy(), r["best_hi"].cpu().numpy()
+    j_gpu = np.where(mode == 1, -b_lo.min(1), b_hi[np.arange(16), row])
+    _, j_ref = oalpha.optimize(inst.net, inst.C, inst.dvec, lo, hi, steps=20)
+    lam = oalpha.plain_lambda(inst.net, inst.C, inst.dvec, lo, hi)
+    j_plain = oalpha.objective(inst.net, inst.C, inst.dvec, lo, hi, lam)
+    gain_ref = j_plain - j_ref
+    gain_gpu = j_plain - j_gpu
+    assert np.all(gain_gpu >= -1e-4 * np.maximum(1, np.abs(j_plain)))
+    assert gain_gpu.sum() >= 0.5 * gain_ref.sum()
+
+
+@pytest.mark.parametrize("n", [0, 1, 17, 33])
+def test_ragged_batches(n):
+    inst, lo, hi = make("acas", max(n, 1), 0.2, seed=13)
+    lo, hi = lo[:n], hi[:n]
+    net, prop = load(inst)
+    eng = E()
+    al = rand_alpha(net, n, 14)
+    g_lo, g_hi, _, tape = eng.bound_boxes_alpha(net, prop, dev(lo).reshape(n, 5),
+                                                dev(hi).reshape(n, 5), dev(al), raw=True)
+    if n == 0:
+        return
+    o_lo, o_hi = slr.propagate(inst.net, inst.C, inst.dvec, lo, hi, alpha=al)
+    s = scale_of(o_lo, o_hi)
+    assert np.all(np.abs(g_lo.cpu().numpy() - o_lo) <= TOL * s)
+    assert np.all(np.abs(g_hi.cpu().numpy() - o_hi) <= TOL * s)
+
+
+def test_rejects_small_tape():
+    inst, lo, hi = make("acas", 32, 0.2)
+    net, prop = load(inst)
+    eng = E()
+    tape = torch.empty(16, dtype=torch.uint8, device="cuda")
+    with pytest.raises(eng.SlrError) as e:
+        eng.bound_boxes_alpha(net, prop, dev(lo), dev(hi), None, tape=tape)
+    assert e.value.code == -2
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_count_exact_alpha_bracket_inside_plain(seed):
+    inst = synth.tiny2d(seed)
+    net, prop = load(inst)
+    D = 10
+    r = E().count_exact(net, prop, inst.lo, inst.hi, D, 1 << 16, alpha_steps=20, alpha_chunk=256)
+    o = count.count_exact(inst.net, inst.C, inst.dvec, inst.lo, inst.hi, D, 1 << 16)
+    assert abs(r["unsafe"] + r["safe"] + r["undecided"] - 1.0) == 0.0
+    assert r["unsafe"] >= o["unsafe"] - 1e-12
+    assert r["unsafe"] + r["undecided"] <= o["unsafe"] + o["undecided"] + 1e-12
+    assert r["n_alpha_boxes"] > 0
+
+
+def test_count_exact_alpha_acas():
+    """The 6 x 50 network: boxes decide only from depth ~20 on (bounds are ~1e2 wide before);
+    alpha then decides some of the boxes the plain bounds leave open, and the bracket tightens."""
+    inst = synth.acas(0)
+    net, prop = load(inst)
+    D, M = 20, 1 << 20
+    eng = E()
+    p = eng.count_exact(net, prop, inst.lo, inst.hi, D, M)
+    a = eng.count_exact(net, prop, inst.lo, inst.hi, D, M, alpha_steps=20, alpha_chunk=16384,
+                        alpha_min_depth=16)
+    assert p["depth_reached"] == D and a["depth_reached"] == D
+    assert a["unsafe"] >= p["unsafe"] and a["safe"] >= p["safe"]
+    assert a["unsafe"] + a["safe"] + a["undecided"] == 1.0
+    assert a["n_alpha_decided"] > 0
+    assert a["n_boxes_bounded"] <= p["n_boxes_bounded"]

@@ -76,5 +76,5 @@ def test_calls_reject_null_handles(eng):
     assert L.bound_boxes(None, None, 0, None, None, None, None, None, 0, None) == -1
     assert L.count_approx(None, None, lo, hi, None, None) == -1
     out = C.c_size_t()
-    assert L.workspace_size(None, None, 10, 0, C.byref(out)) == -1
+    assert L.workspace_size(None, None, 10, 0, 0, C.byref(out)) == -1
     assert "net is NULL" in eng.last_error()
