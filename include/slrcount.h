@@ -90,10 +90,15 @@ int bound_boxes(const slr_net* net, const slr_property* prop, int64_t n, const f
 
 /*
  * bound_kernel_variant: process-wide choice of the bound kernel.
- *   0  automatic (default): currently the LDS-staged kernel, which measured faster;
+ *   0  automatic (default): the LDS-staged kernel where the shape fits its 160 KiB tiles, else
+ *      (count_exact / count_approx only) the tape-state kernel of the alpha mode with the plain
+ *      slopes, whose near-threshold boxes are re-decided in FP64 like the others';
  *   1  always the LDS-staged kernel;
- *   2  the register-resident kernel (shapes it cannot take then fail with SLR_EUNSUPPORTED).
- * Both kernels compute the same bounds.  Not synchronized with calls in flight on other threads.
+ *   2  the register-resident kernel (shapes it cannot take then fail with SLR_EUNSUPPORTED);
+ *   3  the tape-state kernel for every shape (count_exact / count_approx; bound_boxes then
+ *      fails with SLR_EUNSUPPORTED).
+ * All compute the same bounds up to float32 rounding.  Not synchronized with calls in flight
+ * on other threads.
  */
 int bound_kernel_variant(int32_t variant);
 

@@ -355,7 +355,7 @@ __global__ __launch_bounds__(kNW * 64) void alpha_fwd_kernel(NetDev net, PropDev
     float* part;
     f32x4* S;
     if constexpr (GS) {
-        S = tape + (size_t)(H + 1) * slot;
+        S = tape + (size_t)(A.fwd_only ? 1 : H + 1) * slot;
         part = lds;
     } else {
         S = reinterpret_cast<f32x4*>(lds);
@@ -421,7 +421,7 @@ __global__ __launch_bounds__(kNW * 64) void alpha_fwd_kernel(NetDev net, PropDev
     int rp = 0, mt_prev = net.mt1;
     for (int l = 0; l < H - 1; ++l) {
         const MidLayer& L = net.mid[l];
-        f32x4* pre = tape + (size_t)(l + 1) * slot;
+        f32x4* pre = tape + (size_t)(A.fwd_only ? 0 : l + 1) * slot;
         const int units = L.mt_out * G::NG;
         for (int u = wave; u < units; u += kNW)
             contract_unit<NC>(L.wfrag, L.ks, L.ks_alloc, u / G::NG, u % G::NG, S, pre, mtS, L.bias, lane);
@@ -450,7 +450,7 @@ __global__ __launch_bounds__(kNW * 64) void alpha_fwd_kernel(NetDev net, PropDev
     }
 
     // ---- property rows (folded last layer), concretized; tile row 4 g + v is row 4 v + g
-    f32x4* pre = tape + (size_t)H * slot;
+    f32x4* pre = tape + (size_t)(A.fwd_only ? 0 : H) * slot;
     for (int u = wave; u < G::NG; u += kNW)
         contract_unit<NC>(prop.wgfrag_a, prop.ks_out, prop.ks_out_alloc, 0, u, S, pre, mtS, prop.bga, lane);
     __syncthreads();
@@ -715,6 +715,35 @@ __global__ __launch_bounds__(256) void scatter_kernel(int64_t m, const unsigned*
     if (i < m && cls2[i] != 0) cls[list[i]] = cls2[i];
 }
 
+// Plain bounds from the tape-state kernel (shapes the LDS bound kernel cannot hold): boxes whose
+// widened bounds leave them undecided but within twice the widening (plus 2^-14 of the row's
+// magnitude) of a decision are marked 3 and listed for the FP64 re-decision, as the LDS kernel
+// does from its rounding-margin column.
+__global__ __launch_bounds__(256) void ambiguity_kernel(int64_t n, int rows,
+                                                       const float* __restrict__ wlo,
+                                                       const float* __restrict__ whi,
+                                                       const float* __restrict__ rlo,
+                                                       const float* __restrict__ rhi,
+                                                       int8_t* __restrict__ cls,
+                                                       unsigned* __restrict__ amb_list,
+                                                       unsigned* __restrict__ amb_count,
+                                                       unsigned base) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= n || cls[i] != 0) return;
+    bool au = true, as = false;
+    for (int r = 0; r < rows; ++r) {
+        const size_t o = (size_t)i * rows + r;
+        const float lo = wlo[o], hi = whi[o];
+        const float t = 2.f * fmaxf(rlo[o] - lo, hi - rhi[o]) + 0x1p-14f * fmaxf(fabsf(lo), fabsf(hi));
+        au = au && lo + t > 0.f;
+        as = as || hi - t <= 0.f;
+    }
+    if (au || as) {
+        cls[i] = 3;
+        if (amb_list) amb_list[atomicAdd(amb_count, 1u)] = base + (unsigned)i;
+    }
+}
+
 int nc_class(int d) {
     const int need = d + 1;
     const int cls[] = {3, 4, 6, 8, 11, 14, 17, 21, 25, 33};
@@ -736,16 +765,17 @@ template <int NC>
 hipError_t launch_fwd_nc(const NetDev& net, const PropDev& prop, const AlphaArgs& a,
                          const AlphaShape& sh, hipStream_t stream) {
     const int64_t blocks = (a.n + 15) / 16;
+    const int slots = a.fwd_only ? sh.slots_fwd : sh.slots;
     (void)hipGetLastError();
     if (sh.global_state) {
         auto kern = alpha_fwd_kernel<NC, true>;
-        hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(kNW * 64), sh.lds_fwd, stream, net, prop, a, sh.slots);
+        hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(kNW * 64), sh.lds_fwd, stream, net, prop, a, slots);
     } else {
         if constexpr (NC <= 11) {
             auto kern = alpha_fwd_kernel<NC, false>;
             hipError_t e = allow_lds_a((const void*)kern, sh.lds_fwd);
             if (e != hipSuccess) return e;
-            hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(kNW * 64), sh.lds_fwd, stream, net, prop, a, sh.slots);
+            hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(kNW * 64), sh.lds_fwd, stream, net, prop, a, slots);
         } else {
             return hipErrorInvalidValue;
         }
@@ -786,13 +816,14 @@ AlphaShape alpha_shape(const NetDev& net, const PropDev& prop) {
     s.lds_fwd = s.global_state ? part : st + part;
     s.lds_bwd = s.global_state ? 0 : 2 * st;
     s.slots = (net.n_affine - 1) + 1 + (s.global_state ? 2 : 0);
+    s.slots_fwd = 1 + (s.global_state ? 1 : 0);
     s.slot_floats = (size_t)(2 * s.nc + 2) * net.mt_max * 256;
     return s;
 }
 
-size_t alpha_tape_bytes(const NetDev& net, const PropDev& prop, int64_t n) {
+size_t alpha_tape_bytes(const NetDev& net, const PropDev& prop, int64_t n, int fwd_only) {
     const AlphaShape s = alpha_shape(net, prop);
-    return sizeof(float) * (size_t)((n + 15) / 16) * s.slots * s.slot_floats;
+    return sizeof(float) * (size_t)((n + 15) / 16) * (fwd_only ? s.slots_fwd : s.slots) * s.slot_floats;
 }
 
 #define SLR_ALPHA_NC(X) X(3) X(4) X(6) X(8) X(11) X(14) X(17) X(21) X(25) X(33)
@@ -856,5 +887,15 @@ hipError_t launch_scatter_classes(int64_t m, const unsigned* list, const int8_t*
     (void)hipGetLastError();
     hipLaunchKernelGGL(scatter_kernel, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, stream, m,
                        list, cls2, cls);
+    return hipGetLastError();
+}
+
+hipError_t launch_ambiguity(int64_t n, int rows, const float* wlo, const float* whi,
+                            const float* rlo, const float* rhi, int8_t* cls, unsigned* amb_list,
+                            unsigned* amb_count, unsigned base, hipStream_t stream) {
+    if (n <= 0) return hipSuccess;
+    (void)hipGetLastError();
+    hipLaunchKernelGGL(ambiguity_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream, n,
+                       rows, wlo, whi, rlo, rhi, cls, amb_list, amb_count, base);
     return hipGetLastError();
 }

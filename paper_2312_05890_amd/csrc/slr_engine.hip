@@ -500,6 +500,11 @@ struct Workspace {
     int8_t* acls;                // [achunk]
     char* aws;                   // alpha_optimize workspace for achunk boxes
     size_t aws_bytes;
+    // shapes the LDS bound kernel cannot hold: plain bounds from the tape-state kernel in
+    // batches of wchunk boxes (forward-only tape, widened and raw bounds)
+    int64_t wchunk;
+    float* wtape;
+    float *wlo, *whi, *rlo, *rhi;   // [wchunk][rows]
     size_t bytes;
 };
 
@@ -522,7 +527,7 @@ AlphaWs layout_alpha(char* base, const NetDev& nd, const PropDev& pd, int64_t n)
         o += align256(bytes);
         return p;
     };
-    w.tape_bytes = alpha_tape_bytes(nd, pd, n);
+    w.tape_bytes = alpha_tape_bytes(nd, pd, n, 0);
     w.tape = (float*)take(w.tape_bytes);
     w.m = (float*)take(sizeof(float) * (size_t)n * nd.nh);
     w.v = (float*)take(sizeof(float) * (size_t)n * nd.nh);
@@ -560,6 +565,15 @@ Workspace layout_ws(char* base, const NetDev& nd, const PropDev& pd, int64_t cap
     w.err = (unsigned*)take(sizeof(unsigned));
     w.samples = (float*)take(sizeof(float) * (size_t)d * std::max(samples, 0));
     w.viol = (int8_t*)take(std::max(samples, 0));
+    w.wchunk = 0;
+    if (!bound_f32_supported(nd, pd) && pd.rows > 0) {
+        w.wchunk = std::min<int64_t>(cap, 4096);
+        w.wtape = (float*)take(alpha_tape_bytes(nd, pd, w.wchunk, 1));
+        w.wlo = (float*)take(sizeof(float) * pd.rows * w.wchunk);
+        w.whi = (float*)take(sizeof(float) * pd.rows * w.wchunk);
+        w.rlo = (float*)take(sizeof(float) * pd.rows * w.wchunk);
+        w.rhi = (float*)take(sizeof(float) * pd.rows * w.wchunk);
+    }
     w.achunk = achunk;
     if (achunk > 0) {
         w.alo = (float*)take(sizeof(float) * d * achunk);
@@ -574,12 +588,15 @@ Workspace layout_ws(char* base, const NetDev& nd, const PropDev& pd, int64_t cap
     return w;
 }
 
-int check_pair(const slr_net* net, const slr_property* prop, const char* who) {
+// need_lds: the call runs the LDS bound kernel itself (otherwise wide shapes take the
+// tape-state kernel)
+int check_pair(const slr_net* net, const slr_property* prop, const char* who, bool need_lds = false) {
     if (!net) return fail(SLR_EINVAL, "%s: net is NULL", who);
     if (!prop) return fail(SLR_EINVAL, "%s: property is NULL", who);
     if (prop->net != net) return fail(SLR_EINVAL, "%s: property was loaded for another net", who);
-    if (!bound_f32_supported(net->dev, prop->dev))
-        return fail(SLR_EUNSUPPORTED, "%s: network shape (d=%d, widths up to %d) exceeds this build's LDS tiles", who, net->dev.d, net->dev.n_max);
+    if (need_lds && !bound_f32_supported(net->dev, prop->dev))
+        return fail(SLR_EUNSUPPORTED, "%s: network shape (d=%d, widths up to %d) exceeds the LDS bound kernel; "
+                    "use bound_boxes_alpha (alpha = NULL) or count_exact", who, net->dev.d, net->dev.n_max);
     return SLR_OK;
 }
 
@@ -623,7 +640,7 @@ extern "C" int bound_boxes(const slr_net* net, const slr_property* prop, int64_t
                            const float* lo, const float* hi, float* g_lo, float* g_hi,
                            int8_t* cls, int32_t raw, void* stream) {
     g_err.clear();
-    int rc = check_pair(net, prop, "bound_boxes");
+    int rc = check_pair(net, prop, "bound_boxes", true);
     if (rc) return rc;
     if (n < 0) return fail(SLR_EINVAL, "bound_boxes: n < 0");
     if (raw != 0 && raw != 1) return fail(SLR_EINVAL, "bound_boxes: raw must be 0 or 1");
@@ -730,7 +747,7 @@ extern "C" int alpha_tape_size(const slr_net* net, const slr_property* prop, int
     int rc = check_alpha_pair(net, prop, "alpha_tape_size");
     if (rc) return rc;
     if (!bytes || n < 0) return fail(SLR_EINVAL, "alpha_tape_size: bad argument");
-    *bytes = alpha_tape_bytes(net->dev, prop->dev, n);
+    *bytes = alpha_tape_bytes(net->dev, prop->dev, n, 0);
     return SLR_OK;
 }
 
@@ -758,7 +775,7 @@ extern "C" int bound_boxes_alpha(const slr_net* net, const slr_property* prop, i
         return fail(SLR_EINVAL, "bound_boxes_alpha: lo, hi, g_lo and g_hi must be device memory");
     if ((alpha && !is_device_ptr(alpha)) || (cls && !is_device_ptr(cls)))
         return fail(SLR_EINVAL, "bound_boxes_alpha: alpha and cls must be device memory");
-    const size_t need = alpha_tape_bytes(net->dev, prop->dev, n);
+    const size_t need = alpha_tape_bytes(net->dev, prop->dev, n, 0);
     if (!tape || tape_bytes < need)
         return fail(SLR_ENOMEM, "bound_boxes_alpha: tape of %zu bytes is smaller than the %zu required", tape_bytes, need);
     if (!is_device_ptr(tape)) return fail(SLR_EINVAL, "bound_boxes_alpha: tape must be device memory");
@@ -790,7 +807,7 @@ extern "C" int bound_boxes_backward(const slr_net* net, const slr_property* prop
     if (!is_device_ptr(dalpha)) return fail(SLR_EINVAL, "bound_boxes_backward: dalpha must be device memory");
     if ((alpha && !is_device_ptr(alpha)) || (dg_lo && !is_device_ptr(dg_lo)) || (dg_hi && !is_device_ptr(dg_hi)))
         return fail(SLR_EINVAL, "bound_boxes_backward: alpha, dg_lo and dg_hi must be device memory");
-    const size_t need = alpha_tape_bytes(net->dev, prop->dev, n);
+    const size_t need = alpha_tape_bytes(net->dev, prop->dev, n, 0);
     if (!tape || tape_bytes < need)
         return fail(SLR_ENOMEM, "bound_boxes_backward: tape of %zu bytes is smaller than the %zu required", tape_bytes, need);
     if (!is_device_ptr(tape)) return fail(SLR_EINVAL, "bound_boxes_backward: tape must be device memory");
@@ -878,14 +895,41 @@ int count_exact_impl(const slr_net* net, const slr_property* prop, const double*
         int unsup = 0;
         HIP_TRY(hipMemsetAsync(w.amb_count, 0, sizeof(unsigned), s), "count_exact: clear");
         if (ev0) HIP_TRY(hipEventRecord(ev0, s), "count_exact: event");
-        for (int64_t off = 0; off < n; off += chunk) {
-            const int64_t m = std::min(chunk, n - off);
-            HIP_TRY(launch_bound_f32(net->dev, prop->dev, m, w.lo[cur] + off * d, w.hi[cur] + off * d,
-                                     nullptr, nullptr, w.cls + off, 0, s, &unsup, w.amb_list,
-                                     w.amb_count, (unsigned)off),
-                    "count_exact: bound kernel");
-            if (unsup) return fail(SLR_EUNSUPPORTED, "count_exact: shape not supported");
-            ++launches;
+        if (w.wchunk > 0) {
+            // tape-state kernel with the plain slopes: widened bounds classify, raw bounds
+            // locate the boxes near a decision for the FP64 re-decision
+            for (int64_t off = 0; off < n; off += w.wchunk) {
+                const int64_t m = std::min(w.wchunk, n - off);
+                AlphaArgs a{};
+                a.n = m;
+                a.lo = w.lo[cur] + off * d;
+                a.hi = w.hi[cur] + off * d;
+                a.tape = w.wtape;
+                a.fwd_only = 1;
+                a.g_lo = w.wlo;
+                a.g_hi = w.whi;
+                a.cls = w.cls + off;
+                HIP_TRY(launch_alpha_forward(net->dev, prop->dev, a, s), "count_exact: bound kernel");
+                a.raw = 1;
+                a.g_lo = w.rlo;
+                a.g_hi = w.rhi;
+                a.cls = nullptr;
+                HIP_TRY(launch_alpha_forward(net->dev, prop->dev, a, s), "count_exact: bound kernel");
+                HIP_TRY(launch_ambiguity(m, prop->dev.rows, w.wlo, w.whi, w.rlo, w.rhi, w.cls + off,
+                                         w.amb_list, w.amb_count, (unsigned)off, s),
+                        "count_exact: ambiguity kernel");
+                launches += 2;
+            }
+        } else {
+            for (int64_t off = 0; off < n; off += chunk) {
+                const int64_t m = std::min(chunk, n - off);
+                HIP_TRY(launch_bound_f32(net->dev, prop->dev, m, w.lo[cur] + off * d, w.hi[cur] + off * d,
+                                         nullptr, nullptr, w.cls + off, 0, s, &unsup, w.amb_list,
+                                         w.amb_count, (unsigned)off),
+                        "count_exact: bound kernel");
+                if (unsup) return fail(SLR_EUNSUPPORTED, "count_exact: shape not supported");
+                ++launches;
+            }
         }
         if (ev1) {
             HIP_TRY(hipEventRecord(ev1, s), "count_exact: event");

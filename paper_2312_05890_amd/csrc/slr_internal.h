@@ -121,8 +121,9 @@ hipError_t launch_volume(const LevelStats* stats, int levels, int stop_level, in
 hipError_t launch_sample_forward(const NetDev& net, const PropDev& prop, int64_t n,
                                  const float* x, int8_t* viol, hipStream_t stream);
 int bound_f32_supported(const NetDev& net, const PropDev& prop);
-// Bound-kernel variant: 0 automatic (register-resident where it fits), 1 LDS-staged,
-// 2 register-resident only.  Returns -1 for an unknown value.
+// Bound-kernel variant: 0 automatic, 1 LDS-staged, 2 register-resident only, 3 none (the exact
+// count then bounds with the tape-state kernel, as for shapes the LDS kernel cannot hold).
+// Returns -1 for an unknown value.
 int set_bound_variant(int v);
 int bound_variant_for(const NetDev& net, const PropDev& prop);
 size_t level_tiles(int64_t n);
@@ -142,6 +143,7 @@ struct AlphaArgs {
     int8_t* cls;           // optional class from the (best) bounds
     float* tape;           // per 16-box tile: pre-activation slots (+ 2 state slots if global)
     int raw, init;
+    int fwd_only;          // forward pass only: one shared pre-activation slot per tile
     const float* dg_lo;    // backward seeds [n][rows], or NULL with obj
     const float* dg_hi;
     const int8_t* obj;     // [n][2] objective (mode, row) for seeds computed on the device
@@ -155,11 +157,12 @@ struct AlphaShape {
     int nc;                // center columns per neuron (class >= d + 1)
     int global_state;      // 1: the tile state lives in the tape's extra slots, not in LDS
     int slots;             // tape slots per tile
+    int slots_fwd;         // tape slots per tile of a forward-only pass
     size_t slot_floats;    // floats per slot
     size_t lds_fwd, lds_bwd;
 };
 AlphaShape alpha_shape(const NetDev& net, const PropDev& prop);
-size_t alpha_tape_bytes(const NetDev& net, const PropDev& prop, int64_t n);
+size_t alpha_tape_bytes(const NetDev& net, const PropDev& prop, int64_t n, int fwd_only);
 hipError_t launch_alpha_forward(const NetDev& net, const PropDev& prop, const AlphaArgs& a,
                                 hipStream_t stream);
 hipError_t launch_alpha_backward(const NetDev& net, const PropDev& prop, const AlphaArgs& a,
@@ -172,6 +175,10 @@ hipError_t launch_gather_boxes(int64_t m, int d, const unsigned* list, const flo
                                const float* hi, float* lo2, float* hi2, hipStream_t stream);
 hipError_t launch_scatter_classes(int64_t m, const unsigned* list, const int8_t* cls2, int8_t* cls,
                                   hipStream_t stream);
+// Class 3 (and the FP64 list) for undecided boxes near a decision, from widened and raw bounds.
+hipError_t launch_ambiguity(int64_t n, int rows, const float* wlo, const float* whi,
+                            const float* rlo, const float* rhi, int8_t* cls, unsigned* amb_list,
+                            unsigned* amb_count, unsigned base, hipStream_t stream);
 hipError_t launch_center_objective(const NetDev& net, const PropDev& prop, int64_t n,
                                    const float* lo, const float* hi, int8_t* obj,
                                    hipStream_t stream);

@@ -1135,7 +1135,7 @@ hipError_t launch_reg_mt(const NetDev& net, const PropDev& prop, int64_t n, cons
     }
 }
 
-int g_variant = 0;   // 0 auto, 1 LDS-staged, 2 register-resident
+int g_variant = 0;   // 0 auto, 1 LDS-staged, 2 register-resident, 3 tape-state only
 
 bool reg_fits(const NetDev& net, const PropDev& prop) {
     return net.mt_max <= 4 && net.d + 3 <= 10 && prop.rows <= 16 &&
@@ -1145,13 +1145,14 @@ bool reg_fits(const NetDev& net, const PropDev& prop) {
 }  // namespace
 
 int set_bound_variant(int v) {
-    if (v < 0 || v > 2) return -1;
+    if (v < 0 || v > 3) return -1;
     g_variant = v;
     return 0;
 }
 
 int bound_variant_for(const NetDev& net, const PropDev& prop) {
     if (g_variant == 2) return reg_fits(net, prop) ? 2 : -1;
+    if (g_variant == 3) return -1;   // the level driver then bounds with the tape-state kernel
     return 1;
 }
 

@@ -217,7 +217,7 @@ def bound_boxes(net: Net, prop: Property, lo, hi, g_lo=None, g_hi=None, cls=None
 
 
 def bound_kernel_variant(variant: int) -> None:
-    """0 automatic, 1 LDS-staged, 2 register-resident (see include/slrcount.h)."""
+    """0 automatic, 1 LDS-staged, 2 register-resident, 3 tape-state (see include/slrcount.h)."""
     _check(lib().bound_kernel_variant(int(variant)))
 
 

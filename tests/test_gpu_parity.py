@@ -39,6 +39,15 @@ def variant(request):
     E().bound_kernel_variant(0)
 
 
+@pytest.fixture(params=[1, 2, 3], ids=["lds", "reg", "tape"])
+def cvariant(request):
+    """Exact counts with each bound kernel: LDS-staged, register-resident and the tape-state
+    kernel (plain slopes, raw/widened ambiguity window, FP64 re-decision)."""
+    E().bound_kernel_variant(request.param)
+    yield request.param
+    E().bound_kernel_variant(0)
+
+
 def need(variant, inst):
     """Skip register-kernel runs on shapes that kernel does not take (d > 7 or width > 64)."""
     widths = inst.sizes[1:-1]
@@ -191,19 +200,20 @@ def compare_counts(inst, D, M, chunk=0):
 
 
 @pytest.mark.parametrize("seed", range(12))
-def test_count_exact_tiny2d(seed, variant):
+def test_count_exact_tiny2d(seed, cvariant):
     inst = synth.tiny2d(seed)
     g, o, div = compare_counts(inst, inst.max_depth, inst.max_leaves)
     assert g["status"] in (0, 1)
 
 
 @pytest.mark.parametrize("seed", [0, 1])
-def test_count_exact_acas_small_budget(seed, variant):
+def test_count_exact_acas_small_budget(seed, cvariant):
+    need(cvariant, synth.acas(seed))
     inst = synth.acas(seed)
     compare_counts(inst, 40, 1 << 12, chunk=1000)
 
 
-def test_count_exact_closed_forms(variant):
+def test_count_exact_closed_forms(cvariant):
     from tests import oracle_pins as P
     for net, lo, hi, D in ((P.abs_net(), np.zeros(2), np.ones(2), 14),
                            (P.irwin_hall_net(), np.zeros(3), np.ones(3), 24)):
@@ -213,9 +223,25 @@ def test_count_exact_closed_forms(variant):
         assert not div
 
 
-def test_count_exact_nav22():
-    inst = synth.nav22(0)
-    compare_counts(inst, 40, 1 << 11)
+@pytest.mark.parametrize("v", [1, 3], ids=["lds", "tape"])
+def test_count_exact_nav22(v):
+    E().bound_kernel_variant(v)
+    try:
+        compare_counts(synth.nav22(0), 40, 1 << 11)
+    finally:
+        E().bound_kernel_variant(0)
+
+
+def test_count_exact_wide20_tape_kernel():
+    """20 inputs, 4 x 256: the LDS kernel cannot hold its state, the exact count runs on the
+    tape-state kernel; parity with the oracle on a shallow tree."""
+    inst = synth.wide20(0)
+    net, prop = load(inst)
+    with pytest.raises(E().SlrError) as e:
+        blo, bhi = synth.random_boxes(inst.lo, inst.hi, 4, 0, 3)
+        E().bound_boxes(net, prop, dev(blo), dev(bhi))
+    assert e.value.code == -5
+    compare_counts(inst, 9, 1 << 12)
 
 
 def test_count_exact_deterministic_and_budget():
@@ -342,6 +368,8 @@ def test_variant_rejects_unknown_and_unfit():
     eng = E()
     with pytest.raises(eng.SlrError):
         eng.bound_kernel_variant(7)
+    with pytest.raises(eng.SlrError):
+        eng.bound_kernel_variant(-1)
     eng.bound_kernel_variant(2)
     try:
         inst = synth.nav22(0)           # d = 22 does not fit the register-resident kernel
