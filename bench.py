@@ -46,6 +46,23 @@ def flops_per_box(sizes, rows):
     return f
 
 
+def alpha_flops_per_box_step(sizes, rows):
+    """Algorithmic flops of one projected-Adam step of one box in alpha mode (contractions only).
+
+    With its own lower slopes a neuron carries two full equations (center and radius, d + 1
+    coefficients each), so every hidden-to-hidden layer costs 4 n_in n_out (d + 1) flops forward
+    (W times the centers, |W| times the radii) and the same again in the adjoint (W^T, |W|^T);
+    the folded output rows likewise with n_out = rows; the first layer 2 d n_1 (centers only).
+    """
+    d = sizes[0]
+    hidden = sizes[1:-1]
+    f = 0
+    for a, b in zip(hidden[:-1], hidden[1:]):
+        f += 4 * a * b * (d + 1)
+    f += 4 * hidden[-1] * rows * (d + 1)
+    return 2 * f + 2 * d * sizes[1]
+
+
 def bytes_per_box(d):
     """Algorithmic HBM bytes of the bound kernel per box: corners in, class out."""
     return 2 * d * 4 + 1
@@ -88,6 +105,84 @@ def cpu_baseline(seed, leaves):
                       f"{r['depth_reached']}), {dt:.1f} s"}
 
 
+def bench_alpha_optimize(E, torch, inst, n, steps, seed, reps=3):
+    """alpha_optimize on n boxes of the workload's domain (widths up to 1/16 of the domain):
+    one init pass, then steps x (adjoint with fused Adam, forward)."""
+    import synth
+    net = E.Net(inst.net)
+    prop = E.Property(net, inst.C, inst.dvec)
+    lo, hi = synth.uniform_boxes(inst.lo, inst.hi, n, seed + 101, 1.0 / 16)
+    lo = torch.from_numpy(lo).cuda()
+    hi = torch.from_numpy(hi).cuda()
+    ws = torch.empty(E.alpha_workspace_size(net, prop, n), dtype=torch.uint8, device="cuda")
+    E.alpha_optimize(net, prop, lo, hi, steps=steps, workspace=ws)
+    torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    ev[0].record()
+    for _ in range(reps):
+        r = E.alpha_optimize(net, prop, lo, hi, steps=steps, workspace=ws)
+    ev[1].record()
+    torch.cuda.synchronize()
+    ms = ev[0].elapsed_time(ev[1]) / reps
+    fps = alpha_flops_per_box_step(inst.sizes, inst.C.shape[0])
+    achieved = n * steps * fps / (ms * 1e-3) / 1e12
+    cls = r["cls"].cpu().numpy()
+    return {"boxes": n, "steps": steps, "ms": ms, "alpha_boxes_per_s": n / (ms * 1e-3),
+            "flops_per_box_step": fps, "achieved_tflops": achieved,
+            "frac_fp32_mfma": achieved / PEAK_FP32_MFMA,
+            "decided": int((cls != 0).sum())}
+
+
+def bench_count(E, torch, inst, D, M, alpha_steps=0, min_depth=0, reps=1):
+    net = E.Net(inst.net)
+    prop = E.Property(net, inst.C, inst.dvec)
+    achunk = 16384 if alpha_steps else 0
+    ws = torch.empty(E.workspace_size(net, prop, M, 0, achunk), dtype=torch.uint8, device="cuda")
+    kw = dict(workspace=ws, alpha_steps=alpha_steps, alpha_min_depth=min_depth,
+              alpha_chunk=achunk)
+    E.count_exact(net, prop, inst.lo, inst.hi, D, M, **kw)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        r = E.count_exact(net, prop, inst.lo, inst.hi, D, M, **kw)
+    dt = (time.perf_counter() - t0) / reps
+    return {"time_to_bracket_ms": dt * 1e3, "bracket": [r["unsafe"], r["unsafe"] + r["undecided"]],
+            "boxes_bounded": r["n_boxes_bounded"], "depth_reached": r["depth_reached"],
+            "alpha_boxes": r["n_alpha_boxes"], "alpha_decided": r["n_alpha_decided"],
+            "boxes_per_s": r["n_boxes_bounded"] / dt}
+
+
+def cpu_alpha_baseline(inst, n, steps, seed):
+    """The FP64 torch oracle of the alpha mode (forward + autograd + Adam), untuned."""
+    import synth
+    from oracle import alpha as oalpha
+    import torch
+    lo, hi = synth.uniform_boxes(inst.lo, inst.hi, n, seed + 101, 1.0 / 16)
+    t0 = time.perf_counter()
+    oalpha.optimize(inst.net, inst.C, inst.dvec, lo, hi, steps=steps)
+    dt = time.perf_counter() - t0
+    return {"value": n / dt, "unit": "alpha-optimized boxes/s", "cores": torch.get_num_threads(),
+            "kind": "oracle",
+            "sample": f"FP64 torch oracle, {n} boxes x {steps} Adam steps, {dt:.1f} s"}
+
+
+def alpha_section(E, torch, seed, cpu):
+    import synth
+    a5 = synth.acas(seed)
+    b5 = synth.wide20(seed)
+    out = {
+        "acas_optimize": bench_alpha_optimize(E, torch, a5, 65536, 20, seed),
+        "wide20_optimize": bench_alpha_optimize(E, torch, b5, 4096, 20, seed),
+        "acas_count_plain": bench_count(E, torch, a5, a5.max_depth, a5.max_leaves),
+        "acas_count_alpha": bench_count(E, torch, a5, a5.max_depth, a5.max_leaves, 20, 16),
+        "wide20_count_plain": bench_count(E, torch, b5, b5.max_depth, 1 << 14),
+        "wide20_count_alpha": bench_count(E, torch, b5, b5.max_depth, 1 << 14, 20, 8),
+    }
+    if cpu:
+        out["cpu_baseline"] = cpu_alpha_baseline(a5, 32, 20, seed)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -96,6 +191,8 @@ def main():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--cpu-leaves", type=int, default=1 << 15)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-alpha", action="store_true",
+                    help="skip the alpha-mode measurements (optimizer throughput, counts with alpha)")
     ap.add_argument("--variant", type=int, default=0,
                     help="bound kernel: 0 automatic, 1 LDS-staged, 2 register-resident")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
@@ -177,6 +274,8 @@ def main():
         "depth_reached": r0["depth_reached"],
         "recheck64_per_step": r0["n_recheck64"],
     }
+    if not args.no_alpha:
+        line["alpha"] = alpha_section(E, torch, args.seed, not args.no_cpu_baseline)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(args.seed, args.cpu_leaves)
     print(json.dumps(line), flush=True)
