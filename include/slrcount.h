@@ -265,6 +265,45 @@ int alpha_optimize(const slr_net* net, const slr_property* prop, int64_t n, cons
                    float* best_hi, int8_t* cls, void* workspace, size_t workspace_bytes,
                    void* stream);
 
+/* ------------------------------------------------------------------------------------------
+ * Batches: many independent exact counts advanced level by level together (§3's
+ * level-parallel bounding applied across instances).  Each instance has its own network,
+ * property, box, depth and leaf budget; results equal those of count_exact on each instance
+ * alone.  Levels run as a fixed launch sequence whose kernels read their work sizes on the
+ * device (persistent bound kernels per kernel class pop tiles from a device work queue), so the
+ * whole count can be captured once in a HIP graph and replayed with one launch and one
+ * read-back.  Shapes: d <= 11, hidden widths <= 128, rows <= 16, max_leaves <= 2^22,
+ * n_inst <= 1024.
+ * ------------------------------------------------------------------------------------------ */
+typedef struct slr_batch slr_batch;   /* opaque; owns its device memory */
+
+/*
+ * batch_create: validates every instance, allocates the batch's device memory (frontiers,
+ * counters, work queues: the only allocation; batch_run allocates nothing) and, with
+ * use_graph = 1, captures the launch sequence of a whole count into a graph.
+ *   nets, props   [n_inst] handles (instances may share them)
+ *   lo, hi        [n_inst] host float64 [d] boxes, exactly representable in float32
+ *   max_depth     [n_inst], max_leaves [n_inst]: as in slr_exact_opts
+ */
+int batch_create(int32_t n_inst, const slr_net* const* nets, const slr_property* const* props,
+                 const double* const* lo, const double* const* hi, const int32_t* max_depth,
+                 const int64_t* max_leaves, int32_t use_graph, slr_batch** out);
+
+/*
+ * batch_run: one complete count of every instance on `stream` (graph replay or the same
+ * launches issued directly), then one read-back; results[i] (host, [n_inst]) as from
+ * count_exact (bound_ms, trace and alpha fields are 0; seconds is the batch's wall time).
+ * Returns SLR_BUDGET if any instance stopped on its depth or leaf budget.  Calls on one batch
+ * must not overlap.
+ */
+int batch_run(slr_batch* batch, void* stream, slr_count_result* results);
+void batch_free(slr_batch* batch);
+
+/* count_exact_batch: batch_create (without graph) + batch_run + batch_free. */
+int count_exact_batch(int32_t n_inst, const slr_net* const* nets, const slr_property* const* props,
+                      const double* const* lo, const double* const* hi, const int32_t* max_depth,
+                      const int64_t* max_leaves, void* stream, slr_count_result* results);
+
 /* Message of the last failed call on this thread ("" if none). */
 const char* last_error(void);
 

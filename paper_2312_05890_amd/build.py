@@ -14,7 +14,7 @@ from concurrent.futures import ThreadPoolExecutor
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libslrcount.so")
-SOURCES = ["slr_engine.hip", "slr_kernels.hip", "slr_alpha.hip"]
+SOURCES = ["slr_engine.hip", "slr_kernels.hip", "slr_alpha.hip", "slr_batch.hip"]
 
 HIPCC_FLAGS = [
     "-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",

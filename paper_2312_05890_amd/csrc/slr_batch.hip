@@ -1,0 +1,363 @@
+// gfx950 kernels of batched exact counts: many independent instances (each with its own network,
+// property, box, depth and leaf budget) advance level by level together.
+//
+// Per level the launch sequence is fixed and every kernel reads its work size on the device:
+//   plan     (one workgroup) applies the previous level's split, then lays out this level's
+//            work: per kernel class, the bound tiles of its instances (prefix offsets), and the
+//            1024-box bookkeeping tiles of all instances;
+//   bound    one persistent kernel per class: workgroups pop tiles from the class's work queue
+//            (an atomic head), find the tile's instance by binary search over the offsets and run
+//            the LDS-staged bound tile on that instance's network (its descriptor is read from
+//            device memory); ambiguous boxes are listed as (instance << 22 | box);
+//   recheck  FP64 re-decision of the listed boxes, one per wavefront;
+//   count    class histograms per instance and level (64-bit atomics: exact and order-free);
+//   advance  the budget rule of each instance (stop at its depth, or when its leaves would
+//            exceed its budget), one thread per instance;
+//   split    bisection of the undecided boxes of the instances that go on.
+// Instances that have stopped get no tiles; levels past every instance's depth are empty.
+// The host can therefore capture all levels once and replay them as one graph.
+#include "slr_device.h"
+
+namespace {
+
+// Largest i in [lo, hi) with pre[i] <= t (pre non-decreasing, pre[lo] = 0 <= t).
+__device__ __forceinline__ int find_owner(const unsigned* __restrict__ pre, int lo, int hi,
+                                          unsigned t) {
+    int a = lo, b = hi - 1;
+    while (a < b) {
+        const int m = (a + b + 1) >> 1;
+        if (pre[m] <= t) a = m;
+        else b = m - 1;
+    }
+    return a;
+}
+
+__global__ __launch_bounds__(256) void batch_init_kernel(BatchInst* insts, int n_inst) {
+    const int i = blockIdx.x;
+    if (i >= n_inst) return;
+    BatchInst& I = insts[i];
+    for (int t = threadIdx.x; t < SLR_MAX_LEVELS; t += blockDim.x) {
+        I.stats[t].unsafe_cnt = 0;
+        I.stats[t].safe_cnt = 0;
+        I.stats[t].undecided_cnt = 0;
+        I.stats[t].pad = 0;
+    }
+    for (int k = threadIdx.x; k < I.d; k += blockDim.x) {
+        I.lo[0][k] = I.root[k];
+        I.hi[0][k] = I.root[I.d + k];
+    }
+    if (threadIdx.x == 0) {
+        I.path[0][0] = 1ull;
+        I.n = 1;
+        I.n_next = 0;
+        I.resolved = 0;
+        I.bounded = 0;
+        I.cur = 0;
+        I.level = 0;
+        I.active = 1;
+        I.split_pending = 0;
+        I.status = 0;
+        I.stop_level = 0;
+        I.stopped = 0;
+        I.levels = 0;
+        I.rechecks = 0;
+        I.err = 0;
+    }
+}
+
+__global__ void batch_plan_kernel(BatchInst* insts, int n_inst, BatchCtl* ctl,
+                                  unsigned* __restrict__ bpre, unsigned* __restrict__ cpre,
+                                  int n_classes) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    for (int c = 0; c < n_classes; ++c) {
+        ctl->ntiles[c] = 0;
+        ctl->head[c] = 0;
+    }
+    ctl->amb_count = 0;
+    unsigned ctot = 0;
+    for (int i = 0; i < n_inst; ++i) {
+        BatchInst& I = insts[i];
+        if (I.split_pending) {
+            I.n = I.n_next;
+            I.cur ^= 1;
+            I.level += 1;
+            I.split_pending = 0;
+        }
+        const long long n = I.active ? I.n : 0;
+        const int T = ctl->tbox[I.cls_id];
+        bpre[i] = ctl->ntiles[I.cls_id];
+        ctl->ntiles[I.cls_id] += (unsigned)((n + T - 1) / T);
+        cpre[i] = ctot;
+        ctot += (unsigned)((n + kTile - 1) / kTile);
+    }
+    cpre[n_inst] = ctot;
+    ctl->ctiles = ctot;
+}
+
+template <int NCOL, int NT, int UW>
+__global__ __launch_bounds__(kNW * 64) void batch_bound_kernel(BatchInst* insts, BatchCtl* ctl,
+                                                               const unsigned* __restrict__ bpre,
+                                                               int cbeg, int cend, int c,
+                                                               unsigned* __restrict__ amb_list) {
+    __shared__ unsigned s_t;
+    const unsigned total = ctl->ntiles[c];
+    for (;;) {
+        if (threadIdx.x == 0) s_t = atomicAdd(&ctl->head[c], 1u);
+        __syncthreads();
+        const unsigned t = s_t;
+        __syncthreads();
+        if (t >= total) break;
+        const int i = find_owner(bpre, cbeg, cend, t);
+        const BatchInst& I = insts[i];
+        const int64_t box0 = (int64_t)(t - bpre[i]) * (NT * 16);
+        bound_tile<NCOL, NT, UW>(I.net, I.prop, I.n, box0, I.lo[I.cur], I.hi[I.cur], nullptr,
+                                 nullptr, I.cls, 0, I.sp, amb_list, &ctl->amb_count,
+                                 (unsigned)i << 22);
+        __syncthreads();   // the tile's LDS is reused by the next tile
+    }
+}
+
+__global__ __launch_bounds__(256) void batch_recheck_kernel(BatchInst* insts, BatchCtl* ctl,
+                                                            const unsigned* __restrict__ amb_list,
+                                                            int nrow, int ncol_max) {
+    extern __shared__ double sm[];
+    const int wave = threadIdx.x >> 6;
+    const int waves = blockDim.x >> 6;
+    double* ws = sm + (size_t)wave * (2 * nrow * ncol_max + 2 * SLR_MAX_D);
+    const unsigned total = ctl->amb_count;
+    for (unsigned k = blockIdx.x * waves + wave; k < total; k += gridDim.x * waves) {
+        const unsigned e = amb_list[k];
+        BatchInst& I = insts[e >> 22];
+        recheck_box(I.net, I.prop, (int64_t)(e & 0x3FFFFFu), I.lo[I.cur], I.hi[I.cur], nullptr,
+                    nullptr, I.cls, &I.rechecks, ws, nrow);
+    }
+}
+
+__global__ __launch_bounds__(256) void batch_count_kernel(BatchInst* insts, int n_inst,
+                                                          BatchCtl* ctl,
+                                                          const unsigned* __restrict__ cpre) {
+    const unsigned total = ctl->ctiles;
+    for (unsigned t = blockIdx.x; t < total; t += gridDim.x) {
+        const int i = find_owner(cpre, 0, n_inst, t);
+        BatchInst& I = insts[i];
+        count_tile(I.n, I.cls, I.tile_und, I.stats + I.level, (int64_t)(t - cpre[i]));
+        __syncthreads();
+    }
+}
+
+__global__ __launch_bounds__(256) void batch_advance_kernel(BatchInst* insts, int n_inst) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n_inst) return;
+    BatchInst& I = insts[i];
+    if (!I.active) return;
+    const LevelStats h = I.stats[I.level];
+    I.bounded += I.n;
+    I.levels = I.level + 1;
+    I.resolved += (long long)(h.unsafe_cnt + h.safe_cnt);
+    const long long und = (long long)h.undecided_cnt;
+    if ((long long)(h.unsafe_cnt + h.safe_cnt) + und != I.n) I.err |= 4u;
+    if (und == 0) {
+        I.active = 0;
+        I.status = 0;
+    } else if (I.level == I.max_depth || I.resolved + 2 * und > I.max_leaves) {
+        I.active = 0;
+        I.stopped = 1;
+        I.stop_level = I.level;
+        I.status = 1;
+    } else {
+        I.split_pending = 1;
+        I.n_next = 2 * und;
+    }
+}
+
+__global__ __launch_bounds__(256) void batch_split_kernel(BatchInst* insts, int n_inst,
+                                                          BatchCtl* ctl,
+                                                          const unsigned* __restrict__ cpre) {
+    const unsigned total = ctl->ctiles;
+    for (unsigned t = blockIdx.x; t < total; t += gridDim.x) {
+        const int i = find_owner(cpre, 0, n_inst, t);
+        BatchInst& I = insts[i];
+        if (!I.split_pending) continue;
+        const int c = I.cur;
+        split_tile(I.n, I.d, I.cls, I.tile_und, I.lo[c], I.hi[c], I.path[c], I.lo[c ^ 1],
+                   I.hi[c ^ 1], I.path[c ^ 1], &I.err, (int64_t)(t - cpre[i]));
+        __syncthreads();
+    }
+}
+
+__global__ __launch_bounds__(256) void batch_volume_kernel(BatchInst* insts, int n_inst) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n_inst) return;
+    BatchInst& I = insts[i];
+    volume_body(I.stats, I.levels, I.stop_level, I.stopped, I.vol, I.counts, &I.err);
+}
+
+// ---------------------------------------------------------------------------------------------
+// Host side: kernel classes and launches
+// ---------------------------------------------------------------------------------------------
+int ncol_class_b(int d) {
+    const int c = d + 3;
+    if (c <= 12) return c;
+    if (c <= 14) return 14;
+    return -1;
+}
+
+void tile_class_b(int mt_max, int* NT, int* UW) {
+    if (mt_max <= 1) { *NT = 4; *UW = 1; }
+    else if (mt_max == 2) { *NT = 2; *UW = 1; }
+    else if (mt_max <= 4) { *NT = 1; *UW = 1; }
+    else { *NT = 1; *UW = 2; }
+}
+
+template <int NCOL, int NT, int UW>
+const void* kern_ptr() {
+    return (const void*)batch_bound_kernel<NCOL, NT, UW>;
+}
+
+const void* class_kernel(int ncol, int nt, int uw) {
+#define SLR_T(C)                                                  \
+    if (ncol == C) {                                              \
+        if (nt == 4 && uw == 1) return kern_ptr<C, 4, 1>();       \
+        if (nt == 2 && uw == 1) return kern_ptr<C, 2, 1>();       \
+        if (nt == 1 && uw == 1) return kern_ptr<C, 1, 1>();       \
+        if (nt == 1 && uw == 2) return kern_ptr<C, 1, 2>();       \
+        return nullptr;                                           \
+    }
+    SLR_T(4) SLR_T(5) SLR_T(6) SLR_T(7) SLR_T(8) SLR_T(9) SLR_T(10) SLR_T(11) SLR_T(12) SLR_T(14)
+#undef SLR_T
+    return nullptr;
+}
+
+int g_cu = 0;
+
+}  // namespace
+
+int batch_num_cu() {
+    if (g_cu == 0) {
+        int dev = 0, cu = 0;
+        if (hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && cu > 0)
+            g_cu = cu;
+        else
+            g_cu = 256;
+        (void)hipGetLastError();
+    }
+    return g_cu;
+}
+
+bool batch_class_supported(int ncol, int nt, int uw) { return class_kernel(ncol, nt, uw) != nullptr; }
+
+int batch_class_of(const NetDev& net, const PropDev& prop, int* ncol, int* nt, int* uw) {
+    (void)prop;
+    *ncol = ncol_class_b(net.d);
+    if (*ncol < 0 || net.mt_max > 8) return -1;
+    tile_class_b(net.mt_max, nt, uw);
+    return batch_class_supported(*ncol, *nt, *uw) ? 0 : -1;
+}
+
+size_t batch_bound_lds(int ncol, int nt, int mt_max, int rows) {
+    const int T = nt * 16;
+    const int SP = 4 * mt_max + ((mt_max & 1) ? 0 : 4);
+    return sizeof(float) * ((size_t)nt * ncol * 64 * SP + 2 * (size_t)mt_max * T + 4 * (size_t)rows * T * ncol);
+}
+
+hipError_t batch_prepare_class(int ncol, int nt, int uw, size_t lds, int* blocks) {
+    const void* k = class_kernel(ncol, nt, uw);
+    if (!k) return hipErrorInvalidValue;
+    if (lds > 64 * 1024) {
+        hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            return e;
+        }
+    }
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k, kNW * 64, lds) != hipSuccess || nb < 1) nb = 1;
+    (void)hipGetLastError();
+    *blocks = nb * batch_num_cu();
+    return hipSuccess;
+}
+
+hipError_t launch_batch_init(BatchInst* insts, int n_inst, hipStream_t stream) {
+    (void)hipGetLastError();
+    hipLaunchKernelGGL(batch_init_kernel, dim3(n_inst), dim3(64), 0, stream, insts, n_inst);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_plan(BatchInst* insts, int n_inst, BatchCtl* ctl, unsigned* bpre,
+                             unsigned* cpre, int n_classes, hipStream_t stream) {
+    (void)hipGetLastError();
+    hipLaunchKernelGGL(batch_plan_kernel, dim3(1), dim3(64), 0, stream, insts, n_inst, ctl, bpre,
+                       cpre, n_classes);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_bound(int ncol, int nt, int uw, int blocks, size_t lds, BatchInst* insts,
+                              BatchCtl* ctl, const unsigned* bpre, int cbeg, int cend, int c,
+                              unsigned* amb_list, hipStream_t stream) {
+    const void* k = class_kernel(ncol, nt, uw);
+    if (!k) return hipErrorInvalidValue;
+    void* args[] = {&insts, &ctl, (void*)&bpre, &cbeg, &cend, &c, &amb_list};
+    (void)hipGetLastError();
+    return hipLaunchKernel(k, dim3(blocks), dim3(kNW * 64), args, lds, stream);
+}
+
+namespace {
+void recheck_shape(int nrow, int ncol_max, int* waves, size_t* lds) {
+    const size_t per_wave = sizeof(double) * (2 * (size_t)nrow * ncol_max + 2 * SLR_MAX_D);
+    int w = 4;
+    while (w > 1 && per_wave * w > 150 * 1024) --w;
+    *waves = w;
+    *lds = per_wave * w;
+}
+}  // namespace
+
+hipError_t batch_prepare_recheck(int nrow, int ncol_max) {
+    int waves;
+    size_t lds;
+    recheck_shape(nrow, ncol_max, &waves, &lds);
+    if (lds <= 64 * 1024) return hipSuccess;
+    hipError_t e = hipFuncSetAttribute((const void*)batch_recheck_kernel,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) (void)hipGetLastError();
+    return e;
+}
+
+hipError_t launch_batch_recheck(BatchInst* insts, BatchCtl* ctl, const unsigned* amb_list,
+                                int nrow, int ncol_max, hipStream_t stream) {
+    int waves;
+    size_t lds;
+    recheck_shape(nrow, ncol_max, &waves, &lds);
+    (void)hipGetLastError();
+    hipLaunchKernelGGL(batch_recheck_kernel, dim3(1024), dim3(64 * waves), lds, stream, insts, ctl,
+                       amb_list, nrow, ncol_max);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_count(BatchInst* insts, int n_inst, BatchCtl* ctl, const unsigned* cpre,
+                              hipStream_t stream) {
+    (void)hipGetLastError();
+    hipLaunchKernelGGL(batch_count_kernel, dim3(2048), dim3(256), 0, stream, insts, n_inst, ctl, cpre);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_advance(BatchInst* insts, int n_inst, hipStream_t stream) {
+    (void)hipGetLastError();
+    hipLaunchKernelGGL(batch_advance_kernel, dim3((n_inst + 255) / 256), dim3(256), 0, stream,
+                       insts, n_inst);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_split(BatchInst* insts, int n_inst, BatchCtl* ctl, const unsigned* cpre,
+                              hipStream_t stream) {
+    (void)hipGetLastError();
+    hipLaunchKernelGGL(batch_split_kernel, dim3(2048), dim3(256), 0, stream, insts, n_inst, ctl, cpre);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_volume(BatchInst* insts, int n_inst, hipStream_t stream) {
+    (void)hipGetLastError();
+    hipLaunchKernelGGL(batch_volume_kernel, dim3((n_inst + 255) / 256), dim3(256), 0, stream,
+                       insts, n_inst);
+    return hipGetLastError();
+}

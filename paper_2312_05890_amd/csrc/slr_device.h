@@ -1,0 +1,702 @@
+// Device code shared by the single-instance kernels (slr_kernels.hip) and the batch kernels
+// (slr_batch.hip): the LDS-staged bound tile, the FP64 re-decision of one box and the level
+// bookkeeping of one 1024-box tile.  Header-only; every translation unit gets its own copy.
+//
+// Bound tile (one branch-and-bound level at a time, §3): a workgroup of four wavefronts takes
+// 16*NT boxes.  For box b and neuron m the state is the center equation c_0..c_d, the radius r
+// (see slr_internal.h) and q, the part of r that comes from rounding margins (it decides which
+// boxes need the FP64 re-decision), NCOL = d + 3 floats, kept in LDS in the layout
+//     S[nt][c][g][j][s]     (j = box within the 16-box N tile, (g, s) = neuron)
+// where neuron k of the layer input sits at g = (k % 16) / 4, s = 4 (k / 16) + k % 4.  That is
+// exactly the B-operand layout of v_mfma_f32_16x16x4f32 (lane 16 g + j supplies B[g][j] of
+// K-step s) and also exactly where the same lane finds output rows 16 mt + 4 g + v of the
+// accumulator D[4 g + v][j] of M tile mt.  So every hidden layer is
+//     MFMA:      acc[c] += W_frag(mt, s) * S[c][s]        (c <= d, A = W)
+//                acc[c] += |W_frag(mt, s)| * S[c][s]       (r and q columns, A = |W|)
+//     epilogue:  lane-local on its 4 neurons x NCOL columns: bias, rounding margin,
+//                concretization, Eq. 1, then one 16-byte LDS store per column.
+// The first affine layer (box -> hidden) is exact and done on the VALU; the output layer with
+// the folded property rows runs as split-K MFMA over the four wavefronts when it fits one tile,
+// else as a VALU contraction over the LDS state.
+
+#pragma once
+
+#include "slr_internal.h"
+
+#include <hip/hip_runtime.h>
+
+#include <float.h>
+#include <math.h>
+
+namespace {
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+constexpr float kU32 = 0x1p-24f;     // unit roundoff of float32
+constexpr float kEta = 0x1p-96f;     // absolute floor: covers flushed subnormal products
+constexpr double kEta64 = 0x1p-960;
+constexpr double kU64 = 0x1p-53;
+constexpr int kNW = 4;               // wavefronts per bound workgroup
+
+// Row 16 mt + 4 g + v of a layer with `tiles` 16-row tiles whose last tile holds r neurons.
+__device__ __forceinline__ bool row_valid(int mt, int g, int v, int tiles, int r) {
+    return mt < tiles - 1 || 4 * v + g < r;
+}
+
+__device__ __forceinline__ f32x4 mfma16(float a, float b, f32x4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+// Scalars of the epilogue: zero margins and no rounding-up in the unwidened mode.
+struct EpiConst {
+    float kconc, krelu, lamfac;
+};
+
+__device__ __forceinline__ EpiConst epi_const(const NetDev& net, int raw) {
+    EpiConst k;
+    k.kconc = raw ? 0.f : net.kconc;
+    k.krelu = raw ? 0.f : net.krelu;
+    // lam = hi * rcp(hi - lo): v_rcp_f32 is within 1 ulp, the product within 1/2 ulp, so a
+    // factor 1 + 2^-20 keeps the computed ratio >= the chord slope (any slope in [chord, 1] is a
+    // valid upper line and a valid lower slope)
+    k.lamfac = raw ? 1.f : 1.f + 0x1p-20f;
+    return k;
+}
+
+// Concretization, rounding margin and ReLU relaxation (Eq. 1) of four neurons of one box,
+// without branches.  In: a[c][v] = pre-activation center coefficients (c = 0..d, bias included),
+// the unwidened radius a[d+1][v] and margin part a[d+2][v]; eps[v] = rounding margin of the
+// affine step.  Out: post-activation state in place; returns max_v bound on |value| over the box.
+template <int NCOL>
+__device__ __forceinline__ float relu_epilogue(float (&a)[NCOL][4], const float (&eps)[4],
+                                               const bool (&valid)[4], const EpiConst& k) {
+    constexpr int D = NCOL - 3;
+    constexpr int R = NCOL - 2, Q = NCOL - 1;
+    float emax = 0.f;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        const float c0 = a[0][v];
+        float S = 0.f;
+#pragma unroll
+        for (int c = 1; c <= D; ++c) S += fabsf(a[c][v]);
+        const float r = a[R][v] + eps[v];
+        const float q = a[Q][v] + eps[v];
+        const float delta = k.kconc * (fabsf(c0) + r + S);
+        const float lo = (c0 - (r + S)) - delta;
+        const float hi = (c0 + (r + S)) + delta;
+        const bool dead = !valid[v] || !(hi > 0.f);
+        const bool act = !dead && lo >= 0.f;
+        const bool cross = !dead && !act;
+        const float den = cross ? hi - lo : 1.f;
+        const float lamc = fminf(1.f, hi * __builtin_amdgcn_rcpf(den) * k.lamfac);
+        const float lam = dead ? 0.f : (act ? 1.f : lamc);
+        const float sh = cross ? -0.5f * lamc * lo : 0.f;
+        const float er = cross ? k.krelu * lamc * ((fabsf(c0) + S + r) - lo) : 0.f;
+        // dead: lam = sh = er = 0 zeroes every (finite) entry; active: lam = 1, sh = er = 0
+#pragma unroll
+        for (int c = 1; c <= D; ++c) a[c][v] *= lam;
+        const float c0n = fmaf(lam, c0, sh);
+        const float rn = fmaf(lam, r, sh) + er;
+        const float qf = cross ? 1.f + lamc : lam;
+        const float qa = cross ? delta + er : 0.f;
+        a[0][v] = c0n;
+        a[R][v] = rn;
+        a[Q][v] = fmaf(qf, q, qa);
+        emax = fmaxf(emax, (fabsf(c0n) + lam * S + rn) * (1.f + 4.f * kU32));
+    }
+    return emax;
+}
+
+template <int NCOL, int NT, int UW>
+__device__ __forceinline__ void bound_tile(
+    const NetDev& net, const PropDev& prop, int64_t n, int64_t box0,
+    const float* __restrict__ blo, const float* __restrict__ bhi, float* __restrict__ g_lo,
+    float* __restrict__ g_hi, int8_t* __restrict__ cls, int raw, int SP,
+    unsigned* __restrict__ amb_list, unsigned* __restrict__ amb_count, unsigned list_base) {
+    extern __shared__ float lds[];
+    constexpr int T = NT * 16;
+    constexpr int D = NCOL - 3;
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6, g = lane >> 4, j = lane & 15;
+    const int d = net.d;
+
+    const EpiConst ek = epi_const(net, raw);
+    float* S = lds;                                   // [NT][NCOL][4][16][SP]
+    float* part = S + NT * NCOL * 64 * SP;            // [2 parity][mt_max][T] bound on |value|
+    float* OUT = part + 2 * net.mt_max * T;           // [rows][T][NCOL]
+    const int colstride = 64 * SP;
+    auto part_at = [&](int par, int mt, int bj) -> float& {
+        return part[(par * net.mt_max + mt) * T + bj];
+    };
+
+    // ---------------- first affine layer: exact on the VALU, then the ReLU epilogue
+    {
+        const int units = net.mt1 * NT;
+#pragma unroll
+        for (int i = 0; i < UW; ++i) {
+            const int u = wave + kNW * i;
+            if (u < units) {
+                const int mt = u / NT, nt = u - (u / NT) * NT;
+                const int64_t b = box0 + nt * 16 + j;
+                const bool bval = b < n;
+                float mid[D], rad[D];
+#pragma unroll
+                for (int k = 0; k < D; ++k) {
+                    float l = 0.f, h = 0.f;
+                    if (bval && k < d) {
+                        l = blo[b * d + k];
+                        h = bhi[b * d + k];
+                    }
+                    const float m = 0.5f * (l + h);
+                    mid[k] = m;
+                    rad[k] = raw ? 0.5f * (h - l) : fmaxf(h - m, m - l) * (1.f + 0x1p-22f);
+                }
+                float a[NCOL][4], eps[4];
+                bool valid[4];
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int m = 16 * mt + 4 * g + v;
+                    valid[v] = row_valid(mt, g, v, net.mt1, net.r1);
+                    float c0 = 0.f, s = 0.f;
+                    if (valid[v]) {
+                        const float bb = net.b1p[m];
+                        c0 = bb;
+                        s = fabsf(bb);
+#pragma unroll
+                        for (int k = 0; k < D; ++k) {
+                            const float w = k < d ? net.w1p[m * d + k] : 0.f;
+                            c0 = fmaf(w, mid[k], c0);
+                            a[k + 1][v] = w * rad[k];
+                            s += fabsf(w) * (fabsf(mid[k]) + rad[k]);
+                        }
+                    } else {
+#pragma unroll
+                        for (int k = 0; k < D; ++k) a[k + 1][v] = 0.f;
+                    }
+                    a[0][v] = c0;
+                    a[NCOL - 2][v] = 0.f;
+                    a[NCOL - 1][v] = 0.f;
+                    eps[v] = raw ? 0.f : net.kfirst * s + kEta;
+                }
+                float emax = relu_epilogue<NCOL>(a, eps, valid, ek);
+                float* sb = S + ((nt * NCOL * 4 + g) * 16 + j) * SP + 4 * mt;
+#pragma unroll
+                for (int c = 0; c < NCOL; ++c) {
+                    f32x4 o = {a[c][0], a[c][1], a[c][2], a[c][3]};
+                    *reinterpret_cast<f32x4*>(sb + c * colstride) = o;
+                }
+                emax = fmaxf(emax, __shfl_xor(emax, 16));
+                emax = fmaxf(emax, __shfl_xor(emax, 32));
+                if (g == 0) part_at(0, mt, nt * 16 + j) = emax;
+            }
+        }
+    }
+    __syncthreads();
+
+    // ---------------- hidden-to-hidden layers on MFMA with fused epilogues
+    int rp = 0;
+    int mt_prev = net.mt1;
+    for (int l = 0; l < net.n_affine - 2; ++l) {
+        const MidLayer* L = &net.mid[l];
+        const int units = L->mt_out * NT;
+        const int ks = L->ks;
+        f32x4 res[UW][NCOL];
+#pragma unroll
+        for (int i = 0; i < UW; ++i) {
+            const int u = wave + kNW * i;
+            if (u < units) {
+                const int mt = u / NT, nt = u - (u / NT) * NT;
+                f32x4 acc[NCOL];
+#pragma unroll
+                for (int c = 0; c < NCOL; ++c) acc[c] = f32x4{0.f, 0.f, 0.f, 0.f};
+                const float* wf = L->wfrag + (size_t)mt * L->ks_alloc * 64 + lane;
+                const float* sb = S + ((nt * NCOL * 4 + g) * 16 + j) * SP;
+                // full quads of K-steps, software-pipelined one quad ahead (A from global/L2,
+                // B from LDS), then the tail quad with per-step guards
+                const int nq = ks >> 2;
+                const int nqa = L->ks_alloc >> 2;
+                float af[4];
+                f32x4 bq[NCOL];
+#pragma unroll
+                for (int ss = 0; ss < 4; ++ss) af[ss] = wf[ss * 64];
+#pragma unroll
+                for (int c = 0; c < NCOL; ++c)
+                    bq[c] = *reinterpret_cast<const f32x4*>(sb + c * colstride);
+                for (int qi = 0; qi < nq; ++qi) {
+                    const int nx = min(qi + 1, nqa - 1) * 4;
+                    float an[4];
+                    f32x4 bn[NCOL];
+#pragma unroll
+                    for (int ss = 0; ss < 4; ++ss) an[ss] = wf[(nx + ss) * 64];
+#pragma unroll
+                    for (int c = 0; c < NCOL; ++c)
+                        bn[c] = *reinterpret_cast<const f32x4*>(sb + c * colstride + nx);
+#pragma unroll
+                    for (int ss = 0; ss < 4; ++ss) {
+                        const float aw = af[ss];
+                        const float aa = fabsf(aw);
+#pragma unroll
+                        for (int c = 0; c < NCOL - 2; ++c) acc[c] = mfma16(aw, bq[c][ss], acc[c]);
+                        acc[NCOL - 2] = mfma16(aa, bq[NCOL - 2][ss], acc[NCOL - 2]);
+                        acc[NCOL - 1] = mfma16(aa, bq[NCOL - 1][ss], acc[NCOL - 1]);
+                    }
+#pragma unroll
+                    for (int ss = 0; ss < 4; ++ss) af[ss] = an[ss];
+#pragma unroll
+                    for (int c = 0; c < NCOL; ++c) bq[c] = bn[c];
+                }
+                const int tail = ks & 3;   // af/bq now hold quad nq (valid when tail > 0)
+#pragma unroll
+                for (int ss = 0; ss < 3; ++ss) {
+                    if (ss < tail) {
+                        const float aw = af[ss];
+                        const float aa = fabsf(aw);
+#pragma unroll
+                        for (int c = 0; c < NCOL - 2; ++c) acc[c] = mfma16(aw, bq[c][ss], acc[c]);
+                        acc[NCOL - 2] = mfma16(aa, bq[NCOL - 2][ss], acc[NCOL - 2]);
+                        acc[NCOL - 1] = mfma16(aa, bq[NCOL - 1][ss], acc[NCOL - 1]);
+                    }
+                }
+#pragma unroll
+                for (int c = 0; c < NCOL; ++c) res[i][c] = acc[c];
+            }
+        }
+        __syncthreads();   // every wave has read the layer input
+#pragma unroll
+        for (int i = 0; i < UW; ++i) {
+            const int u = wave + kNW * i;
+            if (u < units) {
+                const int mt = u / NT, nt = u - (u / NT) * NT;
+                const int bj = nt * 16 + j;
+                float emax_in = 0.f;
+                for (int q = 0; q < mt_prev; ++q) emax_in = fmaxf(emax_in, part_at(rp, q, bj));
+                float a[NCOL][4], eps[4];
+                bool valid[4];
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int m = 16 * mt + 4 * g + v;
+                    valid[v] = row_valid(mt, g, v, L->mt_out, L->r_out);
+                    const float bb = L->bias[m];
+                    const float A = L->absrow[m];
+#pragma unroll
+                    for (int c = 0; c < NCOL; ++c) a[c][v] = res[i][c][v];
+                    a[0][v] += bb;
+                    eps[v] = raw ? 0.f : L->kgam * (A * emax_in + fabsf(bb)) + kEta;
+                }
+                float emax = relu_epilogue<NCOL>(a, eps, valid, ek);
+                float* sb = S + ((nt * NCOL * 4 + g) * 16 + j) * SP + 4 * mt;
+#pragma unroll
+                for (int c = 0; c < NCOL; ++c) {
+                    f32x4 o = {a[c][0], a[c][1], a[c][2], a[c][3]};
+                    *reinterpret_cast<f32x4*>(sb + c * colstride) = o;
+                }
+                emax = fmaxf(emax, __shfl_xor(emax, 16));
+                emax = fmaxf(emax, __shfl_xor(emax, 32));
+                if (g == 0) part_at(rp ^ 1, mt, bj) = emax;
+            }
+        }
+        rp ^= 1;
+        mt_prev = L->mt_out;
+        __syncthreads();   // the layer output is complete
+    }
+
+    // ---------------- output layer: folded property rows
+    const int rows = prop.rows;
+    const bool mfma_out = rows * NT * NCOL <= 64;
+    if (mfma_out) {
+        // split-K on MFMA: wave w takes K-quads w, w + 4, ...; partial sums of the valid rows go
+        // to OUT as [wave][nt][c][row][box] and are added in the final loop
+        const int ksq = (prop.ks_out + 3) >> 2;
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) {
+            f32x4 G[NCOL];
+#pragma unroll
+            for (int c = 0; c < NCOL; ++c) G[c] = f32x4{0.f, 0.f, 0.f, 0.f};
+            const float* sb = S + ((nt * NCOL * 4 + g) * 16 + j) * SP;
+            for (int q = wave; q < ksq; q += kNW) {
+                f32x4 bq[NCOL];
+#pragma unroll
+                for (int c = 0; c < NCOL; ++c)
+                    bq[c] = *reinterpret_cast<const f32x4*>(sb + c * colstride + 4 * q);
+#pragma unroll
+                for (int ss = 0; ss < 4; ++ss) {
+                    if (4 * q + ss < prop.ks_out) {
+                        const float aw = prop.wgfrag[(4 * q + ss) * 64 + lane];
+                        const float aa = fabsf(aw);
+#pragma unroll
+                        for (int c = 0; c < NCOL - 2; ++c) G[c] = mfma16(aw, bq[c][ss], G[c]);
+                        G[NCOL - 2] = mfma16(aa, bq[NCOL - 2][ss], G[NCOL - 2]);
+                        G[NCOL - 1] = mfma16(aa, bq[NCOL - 1][ss], G[NCOL - 1]);
+                    }
+                }
+            }
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int row = 4 * g + v;
+                if (row < rows) {
+#pragma unroll
+                    for (int c = 0; c < NCOL; ++c)
+                        OUT[(((wave * NT + nt) * NCOL + c) * rows + row) * 16 + j] = G[c][v];
+                }
+            }
+        }
+    } else {
+        // VALU contraction over the state
+        const int K = prop.kpad;
+        const int items = rows * T * NCOL;
+        for (int it = tid; it < items; it += kNW * 64) {
+            const int c = it % NCOL;
+            const int bj = (it / NCOL) % T;
+            const int r = it / (NCOL * T);
+            const int nt = bj >> 4, jj = bj & 15;
+            const float* wr = prop.wgp + r * K;
+            const float* col = S + (nt * NCOL + c) * colstride + jj * SP;
+            float sacc = 0.f;
+            for (int k = 0; k < K; ++k) {
+                const int gg = (k >> 2) & 3;
+                const int sidx = 4 * (k >> 4) + (k & 3);
+                float w = wr[k];
+                if (c >= NCOL - 2) w = fabsf(w);
+                sacc = fmaf(w, col[gg * 16 * SP + sidx], sacc);
+            }
+            OUT[(r * T + bj) * NCOL + c] = sacc;
+        }
+    }
+    __syncthreads();
+    auto outv = [&](int r, int bj, int c) -> float {
+        if (!mfma_out) return OUT[(r * T + bj) * NCOL + c];
+        const int nt = bj >> 4, jj = bj & 15;
+        float acc = 0.f;
+#pragma unroll
+        for (int w = 0; w < kNW; ++w) acc += OUT[(((w * NT + nt) * NCOL + c) * rows + r) * 16 + jj];
+        return acc;
+    };
+    for (int bj = tid; bj < T; bj += kNW * 64) {
+        const int64_t b = box0 + bj;
+        if (b >= n) continue;
+        float emax = 0.f;
+        for (int q = 0; q < net.mt_last; ++q) emax = fmaxf(emax, part_at(rp, q, bj));
+        bool unsafe = true, safe = false, amb_unsafe = true, amb_safe = false;
+        for (int r = 0; r < rows; ++r) {
+            const float bg = prop.bg[r];
+            const float G0 = outv(r, bj, 0) + bg;
+            float Sg = 0.f;
+            for (int c = 1; c <= D; ++c) Sg += fabsf(outv(r, bj, c));
+            const float eps = raw ? 0.f : prop.kout * (prop.ag[r] * emax + fabsf(bg)) + kEta;
+            const float R = outv(r, bj, NCOL - 2) + eps;
+            const float delta = raw ? 0.f : net.kconc * (fabsf(G0) + R + Sg);
+            const float glo = (G0 - (R + Sg)) - delta;
+            const float ghi = (G0 + (R + Sg)) + delta;
+            // distance within which the exact-arithmetic decision may differ from this one:
+            // twice the propagated margins plus 2^-14 of the row's magnitude
+            const float tau = 2.f * (outv(r, bj, NCOL - 1) + eps + delta) +
+                              0x1p-14f * fmaxf(fabsf(glo), fabsf(ghi));
+            if (g_lo) g_lo[b * rows + r] = glo;
+            if (g_hi) g_hi[b * rows + r] = ghi;
+            unsafe = unsafe && (glo > 0.f);
+            safe = safe || (ghi <= 0.f);
+            amb_unsafe = amb_unsafe && (glo + tau > 0.f);
+            amb_safe = amb_safe || (ghi - tau <= 0.f);
+        }
+        int8_t k = unsafe ? 1 : (safe ? 2 : 0);
+        if (k == 0 && !raw && (amb_unsafe || amb_safe)) {
+            k = 3;
+            if (amb_list) amb_list[atomicAdd(amb_count, 1u)] = list_base + (unsigned)b;
+        }
+        if (cls) cls[b] = k;
+    }
+}
+
+// ------------------------------------------------------------------------------------------
+// FP64 re-decision of boxes the float32 pass marked ambiguous (class 3): the same center/radius
+// propagation on the VALU in double precision, one box per wavefront, neurons across lanes.
+// ------------------------------------------------------------------------------------------
+
+// LDS ordering between lanes of one wavefront.
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ __forceinline__ double wave_max(double v) {
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
+    return v;
+}
+
+__device__ __forceinline__ double relu64(double* st, int ncol, double eps, double kconc,
+                                         double krelu) {
+    // st: one neuron's row (center c_0..c_d, then the unwidened radius); returns |value| bound
+    const int D = ncol - 2;
+    double c0 = st[0];
+    double S = 0.0;
+    for (int c = 1; c <= D; ++c) S += fabs(st[c]);
+    double r = st[ncol - 1] + eps;
+    const double delta = kconc * (fabs(c0) + r + S);
+    const double lo = (c0 - (r + S)) - delta;
+    const double hi = (c0 + (r + S)) + delta;
+    if (hi <= 0.0) {
+        for (int c = 0; c < ncol; ++c) st[c] = 0.0;
+        return 0.0;
+    }
+    if (lo >= 0.0) {
+        st[ncol - 1] = r;
+        return fabs(c0) + S + r;
+    }
+    const double lam = fmin(1.0, (hi / (hi - lo)) * (1.0 + 4.0 * kU64));
+    const double sh = -0.5 * lam * lo;
+    const double er = krelu * lam * ((fabs(c0) + S + r) - lo);
+    for (int c = 1; c <= D; ++c) st[c] *= lam;
+    c0 = fma(lam, c0, sh);
+    r = fma(lam, r, sh) + er;
+    st[0] = c0;
+    st[ncol - 1] = r;
+    return (fabs(c0) + lam * S + r) * (1.0 + 4.0 * kU64);
+}
+
+// One box on one wavefront.  ws: this wave's LDS (2 * nrow * ncol + 2 * 32 doubles).
+__device__ void recheck_box(const NetDev& net, const PropDev& prop, int64_t b,
+                            const float* __restrict__ blo, const float* __restrict__ bhi,
+                            float* __restrict__ g_lo, float* __restrict__ g_hi,
+                            int8_t* __restrict__ cls, unsigned long long* counter, double* ws,
+                            int nrow) {
+    const int lane = threadIdx.x & 63;
+    const int d = net.d, ncol = d + 2;
+    double* A = ws;
+    double* B = A + nrow * ncol;
+    double* mid = B + nrow * ncol;
+    double* rad = mid + SLR_MAX_D;
+    if (lane < d) {
+        const double l = blo[b * d + lane], h = bhi[b * d + lane];
+        const double m = 0.5 * (l + h);
+        mid[lane] = m;
+        rad[lane] = fmax(h - m, m - l) * (1.0 + 0x1p-50);
+    }
+    wave_sync();
+    double e = 0.0;
+    for (int j = lane; j < net.n1; j += 64) {
+        double* st = A + j * ncol;
+        const double bb = net.b1[j];
+        double c0 = bb, s = fabs(bb);
+        for (int k = 0; k < d; ++k) {
+            const double w = net.w1[j * d + k];
+            c0 = fma(w, mid[k], c0);
+            st[k + 1] = w * rad[k];
+            s += fabs(w) * (fabs(mid[k]) + rad[k]);
+        }
+        st[0] = c0;
+        st[ncol - 1] = 0.0;
+        e = fmax(e, relu64(st, ncol, net.kfirst64 * s + kEta64, net.kconc64, net.krelu64));
+    }
+    double emax = wave_max(e);
+    wave_sync();
+    double* in = A;
+    double* out = B;
+    for (int l = 0; l < net.n_affine - 2; ++l) {
+        const MidLayer* L = &net.mid[l];
+        e = 0.0;
+        for (int j = lane; j < L->n_out; j += 64) {
+            double* st = out + j * ncol;
+            for (int c = 0; c < ncol; ++c) st[c] = 0.0;
+            double A_row = 0.0;
+            for (int k = 0; k < L->n_in; ++k) {
+                const double w = L->wt[(size_t)k * L->n_out + j];
+                const double* x = in + k * ncol;
+                for (int c = 0; c < ncol - 1; ++c) st[c] = fma(w, x[c], st[c]);
+                st[ncol - 1] = fma(fabs(w), x[ncol - 1], st[ncol - 1]);
+                A_row += fabs(w);
+            }
+            const double bb = L->b[j];
+            st[0] += bb;
+            const double eps = L->kgam64 * (A_row * (1.0 + 0x1p-40) * emax + fabs(bb)) + kEta64;
+            e = fmax(e, relu64(st, ncol, eps, net.kconc64, net.krelu64));
+        }
+        emax = wave_max(e);
+        wave_sync();
+        double* t = in;
+        in = out;
+        out = t;
+    }
+    // output rows: one (row, column) item per lane
+    const int rows = prop.rows;
+    const int K = prop.n_last;
+    for (int it = lane; it < rows * ncol; it += 64) {
+        const int r = it / ncol, c = it % ncol;
+        double s = 0.0;
+        for (int k = 0; k < K; ++k) {
+            double w = prop.wg64[r * K + k];
+            if (c == ncol - 1) w = fabs(w);
+            s = fma(w, in[k * ncol + c], s);
+        }
+        out[it] = s;
+    }
+    wave_sync();
+    if (lane == 0) {
+        bool unsafe = true, safe = false;
+        for (int r = 0; r < rows; ++r) {
+            const double* o = out + r * ncol;
+            const double bg = prop.bg64[r];
+            const double G0 = o[0] + bg;
+            double Sg = 0.0;
+            for (int c = 1; c <= d; ++c) Sg += fabs(o[c]);
+            const double eps = prop.kout64 * (prop.ag64[r] * emax + fabs(bg)) + kEta64;
+            const double R = o[ncol - 1] + eps;
+            const double delta = net.kconc64 * (fabs(G0) + R + Sg);
+            const double glo = (G0 - (R + Sg)) - delta;
+            const double ghi = (G0 + (R + Sg)) + delta;
+            // float32 copies rounded outward
+            float flo = (float)glo;
+            if ((double)flo > glo) flo = nextafterf(flo, -INFINITY);
+            float fhi = (float)ghi;
+            if ((double)fhi < ghi) fhi = nextafterf(fhi, INFINITY);
+            if (g_lo) g_lo[b * rows + r] = flo;
+            if (g_hi) g_hi[b * rows + r] = fhi;
+            unsafe = unsafe && (glo > 0.0);
+            safe = safe || (ghi <= 0.0);
+        }
+        cls[b] = unsafe ? 1 : (safe ? 2 : 0);
+        if (counter) atomicAdd(counter, 1ull);
+    }
+    wave_sync();
+}
+
+// List mode (list != NULL): boxes list[0 .. *list_count) (indices into lo/hi/cls), one per wave.
+// Scan mode: every box with cls == 3 among the n boxes.
+// ------------------------------------------------------------------------------------------
+// Level bookkeeping: per-tile undecided counts, class histograms, compaction + bisection.
+// ------------------------------------------------------------------------------------------
+constexpr int kTile = 1024;   // boxes per bookkeeping workgroup (256 threads x 4)
+
+__device__ __forceinline__ unsigned block_sum256(unsigned v, unsigned* red) {
+    // returns the total; red holds 4 wave partials
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    if (lane == 0) red[wave] = v;
+    __syncthreads();
+    const unsigned t = red[0] + red[1] + red[2] + red[3];
+    __syncthreads();
+    return t;
+}
+
+// Class histogram of one 1024-box tile and its undecided count.
+__device__ __forceinline__ void count_tile(int64_t n, const int8_t* __restrict__ cls,
+                                           unsigned* __restrict__ tile_und, LevelStats* stats,
+                                           int64_t tile) {
+    __shared__ unsigned red[4];
+    const int64_t base = (int64_t)tile * kTile + threadIdx.x * 4;
+    unsigned nu = 0, ns = 0, nd = 0;
+    for (int q = 0; q < 4; ++q) {
+        const int64_t i = base + q;
+        if (i < n) {
+            const int8_t c = cls[i];
+            nu += c == 1;
+            ns += c == 2;
+            nd += c == 0;
+        }
+    }
+    nu = block_sum256(nu, red);
+    ns = block_sum256(ns, red);
+    nd = block_sum256(nd, red);
+    if (threadIdx.x == 0) {
+        tile_und[tile] = nd;
+        if (nu) atomicAdd(&stats->unsafe_cnt, (unsigned long long)nu);
+        if (ns) atomicAdd(&stats->safe_cnt, (unsigned long long)ns);
+        if (nd) atomicAdd(&stats->undecided_cnt, (unsigned long long)nd);
+    }
+}
+
+// Children of the undecided boxes of one 1024-box tile, written in parent order after those of
+// all earlier tiles.
+__device__ __forceinline__ void split_tile(int64_t n, int d, const int8_t* __restrict__ cls,
+                                           const unsigned* __restrict__ tile_und,
+                                           const float* __restrict__ lo,
+                                           const float* __restrict__ hi,
+                                           const unsigned long long* __restrict__ path,
+                                           float* __restrict__ lo2, float* __restrict__ hi2,
+                                           unsigned long long* __restrict__ path2,
+                                           unsigned* err, int64_t tile) {
+    __shared__ unsigned red[4];
+    __shared__ unsigned wpre[4];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    // offset of this tile: undecided boxes of all earlier tiles
+    unsigned pre = 0;
+    for (unsigned k = tid; k < tile; k += 256) pre += tile_und[k];
+    const unsigned base_out = block_sum256(pre, red);
+    if (tile_und[tile] == 0) return;
+    const int64_t base = (int64_t)tile * kTile + tid * 4;
+    unsigned flags = 0, cnt = 0;
+    for (int q = 0; q < 4; ++q) {
+        const int64_t i = base + q;
+        if (i < n && cls[i] == 0) {
+            flags |= 1u << q;
+            ++cnt;
+        }
+    }
+    // exclusive scan of cnt over the workgroup (thread order = box order)
+    unsigned incl = cnt;
+    for (int o = 1; o < 64; o <<= 1) {
+        const unsigned t = __shfl_up(incl, o);
+        if (lane >= o) incl += t;
+    }
+    if (lane == 63) wpre[wave] = incl;
+    __syncthreads();
+    unsigned woff = 0;
+    for (int w = 0; w < wave; ++w) woff += wpre[w];
+    unsigned rank = base_out + woff + incl - cnt;
+    for (int q = 0; q < 4; ++q) {
+        if (!(flags & (1u << q))) continue;
+        const int64_t i = base + q;
+        const float* l = lo + i * d;
+        const float* h = hi + i * d;
+        int js = 0;
+        float wbest = h[0] - l[0];
+        for (int k = 1; k < d; ++k) {
+            const float w = h[k] - l[k];
+            if (w > wbest) {
+                wbest = w;
+                js = k;
+            }
+        }
+        const float m = 0.5f * (l[js] + h[js]);
+        if (!(m - l[js] == h[js] - m && l[js] < m && m < h[js])) atomicOr(err, 1u);
+        const int64_t o0 = 2 * (int64_t)rank, o1 = o0 + 1;
+        for (int k = 0; k < d; ++k) {
+            lo2[o0 * d + k] = l[k];
+            hi2[o0 * d + k] = k == js ? m : h[k];
+            lo2[o1 * d + k] = k == js ? m : l[k];
+            hi2[o1 * d + k] = h[k];
+        }
+        const unsigned long long p = path[i];
+        path2[o0] = 2ull * p;
+        path2[o1] = 2ull * p + 1ull;
+        ++rank;
+    }
+}
+
+// Exact leaf-volume sums: sum_t count_t 2^(Dm - t) in 64-bit integers (the totals partition
+// 2^Dm exactly), converted to float64 fractions with a single rounding.
+__device__ __forceinline__ void volume_body(const LevelStats* stats, int levels, int stop_level,
+                                            int stopped, double* out3,
+                                            unsigned long long* out_counts, unsigned* err) {
+    const int Dm = levels - 1;
+    unsigned long long su = 0, ss = 0, sd = 0, nu = 0, ns = 0, nd = 0;
+    for (int t = 0; t < levels; ++t) {
+        su += stats[t].unsafe_cnt << (Dm - t);
+        ss += stats[t].safe_cnt << (Dm - t);
+        nu += stats[t].unsafe_cnt;
+        ns += stats[t].safe_cnt;
+    }
+    if (stopped) {
+        sd = stats[stop_level].undecided_cnt << (Dm - stop_level);
+        nd = stats[stop_level].undecided_cnt;
+    }
+    if (su + ss + sd != (1ull << Dm)) atomicOr(err, 2u);
+    out3[0] = ldexp((double)su, -Dm);
+    out3[1] = ldexp((double)ss, -Dm);
+    out3[2] = ldexp((double)sd, -Dm);
+    out_counts[0] = nu;
+    out_counts[1] = ns;
+    out_counts[2] = nd;
+}
+
+}  // namespace

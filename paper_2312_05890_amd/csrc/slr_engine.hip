@@ -1186,3 +1186,298 @@ extern "C" int count_approx(const slr_net* net, const slr_property* prop, const 
     out->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     return SLR_OK;
 }
+
+// ------------------------------------------------------------------------------------------
+// Batches of independent exact counts
+// ------------------------------------------------------------------------------------------
+struct slr_batch {
+    int n_inst = 0, levels = 0;
+    std::vector<int> order;           // device position -> caller index
+    void* mem = nullptr;
+    BatchInst* insts = nullptr;
+    BatchCtl* ctl = nullptr;
+    unsigned *bpre = nullptr, *cpre = nullptr, *amb = nullptr;
+    struct Cls {
+        int ncol, nt, uw, cbeg, cend, blocks;
+        size_t lds;
+    };
+    std::vector<Cls> cls;
+    int nrow = 0, ncol_max = 0;
+    hipStream_t cap = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    std::vector<BatchInst> host;
+};
+
+namespace {
+
+// The whole batch count: init, then every level's fixed launch sequence, then the volumes.
+int batch_enqueue(const slr_batch* b, hipStream_t s) {
+    HIP_TRY(launch_batch_init(b->insts, b->n_inst, s), "batch: init kernel");
+    for (int t = 0; t < b->levels; ++t) {
+        HIP_TRY(launch_batch_plan(b->insts, b->n_inst, b->ctl, b->bpre, b->cpre, (int)b->cls.size(), s),
+                "batch: plan kernel");
+        for (size_t c = 0; c < b->cls.size(); ++c) {
+            const auto& k = b->cls[c];
+            HIP_TRY(launch_batch_bound(k.ncol, k.nt, k.uw, k.blocks, k.lds, b->insts, b->ctl, b->bpre,
+                                       k.cbeg, k.cend, (int)c, b->amb, s),
+                    "batch: bound kernel");
+        }
+        HIP_TRY(launch_batch_recheck(b->insts, b->ctl, b->amb, b->nrow, b->ncol_max, s), "batch: recheck kernel");
+        HIP_TRY(launch_batch_count(b->insts, b->n_inst, b->ctl, b->cpre, s), "batch: count kernel");
+        HIP_TRY(launch_batch_advance(b->insts, b->n_inst, s), "batch: advance kernel");
+        HIP_TRY(launch_batch_split(b->insts, b->n_inst, b->ctl, b->cpre, s), "batch: split kernel");
+    }
+    HIP_TRY(launch_batch_volume(b->insts, b->n_inst, s), "batch: volume kernel");
+    return SLR_OK;
+}
+
+}  // namespace
+
+extern "C" void batch_free(slr_batch* b) {
+    if (!b) return;
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    if (b->cap) (void)hipStreamDestroy(b->cap);
+    if (b->mem) (void)hipFree(b->mem);
+    delete b;
+}
+
+extern "C" int batch_create(int32_t n_inst, const slr_net* const* nets,
+                            const slr_property* const* props, const double* const* lo,
+                            const double* const* hi, const int32_t* max_depth,
+                            const int64_t* max_leaves, int32_t use_graph, slr_batch** out) {
+    g_err.clear();
+    if (!out) return fail(SLR_EINVAL, "batch_create: out is NULL");
+    *out = nullptr;
+    if (n_inst < 1 || n_inst > SLR_MAX_BATCH)
+        return fail(SLR_EINVAL, "batch_create: n_inst must be in [1, %d]", SLR_MAX_BATCH);
+    if (!nets || !props || !lo || !hi || !max_depth || !max_leaves)
+        return fail(SLR_EINVAL, "batch_create: NULL array");
+    if (use_graph != 0 && use_graph != 1) return fail(SLR_EINVAL, "batch_create: use_graph must be 0 or 1");
+    struct Info {
+        int ncol, nt, uw, key;
+    };
+    std::vector<Info> info(n_inst);
+    for (int i = 0; i < n_inst; ++i) {
+        char who[64];
+        snprintf(who, sizeof who, "batch_create: instance %d", i);
+        int rc = check_pair(nets[i], props[i], who);
+        if (rc) return rc;
+        if ((rc = check_box(nets[i], lo[i], hi[i], who))) return rc;
+        if (max_depth[i] < 0 || max_depth[i] > kMaxLevels - 1)
+            return fail(SLR_EINVAL, "%s: max_depth must be in [0, %d]", who, kMaxLevels - 1);
+        if (max_leaves[i] < 1 || max_leaves[i] > (1 << 22))
+            return fail(SLR_EINVAL, "%s: max_leaves must be in [1, 2^22]", who);
+        Info& f = info[i];
+        if (batch_class_of(nets[i]->dev, props[i]->dev, &f.ncol, &f.nt, &f.uw) != 0)
+            return fail(SLR_EUNSUPPORTED, "%s: shape (d=%d, widths up to %d) outside the batch kernels "
+                        "(d <= 11, widths <= 128)", who, nets[i]->dev.d, nets[i]->dev.n_max);
+        f.key = (f.ncol * 8 + f.nt) * 8 + f.uw;
+    }
+    slr_batch* b = new slr_batch;
+    b->n_inst = n_inst;
+    b->order.resize(n_inst);
+    for (int i = 0; i < n_inst; ++i) b->order[i] = i;
+    std::stable_sort(b->order.begin(), b->order.end(), [&](int x, int y) { return info[x].key < info[y].key; });
+    // classes, in device order
+    std::vector<int> cls_of(n_inst);
+    for (int p = 0; p < n_inst; ++p) {
+        const Info& f = info[b->order[p]];
+        if (b->cls.empty() || b->cls.back().ncol != f.ncol || b->cls.back().nt != f.nt || b->cls.back().uw != f.uw) {
+            if ((int)b->cls.size() == SLR_MAX_CLASSES) {
+                batch_free(b);
+                return fail(SLR_EINTERNAL, "batch_create: too many kernel classes");
+            }
+            b->cls.push_back({f.ncol, f.nt, f.uw, p, p, 0, 0});
+        }
+        b->cls.back().cend = p + 1;
+        cls_of[p] = (int)b->cls.size() - 1;
+    }
+    // device memory: control block, offsets, FP64 list, then per-instance regions
+    size_t o = 0;
+    auto take = [&](size_t bytes) {
+        const size_t at = o;
+        o += align256(bytes);
+        return at;
+    };
+    const size_t o_insts = take(sizeof(BatchInst) * n_inst);
+    const size_t o_ctl = take(sizeof(BatchCtl));
+    const size_t o_bpre = take(sizeof(unsigned) * (n_inst + 1));
+    const size_t o_cpre = take(sizeof(unsigned) * (n_inst + 1));
+    size_t amb_cap = 0;
+    for (int i = 0; i < n_inst; ++i) amb_cap += (size_t)max_leaves[i];
+    const size_t o_amb = take(sizeof(unsigned) * amb_cap);
+    struct Reg {
+        size_t lo[2], hi[2], path[2], cls, tile_und, stats, root;
+    };
+    std::vector<Reg> reg(n_inst);
+    for (int p = 0; p < n_inst; ++p) {
+        const int i = b->order[p];
+        const int d = nets[i]->dev.d;
+        const int64_t cap = max_leaves[i];
+        Reg& r = reg[p];
+        for (int k = 0; k < 2; ++k) {
+            r.lo[k] = take(sizeof(float) * d * cap);
+            r.hi[k] = take(sizeof(float) * d * cap);
+            r.path[k] = take(sizeof(unsigned long long) * cap);
+        }
+        r.cls = take(cap);
+        r.tile_und = take(sizeof(unsigned) * level_tiles(cap));
+        r.stats = take(sizeof(LevelStats) * SLR_MAX_LEVELS);
+        r.root = take(sizeof(float) * 2 * d);
+    }
+    hipError_t e = hipMalloc(&b->mem, o);
+    if (e != hipSuccess) {
+        delete b;
+        return fail(SLR_ENOMEM, "batch_create: hipMalloc(%zu): %s", o, hipGetErrorString(e));
+    }
+    char* base = (char*)b->mem;
+    b->insts = (BatchInst*)(base + o_insts);
+    b->ctl = (BatchCtl*)(base + o_ctl);
+    b->bpre = (unsigned*)(base + o_bpre);
+    b->cpre = (unsigned*)(base + o_cpre);
+    b->amb = (unsigned*)(base + o_amb);
+    b->host.assign(n_inst, BatchInst{});
+    int levels = 0;
+    for (int p = 0; p < n_inst; ++p) {
+        const int i = b->order[p];
+        BatchInst& I = b->host[p];
+        const Reg& r = reg[p];
+        I.net = nets[i]->dev;
+        I.prop = props[i]->dev;
+        for (int k = 0; k < 2; ++k) {
+            I.lo[k] = (float*)(base + r.lo[k]);
+            I.hi[k] = (float*)(base + r.hi[k]);
+            I.path[k] = (unsigned long long*)(base + r.path[k]);
+        }
+        I.cls = (int8_t*)(base + r.cls);
+        I.tile_und = (unsigned*)(base + r.tile_und);
+        I.stats = (LevelStats*)(base + r.stats);
+        I.root = (const float*)(base + r.root);
+        I.d = I.net.d;
+        I.max_depth = max_depth[i];
+        I.max_leaves = max_leaves[i];
+        I.cls_id = cls_of[p];
+        I.sp = 4 * I.net.mt_max + ((I.net.mt_max & 1) ? 0 : 4);
+        levels = std::max(levels, max_depth[i] + 1);
+        std::vector<float> root(2 * I.d);
+        for (int k = 0; k < I.d; ++k) {
+            root[k] = (float)lo[i][k];
+            root[I.d + k] = (float)hi[i][k];
+        }
+        e = hipMemcpy(base + r.root, root.data(), root.size() * sizeof(float), hipMemcpyHostToDevice);
+        if (e != hipSuccess) {
+            batch_free(b);
+            return hip_fail(e, "batch_create: upload");
+        }
+        b->cls[cls_of[p]].lds = std::max(b->cls[cls_of[p]].lds,
+                                         batch_bound_lds(b->cls[cls_of[p]].ncol, b->cls[cls_of[p]].nt,
+                                                         I.net.mt_max, I.prop.rows));
+        const int ncol = I.d + 2;
+        b->ncol_max = std::max(b->ncol_max, ncol);
+        b->nrow = std::max(b->nrow, std::max(I.net.n_max, I.prop.rows * ncol));
+    }
+    b->levels = levels;
+    BatchCtl hc{};
+    for (size_t c = 0; c < b->cls.size(); ++c) hc.tbox[c] = 16 * b->cls[c].nt;
+    e = hipMemcpy(b->ctl, &hc, sizeof hc, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(b->insts, b->host.data(), sizeof(BatchInst) * n_inst, hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        batch_free(b);
+        return hip_fail(e, "batch_create: upload");
+    }
+    for (auto& k : b->cls) {
+        if (k.lds > 160 * 1024) {
+            batch_free(b);
+            return fail(SLR_EUNSUPPORTED, "batch_create: a kernel class needs %zu bytes of LDS", k.lds);
+        }
+        e = batch_prepare_class(k.ncol, k.nt, k.uw, k.lds, &k.blocks);
+        if (e != hipSuccess) {
+            batch_free(b);
+            return hip_fail(e, "batch_create: kernel class");
+        }
+    }
+    e = batch_prepare_recheck(b->nrow, b->ncol_max);
+    if (e != hipSuccess) {
+        batch_free(b);
+        return hip_fail(e, "batch_create: recheck kernel");
+    }
+    if (use_graph) {
+        // capture the launch sequence once on a private stream (default priority)
+        e = hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking);
+        if (e == hipSuccess) e = hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal);
+        if (e != hipSuccess) {
+            batch_free(b);
+            return hip_fail(e, "batch_create: capture");
+        }
+        int rc = batch_enqueue(b, b->cap);
+        hipGraph_t g = nullptr;
+        e = hipStreamEndCapture(b->cap, &g);
+        b->graph = g;
+        if (rc) {
+            const std::string msg = g_err;
+            batch_free(b);
+            return fail(rc, "%s", msg.c_str());
+        }
+        if (e == hipSuccess) e = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0);
+        if (e != hipSuccess) {
+            batch_free(b);
+            return hip_fail(e, "batch_create: graph");
+        }
+    }
+    *out = b;
+    return SLR_OK;
+}
+
+extern "C" int batch_run(slr_batch* b, void* stream, slr_count_result* results) {
+    g_err.clear();
+    if (!b || !results) return fail(SLR_EINVAL, "batch_run: NULL argument");
+    const auto t0 = std::chrono::steady_clock::now();
+    hipStream_t s = (hipStream_t)stream;
+    if (b->exec) {
+        HIP_TRY(hipGraphLaunch(b->exec, s), "batch_run: graph launch");
+    } else {
+        int rc = batch_enqueue(b, s);
+        if (rc) return rc;
+    }
+    HIP_TRY(hipMemcpyAsync(b->host.data(), b->insts, sizeof(BatchInst) * b->n_inst, hipMemcpyDeviceToHost, s),
+            "batch_run: readback");
+    HIP_TRY(hipStreamSynchronize(s), "batch_run: sync");
+    const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    int worst = SLR_OK;
+    for (int p = 0; p < b->n_inst; ++p) {
+        const BatchInst& I = b->host[p];
+        if (I.err & 1u) return fail(SLR_EINTERNAL, "batch_run: instance %d: a bisection midpoint is not exact in float32", b->order[p]);
+        if (I.err & 2u) return fail(SLR_EINTERNAL, "batch_run: instance %d: leaf volumes do not sum to the box volume", b->order[p]);
+        if (I.err & 4u) return fail(SLR_EINTERNAL, "batch_run: instance %d: level counts do not add up", b->order[p]);
+        if (I.active) return fail(SLR_EINTERNAL, "batch_run: instance %d did not finish", b->order[p]);
+        slr_count_result& r = results[b->order[p]];
+        memset(&r, 0, sizeof r);
+        r.unsafe = I.vol[0];
+        r.safe = I.vol[1];
+        r.undecided = I.vol[2];
+        r.n_unsafe = (int64_t)I.counts[0];
+        r.n_safe = (int64_t)I.counts[1];
+        r.n_undecided = (int64_t)I.counts[2];
+        r.n_boxes_bounded = I.bounded;
+        r.n_recheck64 = (int64_t)I.rechecks;
+        r.depth_reached = I.levels - 1;
+        r.status = I.status;
+        r.seconds = secs;
+        if (I.status == SLR_BUDGET) worst = SLR_BUDGET;
+    }
+    return worst;
+}
+
+extern "C" int count_exact_batch(int32_t n_inst, const slr_net* const* nets,
+                                 const slr_property* const* props, const double* const* lo,
+                                 const double* const* hi, const int32_t* max_depth,
+                                 const int64_t* max_leaves, void* stream, slr_count_result* results) {
+    slr_batch* b = nullptr;
+    int rc = batch_create(n_inst, nets, props, lo, hi, max_depth, max_leaves, 0, &b);
+    if (rc) return rc;
+    rc = batch_run(b, stream, results);
+    batch_free(b);
+    return rc;
+}

@@ -24,6 +24,9 @@
 #define SLR_MAX_WIDTH 256
 #define SLR_MAX_ROWS 16
 #define SLR_MAX_OUT 64
+#define SLR_MAX_LEVELS 63
+#define SLR_MAX_BATCH 1024
+#define SLR_MAX_CLASSES 64
 
 // One hidden-to-hidden affine layer (its input is a hidden ReLU layer).
 struct MidLayer {
@@ -182,3 +185,61 @@ hipError_t launch_ambiguity(int64_t n, int rows, const float* wlo, const float* 
 hipError_t launch_center_objective(const NetDev& net, const PropDev& prop, int64_t n,
                                    const float* lo, const float* hi, int8_t* obj,
                                    hipStream_t stream);
+
+// ---------------------------------------------------------------------------------------------
+// Batches of independent instances (slr_batch.hip): every instance keeps its own frontier and
+// counters in device memory; one level of all instances is a fixed sequence of launches that
+// read their work sizes on the device, so the whole count can be captured in one graph.
+// ---------------------------------------------------------------------------------------------
+struct BatchInst {
+    NetDev net;
+    PropDev prop;
+    float* lo[2];
+    float* hi[2];
+    unsigned long long* path[2];
+    int8_t* cls;
+    unsigned* tile_und;
+    LevelStats* stats;           // [SLR_MAX_LEVELS]
+    const float* root;           // [2 d]: lower corner, then upper corner
+    int d, max_depth, cls_id, sp;
+    long long max_leaves;
+    // dynamic state, reset by the init kernel
+    long long n, n_next, resolved, bounded;
+    int cur, level, active, split_pending;
+    int status, stop_level, stopped, levels;
+    unsigned long long rechecks;
+    unsigned err;
+    unsigned pad;
+    double vol[3];
+    unsigned long long counts[3];
+};
+
+struct BatchCtl {
+    unsigned head[SLR_MAX_CLASSES];     // bound work-queue heads (one queue per kernel class)
+    unsigned ntiles[SLR_MAX_CLASSES];   // bound tiles per class at the current level
+    int tbox[SLR_MAX_CLASSES];          // boxes per bound tile of each class
+    unsigned amb_count;                 // boxes listed for the FP64 re-decision
+    unsigned ctiles;                    // 1024-box bookkeeping tiles at the current level
+};
+
+// Kernel class of the batch bound kernel: (NCOL, NT, UW) of the LDS-staged tile.
+bool batch_class_supported(int ncol, int nt, int uw);
+int batch_class_of(const NetDev& net, const PropDev& prop, int* ncol, int* nt, int* uw);
+size_t batch_bound_lds(int ncol, int nt, int mt_max, int rows);
+hipError_t batch_prepare_class(int ncol, int nt, int uw, size_t lds, int* blocks);
+hipError_t launch_batch_init(BatchInst* insts, int n_inst, hipStream_t stream);
+hipError_t launch_batch_plan(BatchInst* insts, int n_inst, BatchCtl* ctl, unsigned* bpre,
+                             unsigned* cpre, int n_classes, hipStream_t stream);
+hipError_t launch_batch_bound(int ncol, int nt, int uw, int blocks, size_t lds, BatchInst* insts,
+                              BatchCtl* ctl, const unsigned* bpre, int cbeg, int cend, int c,
+                              unsigned* amb_list, hipStream_t stream);
+hipError_t batch_prepare_recheck(int nrow, int ncol_max);
+hipError_t launch_batch_recheck(BatchInst* insts, BatchCtl* ctl, const unsigned* amb_list,
+                                int nrow, int ncol_max, hipStream_t stream);
+hipError_t launch_batch_count(BatchInst* insts, int n_inst, BatchCtl* ctl, const unsigned* cpre,
+                              hipStream_t stream);
+hipError_t launch_batch_advance(BatchInst* insts, int n_inst, hipStream_t stream);
+hipError_t launch_batch_split(BatchInst* insts, int n_inst, BatchCtl* ctl, const unsigned* cpre,
+                              hipStream_t stream);
+hipError_t launch_batch_volume(BatchInst* insts, int n_inst, hipStream_t stream);
+int batch_num_cu();

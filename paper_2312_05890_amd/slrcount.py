@@ -22,7 +22,8 @@ UNDECIDED, UNSAFE, SAFE = 0, 1, 2
 EXPORTS = ("load_net", "free_net", "load_property", "free_property", "bound_boxes",
            "workspace_size", "count_exact", "count_approx", "sample_violations", "last_error",
            "bound_kernel_variant", "alpha_size", "alpha_tape_size", "bound_boxes_alpha",
-           "bound_boxes_backward", "alpha_workspace_size", "alpha_optimize")
+           "bound_boxes_backward", "alpha_workspace_size", "alpha_optimize", "batch_create",
+           "batch_run", "batch_free", "count_exact_batch")
 
 
 class SlrError(RuntimeError):
@@ -116,6 +117,18 @@ def lib() -> C.CDLL:
         L.alpha_optimize.argtypes = [vp, vp, i64, vp, vp, C.POINTER(AlphaOpts), vp, vp, vp, vp,
                                      vp, C.c_size_t, vp]
         L.alpha_optimize.restype = C.c_int
+        L.batch_create.argtypes = [i32, C.POINTER(vp), C.POINTER(vp), C.POINTER(vp),
+                                   C.POINTER(vp), C.POINTER(C.c_int32), C.POINTER(C.c_int64),
+                                   i32, C.POINTER(vp)]
+        L.batch_create.restype = C.c_int
+        L.batch_run.argtypes = [vp, vp, C.POINTER(CountResult)]
+        L.batch_run.restype = C.c_int
+        L.batch_free.argtypes = [vp]
+        L.batch_free.restype = None
+        L.count_exact_batch.argtypes = [i32, C.POINTER(vp), C.POINTER(vp), C.POINTER(vp),
+                                        C.POINTER(vp), C.POINTER(C.c_int32),
+                                        C.POINTER(C.c_int64), vp, C.POINTER(CountResult)]
+        L.count_exact_batch.restype = C.c_int
         L.last_error.argtypes = []
         L.last_error.restype = C.c_char_p
         _LIB = L
@@ -462,3 +475,70 @@ def __getattr__(name):
             _SLRBOUND = _make_slr_bound()
         return _SLRBOUND
     raise AttributeError(name)
+
+
+# ---------------------------------------------------------------------------------------------
+# batches of independent exact counts
+# ---------------------------------------------------------------------------------------------
+def _batch_arrays(items):
+    """items: sequence of (net, prop, lo, hi, max_depth, max_leaves)."""
+    n = len(items)
+    keep = []
+    nets = (C.c_void_p * n)(*[it[0].handle.value for it in items])
+    props = (C.c_void_p * n)(*[it[1].handle.value for it in items])
+    los, his = [], []
+    for it in items:
+        lo = np.ascontiguousarray(it[2], np.float64)
+        hi = np.ascontiguousarray(it[3], np.float64)
+        keep += [lo, hi]
+        los.append(lo.ctypes.data)
+        his.append(hi.ctypes.data)
+    lo_a = (C.c_void_p * n)(*los)
+    hi_a = (C.c_void_p * n)(*his)
+    depth = (C.c_int32 * n)(*[int(it[4]) for it in items])
+    leaves = (C.c_int64 * n)(*[int(it[5]) for it in items])
+    return nets, props, lo_a, hi_a, depth, leaves, keep
+
+
+def _results(res, rc):
+    out = []
+    for r in res:
+        d = {f: getattr(r, f) for f, _ in CountResult._fields_}
+        d["rc"] = rc
+        out.append(d)
+    return out
+
+
+class Batch:
+    """Many exact counts advanced together on the device (``batch_create``); ``run()`` replays
+    the captured graph (or issues the same launches) and returns one result dict per instance."""
+
+    def __init__(self, items, use_graph: bool = True):
+        self.items = list(items)   # keeps nets and properties alive
+        self.n = len(self.items)
+        nets, props, lo, hi, depth, leaves, self._keep = _batch_arrays(self.items)
+        h = C.c_void_p()
+        _check(lib().batch_create(self.n, nets, props, lo, hi, depth, leaves,
+                                  int(bool(use_graph)), C.byref(h)))
+        self.handle = h
+
+    def run(self, stream=None):
+        res = (CountResult * self.n)()
+        rc = _check(lib().batch_run(self.handle, _stream(stream), res))
+        return _results(res, rc)
+
+    def __del__(self):
+        if getattr(self, "handle", None) and _LIB is not None:
+            _LIB.batch_free(self.handle)
+            self.handle = None
+
+
+def count_exact_batch(items, stream=None):
+    """One-shot batch (no graph): items are (net, prop, lo, hi, max_depth, max_leaves)."""
+    items = list(items)
+    n = len(items)
+    nets, props, lo, hi, depth, leaves, keep = _batch_arrays(items)
+    res = (CountResult * n)()
+    rc = _check(lib().count_exact_batch(n, nets, props, lo, hi, depth, leaves, _stream(stream),
+                                        res))
+    return _results(res, rc)
