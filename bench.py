@@ -68,9 +68,15 @@ def bytes_per_box(d):
     return 2 * d * 4 + 1
 
 
+KERNEL_SOURCES = ("paper_2312_05890_amd/csrc/slr_device.h", "paper_2312_05890_amd/csrc/slr_kernels.hip")
+
+
 def kernel_source_hash():
-    src = os.path.join(ROOT, "paper_2312_05890_amd", "csrc", "slr_kernels.hip")
-    return hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    """Hash of the bound kernel's sources: counter readings taken on other code are stale."""
+    m = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        m.update(open(os.path.join(ROOT, f), "rb").read())
+    return m.hexdigest()[:16]
 
 
 def measured_traffic():
@@ -166,6 +172,54 @@ def cpu_alpha_baseline(inst, n, steps, seed):
             "sample": f"FP64 torch oracle, {n} boxes x {steps} Adam steps, {dt:.1f} s"}
 
 
+def batch_section(E, torch, seed, reps=3):
+    """256 uneven instances (d 5..10, 3..6 hidden layers of 32..128, 2..5 outputs, random
+    linear property, depth 4 d, 2^16 leaves each) counted as one batch (captured graph, and the
+    same launches issued directly) and one instance at a time with count_exact."""
+    import synth
+    insts = synth.batch(seed)
+    items = []
+    for inst in insts:
+        net = E.Net(inst.net)
+        items.append((net, E.Property(net, inst.C, inst.dvec), inst.lo, inst.hi,
+                      inst.max_depth, inst.max_leaves))
+    t0 = time.perf_counter()
+    b = E.Batch(items, use_graph=True)
+    t_create = time.perf_counter() - t0
+    res = b.run()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        res = b.run()
+    t_graph = (time.perf_counter() - t0) / reps
+    d = E.Batch(items, use_graph=False)
+    d.run()
+    t0 = time.perf_counter()
+    d.run()
+    t_direct = time.perf_counter() - t0
+    ws_bytes = max(E.workspace_size(it[0], it[1], it[5]) for it in items)
+    ws = torch.empty(ws_bytes, dtype=torch.uint8, device="cuda")
+    E.count_exact(*items[0][:4], items[0][4], items[0][5], workspace=ws)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    seq = [E.count_exact(*it[:4], it[4], it[5], workspace=ws) for it in items]
+    t_seq = time.perf_counter() - t0
+    boxes = sum(r["n_boxes_bounded"] for r in res)
+    flops = sum(r["n_boxes_bounded"] * flops_per_box(inst.sizes, inst.C.shape[0])
+                for r, inst in zip(res, insts))
+    agree = all(r[k] == q[k] for r, q in zip(res, seq)
+                for k in ("unsafe", "safe", "undecided", "n_boxes_bounded"))
+    return {"workload": "256 instances: d 5..10, 3..6 hidden layers of 32/64/96/128, 2..5 "
+                        "outputs, c ~ N(0,1), [0,1]^d, depth 4d, 2^16 leaves each (seed %d)" % seed,
+            "boxes_per_batch": boxes, "graph_ms": t_graph * 1e3, "direct_ms": t_direct * 1e3,
+            "sequential_ms": t_seq * 1e3, "create_ms": t_create * 1e3,
+            "boxes_per_s_graph": boxes / t_graph, "boxes_per_s_sequential": boxes / t_seq,
+            "speedup_vs_sequential": t_seq / t_graph,
+            "achieved_tflops_graph": flops / t_graph / 1e12,
+            "results_equal_sequential": agree,
+            "instances_resolved": sum(1 for r in res if r["undecided"] == 0.0)}
+
+
 def alpha_section(E, torch, seed, cpu):
     import synth
     a5 = synth.acas(seed)
@@ -193,6 +247,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-alpha", action="store_true",
                     help="skip the alpha-mode measurements (optimizer throughput, counts with alpha)")
+    ap.add_argument("--no-batch", action="store_true",
+                    help="skip the batched-instances measurement")
     ap.add_argument("--variant", type=int, default=0,
                     help="bound kernel: 0 automatic, 1 LDS-staged, 2 register-resident")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
@@ -274,6 +330,8 @@ def main():
         "depth_reached": r0["depth_reached"],
         "recheck64_per_step": r0["n_recheck64"],
     }
+    if not args.no_batch:
+        line["batch"] = batch_section(E, torch, args.seed)
     if not args.no_alpha:
         line["alpha"] = alpha_section(E, torch, args.seed, not args.no_cpu_baseline)
     if not args.no_cpu_baseline:
