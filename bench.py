@@ -79,14 +79,17 @@ def kernel_source_hash():
     return m.hexdigest()[:16]
 
 
-def measured_traffic():
-    """HBM bytes per bound launch from the committed rocprofv3 counter summary, if current."""
+def measured_traffic(shape):
+    """HBM bytes per bound launch from the committed rocprofv3 counter summary, if it was taken
+    on the same kernel sources and tile shape."""
     path = os.path.join(ROOT, "profiles", "bound_f32_acas_traffic.json")
     try:
         rec = json.load(open(path))
     except (OSError, ValueError):
         return None
     if rec.get("kernel_source_sha256_16") != kernel_source_hash():
+        return None
+    if list(rec.get("tile_shape", [])) != list(shape):
         return None
     return rec.get("bytes_per_launch")
 
@@ -249,6 +252,8 @@ def main():
                     help="skip the alpha-mode measurements (optimizer throughput, counts with alpha)")
     ap.add_argument("--no-batch", action="store_true",
                     help="skip the batched-instances measurement")
+    ap.add_argument("--no-tile-cache", action="store_true",
+                    help="ignore the autotuner's tile-shape cache (default shapes)")
     ap.add_argument("--variant", type=int, default=0,
                     help="bound kernel: 0 automatic, 1 LDS-staged, 2 register-resident")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
@@ -265,8 +270,11 @@ def main():
     import synth
     import paper_2312_05890_amd as E
 
+    from paper_2312_05890_amd import autotune
+    tuned = 0 if args.no_tile_cache else autotune.load()
     E.bound_kernel_variant(args.variant)
     inst = synth.acas(args.seed)
+    shape = E.slrcount.current_tile_shape(inst.sizes)
     net = E.Net(inst.net)
     prop = E.Property(net, inst.C, inst.dvec)
     chunk = 65536
@@ -298,7 +306,7 @@ def main():
     bound_s = sum(r["bound_ms"] for r in res) / 1e3
     launches = sum(r["bound_launches"] for r in res)
     achieved = boxes * fpb / bound_s / 1e12
-    traffic = measured_traffic()
+    traffic = measured_traffic(shape)
     r0 = res[-1]
     line = {
         "metric": METRIC,
@@ -316,7 +324,8 @@ def main():
         "config": {"workload": "exact count, 5-50x6-5 ReLU MLP (He-normal seed %d), [0,1]^5, "
                                "unsafe iff y0-y1>0, max depth 40, 2^20-leaf budget, 65536-box "
                                "launches" % args.seed,
-                   "mode": "plain", "kernel_variant": args.variant},
+                   "mode": "plain", "kernel_variant": args.variant,
+                   "tile_shape": list(shape), "tile_cache_entries": tuned},
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_FP32_MFMA,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_MFMA,
                      "traffic": traffic},

@@ -102,6 +102,17 @@ int bound_boxes(const slr_net* net, const slr_property* prop, int64_t n, const f
  */
 int bound_kernel_variant(int32_t variant);
 
+/*
+ * bound_tile_shape: process-wide tile shape of the LDS-staged bound kernel for networks with
+ * input dimension class of d and mt_max = ceil(max hidden width / 16): nt 16-box N tiles per
+ * workgroup, uw output tiles per wavefront per layer, nw wavefronts per workgroup.  Instantiated
+ * shapes: (4,1,4) (2,1,4) (1,1,4) (1,2,4), (1,1,8) for d <= 23, (1,4,4) for d <= 15, (1,2,8) for
+ * d <= 11; the shape must cover the hidden tiles (mt_max * nt <= uw * nw).  nt = 0 restores the
+ * default.  Results do not depend on the shape.  Used by the autotuner (a JSON cache of the
+ * measured best shape per class); batches use the shape when their kernels have it.
+ */
+int bound_tile_shape(int32_t d, int32_t mt_max, int32_t nt, int32_t uw, int32_t nw);
+
 /* Options of the exact count (Alg. 1). */
 typedef struct {
     int32_t max_depth;      /* boxes still undecided at this depth are not split (0..62)   */

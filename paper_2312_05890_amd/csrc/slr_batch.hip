@@ -94,23 +94,25 @@ __global__ void batch_plan_kernel(BatchInst* insts, int n_inst, BatchCtl* ctl,
     ctl->ctiles = ctot;
 }
 
-template <int NCOL, int NT, int UW>
-__global__ __launch_bounds__(kNW * 64) void batch_bound_kernel(BatchInst* insts, BatchCtl* ctl,
-                                                               const unsigned* __restrict__ bpre,
-                                                               int cbeg, int cend, int c,
-                                                               unsigned* __restrict__ amb_list) {
+template <int NCOL, int NT, int UW, int NW>
+__global__ __launch_bounds__(NW * 64) void batch_bound_kernel(BatchInst* insts, BatchCtl* ctl,
+                                                              const unsigned* __restrict__ bpre,
+                                                              int cbeg, int cend, int c,
+                                                              unsigned* __restrict__ amb_list) {
     __shared__ unsigned s_t;
     const unsigned total = ctl->ntiles[c];
     for (;;) {
         if (threadIdx.x == 0) s_t = atomicAdd(&ctl->head[c], 1u);
         __syncthreads();
-        const unsigned t = s_t;
+        // uniform across the workgroup: keeps the instance index and every descriptor field
+        // in scalar registers (scalar loads) instead of per-lane copies
+        const unsigned t = __builtin_amdgcn_readfirstlane(s_t);
         __syncthreads();
         if (t >= total) break;
         const int i = find_owner(bpre, cbeg, cend, t);
         const BatchInst& I = insts[i];
         const int64_t box0 = (int64_t)(t - bpre[i]) * (NT * 16);
-        bound_tile<NCOL, NT, UW>(I.net, I.prop, I.n, box0, I.lo[I.cur], I.hi[I.cur], nullptr,
+        bound_tile<NCOL, NT, UW, NW>(I.net, I.prop, I.n, box0, I.lo[I.cur], I.hi[I.cur], nullptr,
                                  nullptr, I.cls, 0, I.sp, amb_list, &ctl->amb_count,
                                  (unsigned)i << 22);
         __syncthreads();   // the tile's LDS is reused by the next tile
@@ -126,7 +128,7 @@ __global__ __launch_bounds__(256) void batch_recheck_kernel(BatchInst* insts, Ba
     double* ws = sm + (size_t)wave * (2 * nrow * ncol_max + 2 * SLR_MAX_D);
     const unsigned total = ctl->amb_count;
     for (unsigned k = blockIdx.x * waves + wave; k < total; k += gridDim.x * waves) {
-        const unsigned e = amb_list[k];
+        const unsigned e = __builtin_amdgcn_readfirstlane(amb_list[k]);   // one box per wave
         BatchInst& I = insts[e >> 22];
         recheck_box(I.net, I.prop, (int64_t)(e & 0x3FFFFFu), I.lo[I.cur], I.hi[I.cur], nullptr,
                     nullptr, I.cls, &I.rechecks, ws, nrow);
@@ -202,26 +204,20 @@ int ncol_class_b(int d) {
     return -1;
 }
 
-void tile_class_b(int mt_max, int* NT, int* UW) {
-    if (mt_max <= 1) { *NT = 4; *UW = 1; }
-    else if (mt_max == 2) { *NT = 2; *UW = 1; }
-    else if (mt_max <= 4) { *NT = 1; *UW = 1; }
-    else { *NT = 1; *UW = 2; }
-}
-
-template <int NCOL, int NT, int UW>
+template <int NCOL, int NT, int UW, int NW>
 const void* kern_ptr() {
-    return (const void*)batch_bound_kernel<NCOL, NT, UW>;
+    return (const void*)batch_bound_kernel<NCOL, NT, UW, NW>;
 }
 
-const void* class_kernel(int ncol, int nt, int uw) {
-#define SLR_T(C)                                                  \
-    if (ncol == C) {                                              \
-        if (nt == 4 && uw == 1) return kern_ptr<C, 4, 1>();       \
-        if (nt == 2 && uw == 1) return kern_ptr<C, 2, 1>();       \
-        if (nt == 1 && uw == 1) return kern_ptr<C, 1, 1>();       \
-        if (nt == 1 && uw == 2) return kern_ptr<C, 1, 2>();       \
-        return nullptr;                                           \
+const void* class_kernel(int ncol, TileShape t) {
+#define SLR_T(C)                                                                    \
+    if (ncol == C) {                                                                \
+        if (t.nt == 4 && t.uw == 1 && t.nw == 4) return kern_ptr<C, 4, 1, 4>();     \
+        if (t.nt == 2 && t.uw == 1 && t.nw == 4) return kern_ptr<C, 2, 1, 4>();     \
+        if (t.nt == 1 && t.uw == 1 && t.nw == 4) return kern_ptr<C, 1, 1, 4>();     \
+        if (t.nt == 1 && t.uw == 2 && t.nw == 4) return kern_ptr<C, 1, 2, 4>();     \
+        if (t.nt == 1 && t.uw == 1 && t.nw == 8) return kern_ptr<C, 1, 1, 8>();     \
+        return nullptr;                                                             \
     }
     SLR_T(4) SLR_T(5) SLR_T(6) SLR_T(7) SLR_T(8) SLR_T(9) SLR_T(10) SLR_T(11) SLR_T(12) SLR_T(14)
 #undef SLR_T
@@ -245,24 +241,29 @@ int batch_num_cu() {
     return g_cu;
 }
 
-bool batch_class_supported(int ncol, int nt, int uw) { return class_kernel(ncol, nt, uw) != nullptr; }
+bool batch_class_supported(int ncol, TileShape t) { return class_kernel(ncol, t) != nullptr; }
 
-int batch_class_of(const NetDev& net, const PropDev& prop, int* ncol, int* nt, int* uw) {
+int batch_class_of(const NetDev& net, const PropDev& prop, int* ncol, TileShape* t) {
     (void)prop;
     *ncol = ncol_class_b(net.d);
     if (*ncol < 0 || net.mt_max > 8) return -1;
-    tile_class_b(net.mt_max, nt, uw);
-    return batch_class_supported(*ncol, *nt, *uw) ? 0 : -1;
+    // the tuned shape of this class when the batch kernels have it, else the default
+    *t = tile_shape_for(net.d, net.mt_max);
+    if (!batch_class_supported(*ncol, *t)) {
+        if (net.mt_max <= 1) *t = {4, 1, 4};
+        else if (net.mt_max == 2) *t = {2, 1, 4};
+        else if (net.mt_max <= 4) *t = {1, 1, 4};
+        else *t = {1, 2, 4};
+    }
+    return batch_class_supported(*ncol, *t) ? 0 : -1;
 }
 
-size_t batch_bound_lds(int ncol, int nt, int mt_max, int rows) {
-    const int T = nt * 16;
-    const int SP = 4 * mt_max + ((mt_max & 1) ? 0 : 4);
-    return sizeof(float) * ((size_t)nt * ncol * 64 * SP + 2 * (size_t)mt_max * T + 4 * (size_t)rows * T * ncol);
+size_t batch_bound_lds(int ncol, TileShape t, int mt_max, int rows) {
+    return bound_lds_bytes(ncol, t, mt_max, rows);
 }
 
-hipError_t batch_prepare_class(int ncol, int nt, int uw, size_t lds, int* blocks) {
-    const void* k = class_kernel(ncol, nt, uw);
+hipError_t batch_prepare_class(int ncol, TileShape t, size_t lds, int* blocks) {
+    const void* k = class_kernel(ncol, t);
     if (!k) return hipErrorInvalidValue;
     if (lds > 64 * 1024) {
         hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
@@ -272,7 +273,7 @@ hipError_t batch_prepare_class(int ncol, int nt, int uw, size_t lds, int* blocks
         }
     }
     int nb = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k, kNW * 64, lds) != hipSuccess || nb < 1) nb = 1;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k, t.nw * 64, lds) != hipSuccess || nb < 1) nb = 1;
     (void)hipGetLastError();
     *blocks = nb * batch_num_cu();
     return hipSuccess;
@@ -292,14 +293,14 @@ hipError_t launch_batch_plan(BatchInst* insts, int n_inst, BatchCtl* ctl, unsign
     return hipGetLastError();
 }
 
-hipError_t launch_batch_bound(int ncol, int nt, int uw, int blocks, size_t lds, BatchInst* insts,
+hipError_t launch_batch_bound(int ncol, TileShape t, int blocks, size_t lds, BatchInst* insts,
                               BatchCtl* ctl, const unsigned* bpre, int cbeg, int cend, int c,
                               unsigned* amb_list, hipStream_t stream) {
-    const void* k = class_kernel(ncol, nt, uw);
+    const void* k = class_kernel(ncol, t);
     if (!k) return hipErrorInvalidValue;
     void* args[] = {&insts, &ctl, (void*)&bpre, &cbeg, &cend, &c, &amb_list};
     (void)hipGetLastError();
-    return hipLaunchKernel(k, dim3(blocks), dim3(kNW * 64), args, lds, stream);
+    return hipLaunchKernel(k, dim3(blocks), dim3(t.nw * 64), args, lds, stream);
 }
 
 namespace {

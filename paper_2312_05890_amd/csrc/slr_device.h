@@ -36,7 +36,7 @@ constexpr float kU32 = 0x1p-24f;     // unit roundoff of float32
 constexpr float kEta = 0x1p-96f;     // absolute floor: covers flushed subnormal products
 constexpr double kEta64 = 0x1p-960;
 constexpr double kU64 = 0x1p-53;
-constexpr int kNW = 4;               // wavefronts per bound workgroup
+constexpr int kNW = 4;               // wavefronts per workgroup of the default bound tile
 
 // Row 16 mt + 4 g + v of a layer with `tiles` 16-row tiles whose last tile holds r neurons.
 __device__ __forceinline__ bool row_valid(int mt, int g, int v, int tiles, int r) {
@@ -107,7 +107,7 @@ __device__ __forceinline__ float relu_epilogue(float (&a)[NCOL][4], const float 
     return emax;
 }
 
-template <int NCOL, int NT, int UW>
+template <int NCOL, int NT, int UW, int NW>
 __device__ __forceinline__ void bound_tile(
     const NetDev& net, const PropDev& prop, int64_t n, int64_t box0,
     const float* __restrict__ blo, const float* __restrict__ bhi, float* __restrict__ g_lo,
@@ -134,7 +134,7 @@ __device__ __forceinline__ void bound_tile(
         const int units = net.mt1 * NT;
 #pragma unroll
         for (int i = 0; i < UW; ++i) {
-            const int u = wave + kNW * i;
+            const int u = wave + NW * i;
             if (u < units) {
                 const int mt = u / NT, nt = u - (u / NT) * NT;
                 const int64_t b = box0 + nt * 16 + j;
@@ -203,7 +203,7 @@ __device__ __forceinline__ void bound_tile(
         f32x4 res[UW][NCOL];
 #pragma unroll
         for (int i = 0; i < UW; ++i) {
-            const int u = wave + kNW * i;
+            const int u = wave + NW * i;
             if (u < units) {
                 const int mt = u / NT, nt = u - (u / NT) * NT;
                 f32x4 acc[NCOL];
@@ -264,7 +264,7 @@ __device__ __forceinline__ void bound_tile(
         __syncthreads();   // every wave has read the layer input
 #pragma unroll
         for (int i = 0; i < UW; ++i) {
-            const int u = wave + kNW * i;
+            const int u = wave + NW * i;
             if (u < units) {
                 const int mt = u / NT, nt = u - (u / NT) * NT;
                 const int bj = nt * 16 + j;
@@ -313,7 +313,7 @@ __device__ __forceinline__ void bound_tile(
 #pragma unroll
             for (int c = 0; c < NCOL; ++c) G[c] = f32x4{0.f, 0.f, 0.f, 0.f};
             const float* sb = S + ((nt * NCOL * 4 + g) * 16 + j) * SP;
-            for (int q = wave; q < ksq; q += kNW) {
+            for (int q = wave; q < ksq; q += NW) {
                 f32x4 bq[NCOL];
 #pragma unroll
                 for (int c = 0; c < NCOL; ++c)
@@ -344,7 +344,7 @@ __device__ __forceinline__ void bound_tile(
         // VALU contraction over the state
         const int K = prop.kpad;
         const int items = rows * T * NCOL;
-        for (int it = tid; it < items; it += kNW * 64) {
+        for (int it = tid; it < items; it += NW * 64) {
             const int c = it % NCOL;
             const int bj = (it / NCOL) % T;
             const int r = it / (NCOL * T);
@@ -368,10 +368,10 @@ __device__ __forceinline__ void bound_tile(
         const int nt = bj >> 4, jj = bj & 15;
         float acc = 0.f;
 #pragma unroll
-        for (int w = 0; w < kNW; ++w) acc += OUT[(((w * NT + nt) * NCOL + c) * rows + r) * 16 + jj];
+        for (int w = 0; w < NW; ++w) acc += OUT[(((w * NT + nt) * NCOL + c) * rows + r) * 16 + jj];
         return acc;
     };
-    for (int bj = tid; bj < T; bj += kNW * 64) {
+    for (int bj = tid; bj < T; bj += NW * 64) {
         const int64_t b = box0 + bj;
         if (b >= n) continue;
         float emax = 0.f;

@@ -629,6 +629,14 @@ extern "C" int workspace_size(const slr_net* net, const slr_property* prop, int6
     return SLR_OK;
 }
 
+extern "C" int bound_tile_shape(int32_t d, int32_t mt_max, int32_t nt, int32_t uw, int32_t nw) {
+    g_err.clear();
+    if (set_tile_shape(d, mt_max, TileShape{nt, uw, nw}) != 0)
+        return fail(SLR_EINVAL, "bound_tile_shape: (%d, %d, %d) is not an instantiated tile shape covering "
+                    "%d hidden tiles for d = %d", nt, uw, nw, mt_max, d);
+    return SLR_OK;
+}
+
 extern "C" int bound_kernel_variant(int32_t variant) {
     g_err.clear();
     if (set_bound_variant(variant) != 0)
@@ -1198,7 +1206,9 @@ struct slr_batch {
     BatchCtl* ctl = nullptr;
     unsigned *bpre = nullptr, *cpre = nullptr, *amb = nullptr;
     struct Cls {
-        int ncol, nt, uw, cbeg, cend, blocks;
+        int ncol;
+        TileShape t;
+        int cbeg, cend, blocks;
         size_t lds;
     };
     std::vector<Cls> cls;
@@ -1219,7 +1229,7 @@ int batch_enqueue(const slr_batch* b, hipStream_t s) {
                 "batch: plan kernel");
         for (size_t c = 0; c < b->cls.size(); ++c) {
             const auto& k = b->cls[c];
-            HIP_TRY(launch_batch_bound(k.ncol, k.nt, k.uw, k.blocks, k.lds, b->insts, b->ctl, b->bpre,
+            HIP_TRY(launch_batch_bound(k.ncol, k.t, k.blocks, k.lds, b->insts, b->ctl, b->bpre,
                                        k.cbeg, k.cend, (int)c, b->amb, s),
                     "batch: bound kernel");
         }
@@ -1256,7 +1266,9 @@ extern "C" int batch_create(int32_t n_inst, const slr_net* const* nets,
         return fail(SLR_EINVAL, "batch_create: NULL array");
     if (use_graph != 0 && use_graph != 1) return fail(SLR_EINVAL, "batch_create: use_graph must be 0 or 1");
     struct Info {
-        int ncol, nt, uw, key;
+        int ncol;
+        TileShape t;
+        int key;
     };
     std::vector<Info> info(n_inst);
     for (int i = 0; i < n_inst; ++i) {
@@ -1270,10 +1282,10 @@ extern "C" int batch_create(int32_t n_inst, const slr_net* const* nets,
         if (max_leaves[i] < 1 || max_leaves[i] > (1 << 22))
             return fail(SLR_EINVAL, "%s: max_leaves must be in [1, 2^22]", who);
         Info& f = info[i];
-        if (batch_class_of(nets[i]->dev, props[i]->dev, &f.ncol, &f.nt, &f.uw) != 0)
+        if (batch_class_of(nets[i]->dev, props[i]->dev, &f.ncol, &f.t) != 0)
             return fail(SLR_EUNSUPPORTED, "%s: shape (d=%d, widths up to %d) outside the batch kernels "
                         "(d <= 11, widths <= 128)", who, nets[i]->dev.d, nets[i]->dev.n_max);
-        f.key = (f.ncol * 8 + f.nt) * 8 + f.uw;
+        f.key = ((f.ncol * 8 + f.t.nt) * 8 + f.t.uw) * 16 + f.t.nw;
     }
     slr_batch* b = new slr_batch;
     b->n_inst = n_inst;
@@ -1284,12 +1296,13 @@ extern "C" int batch_create(int32_t n_inst, const slr_net* const* nets,
     std::vector<int> cls_of(n_inst);
     for (int p = 0; p < n_inst; ++p) {
         const Info& f = info[b->order[p]];
-        if (b->cls.empty() || b->cls.back().ncol != f.ncol || b->cls.back().nt != f.nt || b->cls.back().uw != f.uw) {
+        if (b->cls.empty() || b->cls.back().ncol != f.ncol || b->cls.back().t.nt != f.t.nt ||
+            b->cls.back().t.uw != f.t.uw || b->cls.back().t.nw != f.t.nw) {
             if ((int)b->cls.size() == SLR_MAX_CLASSES) {
                 batch_free(b);
                 return fail(SLR_EINTERNAL, "batch_create: too many kernel classes");
             }
-            b->cls.push_back({f.ncol, f.nt, f.uw, p, p, 0, 0});
+            b->cls.push_back({f.ncol, f.t, p, p, 0, 0});
         }
         b->cls.back().cend = p + 1;
         cls_of[p] = (int)b->cls.size() - 1;
@@ -1372,7 +1385,7 @@ extern "C" int batch_create(int32_t n_inst, const slr_net* const* nets,
             return hip_fail(e, "batch_create: upload");
         }
         b->cls[cls_of[p]].lds = std::max(b->cls[cls_of[p]].lds,
-                                         batch_bound_lds(b->cls[cls_of[p]].ncol, b->cls[cls_of[p]].nt,
+                                         batch_bound_lds(b->cls[cls_of[p]].ncol, b->cls[cls_of[p]].t,
                                                          I.net.mt_max, I.prop.rows));
         const int ncol = I.d + 2;
         b->ncol_max = std::max(b->ncol_max, ncol);
@@ -1380,7 +1393,7 @@ extern "C" int batch_create(int32_t n_inst, const slr_net* const* nets,
     }
     b->levels = levels;
     BatchCtl hc{};
-    for (size_t c = 0; c < b->cls.size(); ++c) hc.tbox[c] = 16 * b->cls[c].nt;
+    for (size_t c = 0; c < b->cls.size(); ++c) hc.tbox[c] = 16 * b->cls[c].t.nt;
     e = hipMemcpy(b->ctl, &hc, sizeof hc, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(b->insts, b->host.data(), sizeof(BatchInst) * n_inst, hipMemcpyHostToDevice);
     if (e != hipSuccess) {
@@ -1392,7 +1405,7 @@ extern "C" int batch_create(int32_t n_inst, const slr_net* const* nets,
             batch_free(b);
             return fail(SLR_EUNSUPPORTED, "batch_create: a kernel class needs %zu bytes of LDS", k.lds);
         }
-        e = batch_prepare_class(k.ncol, k.nt, k.uw, k.lds, &k.blocks);
+        e = batch_prepare_class(k.ncol, k.t, k.lds, &k.blocks);
         if (e != hipSuccess) {
             batch_free(b);
             return hip_fail(e, "batch_create: kernel class");

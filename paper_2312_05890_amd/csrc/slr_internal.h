@@ -124,6 +124,17 @@ hipError_t launch_volume(const LevelStats* stats, int levels, int stop_level, in
 hipError_t launch_sample_forward(const NetDev& net, const PropDev& prop, int64_t n,
                                  const float* x, int8_t* viol, hipStream_t stream);
 int bound_f32_supported(const NetDev& net, const PropDev& prop);
+// Tile shape of the LDS-staged bound kernel: NT 16-box N tiles per workgroup, UW units per wave,
+// NW wavefronts per workgroup.  The default depends on the hidden tiles (mt_max); a per-class
+// override (input-dimension class x mt_max) can replace it, e.g. from the autotuner.
+struct TileShape {
+    int nt, uw, nw;
+};
+int ncol_class_of(int d);
+TileShape tile_shape_for(int d, int mt_max);
+bool tile_shape_valid(int ncol, int mt_max, TileShape t);
+int set_tile_shape(int d, int mt_max, TileShape t);   // nt = 0 restores the default; -1 = invalid
+size_t bound_lds_bytes(int ncol, TileShape t, int mt_max, int rows);
 // Bound-kernel variant: 0 automatic, 1 LDS-staged, 2 register-resident only, 3 none (the exact
 // count then bounds with the tape-state kernel, as for shapes the LDS kernel cannot hold).
 // Returns -1 for an unknown value.
@@ -222,15 +233,15 @@ struct BatchCtl {
     unsigned ctiles;                    // 1024-box bookkeeping tiles at the current level
 };
 
-// Kernel class of the batch bound kernel: (NCOL, NT, UW) of the LDS-staged tile.
-bool batch_class_supported(int ncol, int nt, int uw);
-int batch_class_of(const NetDev& net, const PropDev& prop, int* ncol, int* nt, int* uw);
-size_t batch_bound_lds(int ncol, int nt, int mt_max, int rows);
-hipError_t batch_prepare_class(int ncol, int nt, int uw, size_t lds, int* blocks);
+// Kernel class of the batch bound kernel: NCOL and the tile shape of the LDS-staged tile.
+bool batch_class_supported(int ncol, TileShape t);
+int batch_class_of(const NetDev& net, const PropDev& prop, int* ncol, TileShape* t);
+size_t batch_bound_lds(int ncol, TileShape t, int mt_max, int rows);
+hipError_t batch_prepare_class(int ncol, TileShape t, size_t lds, int* blocks);
 hipError_t launch_batch_init(BatchInst* insts, int n_inst, hipStream_t stream);
 hipError_t launch_batch_plan(BatchInst* insts, int n_inst, BatchCtl* ctl, unsigned* bpre,
                              unsigned* cpre, int n_classes, hipStream_t stream);
-hipError_t launch_batch_bound(int ncol, int nt, int uw, int blocks, size_t lds, BatchInst* insts,
+hipError_t launch_batch_bound(int ncol, TileShape t, int blocks, size_t lds, BatchInst* insts,
                               BatchCtl* ctl, const unsigned* bpre, int cbeg, int cend, int c,
                               unsigned* amb_list, hipStream_t stream);
 hipError_t batch_prepare_recheck(int nrow, int ncol_max);

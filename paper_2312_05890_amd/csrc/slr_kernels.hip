@@ -5,14 +5,14 @@
 
 namespace {
 
-template <int NCOL, int NT, int UW>
-__global__ __launch_bounds__(kNW * 64) void bound_f32_kernel(
+template <int NCOL, int NT, int UW, int NW>
+__global__ __launch_bounds__(NW * 64) void bound_f32_kernel(
     NetDev net, PropDev prop, int64_t n, const float* __restrict__ blo,
     const float* __restrict__ bhi, float* __restrict__ g_lo, float* __restrict__ g_hi,
     int8_t* __restrict__ cls, int raw, int SP, unsigned* __restrict__ amb_list,
     unsigned* __restrict__ amb_count, unsigned list_base) {
-    bound_tile<NCOL, NT, UW>(net, prop, n, (int64_t)blockIdx.x * (NT * 16), blo, bhi, g_lo, g_hi,
-                             cls, raw, SP, amb_list, amb_count, list_base);
+    bound_tile<NCOL, NT, UW, NW>(net, prop, n, (int64_t)blockIdx.x * (NT * 16), blo, bhi, g_lo,
+                                 g_hi, cls, raw, SP, amb_list, amb_count, list_base);
 }
 
 __global__ __launch_bounds__(256) void recheck64_kernel(NetDev net, PropDev prop, int64_t n,
@@ -373,52 +373,48 @@ int ncol_class(int d) {
     return 35;
 }
 
-void tile_class(int mt_max, int* NT, int* UW) {
-    if (mt_max <= 1) { *NT = 4; *UW = 1; }
-    else if (mt_max == 2) { *NT = 2; *UW = 1; }
-    else if (mt_max <= 4) { *NT = 1; *UW = 1; }
-    else if (mt_max <= 8) { *NT = 1; *UW = 2; }
-    else { *NT = 1; *UW = 4; }
-}
-
 int state_stride(int mt_max) { return 4 * mt_max + ((mt_max & 1) ? 0 : 4); }
 
-size_t bound_lds_bytes(int NCOL, int NT, int mt_max, int rows) {
-    const int T = NT * 16;
-    const int SP = state_stride(mt_max);
-    return sizeof(float) * ((size_t)NT * NCOL * 64 * SP + 2 * (size_t)mt_max * T + 4 * (size_t)rows * T * NCOL);
-}
-
-template <int NCOL, int NT, int UW>
+template <int NCOL, int NT, int UW, int NW>
 hipError_t launch_inst(const NetDev& net, const PropDev& prop, int64_t n, const float* lo,
                        const float* hi, float* g_lo, float* g_hi, int8_t* cls, int raw,
                        hipStream_t stream, unsigned* amb_list, unsigned* amb_count,
                        unsigned list_base) {
-    const size_t lds = bound_lds_bytes(NCOL, NT, net.mt_max, prop.rows);
-    auto kern = bound_f32_kernel<NCOL, NT, UW>;
+    const size_t lds = bound_lds_bytes(NCOL, TileShape{NT, UW, NW}, net.mt_max, prop.rows);
+    auto kern = bound_f32_kernel<NCOL, NT, UW, NW>;
     hipError_t e = allow_lds((const void*)kern, lds);
     if (e != hipSuccess) return e;
     const int64_t blocks = (n + NT * 16 - 1) / (NT * 16);
     (void)hipGetLastError();
-    hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(kNW * 64), lds, stream, net, prop, n,
+    hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(NW * 64), lds, stream, net, prop, n,
                        lo, hi, g_lo, g_hi, cls, raw, state_stride(net.mt_max), amb_list,
                        amb_count, list_base);
     return hipGetLastError();
 }
 
+// Tile shapes instantiated for the LDS-staged kernel: (NT, UW, NW).
 template <int NCOL>
-hipError_t launch_ncol(int NT, int UW, const NetDev& net, const PropDev& prop, int64_t n,
+hipError_t launch_ncol(TileShape t, const NetDev& net, const PropDev& prop, int64_t n,
                        const float* lo, const float* hi, float* g_lo, float* g_hi, int8_t* cls,
                        int raw, hipStream_t stream, unsigned* al, unsigned* ac, unsigned lb) {
-    if (NT == 4) return launch_inst<NCOL, 4, 1>(net, prop, n, lo, hi, g_lo, g_hi, cls, raw, stream, al, ac, lb);
-    if (NT == 2) return launch_inst<NCOL, 2, 1>(net, prop, n, lo, hi, g_lo, g_hi, cls, raw, stream, al, ac, lb);
-    if (UW == 1) return launch_inst<NCOL, 1, 1>(net, prop, n, lo, hi, g_lo, g_hi, cls, raw, stream, al, ac, lb);
-    if (UW == 2) return launch_inst<NCOL, 1, 2>(net, prop, n, lo, hi, g_lo, g_hi, cls, raw, stream, al, ac, lb);
-    if constexpr (NCOL <= 18)
-        return launch_inst<NCOL, 1, 4>(net, prop, n, lo, hi, g_lo, g_hi, cls, raw, stream, al, ac, lb);
+#define SLR_SHAPE(A, B, C)                                                                       \
+    if (t.nt == A && t.uw == B && t.nw == C)                                                      \
+        return launch_inst<NCOL, A, B, C>(net, prop, n, lo, hi, g_lo, g_hi, cls, raw, stream, al, \
+                                          ac, lb);
+    SLR_SHAPE(4, 1, 4) SLR_SHAPE(2, 1, 4) SLR_SHAPE(1, 1, 4) SLR_SHAPE(1, 2, 4)
+    // eight wavefronts leave 256 registers per lane: only the shapes that do not spill
+    if constexpr (NCOL <= 26) {
+        SLR_SHAPE(1, 1, 8)
+    }
+    if constexpr (NCOL <= 18) {
+        SLR_SHAPE(1, 4, 4)
+    }
+    if constexpr (NCOL <= 14) {
+        SLR_SHAPE(1, 2, 8)
+    }
+#undef SLR_SHAPE
     return hipErrorInvalidValue;
 }
-
 
 int g_num_cu = 0;
 
@@ -504,15 +500,64 @@ int bound_variant_for(const NetDev& net, const PropDev& prop) {
 }
 
 
+namespace {
+
+TileShape g_shape_override[64][17];   // [ncol class][mt_max]: nt = 0 -> default
+
+TileShape default_shape(int mt_max) {
+    if (mt_max <= 1) return {4, 1, 4};
+    if (mt_max == 2) return {2, 1, 4};
+    if (mt_max <= 4) return {1, 1, 4};
+    if (mt_max <= 8) return {1, 2, 4};
+    return {1, 4, 4};
+}
+
+}  // namespace
+
+int ncol_class_of(int d) { return ncol_class(d); }
+
+size_t bound_lds_bytes(int NCOL, TileShape t, int mt_max, int rows) {
+    const int T = t.nt * 16;
+    const int SP = state_stride(mt_max);
+    return sizeof(float) * ((size_t)t.nt * NCOL * 64 * SP + 2 * (size_t)mt_max * T +
+                            (size_t)t.nw * rows * T * NCOL);
+}
+
+bool tile_shape_valid(int ncol, int mt_max, TileShape t) {
+    const bool inst = (t.nt == 4 && t.uw == 1 && t.nw == 4) || (t.nt == 2 && t.uw == 1 && t.nw == 4) ||
+                      (t.nt == 1 && t.uw == 1 && t.nw == 4) || (t.nt == 1 && t.uw == 2 && t.nw == 4) ||
+                      (ncol <= 26 && t.nt == 1 && t.uw == 1 && t.nw == 8) ||
+                      (ncol <= 18 && t.nt == 1 && t.uw == 4 && t.nw == 4) ||
+                      (ncol <= 14 && t.nt == 1 && t.uw == 2 && t.nw == 8);
+    return inst && mt_max >= 1 && mt_max * t.nt <= t.uw * t.nw;
+}
+
+TileShape tile_shape_for(int d, int mt_max) {
+    const int c = ncol_class(d);
+    if (c < 64 && mt_max <= 16 && g_shape_override[c][mt_max].nt > 0) return g_shape_override[c][mt_max];
+    return default_shape(mt_max);
+}
+
+int set_tile_shape(int d, int mt_max, TileShape t) {
+    const int c = ncol_class(d);
+    if (d < 1 || d > SLR_MAX_D || mt_max < 1 || mt_max > 16) return -1;
+    if (t.nt == 0) {
+        g_shape_override[c][mt_max] = TileShape{0, 0, 0};
+        return 0;
+    }
+    if (!tile_shape_valid(c, mt_max, t)) return -1;
+    g_shape_override[c][mt_max] = t;
+    return 0;
+}
+
 int bound_f32_supported(const NetDev& net, const PropDev& prop) {
     const int v = bound_variant_for(net, prop);
     if (v == 2) return 1;
     if (v < 0) return 0;
     const int NCOL = ncol_class(net.d);
-    int NT, UW;
-    tile_class(net.mt_max, &NT, &UW);
-    if (UW == 4 && NCOL > 18) return 0;
-    if (bound_lds_bytes(NCOL, NT, net.mt_max, prop.rows) > 160 * 1024) return 0;
+    const TileShape t = tile_shape_for(net.d, net.mt_max);
+    if (!tile_shape_valid(NCOL, net.mt_max, t)) return 0;
+    if (bound_lds_bytes(NCOL, t, net.mt_max, prop.rows) > 160 * 1024) return 0;
     return 1;
 }
 
@@ -536,11 +581,10 @@ hipError_t launch_bound_f32(const NetDev& net, const PropDev& prop, int64_t n, c
             default: break;
         }
     }
-    int NT, UW;
-    tile_class(net.mt_max, &NT, &UW);
+    const TileShape t = tile_shape_for(net.d, net.mt_max);
     switch (ncol_class(net.d)) {
 #define SLR_CASE(C) \
-    case C: return launch_ncol<C>(NT, UW, net, prop, n, lo, hi, g_lo, g_hi, cls, raw, stream, \
+    case C: return launch_ncol<C>(t, net, prop, n, lo, hi, g_lo, g_hi, cls, raw, stream, \
                                   amb_list, amb_count, list_base);
         SLR_CASE(4) SLR_CASE(5) SLR_CASE(6) SLR_CASE(7) SLR_CASE(8) SLR_CASE(9)
         SLR_CASE(10) SLR_CASE(11) SLR_CASE(12) SLR_CASE(14) SLR_CASE(18) SLR_CASE(26) SLR_CASE(35)

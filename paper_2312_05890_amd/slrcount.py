@@ -23,7 +23,7 @@ EXPORTS = ("load_net", "free_net", "load_property", "free_property", "bound_boxe
            "workspace_size", "count_exact", "count_approx", "sample_violations", "last_error",
            "bound_kernel_variant", "alpha_size", "alpha_tape_size", "bound_boxes_alpha",
            "bound_boxes_backward", "alpha_workspace_size", "alpha_optimize", "batch_create",
-           "batch_run", "batch_free", "count_exact_batch")
+           "batch_run", "batch_free", "count_exact_batch", "bound_tile_shape")
 
 
 class SlrError(RuntimeError):
@@ -129,6 +129,8 @@ def lib() -> C.CDLL:
                                         C.POINTER(vp), C.POINTER(C.c_int32),
                                         C.POINTER(C.c_int64), vp, C.POINTER(CountResult)]
         L.count_exact_batch.restype = C.c_int
+        L.bound_tile_shape.argtypes = [i32, i32, i32, i32, i32]
+        L.bound_tile_shape.restype = C.c_int
         L.last_error.argtypes = []
         L.last_error.restype = C.c_char_p
         _LIB = L
@@ -232,6 +234,29 @@ def bound_boxes(net: Net, prop: Property, lo, hi, g_lo=None, g_hi=None, cls=None
 def bound_kernel_variant(variant: int) -> None:
     """0 automatic, 1 LDS-staged, 2 register-resident, 3 tape-state (see include/slrcount.h)."""
     _check(lib().bound_kernel_variant(int(variant)))
+
+
+def bound_tile_shape(d: int, mt_max: int, nt: int, uw: int, nw: int) -> None:
+    """Tile shape of the LDS-staged bound kernel for a (d class, mt_max); nt = 0 = default."""
+    _check(lib().bound_tile_shape(int(d), int(mt_max), int(nt), int(uw), int(nw)))
+    if nt == 0:
+        _SHAPES.pop((int(d), int(mt_max)), None)
+    else:
+        _SHAPES[(int(d), int(mt_max))] = (int(nt), int(uw), int(nw))
+
+
+_SHAPES = {}
+
+
+def current_tile_shape(sizes):
+    """(nt, uw, nw) last installed with bound_tile_shape for this network shape, else the
+    library default for its hidden tiles."""
+    mt = max((w + 15) // 16 for w in sizes[1:-1])
+    got = _SHAPES.get((sizes[0], mt))
+    if got:
+        return got
+    return (4, 1, 4) if mt <= 1 else (2, 1, 4) if mt == 2 else (1, 1, 4) if mt <= 4 else \
+        (1, 2, 4) if mt <= 8 else (1, 4, 4)
 
 
 def workspace_size(net: Net, prop: Property, max_leaves: int, samples: int = 0,

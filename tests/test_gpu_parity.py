@@ -380,3 +380,54 @@ def test_variant_rejects_unknown_and_unfit():
         assert e.value.code == -5
     finally:
         eng.bound_kernel_variant(0)
+
+
+@pytest.mark.parametrize("name", ["acas", "tiny2d", "b64", "b128"])
+def test_tile_shapes_agree(name):
+    """Every instantiated tile shape gives the same classes and bounds (float32 rounding of the
+    split output sums aside) as the default shape."""
+    from paper_2312_05890_amd import autotune
+    eng = E()
+    if name in ("acas", "tiny2d"):
+        inst = getattr(synth, name)(0)
+    else:
+        width = int(name[1:])
+        inst = next(i for i in synth.batch(0) if max(i.sizes[1:-1]) == width)
+    blo, bhi = synth.random_boxes(inst.lo, inst.hi, 3000, 5, 8)
+    ref = gpu_bounds(inst, blo, bhi, raw=False)
+    d, mt = inst.sizes[0], autotune.mt_of(inst.sizes)
+    shapes = autotune.candidates(d, mt)
+    assert len(shapes) >= 2
+    try:
+        for shape in shapes:
+            eng.bound_tile_shape(d, mt, *shape)
+            lo_, hi_, c_ = gpu_bounds(inst, blo, bhi, raw=False)
+            sc = 1e-5 * np.maximum(1.0, np.maximum(np.abs(ref[0]), np.abs(ref[1])))
+            assert np.all(np.abs(lo_ - ref[0]) <= sc) and np.all(np.abs(hi_ - ref[1]) <= sc), shape
+            m = margin(ref[0], ref[1]) > 1e-4
+            assert np.array_equal(c_[m], ref[2][m]), shape
+    finally:
+        eng.bound_tile_shape(d, mt, 0, 0, 0)
+
+
+def test_batch_with_tuned_shapes_equals_single():
+    """Batches pick up an installed shape when their kernels have it; results stay equal."""
+    eng = E()
+    insts = [i for i in synth.batch(3, count=40) if max(i.sizes[1:-1]) >= 96][:6]
+    items = []
+    for inst in insts:
+        net, prop = load(inst)
+        items.append((net, prop, inst.lo, inst.hi, inst.max_depth, 1 << 11))
+    from paper_2312_05890_amd import autotune
+    keys = {(i.sizes[0], autotune.mt_of(i.sizes)) for i in insts}
+    try:
+        for d, mt in keys:
+            eng.bound_tile_shape(d, mt, 1, 1, 8)
+        res = eng.Batch(items).run()
+        for it, r in zip(items, res):
+            s = eng.count_exact(*it[:4], it[4], it[5])
+            for k in ("unsafe", "safe", "undecided", "n_boxes_bounded", "n_recheck64"):
+                assert r[k] == s[k]
+    finally:
+        for d, mt in keys:
+            eng.bound_tile_shape(d, mt, 0, 0, 0)

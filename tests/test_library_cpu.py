@@ -78,3 +78,21 @@ def test_calls_reject_null_handles(eng):
     out = C.c_size_t()
     assert L.workspace_size(None, None, 10, 0, 0, C.byref(out)) == -1
     assert "net is NULL" in eng.last_error()
+
+
+def test_tile_shape_validation_and_cache_roundtrip(tmp_path):
+    """bound_tile_shape accepts instantiated shapes that cover the tiles and rejects others;
+    the autotuner's cache installs its entries (host-only calls, no GPU needed)."""
+    import paper_2312_05890_amd as E
+    from paper_2312_05890_amd import autotune
+    E.bound_tile_shape(5, 4, 1, 1, 8)
+    E.bound_tile_shape(5, 4, 0, 0, 0)
+    with pytest.raises(E.SlrError):
+        E.bound_tile_shape(5, 4, 4, 1, 4)        # 4 tiles x 4 N tiles > 1 x 4 units
+    with pytest.raises(E.SlrError):
+        E.bound_tile_shape(30, 4, 1, 2, 8)       # not instantiated for wide states
+    assert (1, 1, 4) in autotune.candidates(5, 4)
+    p = tmp_path / "cache.json"
+    autotune.save([{"key": "d5_mt4", "d": 5, "mt_max": 4, "best": [1, 1, 8]}], str(p))
+    assert autotune.load(str(p)) == 1
+    E.bound_tile_shape(5, 4, 0, 0, 0)
