@@ -217,6 +217,7 @@ const void* class_kernel(int ncol, TileShape t) {
         if (t.nt == 1 && t.uw == 1 && t.nw == 4) return kern_ptr<C, 1, 1, 4>();     \
         if (t.nt == 1 && t.uw == 2 && t.nw == 4) return kern_ptr<C, 1, 2, 4>();     \
         if (t.nt == 1 && t.uw == 1 && t.nw == 8) return kern_ptr<C, 1, 1, 8>();     \
+        if (t.nt == 1 && t.uw == 2 && t.nw == 8) return kern_ptr<C, 1, 2, 8>();     \
         return nullptr;                                                             \
     }
     SLR_T(4) SLR_T(5) SLR_T(6) SLR_T(7) SLR_T(8) SLR_T(9) SLR_T(10) SLR_T(11) SLR_T(12) SLR_T(14)
