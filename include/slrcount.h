@@ -220,6 +220,11 @@ int sample_violations(const slr_net* net, const slr_property* prop, int64_t n, c
  * hidden layer first.  Only the slopes of crossing neurons are used; values are clamped to [0, 1].
  * ------------------------------------------------------------------------------------------ */
 
+/* alpha_state_variant: process-wide placement of the alpha kernels' tile state: 0 automatic
+   (LDS where it fits), 1 the same, 2 always global memory (the tape's extra slots; frees LDS for
+   more resident workgroups).  Tape sizes depend on it: query alpha_tape_size after setting it. */
+int alpha_state_variant(int32_t variant);
+
 /* alpha_size: nh, the slopes per box. */
 int alpha_size(const slr_net* net, int64_t* nh);
 

@@ -60,16 +60,20 @@ template <> struct Groups<33> { static constexpr int CG = 11, NG = 6; static con
 // Unroll factor of the epilogues' column sweeps: full for narrow states; wide states are swept
 // in pairs so that the second sweep reloads (from L1/LDS) instead of keeping every column live.
 template <int NC> constexpr int sweep_unroll() { return NC <= 8 ? NC : 2; }
+// The adjoint's sweeps keep four column sets live (pre-activation C, R and its adjoint): sweep in
+// pairs from NC = 6 on, which keeps it within 256 registers per lane (two wavefronts per SIMD).
+template <int NC> constexpr int bwd_unroll() { return NC <= 4 ? NC : 2; }
 
-// One contraction unit: output tile mt, column group grp.
-//   out[c][mt] = A(mt) * in[c]  (A = frag for center columns, |frag| for radius columns),
-// summed over ks K-steps (frag is zero beyond them up to ks_alloc, a multiple of 4); bias (by
-// relabeled row) is added to column 0.  A comes from global memory (L2-resident), B from the
-// tile buffer; the loop is software-pipelined one K-quad ahead.
-template <int NC, typename PIn, typename POut>
-__device__ __forceinline__ void contract_unit(const float* __restrict__ frag, int ks, int ks_alloc,
-                                              int mt, int grp, PIn in, POut out, int mtS,
-                                              const float* __restrict__ bias, int lane) {
+// One contraction unit: output tile mt, column group grp, accumulated in registers:
+//   acc[cc] = A(mt) * in[cb + cc]  (A = frag for center columns, |frag| for radius columns),
+// summed over ks K-steps (frag is zero beyond them up to ks_alloc, a multiple of 4).  A comes
+// from global memory (L2-resident), B from the tile buffer; the loop is software-pipelined one
+// K-quad ahead.  Returns the first column cb and the number of real columns of the group.
+template <int NC, typename PIn>
+__device__ __forceinline__ void contract_acc(const float* __restrict__ frag, int ks, int ks_alloc,
+                                             int mt, int grp, PIn in, int mtS, int lane,
+                                             f32x4 (&acc)[Groups<NC>::CG], int& cb_out,
+                                             int& ncols_out) {
     using G = Groups<NC>;
     constexpr int CG = G::CG;
     const int ngh = G::NG > 1 ? G::NG / 2 : 1;
@@ -77,7 +81,8 @@ __device__ __forceinline__ void contract_unit(const float* __restrict__ frag, in
     const int first = G::SPLIT ? (grp - half * ngh) * CG : 0;
     const int cb = G::SPLIT ? half * NC + first : 0;
     const int ncols = G::SPLIT ? min(CG, NC - first) : CG;
-    f32x4 acc[CG];
+    cb_out = cb;
+    ncols_out = ncols;
 #pragma unroll
     for (int cc = 0; cc < CG; ++cc) acc[cc] = f32x4{0.f, 0.f, 0.f, 0.f};
     const float* wf = frag + (size_t)mt * ks_alloc * 64 + lane;
@@ -113,6 +118,18 @@ __device__ __forceinline__ void contract_unit(const float* __restrict__ frag, in
 #pragma unroll
         for (int cc = 0; cc < CG; ++cc) bq[cc] = bn[cc];
     }
+}
+
+// contract_acc, then out[c][mt] = acc (+ bias by relabeled row on column 0).
+template <int NC, typename PIn, typename POut>
+__device__ __forceinline__ void contract_unit(const float* __restrict__ frag, int ks, int ks_alloc,
+                                              int mt, int grp, PIn in, POut out, int mtS,
+                                              const float* __restrict__ bias, int lane) {
+    using G = Groups<NC>;
+    constexpr int CG = G::CG;
+    f32x4 acc[CG];
+    int cb, ncols;
+    contract_acc<NC>(frag, ks, ks_alloc, mt, grp, in, mtS, lane, acc, cb, ncols);
     const int g = lane >> 4;
 #pragma unroll
     for (int cc = 0; cc < CG; ++cc) {
@@ -156,25 +173,37 @@ __device__ __forceinline__ Phase phase_of(float lo, float hi, bool valid, float 
 
 // Forward epilogue of one hidden tile (4 neurons per lane): widen the radius constant by the
 // affine rounding margin eps, concretize, apply the alpha relaxation and write the
-// post-activation state.  Pre-activation columns are read from the tape slot (and the widened
-// radius constant and l, u written back).  Returns a bound on sum_c |C_c| + |R_c| over the lane's
+// post-activation state.  get(c) yields pre-activation column c (from the tape slot, or from the
+// contraction's registers); the tape receives the widened radius constant and l, u (and, with
+// cols, every pre-activation column).  Returns a bound on sum_c |C_c| + |R_c| over the lane's
 // neurons (for the next layer's rounding margin).
-template <int NC, typename PT, typename PS>
-__device__ __forceinline__ float fwd_relu(PT pre, PS post, int mtS, int mt, int lane,
-                                          const float (&eps)[4], const bool (&valid)[4],
-                                          float* __restrict__ arow, const int* __restrict__ rowmap,
-                                          int init, const EpiK& k) {
+template <int NC, int UNR, typename Get, typename PT, typename PS>
+__device__ __forceinline__ float fwd_relu_core(Get get, PT tape, bool cols, PS post, int mtS,
+                                               int mt, int lane, const float (&eps)[4],
+                                               const bool (&valid)[4], float* __restrict__ arow,
+                                               const int* __restrict__ rowmap, int init,
+                                               const EpiK& k) {
     auto at = [&](int c) { return (size_t)(c * mtS + mt) * 64 + lane; };
     const int g = lane >> 4;
-    f32x4 C0 = pre[at(0)];
-    f32x4 R0 = pre[at(NC)];
+    f32x4 C0 = get(0);
+    f32x4 R0 = get(NC);
 #pragma unroll
     for (int v = 0; v < 4; ++v) R0[v] += eps[v];
-    pre[at(NC)] = R0;
+    if (tape) {
+        tape[at(NC)] = R0;
+        if (cols) {
+            tape[at(0)] = C0;
+#pragma unroll
+            for (int c = 1; c < NC; ++c) {
+                tape[at(c)] = get(c);
+                tape[at(NC + c)] = get(NC + c);
+            }
+        }
+    }
     f32x4 SL = {0.f, 0.f, 0.f, 0.f}, SU = SL, M = SL;
-#pragma unroll sweep_unroll<NC>()
+#pragma unroll UNR
     for (int c = 1; c < NC; ++c) {
-        const f32x4 Cc = pre[at(c)], Rc = pre[at(NC + c)];
+        const f32x4 Cc = get(c), Rc = get(NC + c);
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
             SL[v] += fabsf(Cc[v] - Rc[v]);
@@ -204,12 +233,14 @@ __device__ __forceinline__ float fwd_relu(PT pre, PS post, int mtS, int mt, int 
         }
         al[v] = p.cross ? a : p.lam;
     }
-    pre[at(2 * NC)] = LO;
-    pre[at(2 * NC + 1)] = HI;
+    if (tape) {
+        tape[at(2 * NC)] = LO;
+        tape[at(2 * NC + 1)] = HI;
+    }
     f32x4 E = {0.f, 0.f, 0.f, 0.f}, mag = E;
-#pragma unroll sweep_unroll<NC>()
+#pragma unroll UNR
     for (int c = 1; c < NC; ++c) {
-        const f32x4 Cc = pre[at(c)], Rc = pre[at(NC + c)];
+        const f32x4 Cc = get(c), Rc = get(NC + c);
         f32x4 Cn, Rn;
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
@@ -239,16 +270,41 @@ __device__ __forceinline__ float fwd_relu(PT pre, PS post, int mtS, int mt, int 
     return emax;
 }
 
+// The epilogue on a tape slot that already holds the pre-activation columns.
+template <int NC, typename PT, typename PS>
+__device__ __forceinline__ float fwd_relu(PT pre, PS post, int mtS, int mt, int lane,
+                                          const float (&eps)[4], const bool (&valid)[4],
+                                          float* __restrict__ arow, const int* __restrict__ rowmap,
+                                          int init, const EpiK& k) {
+    auto get = [&](int c) { return pre[(size_t)(c * mtS + mt) * 64 + lane]; };
+    return fwd_relu_core<NC, sweep_unroll<NC>()>(get, pre, false, post, mtS, mt, lane, eps, valid,
+                                                 arow, rowmap, init, k);
+}
+
+// The epilogue on pre-activation columns held in registers (narrow states); the tape (NULL in a
+// forward-only pass) receives every column.
+template <int NC, typename PT, typename PS>
+__device__ __forceinline__ float fwd_relu_reg(const f32x4 (&a)[2 * NC], PT tape, PS post, int mtS,
+                                              int mt, int lane, const float (&eps)[4],
+                                              const bool (&valid)[4], float* __restrict__ arow,
+                                              const int* __restrict__ rowmap, int init,
+                                              const EpiK& k) {
+    auto get = [&](int c) { return a[c]; };
+    return fwd_relu_core<NC, NC>(get, tape, true, post, mtS, mt, lane, eps, valid, arow, rowmap,
+                                 init, k);
+}
+
 // Adjoint of fwd_relu for one hidden tile.  In: dpost = d J / d(post-activation C, R); the tape
 // slot (pre-activation, widened radius constant, l, u).  Out: dpre = d J / d(pre-activation C, R),
 // d J / d alpha of the crossing neurons (written to drow and/or applied by projected Adam).
 // The rounding margins are treated as constants.
-template <int NC, typename PT, typename PS>
-__device__ __forceinline__ void bwd_relu(PT pre, PS dpost, PS dpre, int mtS, int mt, int lane,
-                                         const bool (&valid)[4], float* __restrict__ arow,
-                                         float* __restrict__ drow, float* __restrict__ mrow,
-                                         float* __restrict__ vrow, const int* __restrict__ rowmap,
-                                         const AlphaArgs& A, const EpiK& k) {
+template <int NC, int UNR, typename GetD, typename PT, typename PS>
+__device__ __forceinline__ void bwd_relu_core(PT pre, GetD getd, PS dpre, int mtS, int mt, int lane,
+                                              const bool (&valid)[4], float* __restrict__ arow,
+                                              float* __restrict__ drow, float* __restrict__ mrow,
+                                              float* __restrict__ vrow,
+                                              const int* __restrict__ rowmap, const AlphaArgs& A,
+                                              const EpiK& k) {
     auto at = [&](int c) { return (size_t)(c * mtS + mt) * 64 + lane; };
     const int g = lane >> 4;
     const f32x4 LO = pre[at(2 * NC)], HI = pre[at(2 * NC + 1)];
@@ -268,10 +324,10 @@ __device__ __forceinline__ void bwd_relu(PT pre, PS dpost, PS dpre, int mtS, int
     }
     // sweep 1: d alpha = dL'.L, d lam = dU'.(U - l e0)
     float dal[4] = {0.f, 0.f, 0.f, 0.f}, dlam[4] = {0.f, 0.f, 0.f, 0.f}, dU0[4];
-#pragma unroll sweep_unroll<NC>()
+#pragma unroll UNR
     for (int c = 0; c < NC; ++c) {
         const f32x4 Cc = pre[at(c)], Rc = pre[at(NC + c)];
-        const f32x4 dC = dpost[at(c)], dR = dpost[at(NC + c)];
+        const f32x4 dC = getd(c), dR = getd(NC + c);
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
             const float dLp = 0.5f * (dC[v] - dR[v]);
@@ -291,10 +347,10 @@ __device__ __forceinline__ void bwd_relu(PT pre, PS dpost, PS dpre, int mtS, int
         du[v] = cross[v] ? -dlam[v] * LO[v] * inv2 : 0.f;
     }
     // sweep 2: adjoint of the pre-activation
-#pragma unroll sweep_unroll<NC>()
+#pragma unroll UNR
     for (int c = 0; c < NC; ++c) {
         const f32x4 Cc = pre[at(c)], Rc = pre[at(NC + c)];
-        const f32x4 dC = dpost[at(c)], dR = dpost[at(NC + c)];
+        const f32x4 dC = getd(c), dR = getd(NC + c);
         f32x4 oC, oR;
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
@@ -326,6 +382,30 @@ __device__ __forceinline__ void bwd_relu(PT pre, PS dpost, PS dpre, int mtS, int
     }
 }
 
+template <int NC, typename PT, typename PS>
+__device__ __forceinline__ void bwd_relu(PT pre, PS dpost, PS dpre, int mtS, int mt, int lane,
+                                         const bool (&valid)[4], float* __restrict__ arow,
+                                         float* __restrict__ drow, float* __restrict__ mrow,
+                                         float* __restrict__ vrow, const int* __restrict__ rowmap,
+                                         const AlphaArgs& A, const EpiK& k) {
+    auto getd = [&](int c) { return dpost[(size_t)(c * mtS + mt) * 64 + lane]; };
+    bwd_relu_core<NC, bwd_unroll<NC>()>(pre, getd, dpre, mtS, mt, lane, valid, arow, drow, mrow,
+                                        vrow, rowmap, A, k);
+}
+
+// The adjoint with d J / d(post-activation) held in registers (narrow states).
+template <int NC, typename PT, typename PS>
+__device__ __forceinline__ void bwd_relu_reg(const f32x4 (&dp)[2 * NC], PT pre, PS dpre, int mtS,
+                                             int mt, int lane, const bool (&valid)[4],
+                                             float* __restrict__ arow, float* __restrict__ drow,
+                                             float* __restrict__ mrow, float* __restrict__ vrow,
+                                             const int* __restrict__ rowmap, const AlphaArgs& A,
+                                             const EpiK& k) {
+    auto getd = [&](int c) { return dp[c]; };
+    bwd_relu_core<NC, NC>(pre, getd, dpre, mtS, mt, lane, valid, arow, drow, mrow, vrow, rowmap,
+                          A, k);
+}
+
 __device__ __forceinline__ int hidden_tiles(const NetDev& net, int h) {
     return h == 0 ? net.mt1 : net.mid[h - 1].mt_out;
 }
@@ -336,8 +416,10 @@ __device__ __forceinline__ int hidden_rem(const NetDev& net, int h) {
 // ---------------------------------------------------------------------------------------------
 // Forward pass: bounds of 16 boxes per workgroup with per-box slopes, tape for the adjoint.
 // ---------------------------------------------------------------------------------------------
-template <int NC, bool GS>
-__global__ __launch_bounds__(kNW * 64) void alpha_fwd_kernel(NetDev net, PropDev prop,
+// RP: every layer's columns fit one contraction unit and its tiles one unit per wavefront, so
+// contraction results stay in registers across the barrier and the epilogue reads no tape.
+template <int NC, bool GS, bool RP>
+__global__ __launch_bounds__(kNW * 64, 2) void alpha_fwd_kernel(NetDev net, PropDev prop,
                                                              AlphaArgs A, int slots) {
     extern __shared__ float lds[];
     using G = Groups<NC>;
@@ -391,6 +473,7 @@ __global__ __launch_bounds__(kNW * 64) void alpha_fwd_kernel(NetDev net, PropDev
                 c0[v] = valid[v] ? net.b1p[m[v]] : 0.f;
                 s[v] = fabsf(c0[v]);
             }
+            f32x4 cols[NC2];
 #pragma unroll
             for (int kk = 0; kk < NC - 1; ++kk) {
                 f32x4 colv;
@@ -401,15 +484,26 @@ __global__ __launch_bounds__(kNW * 64) void alpha_fwd_kernel(NetDev net, PropDev
                     colv[v] = w * rad[kk];
                     s[v] += fabsf(w) * (fabsf(mid[kk]) + rad[kk]);
                 }
-                pre[at(1 + kk)] = colv;
+                if constexpr (RP) cols[1 + kk] = colv;
+                else pre[at(1 + kk)] = colv;
             }
-            pre[at(0)] = f32x4{c0[0], c0[1], c0[2], c0[3]};
-#pragma unroll
-            for (int c = NC; c < NC2; ++c) pre[at(c)] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
             for (int v = 0; v < 4; ++v) eps[v] = A.raw ? 0.f : net.kfirst * s[v] + kEta;
-            float emax = fwd_relu<NC>(pre, S, mtS, mt, lane, eps, valid,
-                                      arow ? arow + net.hoff[0] : nullptr, net.rowmap[0], A.init, k);
+            float emax;
+            if constexpr (RP) {
+                cols[0] = f32x4{c0[0], c0[1], c0[2], c0[3]};
+#pragma unroll
+                for (int c = NC; c < NC2; ++c) cols[c] = f32x4{0.f, 0.f, 0.f, 0.f};
+                emax = fwd_relu_reg<NC>(cols, A.fwd_only ? nullptr : pre, S, mtS, mt, lane, eps,
+                                        valid, arow ? arow + net.hoff[0] : nullptr, net.rowmap[0],
+                                        A.init, k);
+            } else {
+                pre[at(0)] = f32x4{c0[0], c0[1], c0[2], c0[3]};
+#pragma unroll
+                for (int c = NC; c < NC2; ++c) pre[at(c)] = f32x4{0.f, 0.f, 0.f, 0.f};
+                emax = fwd_relu<NC>(pre, S, mtS, mt, lane, eps, valid,
+                                    arow ? arow + net.hoff[0] : nullptr, net.rowmap[0], A.init, k);
+            }
             emax = fmaxf(emax, __shfl_xor(emax, 16));
             emax = fmaxf(emax, __shfl_xor(emax, 32));
             if (g == 0) part_at(0, mt) = emax;
@@ -423,8 +517,16 @@ __global__ __launch_bounds__(kNW * 64) void alpha_fwd_kernel(NetDev net, PropDev
         const MidLayer& L = net.mid[l];
         f32x4* pre = tape + (size_t)(A.fwd_only ? 0 : l + 1) * slot;
         const int units = L.mt_out * G::NG;
-        for (int u = wave; u < units; u += kNW)
-            contract_unit<NC>(L.wfrag, L.ks, L.ks_alloc, u / G::NG, u % G::NG, S, pre, mtS, L.bias, lane);
+        f32x4 acc[G::CG];
+        if constexpr (RP) {
+            int cb, ncols;
+            if (wave < L.mt_out)
+                contract_acc<NC>(L.wfrag, L.ks, L.ks_alloc, wave, 0, S, mtS, lane, acc, cb, ncols);
+        } else {
+            for (int u = wave; u < units; u += kNW)
+                contract_unit<NC>(L.wfrag, L.ks, L.ks_alloc, u / G::NG, u % G::NG, S, pre, mtS,
+                                  L.bias, lane);
+        }
         __syncthreads();
         for (int mt = wave; mt < L.mt_out; mt += kNW) {
             float emax_in = 0.f;
@@ -437,9 +539,18 @@ __global__ __launch_bounds__(kNW * 64) void alpha_fwd_kernel(NetDev net, PropDev
                 valid[v] = row_valid(mt, g, v, L.mt_out, L.r_out);
                 eps[v] = A.raw ? 0.f : L.kgam * (L.absrow[m] * emax_in + fabsf(L.bias[m])) + kEta;
             }
-            float emax = fwd_relu<NC>(pre, S, mtS, mt, lane, eps, valid,
-                                      arow ? arow + net.hoff[l + 1] : nullptr, net.rowmap[l + 1],
-                                      A.init, k);
+            float emax;
+            if constexpr (RP) {
+#pragma unroll
+                for (int v = 0; v < 4; ++v) acc[0][v] += L.bias[16 * mt + 4 * g + v];
+                emax = fwd_relu_reg<NC>(acc, A.fwd_only ? nullptr : pre, S, mtS, mt, lane, eps,
+                                        valid, arow ? arow + net.hoff[l + 1] : nullptr,
+                                        net.rowmap[l + 1], A.init, k);
+            } else {
+                emax = fwd_relu<NC>(pre, S, mtS, mt, lane, eps, valid,
+                                    arow ? arow + net.hoff[l + 1] : nullptr, net.rowmap[l + 1],
+                                    A.init, k);
+            }
             emax = fmaxf(emax, __shfl_xor(emax, 16));
             emax = fmaxf(emax, __shfl_xor(emax, 32));
             if (g == 0) part_at(rp ^ 1, mt) = emax;
@@ -518,8 +629,8 @@ __global__ __launch_bounds__(kNW * 64) void alpha_fwd_kernel(NetDev net, PropDev
 // Adjoint pass: d J / d alpha through the property rows, the transposed contractions W^T, |W|^T
 // on MFMA and every alpha epilogue, from the tape of the forward pass with the same slopes.
 // ---------------------------------------------------------------------------------------------
-template <int NC, bool GS>
-__global__ __launch_bounds__(kNW * 64) void alpha_bwd_kernel(NetDev net, PropDev prop,
+template <int NC, bool GS, bool RP>
+__global__ __launch_bounds__(kNW * 64, 2) void alpha_bwd_kernel(NetDev net, PropDev prop,
                                                              AlphaArgs A, int slots) {
     extern __shared__ float lds[];
     using G = Groups<NC>;
@@ -593,6 +704,39 @@ __global__ __launch_bounds__(kNW * 64) void alpha_bwd_kernel(NetDev net, PropDev
         }
     }
     __syncthreads();
+    float* arow = (A.alpha && bval) ? A.alpha + (size_t)b * net.nh : nullptr;
+    float* drow = (A.dalpha && bval) ? A.dalpha + (size_t)b * net.nh : nullptr;
+    float* mrow = (A.adam_m && bval) ? A.adam_m + (size_t)b * net.nh : nullptr;
+    float* vrow = (A.adam_v && bval) ? A.adam_v + (size_t)b * net.nh : nullptr;
+    if constexpr (RP) {
+        // one LDS buffer: each wave holds the post-activation adjoint of its tile in registers
+        f32x4 acc[G::CG];
+        int cb, ncols;
+        if (wave < net.mt_last)
+            contract_acc<NC>(prop.wgtfrag, prop.ks_rows, prop.ks_rows_alloc, wave, 0, dA, mtS, lane,
+                             acc, cb, ncols);
+        __syncthreads();
+        for (int h = H - 1; h >= 0; --h) {
+            const int tiles = hidden_tiles(net, h), rem = hidden_rem(net, h);
+            const int off = net.hoff[h];
+            if (wave < tiles) {
+                bool valid[4];
+#pragma unroll
+                for (int v = 0; v < 4; ++v) valid[v] = row_valid(wave, g, v, tiles, rem);
+                bwd_relu_reg<NC>(acc, tape + (size_t)h * slot, dA, mtS, wave, lane, valid,
+                                 arow ? arow + off : nullptr, drow ? drow + off : nullptr,
+                                 mrow ? mrow + off : nullptr, vrow ? vrow + off : nullptr,
+                                 net.rowmap[h], A, k);
+            }
+            if (h == 0) break;
+            __syncthreads();
+            const MidLayer& L = net.mid[h - 1];
+            if (wave < L.mt_in)
+                contract_acc<NC>(L.wtfrag, L.kst, L.kst_alloc, wave, 0, dA, mtS, lane, acc, cb, ncols);
+            __syncthreads();
+        }
+        return;
+    }
     {
         const int units = net.mt_last * G::NG;
         for (int u = wave; u < units; u += kNW)
@@ -601,10 +745,6 @@ __global__ __launch_bounds__(kNW * 64) void alpha_bwd_kernel(NetDev net, PropDev
     }
     __syncthreads();
 
-    float* arow = (A.alpha && bval) ? A.alpha + (size_t)b * net.nh : nullptr;
-    float* drow = (A.dalpha && bval) ? A.dalpha + (size_t)b * net.nh : nullptr;
-    float* mrow = (A.adam_m && bval) ? A.adam_m + (size_t)b * net.nh : nullptr;
-    float* vrow = (A.adam_v && bval) ? A.adam_v + (size_t)b * net.nh : nullptr;
     for (int h = H - 1; h >= 0; --h) {
         const int tiles = hidden_tiles(net, h), rem = hidden_rem(net, h);
         const f32x4* pre = tape + (size_t)h * slot;
@@ -768,11 +908,14 @@ hipError_t launch_fwd_nc(const NetDev& net, const PropDev& prop, const AlphaArgs
     const int slots = a.fwd_only ? sh.slots_fwd : sh.slots;
     (void)hipGetLastError();
     if (sh.global_state) {
-        auto kern = alpha_fwd_kernel<NC, true>;
+        auto kern = alpha_fwd_kernel<NC, true, false>;
         hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(kNW * 64), sh.lds_fwd, stream, net, prop, a, slots);
     } else {
         if constexpr (NC <= 11) {
-            auto kern = alpha_fwd_kernel<NC, false>;
+            auto kern = alpha_fwd_kernel<NC, false, false>;
+            if constexpr (Groups<NC>::NG == 1) {
+                if (sh.reg_path) kern = alpha_fwd_kernel<NC, false, true>;
+            }
             hipError_t e = allow_lds_a((const void*)kern, sh.lds_fwd);
             if (e != hipSuccess) return e;
             hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(kNW * 64), sh.lds_fwd, stream, net, prop, a, slots);
@@ -789,11 +932,14 @@ hipError_t launch_bwd_nc(const NetDev& net, const PropDev& prop, const AlphaArgs
     const int64_t blocks = (a.n + 15) / 16;
     (void)hipGetLastError();
     if (sh.global_state) {
-        auto kern = alpha_bwd_kernel<NC, true>;
+        auto kern = alpha_bwd_kernel<NC, true, false>;
         hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(kNW * 64), 0, stream, net, prop, a, sh.slots);
     } else {
         if constexpr (NC <= 11) {
-            auto kern = alpha_bwd_kernel<NC, false>;
+            auto kern = alpha_bwd_kernel<NC, false, false>;
+            if constexpr (NC <= 6) {
+                if (sh.reg_path_bwd) kern = alpha_bwd_kernel<NC, false, true>;
+            }
             hipError_t e = allow_lds_a((const void*)kern, sh.lds_bwd);
             if (e != hipSuccess) return e;
             hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(kNW * 64), sh.lds_bwd, stream, net, prop, a, sh.slots);
@@ -806,15 +952,29 @@ hipError_t launch_bwd_nc(const NetDev& net, const PropDev& prop, const AlphaArgs
 
 }  // namespace
 
+namespace {
+int g_alpha_state = 0;   // 0 automatic, 1 LDS where it fits, 2 always the tape's global slots
+}  // namespace
+
+int set_alpha_state_variant(int v) {
+    if (v < 0 || v > 2) return -1;
+    g_alpha_state = v;
+    return 0;
+}
+
 AlphaShape alpha_shape(const NetDev& net, const PropDev& prop) {
     (void)prop;
     AlphaShape s{};
     s.nc = nc_class(net.d);
     const size_t part = sizeof(float) * 2 * net.mt_max * 16;
     const size_t st = state_bytes(s.nc, net.mt_max);
-    s.global_state = (s.nc > 11 || 2 * st + part > 150 * 1024) ? 1 : 0;
+    s.global_state = (s.nc > 11 || 2 * st + part > 150 * 1024 || g_alpha_state == 2) ? 1 : 0;
+    // register path: one contraction unit per layer tile and at most one tile per wavefront
+    s.reg_path = (!s.global_state && s.nc <= 8 && net.mt_max <= 4) ? 1 : 0;
+    // the adjoint's register path spills beyond NC = 6 at two wavefronts per SIMD
+    s.reg_path_bwd = (s.reg_path && s.nc <= 6) ? 1 : 0;
     s.lds_fwd = s.global_state ? part : st + part;
-    s.lds_bwd = s.global_state ? 0 : 2 * st;
+    s.lds_bwd = s.global_state ? 0 : (s.reg_path_bwd ? st : 2 * st);
     s.slots = (net.n_affine - 1) + 1 + (s.global_state ? 2 : 0);
     s.slots_fwd = 1 + (s.global_state ? 1 : 0);
     s.slot_floats = (size_t)(2 * s.nc + 2) * net.mt_max * 256;

@@ -637,6 +637,13 @@ extern "C" int bound_tile_shape(int32_t d, int32_t mt_max, int32_t nt, int32_t u
     return SLR_OK;
 }
 
+extern "C" int alpha_state_variant(int32_t variant) {
+    g_err.clear();
+    if (set_alpha_state_variant(variant) != 0)
+        return fail(SLR_EINVAL, "alpha_state_variant: %d is not 0, 1 or 2", variant);
+    return SLR_OK;
+}
+
 extern "C" int bound_kernel_variant(int32_t variant) {
     g_err.clear();
     if (set_bound_variant(variant) != 0)

@@ -170,12 +170,17 @@ struct AlphaArgs {
 struct AlphaShape {
     int nc;                // center columns per neuron (class >= d + 1)
     int global_state;      // 1: the tile state lives in the tape's extra slots, not in LDS
+    int reg_path;          // 1: contraction results stay in registers (narrow states)
+    int reg_path_bwd;      // the same for the adjoint
     int slots;             // tape slots per tile
     int slots_fwd;         // tape slots per tile of a forward-only pass
     size_t slot_floats;    // floats per slot
     size_t lds_fwd, lds_bwd;
 };
 AlphaShape alpha_shape(const NetDev& net, const PropDev& prop);
+// Where the alpha kernels keep the tile state: 0 automatic (LDS where it fits), 1 the same,
+// 2 always in the tape's global slots.  Returns -1 for an unknown value.
+int set_alpha_state_variant(int v);
 size_t alpha_tape_bytes(const NetDev& net, const PropDev& prop, int64_t n, int fwd_only);
 hipError_t launch_alpha_forward(const NetDev& net, const PropDev& prop, const AlphaArgs& a,
                                 hipStream_t stream);

@@ -23,7 +23,8 @@ EXPORTS = ("load_net", "free_net", "load_property", "free_property", "bound_boxe
            "workspace_size", "count_exact", "count_approx", "sample_violations", "last_error",
            "bound_kernel_variant", "alpha_size", "alpha_tape_size", "bound_boxes_alpha",
            "bound_boxes_backward", "alpha_workspace_size", "alpha_optimize", "batch_create",
-           "batch_run", "batch_free", "count_exact_batch", "bound_tile_shape")
+           "batch_run", "batch_free", "count_exact_batch", "bound_tile_shape",
+           "alpha_state_variant")
 
 
 class SlrError(RuntimeError):
@@ -129,6 +130,8 @@ def lib() -> C.CDLL:
                                         C.POINTER(vp), C.POINTER(C.c_int32),
                                         C.POINTER(C.c_int64), vp, C.POINTER(CountResult)]
         L.count_exact_batch.restype = C.c_int
+        L.alpha_state_variant.argtypes = [i32]
+        L.alpha_state_variant.restype = C.c_int
         L.bound_tile_shape.argtypes = [i32, i32, i32, i32, i32]
         L.bound_tile_shape.restype = C.c_int
         L.last_error.argtypes = []
@@ -370,6 +373,11 @@ def sample_violations(net: Net, prop: Property, x, viol=None, stream=None):
 # ---------------------------------------------------------------------------------------------
 # alpha mode
 # ---------------------------------------------------------------------------------------------
+def alpha_state_variant(variant: int) -> None:
+    """0 automatic, 1 LDS where it fits, 2 global (see include/slrcount.h)."""
+    _check(lib().alpha_state_variant(int(variant)))
+
+
 def alpha_size(net: Net) -> int:
     """Slopes per box: the sum of the hidden widths."""
     out = C.c_int64()

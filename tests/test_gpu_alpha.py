@@ -280,3 +280,23 @@ def test_count_exact_alpha_acas():
     assert a["unsafe"] + a["safe"] + a["undecided"] == 1.0
     assert a["n_alpha_decided"] > 0
     assert a["n_boxes_bounded"] <= p["n_boxes_bounded"]
+
+
+def test_state_placement_variants_agree():
+    """Tile state in LDS or in the tape's global slots: identical bounds and gradients."""
+    inst, lo, hi = make("acas", 40, 0.2, seed=21)
+    net, prop = load(inst)
+    eng = E()
+    al = dev(rand_alpha(net, 40, 22))
+    dlo = torch.randn((40, 1), device="cuda")
+    out = []
+    try:
+        for v in (1, 2):
+            eng.alpha_state_variant(v)
+            g_lo, g_hi, _, tape = eng.bound_boxes_alpha(net, prop, dev(lo), dev(hi), al, raw=True)
+            da = eng.bound_boxes_backward(net, prop, tape, al, dlo, None, raw=True)
+            out.append((g_lo, g_hi, da))
+    finally:
+        eng.alpha_state_variant(0)
+    for a, b in zip(out[0], out[1]):
+        assert torch.equal(a, b)
