@@ -120,6 +120,113 @@ __device__ __forceinline__ void contract_acc(const float* __restrict__ frag, int
     }
 }
 
+template <int NC, typename PIn, typename POut>
+__device__ __forceinline__ void contract_unit(const float* __restrict__ frag, int ks, int ks_alloc,
+                                              int mt, int grp, PIn in, POut out, int mtS,
+                                              const float* __restrict__ bias, int lane);
+
+// Two output tiles (mt0, mt0 + 1) of one column group sharing every B-operand load: wide states
+// keep their tile state in global memory, where B reads are the contraction's main traffic.
+// The second tile is skipped when it does not exist (mt_out odd).
+template <int NC, typename PIn, typename POut>
+__device__ __forceinline__ void contract_unit2(const float* __restrict__ frag, int ks, int ks_alloc,
+                                               int mt0, int mt_out, int grp, PIn in, POut out,
+                                               int mtS, const float* __restrict__ bias, int lane) {
+    using G = Groups<NC>;
+    constexpr int CG = G::CG;
+    const int ngh = G::NG > 1 ? G::NG / 2 : 1;
+    const int half = G::SPLIT ? grp / ngh : 0;
+    const int first = G::SPLIT ? (grp - half * ngh) * CG : 0;
+    const int cb = G::SPLIT ? half * NC + first : 0;
+    const int ncols = G::SPLIT ? min(CG, NC - first) : CG;
+    const bool two = mt0 + 1 < mt_out;
+    f32x4 acc[2][CG];
+#pragma unroll
+    for (int m = 0; m < 2; ++m)
+#pragma unroll
+        for (int cc = 0; cc < CG; ++cc) acc[m][cc] = f32x4{0.f, 0.f, 0.f, 0.f};
+    const float* wf0 = frag + (size_t)mt0 * ks_alloc * 64 + lane;
+    const float* wf1 = frag + (size_t)(two ? mt0 + 1 : mt0) * ks_alloc * 64 + lane;
+    const int nq = (ks + 3) >> 2;
+    auto col = [&](int cc) { return cb + (G::SPLIT ? min(cc, ncols - 1) : cc); };
+    float af[2][4];
+    f32x4 bq[CG];
+#pragma unroll
+    for (int ss = 0; ss < 4; ++ss) {
+        af[0][ss] = wf0[ss * 64];
+        af[1][ss] = wf1[ss * 64];
+    }
+#pragma unroll
+    for (int cc = 0; cc < CG; ++cc) bq[cc] = in[(size_t)(col(cc) * mtS) * 64 + lane];
+    for (int q = 0; q < nq; ++q) {
+        const int nx = min(q + 1, nq - 1);
+        float an[2][4];
+        f32x4 bn[CG];
+#pragma unroll
+        for (int ss = 0; ss < 4; ++ss) {
+            an[0][ss] = wf0[(4 * nx + ss) * 64];
+            an[1][ss] = wf1[(4 * nx + ss) * 64];
+        }
+#pragma unroll
+        for (int cc = 0; cc < CG; ++cc) bn[cc] = in[(size_t)(col(cc) * mtS + nx) * 64 + lane];
+#pragma unroll
+        for (int ss = 0; ss < 4; ++ss) {
+#pragma unroll
+            for (int m = 0; m < 2; ++m) {
+                const float aw = af[m][ss];
+                const float aa = fabsf(aw);
+                const float ah = (G::SPLIT && half) ? aa : aw;
+#pragma unroll
+                for (int cc = 0; cc < CG; ++cc) {
+                    const float a = G::SPLIT ? ah : (cc >= NC ? aa : aw);
+                    acc[m][cc] = mfma16(a, bq[cc][ss], acc[m][cc]);
+                }
+            }
+        }
+#pragma unroll
+        for (int ss = 0; ss < 4; ++ss) {
+            af[0][ss] = an[0][ss];
+            af[1][ss] = an[1][ss];
+        }
+#pragma unroll
+        for (int cc = 0; cc < CG; ++cc) bq[cc] = bn[cc];
+    }
+    const int g = lane >> 4;
+#pragma unroll
+    for (int m = 0; m < 2; ++m) {
+        if (m == 1 && !two) break;
+        const int mt = mt0 + m;
+#pragma unroll
+        for (int cc = 0; cc < CG; ++cc) {
+            if (G::SPLIT && cc >= ncols) continue;
+            f32x4 o = acc[m][cc];
+            if (bias && cb + cc == 0) {
+#pragma unroll
+                for (int v = 0; v < 4; ++v) o[v] += bias[16 * mt + 4 * g + v];
+            }
+            out[(size_t)((cb + cc) * mtS + mt) * 64 + lane] = o;
+        }
+    }
+}
+
+// Every unit of one contraction layer (mt_out output tiles x NG column groups) over the
+// workgroup's wavefronts: pairs of output tiles for split (wide) states, single tiles otherwise.
+template <int NC, typename PIn, typename POut>
+__device__ __forceinline__ void contract_layer(const float* __restrict__ frag, int ks, int ks_alloc,
+                                               int mt_out, PIn in, POut out, int mtS,
+                                               const float* __restrict__ bias, int wave, int lane) {
+    using G = Groups<NC>;
+    if constexpr (G::SPLIT && NC <= 25) {   // (the widest class would spill with two tiles)
+        const int pairs = (mt_out + 1) >> 1;
+        for (int u = wave; u < pairs * G::NG; u += kNW)
+            contract_unit2<NC>(frag, ks, ks_alloc, 2 * (u / G::NG), mt_out, u % G::NG, in, out, mtS,
+                               bias, lane);
+    } else {
+        for (int u = wave; u < mt_out * G::NG; u += kNW)
+            contract_unit<NC>(frag, ks, ks_alloc, u / G::NG, u % G::NG, in, out, mtS, bias, lane);
+    }
+}
+
 // contract_acc, then out[c][mt] = acc (+ bias by relabeled row on column 0).
 template <int NC, typename PIn, typename POut>
 __device__ __forceinline__ void contract_unit(const float* __restrict__ frag, int ks, int ks_alloc,
@@ -523,9 +630,7 @@ __global__ __launch_bounds__(kNW * 64, 2) void alpha_fwd_kernel(NetDev net, Prop
             if (wave < L.mt_out)
                 contract_acc<NC>(L.wfrag, L.ks, L.ks_alloc, wave, 0, S, mtS, lane, acc, cb, ncols);
         } else {
-            for (int u = wave; u < units; u += kNW)
-                contract_unit<NC>(L.wfrag, L.ks, L.ks_alloc, u / G::NG, u % G::NG, S, pre, mtS,
-                                  L.bias, lane);
+            contract_layer<NC>(L.wfrag, L.ks, L.ks_alloc, L.mt_out, S, pre, mtS, L.bias, wave, lane);
         }
         __syncthreads();
         for (int mt = wave; mt < L.mt_out; mt += kNW) {
@@ -738,10 +843,8 @@ __global__ __launch_bounds__(kNW * 64, 2) void alpha_bwd_kernel(NetDev net, Prop
         return;
     }
     {
-        const int units = net.mt_last * G::NG;
-        for (int u = wave; u < units; u += kNW)
-            contract_unit<NC>(prop.wgtfrag, prop.ks_rows, prop.ks_rows_alloc, u / G::NG, u % G::NG,
-                              dA, dB, mtS, nullptr, lane);
+        contract_layer<NC>(prop.wgtfrag, prop.ks_rows, prop.ks_rows_alloc, net.mt_last, dA, dB, mtS,
+                           nullptr, wave, lane);
     }
     __syncthreads();
 
@@ -760,10 +863,7 @@ __global__ __launch_bounds__(kNW * 64, 2) void alpha_bwd_kernel(NetDev net, Prop
         if (h == 0) break;
         __syncthreads();
         const MidLayer& L = net.mid[h - 1];
-        const int units = L.mt_in * G::NG;
-        for (int u = wave; u < units; u += kNW)
-            contract_unit<NC>(L.wtfrag, L.kst, L.kst_alloc, u / G::NG, u % G::NG, dA, dB, mtS,
-                              nullptr, lane);
+        contract_layer<NC>(L.wtfrag, L.kst, L.kst_alloc, L.mt_in, dA, dB, mtS, nullptr, wave, lane);
         __syncthreads();
     }
 }
