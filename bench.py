@@ -223,6 +223,50 @@ def batch_section(E, torch, seed, reps=3):
             "instances_resolved": sum(1 for r in res if r["undecided"] == 0.0)}
 
 
+def approx_section(E, torch, seed, cpu):
+    """CountingProVe with SLR leaves on the 22-input network (22-64x3-3, y2 strict argmax,
+    [0,1]^22): 20 trials, 1000 samples per split, 99% confidence, leaf counts of depth 48 and
+    2^16 leaves; the FP64 oracle on a bounded sample of the same procedure beside it."""
+    import synth
+    inst = synth.nav22(seed)
+    net = E.Net(inst.net)
+    prop = E.Property(net, inst.C, inst.dvec)
+    kw = dict(trials=20, samples=1000, confidence=0.99, seed=seed, max_splits=60, grid_bits=16,
+              resolve_tol=0.01, leaf_depth=48, leaf_leaves=1 << 16)
+    E.count_approx(net, prop, inst.lo, inst.hi, **dict(kw, trials=1))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    r = E.count_approx(net, prop, inst.lo, inst.hi, **kw)
+    dt = time.perf_counter() - t0
+    small = dict(kw, trials=1, leaf_leaves=1 << 10, max_splits=12)
+    t0 = time.perf_counter()
+    rs = E.count_approx(net, prop, inst.lo, inst.hi, **small)
+    dts = time.perf_counter() - t0
+    out = {"workload": "count_approx, 22-64x3-3 network (seed %d), [0,1]^22, unsafe iff y2 is the "
+                       "strict argmax, 20 trials x 1000 samples, 99%% confidence, leaves: depth 48, "
+                       "2^16 leaves, resolved at <= 1%% undecided" % seed,
+           "seconds": dt, "lower_bound": r["lower_bound"],
+           "mean_estimate": sum(r["estimates"]) / len(r["estimates"]),
+           "splits": r["splits"],
+           "small_sample": {"params": "1 trial, 2^10-leaf leaf counts, <= 12 splits",
+                            "seconds": dts, "estimate": rs["estimates"][0],
+                            "splits": rs["splits"][0]}}
+    if cpu:
+        from oracle import count
+        t0 = time.perf_counter()
+        o = count.count_approx(inst.net, inst.C, inst.dvec, inst.lo, inst.hi, trials=1,
+                               samples=1000, confidence=0.99, seed=seed, leaf_depth=48,
+                               leaf_leaves=1 << 10, resolve_tol=0.01, max_splits=12,
+                               grid_bits=16)
+        dto = time.perf_counter() - t0
+        out["cpu_baseline"] = {"value": 1.0 / dto, "unit": "trials/s (small sample)",
+                               "cores": os.cpu_count(), "kind": "oracle",
+                               "sample": "FP64 oracle count_approx, the small-sample parameters, "
+                                         "%.1f s, estimate %.6g" % (dto, o["estimates"][0])}
+        out["small_sample"]["gpu_trials_per_s"] = 1.0 / dts
+    return out
+
+
 def alpha_section(E, torch, seed, cpu):
     import synth
     a5 = synth.acas(seed)
@@ -252,6 +296,8 @@ def main():
                     help="skip the alpha-mode measurements (optimizer throughput, counts with alpha)")
     ap.add_argument("--no-batch", action="store_true",
                     help="skip the batched-instances measurement")
+    ap.add_argument("--no-approx", action="store_true",
+                    help="skip the approximate-count measurement")
     ap.add_argument("--no-tile-cache", action="store_true",
                     help="ignore the autotuner's tile-shape cache (default shapes)")
     ap.add_argument("--variant", type=int, default=0,
@@ -341,6 +387,8 @@ def main():
     }
     if not args.no_batch:
         line["batch"] = batch_section(E, torch, args.seed)
+    if not args.no_approx:
+        line["approx"] = approx_section(E, torch, args.seed, not args.no_cpu_baseline)
     if not args.no_alpha:
         line["alpha"] = alpha_section(E, torch, args.seed, not args.no_cpu_baseline)
     if not args.no_cpu_baseline:
