@@ -231,7 +231,7 @@ def approx_section(E, torch, seed, cpu):
     inst = synth.nav22(seed)
     net = E.Net(inst.net)
     prop = E.Property(net, inst.C, inst.dvec)
-    kw = dict(trials=20, samples=1000, confidence=0.99, seed=seed, max_splits=60, grid_bits=16,
+    kw = dict(trials=20, samples=1000, confidence=0.99, seed=seed, max_splits=300, grid_bits=16,
               resolve_tol=0.01, leaf_depth=48, leaf_leaves=1 << 16)
     E.count_approx(net, prop, inst.lo, inst.hi, **dict(kw, trials=1))
     torch.cuda.synchronize()
@@ -243,8 +243,8 @@ def approx_section(E, torch, seed, cpu):
     rs = E.count_approx(net, prop, inst.lo, inst.hi, **small)
     dts = time.perf_counter() - t0
     out = {"workload": "count_approx, 22-64x3-3 network (seed %d), [0,1]^22, unsafe iff y2 is the "
-                       "strict argmax, 20 trials x 1000 samples, 99%% confidence, leaves: depth 48, "
-                       "2^16 leaves, resolved at <= 1%% undecided" % seed,
+                       "strict argmax, 20 trials x 1000 samples, 99%% confidence, <= 300 splits, "
+                       "leaves: depth 48, 2^16 leaves, resolved at <= 1%% undecided" % seed,
            "seconds": dt, "lower_bound": r["lower_bound"],
            "mean_estimate": sum(r["estimates"]) / len(r["estimates"]),
            "splits": r["splits"],

@@ -76,6 +76,12 @@ def lib() -> C.CDLL:
     """Load the HIP library (once).  Raises if it has not been built."""
     global _LIB
     if _LIB is None:
+        # torch first: it brings its own HIP runtime, and the library must bind to that same
+        # runtime (loaded the other way round, torch later finds no GPU)
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         if not os.path.exists(LIB_PATH):
             raise ImportError(f"{LIB_PATH} is missing: build it with "
                               "`python -m paper_2312_05890_amd.build`")
@@ -335,7 +341,7 @@ def count_exact(net: Net, prop: Property, lo, hi, max_depth: int, max_leaves: in
 
 
 def count_approx(net: Net, prop: Property, lo, hi, trials: int = 20, samples: int = 1000,
-                 confidence: float = 0.99, seed: int = 0, max_splits: int = 60,
+                 confidence: float = 0.99, seed: int = 0, max_splits: int = 300,
                  grid_bits: int = 16, resolve_tol: float = 0.01, leaf_depth: int = 48,
                  leaf_leaves: int = 1 << 16, chunk: int = 0, workspace=None,
                  stream=None) -> dict:
