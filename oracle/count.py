@@ -18,7 +18,9 @@ Approximate count (CountingProVe with the exact count as its leaf backend): per 
 repeatedly try the exact count on the current subdomain; if more than ``resolve_tol`` of it
 stays undecided, draw uniform samples, split one random dimension at the lower median of the
 violating samples' coordinates (all samples if none violates), snapped to a fixed dyadic
-grid of the domain, and keep a random half.  A trial that ends after s splits on a
+grid of the domain, and keep a random half; a trial also stops when the drawn dimension of the
+subdomain is already narrower than two grid steps, or after ``max_splits``.  A trial that ends
+after s splits on a
 subdomain holding the fraction v of the domain, with unsafe fraction f (lower end of the
 bracket) inside it, estimates E = 2^s v f.  The returned bound is 2^-beta min_i E_i with
 beta = log2(1/(1-confidence)) / trials; since E[2^s v f] <= VR for any split points, Markov's
@@ -169,6 +171,9 @@ def count_approx(net, C, dvec, lo, hi, trials: int = 20, samples: int = 1000,
             pts = (slo + u * (shi - slo)).astype(np.float32).astype(np.float64)
             viol = np.all(slr.property_values(net, C, dvec, pts) > 0.0, axis=1)
             dim, side = philox.split_choice(seed, t, s, d)
+            # the drawn side is already as narrow as two grid steps: the trial stops here
+            if float(shi[dim]) - float(slo[dim]) < 2.0 * (float(hi[dim]) - float(lo[dim])) * 2.0 ** -grid_bits:
+                break
             vals = pts[viol, dim] if viol.any() else pts[:, dim]
             med = float(np.sort(vals)[(vals.shape[0] - 1) // 2])
             m = snap_split(med, float(slo[dim]), float(shi[dim]), float(lo[dim]),

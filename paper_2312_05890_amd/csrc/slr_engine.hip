@@ -1176,6 +1176,9 @@ extern "C" int count_approx(const slr_net* net, const slr_property* prop, const 
             Philox::block(sctr, key, sw);
             const int dim = (int)(((uint64_t)sw[0] * (uint64_t)d) >> 32);
             const int side = (int)(sw[1] & 1u);
+            // a side as narrow as two grid steps is not split further: the trial stops here (the
+            // bound holds for any stopping rule; this keeps every leaf bisection exact in float32)
+            if (shi[dim] - slo[dim] < 2.0 * (hi[dim] - lo[dim]) * std::ldexp(1.0, -o.grid_bits)) break;
             coords.clear();
             for (int p = 0; p < o.samples; ++p)
                 if (viol[p]) coords.push_back(pts[(size_t)p * d + dim]);
