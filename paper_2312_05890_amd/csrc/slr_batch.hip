@@ -182,7 +182,7 @@ __global__ __launch_bounds__(256) void batch_split_kernel(BatchInst* insts, int 
         if (!I.split_pending) continue;
         const int c = I.cur;
         split_tile(I.n, I.d, I.cls, I.tile_und, I.lo[c], I.hi[c], I.path[c], I.lo[c ^ 1],
-                   I.hi[c ^ 1], I.path[c ^ 1], &I.err, (int64_t)(t - cpre[i]));
+                   I.hi[c ^ 1], I.path[c ^ 1], &I.err, I.max_leaves, (int64_t)(t - cpre[i]));
         __syncthreads();
     }
 }

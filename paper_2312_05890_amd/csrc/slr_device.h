@@ -245,17 +245,18 @@ __device__ __forceinline__ void bound_tile(
 #pragma unroll
                     for (int c = 0; c < NCOL; ++c) bq[c] = bn[c];
                 }
-                const int tail = ks & 3;   // af/bq now hold quad nq (valid when tail > 0)
+                // the last K-steps (ks % 4 of them) one at a time, B read as scalars: a plain
+                // loop keeps the accumulators in place (no per-step selects of the whole set)
+                for (int st = 4 * nq; st < ks; ++st) {
+                    const float aw = wf[st * 64];
+                    const float aa = fabsf(aw);
+                    float bs[NCOL];
 #pragma unroll
-                for (int ss = 0; ss < 3; ++ss) {
-                    if (ss < tail) {
-                        const float aw = af[ss];
-                        const float aa = fabsf(aw);
+                    for (int c = 0; c < NCOL; ++c) bs[c] = sb[c * colstride + st];
 #pragma unroll
-                        for (int c = 0; c < NCOL - 2; ++c) acc[c] = mfma16(aw, bq[c][ss], acc[c]);
-                        acc[NCOL - 2] = mfma16(aa, bq[NCOL - 2][ss], acc[NCOL - 2]);
-                        acc[NCOL - 1] = mfma16(aa, bq[NCOL - 1][ss], acc[NCOL - 1]);
-                    }
+                    for (int c = 0; c < NCOL - 2; ++c) acc[c] = mfma16(aw, bs[c], acc[c]);
+                    acc[NCOL - 2] = mfma16(aa, bs[NCOL - 2], acc[NCOL - 2]);
+                    acc[NCOL - 1] = mfma16(aa, bs[NCOL - 1], acc[NCOL - 1]);
                 }
 #pragma unroll
                 for (int c = 0; c < NCOL; ++c) res[i][c] = acc[c];
@@ -606,7 +607,7 @@ __device__ __forceinline__ void count_tile(int64_t n, const int8_t* __restrict__
 }
 
 // Children of the undecided boxes of one 1024-box tile, written in parent order after those of
-// all earlier tiles.
+// all earlier tiles; children at index >= cap (the frontier capacity) are not written.
 __device__ __forceinline__ void split_tile(int64_t n, int d, const int8_t* __restrict__ cls,
                                            const unsigned* __restrict__ tile_und,
                                            const float* __restrict__ lo,
@@ -614,7 +615,7 @@ __device__ __forceinline__ void split_tile(int64_t n, int d, const int8_t* __res
                                            const unsigned long long* __restrict__ path,
                                            float* __restrict__ lo2, float* __restrict__ hi2,
                                            unsigned long long* __restrict__ path2,
-                                           unsigned* err, int64_t tile) {
+                                           unsigned* err, int64_t cap, int64_t tile) {
     __shared__ unsigned red[4];
     __shared__ unsigned wpre[4];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -660,6 +661,10 @@ __device__ __forceinline__ void split_tile(int64_t n, int d, const int8_t* __res
         const float m = 0.5f * (l[js] + h[js]);
         if (!(m - l[js] == h[js] - m && l[js] < m && m < h[js])) atomicOr(err, 1u);
         const int64_t o0 = 2 * (int64_t)rank, o1 = o0 + 1;
+        if (o1 >= cap) {   // beyond the frontier buffers: only a split the caller will discard
+            ++rank;
+            continue;
+        }
         for (int k = 0; k < d; ++k) {
             lo2[o0 * d + k] = l[k];
             hi2[o0 * d + k] = k == js ? m : h[k];

@@ -490,7 +490,7 @@ struct Workspace {
     double* vol;                 // [3]
     unsigned long long* counts;  // [3]
     unsigned long long* rechecks;
-    unsigned* err;
+    unsigned* err;               // [kMaxLevels + 1]: per-level split errors, then the volume check
     float* samples;              // [samples][d]
     int8_t* viol;                // [samples]
     // alpha batches of up to achunk boxes
@@ -562,7 +562,7 @@ Workspace layout_ws(char* base, const NetDev& nd, const PropDev& pd, int64_t cap
     w.vol = (double*)take(sizeof(double) * 3);
     w.counts = (unsigned long long*)take(sizeof(unsigned long long) * 3);
     w.rechecks = (unsigned long long*)take(sizeof(unsigned long long));
-    w.err = (unsigned*)take(sizeof(unsigned));
+    w.err = (unsigned*)take(sizeof(unsigned) * (kMaxLevels + 1));
     w.samples = (float*)take(sizeof(float) * (size_t)d * std::max(samples, 0));
     w.viol = (int8_t*)take(std::max(samples, 0));
     w.wchunk = 0;
@@ -865,6 +865,29 @@ extern "C" int alpha_optimize(const slr_net* net, const slr_property* prop, int6
 
 namespace {
 
+// Pinned host staging for the per-level read-back (a pageable destination costs an extra staged
+// copy on every level).  Allocated once per process on first use and kept; a thread-local slot
+// keeps concurrent calls on different threads apart.
+struct PinnedStats {
+    LevelStats* p = nullptr;
+    ~PinnedStats() {
+        if (p) (void)hipHostFree(p);
+    }
+};
+
+LevelStats* pinned_stats() {
+    thread_local PinnedStats ps;
+    if (!ps.p) {
+        void* q = nullptr;
+        if (hipHostMalloc(&q, sizeof(LevelStats) * 2, hipHostMallocDefault) != hipSuccess) {
+            (void)hipGetLastError();
+            return nullptr;
+        }
+        ps.p = (LevelStats*)q;
+    }
+    return ps.p;
+}
+
 int count_exact_impl(const slr_net* net, const slr_property* prop, const double* lo,
                      const double* hi, const slr_exact_opts* o, const Workspace& w,
                      slr_count_result* out) {
@@ -877,7 +900,7 @@ int count_exact_impl(const slr_net* net, const slr_property* prop, const double*
 
     HIP_TRY(hipMemsetAsync(w.stats, 0, sizeof(LevelStats) * kMaxLevels, s), "count_exact: clear");
     HIP_TRY(hipMemsetAsync(w.rechecks, 0, sizeof(unsigned long long), s), "count_exact: clear");
-    HIP_TRY(hipMemsetAsync(w.err, 0, sizeof(unsigned), s), "count_exact: clear");
+    HIP_TRY(hipMemsetAsync(w.err, 0, sizeof(unsigned) * (kMaxLevels + 1), s), "count_exact: clear");
     std::vector<float> root(2 * d);
     for (int k = 0; k < d; ++k) {
         root[k] = (float)lo[k];
@@ -893,13 +916,19 @@ int count_exact_impl(const slr_net* net, const slr_property* prop, const double*
         HIP_TRY(hipEventCreate(&ev0), "count_exact: event");
         HIP_TRY(hipEventCreate(&ev1), "count_exact: event");
     }
+    hipEvent_t evr = nullptr;   // marks the end of a level's read-back
+    if (hipEventCreateWithFlags(&evr, hipEventDisableTiming) != hipSuccess) {
+        (void)hipGetLastError();
+        evr = nullptr;
+    }
     struct EventGuard {
-        hipEvent_t a, b;
+        hipEvent_t a, b, c;
         ~EventGuard() {
             if (a) (void)hipEventDestroy(a);
             if (b) (void)hipEventDestroy(b);
+            if (c) (void)hipEventDestroy(c);
         }
-    } guard{ev0, ev1};
+    } guard{ev0, ev1, evr};
     double bound_ms = 0.0, alpha_ms = 0.0;
     int64_t launches = 0, alpha_boxes = 0, alpha_decided = 0, alpha_und_before = 0;
     int64_t n = 1, resolved = 0, bounded = 0, tcount = 0;
@@ -991,8 +1020,13 @@ int count_exact_impl(const slr_net* net, const slr_property* prop, const double*
             }
         }
         HIP_TRY(launch_level_count(n, w.cls, w.tile_und, w.stats + t, s), "count_exact: count kernel");
+        // the split is enqueued before the host reads this level's counts (it runs while the
+        // read-back travels); if the level turns out to be the last one its output is unused,
+        // children beyond the buffers are not written and its error slot is ignored
         LevelStats hs;
-        HIP_TRY(hipMemcpyAsync(&hs, w.stats + t, sizeof hs, hipMemcpyDeviceToHost, s), "count_exact: readback");
+        LevelStats* pin = pinned_stats();
+        HIP_TRY(hipMemcpyAsync(pin ? pin : &hs, w.stats + t, sizeof hs, hipMemcpyDeviceToHost, s),
+                "count_exact: readback");
         if (o->trace_capacity > 0 && o->trace_path && o->trace_cls && o->trace_depth && tcount < o->trace_capacity) {
             const int64_t m = std::min<int64_t>(n, o->trace_capacity - tcount);
             hpath.resize(m);
@@ -1007,7 +1041,21 @@ int count_exact_impl(const slr_net* net, const slr_property* prop, const double*
             }
             tcount += m;
         }
-        HIP_TRY(hipStreamSynchronize(s), "count_exact: sync");
+        // When the leaf budget cannot stop the search at this level, the split is enqueued
+        // before the host reads the counts back and runs while the read-back travels (its output
+        // is unused if nothing is left undecided; its error slot is checked only for levels the
+        // search continues from).  Otherwise the host decides first.
+        const bool spec = t < D && pin && evr && resolved + 2 * n <= M;
+        if (spec) {
+            HIP_TRY(hipEventRecord(evr, s), "count_exact: event");
+            HIP_TRY(launch_split(n, d, w.cls, w.tile_und, w.lo[cur], w.hi[cur], w.path[cur],
+                                 w.lo[cur ^ 1], w.hi[cur ^ 1], w.path[cur ^ 1], w.err + t, M, s),
+                    "count_exact: split kernel");
+            HIP_TRY(hipEventSynchronize(evr), "count_exact: sync");
+        } else {
+            HIP_TRY(hipStreamSynchronize(s), "count_exact: sync");
+        }
+        if (pin) hs = *pin;
         if (ev0 && o->alpha_steps <= 0) {
             float ms = 0.f;
             HIP_TRY(hipEventElapsedTime(&ms, ev0, ev1), "count_exact: event");
@@ -1031,21 +1079,25 @@ int count_exact_impl(const slr_net* net, const slr_property* prop, const double*
             status = SLR_BUDGET;
             break;
         }
-        HIP_TRY(launch_split(n, d, w.cls, w.tile_und, w.lo[cur], w.hi[cur], w.path[cur],
-                             w.lo[cur ^ 1], w.hi[cur ^ 1], w.path[cur ^ 1], w.err, s),
-                "count_exact: split kernel");
+        if (!spec)
+            HIP_TRY(launch_split(n, d, w.cls, w.tile_und, w.lo[cur], w.hi[cur], w.path[cur],
+                                 w.lo[cur ^ 1], w.hi[cur ^ 1], w.path[cur ^ 1], w.err + t, M, s),
+                    "count_exact: split kernel");
         n = 2 * und;
         cur ^= 1;
     }
-    HIP_TRY(launch_volume(w.stats, levels, stop_level, stopped, w.vol, w.counts, w.err, s), "count_exact: volume kernel");
+    HIP_TRY(launch_volume(w.stats, levels, stop_level, stopped, w.vol, w.counts, w.err + kMaxLevels, s),
+            "count_exact: volume kernel");
     double vol[3];
     unsigned long long counts[3], rechecks = 0;
-    unsigned err = 0;
+    unsigned errs[kMaxLevels + 1];
     HIP_TRY(hipMemcpyAsync(vol, w.vol, sizeof vol, hipMemcpyDeviceToHost, s), "count_exact: readback");
     HIP_TRY(hipMemcpyAsync(counts, w.counts, sizeof counts, hipMemcpyDeviceToHost, s), "count_exact: readback");
     HIP_TRY(hipMemcpyAsync(&rechecks, w.rechecks, sizeof rechecks, hipMemcpyDeviceToHost, s), "count_exact: readback");
-    HIP_TRY(hipMemcpyAsync(&err, w.err, sizeof err, hipMemcpyDeviceToHost, s), "count_exact: readback");
+    HIP_TRY(hipMemcpyAsync(errs, w.err, sizeof errs, hipMemcpyDeviceToHost, s), "count_exact: readback");
     HIP_TRY(hipStreamSynchronize(s), "count_exact: sync");
+    unsigned err = errs[kMaxLevels];
+    for (int t = 0; t + 1 < levels; ++t) err |= errs[t];   // the levels that were continued
     if (err & 1u) return fail(SLR_EINTERNAL, "count_exact: a bisection midpoint is not exact in float32 (box too deep for its coordinates)");
     if (err & 2u) return fail(SLR_EINTERNAL, "count_exact: leaf volumes do not sum to the box volume");
     out->unsafe = vol[0];

@@ -117,7 +117,7 @@ hipError_t launch_level_count(int64_t n, const int8_t* cls, unsigned int* tile_u
 hipError_t launch_split(int64_t n, int d, const int8_t* cls, const unsigned int* tile_und,
                         const float* lo, const float* hi, const unsigned long long* path,
                         float* lo2, float* hi2, unsigned long long* path2, unsigned int* err,
-                        hipStream_t stream);
+                        int64_t cap, hipStream_t stream);
 hipError_t launch_volume(const LevelStats* stats, int levels, int stop_level, int stopped,
                          double* out3, unsigned long long* out_counts, unsigned int* err,
                          hipStream_t stream);

@@ -64,8 +64,8 @@ __global__ __launch_bounds__(256) void split_kernel(int64_t n, int d, const int8
                                                     const unsigned long long* __restrict__ path,
                                                     float* __restrict__ lo2, float* __restrict__ hi2,
                                                     unsigned long long* __restrict__ path2,
-                                                    unsigned* err) {
-    split_tile(n, d, cls, tile_und, lo, hi, path, lo2, hi2, path2, err, blockIdx.x);
+                                                    unsigned* err, int64_t cap) {
+    split_tile(n, d, cls, tile_und, lo, hi, path, lo2, hi2, path2, err, cap, blockIdx.x);
 }
 
 __global__ void volume_kernel(const LevelStats* stats, int levels, int stop_level, int stopped,
@@ -628,11 +628,11 @@ hipError_t launch_level_count(int64_t n, const int8_t* cls, unsigned* tile_und, 
 hipError_t launch_split(int64_t n, int d, const int8_t* cls, const unsigned* tile_und,
                         const float* lo, const float* hi, const unsigned long long* path,
                         float* lo2, float* hi2, unsigned long long* path2, unsigned* err,
-                        hipStream_t stream) {
+                        int64_t cap, hipStream_t stream) {
     if (n <= 0) return hipSuccess;
     (void)hipGetLastError();
     hipLaunchKernelGGL(split_kernel, dim3((unsigned)level_tiles(n)), dim3(256), 0, stream, n, d,
-                       cls, tile_und, lo, hi, path, lo2, hi2, path2, err);
+                       cls, tile_und, lo, hi, path, lo2, hi2, path2, err, cap);
     return hipGetLastError();
 }
 
