@@ -12,7 +12,10 @@
 // K-step s) and also exactly where the same lane finds output rows 16 mt + 4 g + v of the
 // accumulator D[4 g + v][j] of M tile mt.  So every hidden layer is
 //     MFMA:      acc[c] += W_frag(mt, s) * S[c][s]        (c <= d, A = W)
-//                acc[c] += |W_frag(mt, s)| * S[c][s]       (r and q columns, A = |W|)
+//                acc[c] += |W_frag(mt, s)| * S[c][s]       (r column, A = |W|)
+//                acc[q] += bf16(|W|) * bf16(S[q])          (q column: one bf16 16x16x16 MFMA
+//                                                           per four K-steps, both operands
+//                                                           rounded up, so q stays an upper bound)
 //     epilogue:  lane-local on its 4 neurons x NCOL columns: bias, rounding margin,
 //                concretization, Eq. 1, then one 16-byte LDS store per column.
 // The first affine layer (box -> hidden) is exact and done on the VALU; the output layer with
@@ -45,6 +48,25 @@ __device__ __forceinline__ bool row_valid(int mt, int g, int v, int tiles, int r
 
 __device__ __forceinline__ f32x4 mfma16(float a, float b, f32x4 c) {
     return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+typedef short bf16x4 __attribute__((ext_vector_type(4)));
+
+// Four non-negative floats as bf16 rounded up (never below the input).
+__device__ __forceinline__ bf16x4 bf16_up4(f32x4 x) {
+    bf16x4 r;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) r[i] = (short)((__float_as_uint(x[i]) + 0xFFFFu) >> 16);
+    return r;
+}
+
+// One 16x16x16 bf16 MFMA: the four K-steps of a quad at once.  Lane 16 g + j supplies A[j][4 g + i]
+// and B[4 g + i][j] (i = 0..3), which are exactly the K-steps 4 q + i of the float32 layout, and
+// accumulates into the same D layout.
+__device__ __forceinline__ f32x4 mfma_bf16_quad(uint64_t a, f32x4 b, f32x4 c) {
+    bf16x4 av;
+    __builtin_memcpy(&av, &a, 8);
+    return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bf16_up4(b), c, 0, 0, 0);
 }
 
 // Scalars of the epilogue: zero margins and no rounding-up in the unwidened mode.
@@ -215,7 +237,9 @@ __device__ __forceinline__ void bound_tile(
                 // B from LDS), then the tail quad with per-step guards
                 const int nq = ks >> 2;
                 const int nqa = L->ks_alloc >> 2;
+                const uint64_t* qf = L->qfrag + (size_t)mt * nqa * 64 + lane;
                 float af[4];
+                uint64_t aq = qf[0];
                 f32x4 bq[NCOL];
 #pragma unroll
                 for (int ss = 0; ss < 4; ++ss) af[ss] = wf[ss * 64];
@@ -225,6 +249,7 @@ __device__ __forceinline__ void bound_tile(
                 for (int qi = 0; qi < nq; ++qi) {
                     const int nx = min(qi + 1, nqa - 1) * 4;
                     float an[4];
+                    const uint64_t aqn = qf[nx * 16];
                     f32x4 bn[NCOL];
 #pragma unroll
                     for (int ss = 0; ss < 4; ++ss) an[ss] = wf[(nx + ss) * 64];
@@ -238,25 +263,31 @@ __device__ __forceinline__ void bound_tile(
 #pragma unroll
                         for (int c = 0; c < NCOL - 2; ++c) acc[c] = mfma16(aw, bq[c][ss], acc[c]);
                         acc[NCOL - 2] = mfma16(aa, bq[NCOL - 2][ss], acc[NCOL - 2]);
-                        acc[NCOL - 1] = mfma16(aa, bq[NCOL - 1][ss], acc[NCOL - 1]);
                     }
+                    acc[NCOL - 1] = mfma_bf16_quad(aq, bq[NCOL - 1], acc[NCOL - 1]);
 #pragma unroll
                     for (int ss = 0; ss < 4; ++ss) af[ss] = an[ss];
+                    aq = aqn;
 #pragma unroll
                     for (int c = 0; c < NCOL; ++c) bq[c] = bn[c];
                 }
                 // the last K-steps (ks % 4 of them) one at a time, B read as scalars: a plain
-                // loop keeps the accumulators in place (no per-step selects of the whole set)
+                // loop keeps the accumulators in place (no per-step selects of the whole set);
+                // the margin column takes the whole partial quad in one bf16 MFMA (its A is
+                // zero beyond ks)
+                if (4 * nq < ks)
+                    acc[NCOL - 1] = mfma_bf16_quad(
+                        qf[nq * 64], *reinterpret_cast<const f32x4*>(sb + (NCOL - 1) * colstride + 4 * nq),
+                        acc[NCOL - 1]);
                 for (int st = 4 * nq; st < ks; ++st) {
                     const float aw = wf[st * 64];
                     const float aa = fabsf(aw);
-                    float bs[NCOL];
+                    float bs[NCOL - 1];
 #pragma unroll
-                    for (int c = 0; c < NCOL; ++c) bs[c] = sb[c * colstride + st];
+                    for (int c = 0; c < NCOL - 1; ++c) bs[c] = sb[c * colstride + st];
 #pragma unroll
                     for (int c = 0; c < NCOL - 2; ++c) acc[c] = mfma16(aw, bs[c], acc[c]);
                     acc[NCOL - 2] = mfma16(aa, bs[NCOL - 2], acc[NCOL - 2]);
-                    acc[NCOL - 1] = mfma16(aa, bs[NCOL - 1], acc[NCOL - 1]);
                 }
 #pragma unroll
                 for (int c = 0; c < NCOL; ++c) res[i][c] = acc[c];
@@ -327,9 +358,9 @@ __device__ __forceinline__ void bound_tile(
 #pragma unroll
                         for (int c = 0; c < NCOL - 2; ++c) G[c] = mfma16(aw, bq[c][ss], G[c]);
                         G[NCOL - 2] = mfma16(aa, bq[NCOL - 2][ss], G[NCOL - 2]);
-                        G[NCOL - 1] = mfma16(aa, bq[NCOL - 1][ss], G[NCOL - 1]);
                     }
                 }
+                G[NCOL - 1] = mfma_bf16_quad(prop.wgqfrag[q * 64 + lane], bq[NCOL - 1], G[NCOL - 1]);
             }
 #pragma unroll
             for (int v = 0; v < 4; ++v) {

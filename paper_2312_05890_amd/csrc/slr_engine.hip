@@ -96,6 +96,30 @@ std::vector<float> pack_fragments(const float* W, int n_in, const std::vector<in
     return f;
 }
 
+// bf16 value >= |x| (x finite): the upper half of the float32 bits, rounded up.
+uint16_t bf16_abs_up(float x) {
+    uint32_t u;
+    const float a = std::fabs(x);
+    memcpy(&u, &a, 4);
+    return (uint16_t)((u + 0xFFFFu) >> 16);
+}
+
+// The margin column's A operand: for each (tile, K-quad, lane) the four |W| values of K-steps
+// 4 qb .. 4 qb + 3 of the float32 fragments, as bf16 rounded up, packed low to high.
+std::vector<uint64_t> pack_quads_bf16(const std::vector<float>& frag, int tiles, int ks_alloc) {
+    const int nq = ks_alloc / 4;
+    std::vector<uint64_t> q((size_t)tiles * nq * 64, 0);
+    for (int mt = 0; mt < tiles; ++mt)
+        for (int qb = 0; qb < nq; ++qb)
+            for (int lane = 0; lane < 64; ++lane) {
+                uint64_t v = 0;
+                for (int i = 0; i < 4; ++i)
+                    v |= (uint64_t)bf16_abs_up(frag[((size_t)mt * ks_alloc + 4 * qb + i) * 64 + lane]) << (16 * i);
+                q[((size_t)mt * nq + qb) * 64 + lane] = v;
+            }
+    return q;
+}
+
 bool all_finite(const float* p, size_t n) {
     for (size_t i = 0; i < n; ++i)
         if (!std::isfinite(p[i])) return false;
@@ -241,7 +265,7 @@ extern "C" int load_net(int32_t n_affine, const int32_t* sizes, const float* con
         nd.hoff[h] = nd.nh;
         nd.nh += sizes[h + 1];
     }
-    struct MidIdx { size_t frag, w, wt, bias, absrow, b, wtfrag; };
+    struct MidIdx { size_t frag, w, wt, bias, absrow, b, wtfrag, qfrag; };
     std::vector<MidIdx> mids;
     for (int l = 1; l <= n_affine - 2; ++l) {
         const int n_in = sizes[l], n_out = sizes[l + 1];
@@ -268,6 +292,8 @@ extern "C" int load_net(int32_t n_affine, const int32_t* sizes, const float* con
         }
         MidIdx mi;
         mi.frag = add(frag.data(), frag.size() * sizeof(float));
+        std::vector<uint64_t> qfrag = pack_quads_bf16(frag, L.mt_out, L.ks_alloc);
+        mi.qfrag = add(qfrag.data(), qfrag.size() * sizeof(uint64_t));
         mi.w = add(W[l], sizeof(float) * n_out * n_in);
         std::vector<float> wt((size_t)n_in * n_out);
         for (int jrow = 0; jrow < n_out; ++jrow)
@@ -313,6 +339,7 @@ extern "C" int load_net(int32_t n_affine, const int32_t* sizes, const float* con
         nd.mid[l].absrow = (const float*)(base + offs[mids[l].absrow]);
         nd.mid[l].b = (const float*)(base + offs[mids[l].b]);
         nd.mid[l].wtfrag = (const float*)(base + offs[mids[l].wtfrag]);
+        nd.mid[l].qfrag = (const uint64_t*)(base + offs[mids[l].qfrag]);
     }
     for (int h = 0; h < n_affine - 1; ++h) nd.rowmap[h] = (const int*)(base + offs[i_rowmap[h]]);
     slr_net* net = new slr_net;
@@ -380,6 +407,7 @@ extern "C" int load_property(const slr_net* net, int32_t rows, const float* C, c
     std::vector<int> row_at(16, -1);
     for (int r = 0; r < rows; ++r) row_at[r] = r;
     std::vector<float> wgfrag = pack_fragments(wg.data(), K, row_at, net->last_at, pd.ks_out, pd.ks_out_alloc);
+    std::vector<uint64_t> wgq = pack_quads_bf16(wgfrag, 1, pd.ks_out_alloc);
     pd.kpad = (int)net->last_at.size();
     std::vector<float> wgp((size_t)rows * pd.kpad, 0.f);
     for (int r = 0; r < rows; ++r)
@@ -405,11 +433,12 @@ extern "C" int load_property(const slr_net* net, int32_t rows, const float* C, c
     const size_t s_fa = (wgfrag_a.size() * 4 + 255) / 256 * 256;
     const size_t s_ft = (wgtfrag.size() * 4 + 255) / 256 * 256;
     const size_t s_16 = 256;
+    const size_t s_q = (wgq.size() * 8 + 255) / 256 * 256;
     const size_t s_wgp = (wgp.size() * 4 + 255) / 256 * 256;
     const size_t s_wg = (wg.size() * 4 + 255) / 256 * 256, s_r = (rows * 4 + 255) / 256 * 256;
     const size_t s_frag = (wgfrag.size() * 4 + 255) / 256 * 256;
     const size_t s_wg64 = (wg64.size() * 8 + 255) / 256 * 256, s_r64 = (rows * 8 + 255) / 256 * 256;
-    const size_t total = s_wg + 2 * s_r + s_wg64 + 2 * s_r64 + s_frag + s_wgp + s_fa + s_ft + 2 * s_16;
+    const size_t total = s_wg + 2 * s_r + s_wg64 + 2 * s_r64 + s_frag + s_wgp + s_fa + s_ft + 2 * s_16 + s_q;
     std::vector<char> host(total, 0);
     size_t o = 0;
     memcpy(host.data() + o, wg.data(), wg.size() * 4);
@@ -435,7 +464,9 @@ extern "C" int load_property(const slr_net* net, int32_t rows, const float* C, c
     memcpy(host.data() + o, bga.data(), 64);
     const size_t o_bga = o; o += s_16;
     memcpy(host.data() + o, aga.data(), 64);
-    const size_t o_aga = o;
+    const size_t o_aga = o; o += s_16;
+    memcpy(host.data() + o, wgq.data(), wgq.size() * 8);
+    const size_t o_q = o;
     void* mem = nullptr;
     hipError_t e = hipMalloc(&mem, total);
     if (e != hipSuccess) return fail(SLR_ENOMEM, "load_property: hipMalloc: %s", hipGetErrorString(e));
@@ -457,6 +488,7 @@ extern "C" int load_property(const slr_net* net, int32_t rows, const float* C, c
     pd.wgtfrag = (const float*)(base + o_ft);
     pd.bga = (const float*)(base + o_bga);
     pd.aga = (const float*)(base + o_aga);
+    pd.wgqfrag = (const uint64_t*)(base + o_q);
     slr_property* p = new slr_property;
     p->dev = pd;
     p->mem = mem;

@@ -31,6 +31,8 @@
 // One hidden-to-hidden affine layer (its input is a hidden ReLU layer).
 struct MidLayer {
     const float* wfrag;   // [mt_out][ks_alloc][64] MFMA A-operand fragments (see pack_fragments)
+    const uint64_t* qfrag;  // [mt_out][ks_alloc / 4][64]: |W| of four K-steps as bf16 rounded up
+                            // (A operand of the bf16 16x16x16 MFMA of the margin column)
     const float* w;       // row-major [n_out][n_in] float32 (sample forward pass)
     const float* wt;      // transposed [n_in][n_out] (FP64 recheck: coalesced across neurons)
     const float* bias;    // [16 * mt_out] by relabeled row, zero padded
@@ -73,6 +75,7 @@ struct PropDev {
     int rows, n_last;
     const float* wg;      // [rows][n_last] folded last layer C W_L, float32
     const float* wgfrag;  // [ks_out_alloc][64] MFMA A fragments of wg (rows padded to 16)
+    const uint64_t* wgqfrag;  // [ks_out_alloc / 4][64] |wg| as bf16 rounded up, four K-steps
     int ks_out, ks_out_alloc;
     const float* wgp;     // [rows][kpad] wg with relabeled, zero-padded columns
     int kpad;             // 16 * tiles of the last hidden layer

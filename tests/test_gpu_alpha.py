@@ -300,3 +300,97 @@ def test_state_placement_variants_agree():
         eng.alpha_state_variant(0)
     for a, b in zip(out[0], out[1]):
         assert torch.equal(a, b)
+
+
+def test_full_size_launch_sampled():
+    """The bench's launch: 65536 boxes of the 5-input domain (widths up to 1/16).  Raw bounds and
+    gradients of 48 sampled boxes against the oracle; the optimizer's bounds sound on them."""
+    inst = synth.acas(0)
+    n = 65536
+    lo, hi = synth.uniform_boxes(inst.lo, inst.hi, n, 101, 1.0 / 16)
+    net, prop = load(inst)
+    eng = E()
+    al = rand_alpha(net, n, 31, 0.05, 0.95)
+    a = dev(al)
+    g_lo, g_hi, _, tape = eng.bound_boxes_alpha(net, prop, dev(lo), dev(hi), a, raw=True)
+    pick = np.random.default_rng(32).choice(n, 48, replace=False)
+    o_lo, o_hi = slr.propagate(inst.net, inst.C, inst.dvec, lo[pick], hi[pick], alpha=al[pick])
+    s = scale_of(o_lo, o_hi)
+    assert np.all(np.abs(g_lo.cpu().numpy()[pick] - o_lo) <= TOL * s)
+    assert np.all(np.abs(g_hi.cpu().numpy()[pick] - o_hi) <= TOL * s)
+    dhi = torch.zeros((n, 1), device="cuda")
+    dhi[torch.from_numpy(pick).cuda()] = 1.0
+    ga = eng.bound_boxes_backward(net, prop, tape, a, None, dhi, raw=True).cpu().numpy()[pick]
+    mode = np.zeros(48, np.int64)
+    row = np.zeros(48, np.int64)
+    import oracle.alpha as OA
+    orig = OA.objective_weights
+    OA.objective_weights = lambda *args, **kw: (mode, row)   # seeds: d J / d g_hi = 1
+    try:
+        go = OA.gradient(inst.net, inst.C, inst.dvec, lo[pick], hi[pick], al[pick])
+    finally:
+        OA.objective_weights = orig
+    ok = robust_boxes(inst, lo[pick], hi[pick], al[pick])
+    assert ok.sum() >= 8
+    sc = np.maximum(1e-3, np.abs(go).max(axis=1, keepdims=True))
+    assert np.all((np.abs(ga - go) / sc)[ok] <= 2e-3)
+    r = eng.alpha_optimize(net, prop, dev(lo), dev(hi), steps=20)
+    b_lo, b_hi = r["best_lo"].cpu().numpy(), r["best_hi"].cpu().numpy()
+    rng = np.random.default_rng(33)
+    for b in pick[:16]:
+        x = slr.sample_points(lo[b], hi[b], 300, rng)
+        gv = slr.property_values(inst.net, inst.C, inst.dvec, x)
+        assert np.all(b_lo[b] <= gv.min(0)) and np.all(gv.max(0) <= b_hi[b])
+
+
+def test_zero_width_boxes():
+    """Point boxes: no neuron crosses, so every slope is unused (zero gradient) and the raw
+    bounds equal the network's value at the point."""
+    inst = synth.acas(2)
+    rng = np.random.default_rng(34)
+    x = rng.uniform(0, 1, size=(20, 5)).astype(np.float32)
+    net, prop = load(inst)
+    eng = E()
+    al = dev(rand_alpha(net, 20, 35))
+    g_lo, g_hi, _, tape = eng.bound_boxes_alpha(net, prop, dev(x), dev(x), al, raw=True)
+    val = slr.property_values(inst.net, inst.C, inst.dvec, x.astype(np.float64))
+    s = scale_of(val, val)
+    assert np.all(np.abs(g_lo.cpu().numpy() - val) <= TOL * s)
+    assert np.all(np.abs(g_hi.cpu().numpy() - val) <= TOL * s)
+    da = eng.bound_boxes_backward(net, prop, tape, al, torch.ones((20, 1), device="cuda"),
+                                  torch.ones((20, 1), device="cuda"), raw=True)
+    assert torch.count_nonzero(da).item() == 0
+
+
+def test_max_input_dimension():
+    """d = 32 (the largest input dimension, widest state class): raw alpha bounds and the
+    adjoint against the oracle; plain exact count against the oracle on a shallow tree."""
+    from tests import test_gpu_parity as P
+    net_l = synth.make_net([32, 48, 48, 2], 5)
+    Cm = np.array([[1.0, -1.0]], np.float32)
+    dv = np.zeros(1, np.float32)
+    lo0, hi0 = np.zeros(32), np.ones(32)
+    inst = synth.Instance("d32", net_l, lo0, hi0, Cm, dv, 6, 1 << 10)
+    lo, hi = synth.uniform_boxes(lo0, hi0, 24, 36, 0.05)
+    net, prop = load(inst)
+    eng = E()
+    al = rand_alpha(net, 24, 37, 0.05, 0.95)
+    g_lo, g_hi, _, tape = eng.bound_boxes_alpha(net, prop, dev(lo), dev(hi), dev(al), raw=True)
+    o_lo, o_hi = slr.propagate(net_l, Cm, dv, lo, hi, alpha=al)
+    s = scale_of(o_lo, o_hi)
+    assert np.all(np.abs(g_lo.cpu().numpy() - o_lo) <= TOL * s)
+    assert np.all(np.abs(g_hi.cpu().numpy() - o_hi) <= TOL * s)
+    ga = eng.bound_boxes_backward(net, prop, tape, dev(al), None,
+                                  torch.ones((24, 1), device="cuda"), raw=True).cpu().numpy()
+    import oracle.alpha as OA
+    orig = OA.objective_weights
+    OA.objective_weights = lambda *args, **kw: (np.zeros(24, np.int64), np.zeros(24, np.int64))
+    try:
+        go = OA.gradient(net_l, Cm, dv, lo, hi, al)
+    finally:
+        OA.objective_weights = orig
+    ok = robust_boxes(inst, lo, hi, al)
+    assert ok.sum() >= 4
+    sc = np.maximum(1e-3, np.abs(go).max(axis=1, keepdims=True))
+    assert np.all((np.abs(ga - go) / sc)[ok] <= 2e-3)
+    P.compare_counts(inst, 6, 1 << 10)
