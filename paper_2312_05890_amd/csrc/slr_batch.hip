@@ -175,6 +175,7 @@ __global__ __launch_bounds__(256) void batch_advance_kernel(BatchInst* insts, in
 __global__ __launch_bounds__(256) void batch_split_kernel(BatchInst* insts, int n_inst,
                                                           BatchCtl* ctl,
                                                           const unsigned* __restrict__ cpre) {
+    extern __shared__ float split_stage[];   // 2 * kTile * kSplitStageD floats
     const unsigned total = ctl->ctiles;
     for (unsigned t = blockIdx.x; t < total; t += gridDim.x) {
         const int i = find_owner(cpre, 0, n_inst, t);
@@ -182,7 +183,8 @@ __global__ __launch_bounds__(256) void batch_split_kernel(BatchInst* insts, int 
         if (!I.split_pending) continue;
         const int c = I.cur;
         split_tile(I.n, I.d, I.cls, I.tile_und, I.lo[c], I.hi[c], I.path[c], I.lo[c ^ 1],
-                   I.hi[c ^ 1], I.path[c ^ 1], &I.err, I.max_leaves, (int64_t)(t - cpre[i]));
+                   I.hi[c ^ 1], I.path[c ^ 1], &I.err, I.max_leaves, (int64_t)(t - cpre[i]),
+                   split_stage);
         __syncthreads();
     }
 }
@@ -353,7 +355,8 @@ hipError_t launch_batch_advance(BatchInst* insts, int n_inst, hipStream_t stream
 hipError_t launch_batch_split(BatchInst* insts, int n_inst, BatchCtl* ctl, const unsigned* cpre,
                               hipStream_t stream) {
     (void)hipGetLastError();
-    hipLaunchKernelGGL(batch_split_kernel, dim3(2048), dim3(256), 0, stream, insts, n_inst, ctl, cpre);
+    hipLaunchKernelGGL(batch_split_kernel, dim3(2048), dim3(256),
+                       2 * sizeof(float) * kTile * kSplitStageD, stream, insts, n_inst, ctl, cpre);
     return hipGetLastError();
 }
 

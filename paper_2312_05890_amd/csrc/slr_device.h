@@ -486,12 +486,51 @@ __device__ __forceinline__ double relu64(double* st, int ncol, double eps, doubl
     return (fabs(c0) + lam * S + r) * (1.0 + 4.0 * kU64);
 }
 
+// NCC consecutive columns of one neuron's pre-activation state (x = the layer input's state
+// from the first of those columns, row stride ncol): dot products over the n_in inputs in k
+// order, with the weights of 16 K-steps loaded before they are used.  RAD: the last column is the
+// radius, multiplied by |w|; ROW: A_row also sums |w| (in the same k order).
+template <int NCC, bool RAD, bool ROW>
+__device__ __forceinline__ void recheck_chunk(const float* __restrict__ wcol, int n_out, int n_in,
+                                              const double* x, int ncol, double* st,
+                                              double& A_row) {
+    double acc[NCC];
+#pragma unroll
+    for (int v = 0; v < NCC; ++v) acc[v] = 0.0;
+    auto step = [&](float wf, const double* xr) {
+        const double w = wf;
+#pragma unroll
+        for (int v = 0; v < NCC; ++v) acc[v] = fma(RAD && v == NCC - 1 ? fabs(w) : w, xr[v], acc[v]);
+        if (ROW) A_row += fabs(w);
+    };
+    int k0 = 0;
+    for (; k0 + 16 <= n_in; k0 += 16) {
+        float wk[16];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) wk[u] = wcol[(size_t)(k0 + u) * n_out];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) step(wk[u], x + (k0 + u) * ncol);
+    }
+    if (k0 < n_in) {   // remainder: loads at clamped indices, uses guarded
+        float wk[16];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) wk[u] = wcol[(size_t)min(k0 + u, n_in - 1) * n_out];
+        const int kn = n_in - k0;
+#pragma unroll
+        for (int u = 0; u < 16; ++u)
+            if (u < kn) step(wk[u], x + (k0 + u) * ncol);
+    }
+#pragma unroll
+    for (int v = 0; v < NCC; ++v) st[v] = acc[v];
+}
+
 // One box on one wavefront.  ws: this wave's LDS (2 * nrow * ncol + 2 * 32 doubles).
-__device__ void recheck_box(const NetDev& net, const PropDev& prop, int64_t b,
-                            const float* __restrict__ blo, const float* __restrict__ bhi,
-                            float* __restrict__ g_lo, float* __restrict__ g_hi,
-                            int8_t* __restrict__ cls, unsigned long long* counter, double* ws,
-                            int nrow) {
+__device__ __forceinline__ void recheck_box(const NetDev& net, const PropDev& prop, int64_t b,
+                                            const float* __restrict__ blo,
+                                            const float* __restrict__ bhi,
+                                            float* __restrict__ g_lo, float* __restrict__ g_hi,
+                                            int8_t* __restrict__ cls, unsigned long long* counter,
+                                            double* ws, int nrow) {
     const int lane = threadIdx.x & 63;
     const int d = net.d, ncol = d + 2;
     double* A = ws;
@@ -529,14 +568,32 @@ __device__ void recheck_box(const NetDev& net, const PropDev& prop, int64_t b,
         e = 0.0;
         for (int j = lane; j < L->n_out; j += 64) {
             double* st = out + j * ncol;
-            for (int c = 0; c < ncol; ++c) st[c] = 0.0;
             double A_row = 0.0;
-            for (int k = 0; k < L->n_in; ++k) {
-                const double w = L->wt[(size_t)k * L->n_out + j];
-                const double* x = in + k * ncol;
-                for (int c = 0; c < ncol - 1; ++c) st[c] = fma(w, x[c], st[c]);
-                st[ncol - 1] = fma(fabs(w), x[ncol - 1], st[ncol - 1]);
-                A_row += fabs(w);
+            // columns in chunks of at most 8 register accumulators; the chunk holding column
+            // ncol-1 (the radius) multiplies it by |w|, the first one also sums |w|
+            const float* wcol = L->wt + j;
+            for (int c0 = 0; c0 < ncol; c0 += 8) {
+                const double* x = in + c0;
+                if (c0 + 8 < ncol) {
+                    if (c0 == 0)
+                        recheck_chunk<8, false, true>(wcol, L->n_out, L->n_in, x, ncol, st, A_row);
+                    else
+                        recheck_chunk<8, false, false>(wcol, L->n_out, L->n_in, x, ncol, st + c0,
+                                                       A_row);
+                    continue;
+                }
+                switch ((ncol - c0) + (c0 == 0 ? 8 : 0)) {
+#define SLR_RC(NC, ROW, K) \
+    case K: recheck_chunk<NC, true, ROW>(wcol, L->n_out, L->n_in, x, ncol, st + c0, A_row); break;
+                    SLR_RC(1, false, 1) SLR_RC(2, false, 2) SLR_RC(3, false, 3)
+                    SLR_RC(4, false, 4) SLR_RC(5, false, 5) SLR_RC(6, false, 6)
+                    SLR_RC(7, false, 7) SLR_RC(8, false, 8) SLR_RC(1, true, 9)
+                    SLR_RC(2, true, 10) SLR_RC(3, true, 11) SLR_RC(4, true, 12)
+                    SLR_RC(5, true, 13) SLR_RC(6, true, 14) SLR_RC(7, true, 15)
+                    SLR_RC(8, true, 16)
+#undef SLR_RC
+                    default: break;
+                }
             }
             const double bb = L->b[j];
             st[0] += bb;
@@ -555,10 +612,17 @@ __device__ void recheck_box(const NetDev& net, const PropDev& prop, int64_t b,
     for (int it = lane; it < rows * ncol; it += 64) {
         const int r = it / ncol, c = it % ncol;
         double s = 0.0;
-        for (int k = 0; k < K; ++k) {
-            double w = prop.wg64[r * K + k];
-            if (c == ncol - 1) w = fabs(w);
-            s = fma(w, in[k * ncol + c], s);
+        for (int k0 = 0; k0 < K; k0 += 8) {
+            double wk[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) wk[u] = prop.wg64[r * K + min(k0 + u, K - 1)];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                if (k0 + u < K) {
+                    const double w = c == ncol - 1 ? fabs(wk[u]) : wk[u];
+                    s = fma(w, in[(k0 + u) * ncol + c], s);
+                }
+            }
         }
         out[it] = s;
     }
@@ -638,28 +702,42 @@ __device__ __forceinline__ void count_tile(int64_t n, const int8_t* __restrict__
 }
 
 // Children of the undecided boxes of one 1024-box tile, written in parent order after those of
-// all earlier tiles; children at index >= cap (the frontier capacity) are not written.
-__device__ __forceinline__ void split_tile(int64_t n, int d, const int8_t* __restrict__ cls,
-                                           const unsigned* __restrict__ tile_und,
-                                           const float* __restrict__ lo,
-                                           const float* __restrict__ hi,
-                                           const unsigned long long* __restrict__ path,
-                                           float* __restrict__ lo2, float* __restrict__ hi2,
-                                           unsigned long long* __restrict__ path2,
-                                           unsigned* err, int64_t cap, int64_t tile) {
+// all earlier tiles; child pairs at index >= cap (the frontier capacity) are not written.
+// Each parent is bisected at the midpoint of its widest coordinate (first one on ties).
+// Phases: (1) local ranks of the undecided boxes by a workgroup scan; (2) with STAGED, a coalesced
+// copy of the tile's corner rows into LDS (kSplitStageD coordinates at most); (3) one thread per
+// parent picks the coordinate and midpoint and writes the child paths; (4) the children's corner
+// rows, one contiguous run per tile, are written element by element (coalesced stores).
+constexpr int kSplitStageD = 8;   // largest d whose 1024 x 2 x d corner floats are staged in LDS
+
+template <bool STAGED>
+__device__ __forceinline__ void split_tile_impl(int64_t n, int d, const int8_t* __restrict__ cls,
+                                                const unsigned* __restrict__ tile_und,
+                                                const float* __restrict__ lo,
+                                                const float* __restrict__ hi,
+                                                const unsigned long long* __restrict__ path,
+                                                float* __restrict__ lo2, float* __restrict__ hi2,
+                                                unsigned long long* __restrict__ path2,
+                                                unsigned* err, int64_t cap, int64_t tile,
+                                                float* stage) {
     __shared__ unsigned red[4];
     __shared__ unsigned wpre[4];
+    __shared__ unsigned short pidx[kTile];   // tile-local box index of the parent of local rank
+    __shared__ unsigned char jsel[kTile];    // its bisected coordinate
+    __shared__ float mval[kTile];            // and the midpoint
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     // offset of this tile: undecided boxes of all earlier tiles
     unsigned pre = 0;
     for (unsigned k = tid; k < tile; k += 256) pre += tile_und[k];
-    const unsigned base_out = block_sum256(pre, red);
+    const int64_t base_out = block_sum256(pre, red);
     if (tile_und[tile] == 0) return;
-    const int64_t base = (int64_t)tile * kTile + tid * 4;
+    const int64_t t0 = tile * kTile;
+    const int nb = (int)min((int64_t)kTile, n - t0);
     unsigned flags = 0, cnt = 0;
+#pragma unroll
     for (int q = 0; q < 4; ++q) {
-        const int64_t i = base + q;
-        if (i < n && cls[i] == 0) {
+        const int i = tid * 4 + q;
+        if (i < nb && cls[t0 + i] == 0) {
             flags |= 1u << q;
             ++cnt;
         }
@@ -672,14 +750,44 @@ __device__ __forceinline__ void split_tile(int64_t n, int d, const int8_t* __res
     }
     if (lane == 63) wpre[wave] = incl;
     __syncthreads();
-    unsigned woff = 0;
-    for (int w = 0; w < wave; ++w) woff += wpre[w];
-    unsigned rank = base_out + woff + incl - cnt;
-    for (int q = 0; q < 4; ++q) {
-        if (!(flags & (1u << q))) continue;
-        const int64_t i = base + q;
-        const float* l = lo + i * d;
-        const float* h = hi + i * d;
+    unsigned rank = incl - cnt;
+    for (int w = 0; w < wave; ++w) rank += wpre[w];
+    const int total = (int)(wpre[0] + wpre[1] + wpre[2] + wpre[3]);
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+        if (flags & (1u << q)) pidx[rank++] = (unsigned short)(tid * 4 + q);
+    const float* rlo = lo + t0 * d;
+    const float* rhi = hi + t0 * d;
+    if (STAGED) {
+        const int m = nb * d;
+        for (int e0 = tid; e0 < m; e0 += 256 * 4) {
+            float a[4], b[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int e = e0 + 256 * u;
+                a[u] = e < m ? rlo[e] : 0.f;
+                b[u] = e < m ? rhi[e] : 0.f;
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int e = e0 + 256 * u;
+                if (e < m) {
+                    stage[e] = a[u];
+                    stage[kTile * d + e] = b[u];
+                }
+            }
+        }
+        rlo = stage;
+        rhi = stage + kTile * d;
+    }
+    __syncthreads();
+    // pairs whose second child still fits the frontier: global rank < floor(cap / 2)
+    const int64_t fit = cap / 2 - base_out;
+    const int npairs = (int)max((int64_t)0, min((int64_t)total, fit));
+    for (int r = tid; r < total; r += 256) {
+        const int p = pidx[r];
+        const float* l = rlo + p * d;
+        const float* h = rhi + p * d;
         int js = 0;
         float wbest = h[0] - l[0];
         for (int k = 1; k < d; ++k) {
@@ -691,22 +799,47 @@ __device__ __forceinline__ void split_tile(int64_t n, int d, const int8_t* __res
         }
         const float m = 0.5f * (l[js] + h[js]);
         if (!(m - l[js] == h[js] - m && l[js] < m && m < h[js])) atomicOr(err, 1u);
-        const int64_t o0 = 2 * (int64_t)rank, o1 = o0 + 1;
-        if (o1 >= cap) {   // beyond the frontier buffers: only a split the caller will discard
-            ++rank;
-            continue;
+        jsel[r] = (unsigned char)js;
+        mval[r] = m;
+        if (r < npairs) {
+            const unsigned long long pp = path[t0 + p];
+            path2[2 * (base_out + r)] = 2ull * pp;
+            path2[2 * (base_out + r) + 1] = 2ull * pp + 1ull;
         }
-        for (int k = 0; k < d; ++k) {
-            lo2[o0 * d + k] = l[k];
-            hi2[o0 * d + k] = k == js ? m : h[k];
-            lo2[o1 * d + k] = k == js ? m : l[k];
-            hi2[o1 * d + k] = h[k];
-        }
-        const unsigned long long p = path[i];
-        path2[o0] = 2ull * p;
-        path2[o1] = 2ull * p + 1ull;
-        ++rank;
     }
+    __syncthreads();
+    // children rows: element e of the run is coordinate k of child c = 2 r + side
+    float* olo = lo2 + 2 * base_out * d;
+    float* ohi = hi2 + 2 * base_out * d;
+    const int m = 2 * npairs * d;
+    for (int e = tid; e < m; e += 256) {
+        const int c = e / d, k = e - c * d;
+        const int r = c >> 1, side = c & 1;
+        const int p = pidx[r];
+        const bool cut = k == jsel[r];
+        const float mv = mval[r];
+        const float lv = rlo[p * d + k], hv = rhi[p * d + k];
+        olo[e] = cut && side ? mv : lv;
+        ohi[e] = cut && !side ? mv : hv;
+    }
+}
+
+// stage: LDS of 2 * kTile * d floats (used when d <= kSplitStageD), or nullptr.
+__device__ __forceinline__ void split_tile(int64_t n, int d, const int8_t* __restrict__ cls,
+                                           const unsigned* __restrict__ tile_und,
+                                           const float* __restrict__ lo,
+                                           const float* __restrict__ hi,
+                                           const unsigned long long* __restrict__ path,
+                                           float* __restrict__ lo2, float* __restrict__ hi2,
+                                           unsigned long long* __restrict__ path2,
+                                           unsigned* err, int64_t cap, int64_t tile,
+                                           float* stage) {
+    if (stage && d <= kSplitStageD)
+        split_tile_impl<true>(n, d, cls, tile_und, lo, hi, path, lo2, hi2, path2, err, cap, tile,
+                              stage);
+    else
+        split_tile_impl<false>(n, d, cls, tile_und, lo, hi, path, lo2, hi2, path2, err, cap, tile,
+                               nullptr);
 }
 
 // Exact leaf-volume sums: sum_t count_t 2^(Dm - t) in 64-bit integers (the totals partition

@@ -65,7 +65,9 @@ __global__ __launch_bounds__(256) void split_kernel(int64_t n, int d, const int8
                                                     float* __restrict__ lo2, float* __restrict__ hi2,
                                                     unsigned long long* __restrict__ path2,
                                                     unsigned* err, int64_t cap) {
-    split_tile(n, d, cls, tile_und, lo, hi, path, lo2, hi2, path2, err, cap, blockIdx.x);
+    extern __shared__ float split_stage[];
+    split_tile(n, d, cls, tile_und, lo, hi, path, lo2, hi2, path2, err, cap, blockIdx.x,
+               d <= kSplitStageD ? split_stage : nullptr);
 }
 
 __global__ void volume_kernel(const LevelStats* stats, int levels, int stop_level, int stopped,
@@ -631,7 +633,8 @@ hipError_t launch_split(int64_t n, int d, const int8_t* cls, const unsigned* til
                         int64_t cap, hipStream_t stream) {
     if (n <= 0) return hipSuccess;
     (void)hipGetLastError();
-    hipLaunchKernelGGL(split_kernel, dim3((unsigned)level_tiles(n)), dim3(256), 0, stream, n, d,
+    const size_t lds = d <= kSplitStageD ? 2 * sizeof(float) * kTile * d : 0;
+    hipLaunchKernelGGL(split_kernel, dim3((unsigned)level_tiles(n)), dim3(256), lds, stream, n, d,
                        cls, tile_und, lo, hi, path, lo2, hi2, path2, err, cap);
     return hipGetLastError();
 }
