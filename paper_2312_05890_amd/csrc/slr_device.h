@@ -129,6 +129,56 @@ __device__ __forceinline__ float relu_epilogue(float (&a)[NCOL][4], const float 
     return emax;
 }
 
+// The full K-quads of one unit (weights fragments wf/qf from global memory, the layer input's
+// state sb from LDS), software-pipelined one quad ahead.  NQ > 0: exactly NQ quads as
+// straight-line code (a loop carries the accumulators and the prefetched operands across its back
+// edge, where the compiler shuffles accumulator registers and folds the prefetch back into the
+// iteration); NQ == 0: a loop over nq quads.
+template <int NCOL, int NQ>
+__device__ __forceinline__ void k_quads(f32x4 (&acc)[NCOL], const float* __restrict__ wf,
+                                        const uint64_t* __restrict__ qf, const float* sb,
+                                        int colstride, int nq, int nqa) {
+    float af[4];
+    uint64_t aq = qf[0];
+    f32x4 bq[NCOL];
+#pragma unroll
+    for (int ss = 0; ss < 4; ++ss) af[ss] = wf[ss * 64];
+#pragma unroll
+    for (int c = 0; c < NCOL; ++c)
+        bq[c] = *reinterpret_cast<const f32x4*>(sb + c * colstride);
+    auto quad = [&](int qi) {
+        const int nx = min(qi + 1, nqa - 1) * 4;
+        float an[4];
+        const uint64_t aqn = qf[nx * 16];
+        f32x4 bn[NCOL];
+#pragma unroll
+        for (int ss = 0; ss < 4; ++ss) an[ss] = wf[(nx + ss) * 64];
+#pragma unroll
+        for (int c = 0; c < NCOL; ++c)
+            bn[c] = *reinterpret_cast<const f32x4*>(sb + c * colstride + nx);
+#pragma unroll
+        for (int ss = 0; ss < 4; ++ss) {
+            const float aw = af[ss];
+            const float aa = fabsf(aw);
+#pragma unroll
+            for (int c = 0; c < NCOL - 2; ++c) acc[c] = mfma16(aw, bq[c][ss], acc[c]);
+            acc[NCOL - 2] = mfma16(aa, bq[NCOL - 2][ss], acc[NCOL - 2]);
+        }
+        acc[NCOL - 1] = mfma_bf16_quad(aq, bq[NCOL - 1], acc[NCOL - 1]);
+#pragma unroll
+        for (int ss = 0; ss < 4; ++ss) af[ss] = an[ss];
+        aq = aqn;
+#pragma unroll
+        for (int c = 0; c < NCOL; ++c) bq[c] = bn[c];
+    };
+    if constexpr (NQ > 0) {
+#pragma unroll
+        for (int qi = 0; qi < NQ; ++qi) quad(qi);
+    } else {
+        for (int qi = 0; qi < nq; ++qi) quad(qi);
+    }
+}
+
 template <int NCOL, int NT, int UW, int NW>
 __device__ __forceinline__ void bound_tile(
     const NetDev& net, const PropDev& prop, int64_t n, int64_t box0,
@@ -238,38 +288,12 @@ __device__ __forceinline__ void bound_tile(
                 const int nq = ks >> 2;
                 const int nqa = L->ks_alloc >> 2;
                 const uint64_t* qf = L->qfrag + (size_t)mt * nqa * 64 + lane;
-                float af[4];
-                uint64_t aq = qf[0];
-                f32x4 bq[NCOL];
-#pragma unroll
-                for (int ss = 0; ss < 4; ++ss) af[ss] = wf[ss * 64];
-#pragma unroll
-                for (int c = 0; c < NCOL; ++c)
-                    bq[c] = *reinterpret_cast<const f32x4*>(sb + c * colstride);
-                for (int qi = 0; qi < nq; ++qi) {
-                    const int nx = min(qi + 1, nqa - 1) * 4;
-                    float an[4];
-                    const uint64_t aqn = qf[nx * 16];
-                    f32x4 bn[NCOL];
-#pragma unroll
-                    for (int ss = 0; ss < 4; ++ss) an[ss] = wf[(nx + ss) * 64];
-#pragma unroll
-                    for (int c = 0; c < NCOL; ++c)
-                        bn[c] = *reinterpret_cast<const f32x4*>(sb + c * colstride + nx);
-#pragma unroll
-                    for (int ss = 0; ss < 4; ++ss) {
-                        const float aw = af[ss];
-                        const float aa = fabsf(aw);
-#pragma unroll
-                        for (int c = 0; c < NCOL - 2; ++c) acc[c] = mfma16(aw, bq[c][ss], acc[c]);
-                        acc[NCOL - 2] = mfma16(aa, bq[NCOL - 2][ss], acc[NCOL - 2]);
-                    }
-                    acc[NCOL - 1] = mfma_bf16_quad(aq, bq[NCOL - 1], acc[NCOL - 1]);
-#pragma unroll
-                    for (int ss = 0; ss < 4; ++ss) af[ss] = an[ss];
-                    aq = aqn;
-#pragma unroll
-                    for (int c = 0; c < NCOL; ++c) bq[c] = bn[c];
+                switch (nq) {   // straight-line quads for the common widths, else a loop
+                    case 1: k_quads<NCOL, 1>(acc, wf, qf, sb, colstride, nq, nqa); break;
+                    case 2: k_quads<NCOL, 2>(acc, wf, qf, sb, colstride, nq, nqa); break;
+                    case 3: k_quads<NCOL, 3>(acc, wf, qf, sb, colstride, nq, nqa); break;
+                    case 4: k_quads<NCOL, 4>(acc, wf, qf, sb, colstride, nq, nqa); break;
+                    default: k_quads<NCOL, 0>(acc, wf, qf, sb, colstride, nq, nqa); break;
                 }
                 // the last K-steps (ks % 4 of them) one at a time, B read as scalars: a plain
                 // loop keeps the accumulators in place (no per-step selects of the whole set);
