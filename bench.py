@@ -94,6 +94,21 @@ def measured_traffic(shape):
     return rec.get("bytes_per_launch")
 
 
+def split_report(res):
+    """The HBM-bound split kernel of the levels the search continued from: algorithmic bytes
+    (every class byte, the undecided parents' corners and paths, two children each, per-tile
+    counts) over its HIP-event time, against the 8 TB/s HBM peak.  Taken on a count after the
+    timed steps: its events would add to the timed region."""
+    ms = sum(r["split_ms"] for r in res)
+    nbytes = sum(r["split_bytes"] for r in res)
+    if ms <= 0:
+        return None
+    gbps = nbytes / (ms * 1e-3) / 1e9
+    return {"bound": "hbm", "achieved": gbps, "peak": PEAK_HBM, "unit": "GB/s",
+            "frac": gbps / PEAK_HBM, "ms_per_step": ms / len(res),
+            "bytes_per_step": nbytes // len(res)}
+
+
 def cpu_baseline(seed, leaves):
     """The FP64 oracle, untuned, on the same network with a smaller leaf budget."""
     from oracle import count
@@ -379,6 +394,7 @@ def main():
                          "avg_launch_us": bound_s / launches * 1e6,
                          "launches_per_step": launches // args.steps,
                          "boxes_per_s": boxes / bound_s},
+        "split_kernel": split_report([step(2)]),
         "time_to_bracket_ms": r0["seconds"] * 1e3,
         "bracket": [r0["unsafe"], r0["unsafe"] + r0["undecided"]],
         "boxes_per_step": r0["n_boxes_bounded"],

@@ -127,7 +127,9 @@ typedef struct {
     int32_t* trace_depth;
     uint64_t* trace_path;
     int8_t* trace_cls;
-    int32_t timing;         /* 1: time the bound-kernel launches with HIP events on `stream` */
+    int32_t timing;         /* bit 0: time the bound-kernel launches with HIP events on
+                               `stream`; bit 1: time the split launches (each timed launch is
+                               bracketed by two events, which cost a few microseconds each) */
     /* alpha mode: boxes that the plain bounds leave undecided at depth >= alpha_min_depth get
        alpha_steps projected-Adam steps of optimized lower slopes (0 = plain only), in batches
        of alpha_chunk boxes (the workspace must be sized for it) */
@@ -146,11 +148,16 @@ typedef struct {
     int32_t status;                   /* SLR_OK or SLR_BUDGET                                */
     double seconds;                   /* wall time of the call                               */
     int64_t trace_count;              /* boxes written to the trace (<= trace_capacity)      */
-    double bound_ms;                  /* with timing: summed bound-kernel time per level (ms) */
+    double bound_ms;                  /* with timing bit 0: summed bound-kernel time (ms)    */
     int64_t bound_launches;           /* bound-kernel launches made by the call              */
     int64_t n_alpha_boxes;            /* boxes given the alpha optimization                  */
     int64_t n_alpha_decided;          /* of those, boxes the optimized bounds decided        */
     double alpha_ms;                  /* with timing: time of the alpha passes (ms)          */
+    double split_ms;                  /* with timing bit 1: time of the split launches of the
+                                         levels the search continued from (ms)               */
+    int64_t split_bytes;              /* algorithmic HBM bytes of those split launches: every
+                                         class byte, undecided parents' corners and paths,
+                                         two children each, per-tile counts                  */
 } slr_count_result;
 
 /*

@@ -920,6 +920,31 @@ LevelStats* pinned_stats() {
     return ps.p;
 }
 
+// Timing events of count_exact, created once per thread and reused (creating them on every call
+// would add their cost to every timed step).
+struct TimingEvents {
+    hipEvent_t ev[6] = {};
+    bool ok = false;
+    ~TimingEvents() {
+        for (hipEvent_t e : ev)
+            if (e) (void)hipEventDestroy(e);
+    }
+};
+
+hipEvent_t* timing_events() {
+    thread_local TimingEvents te;
+    if (!te.ok) {
+        for (hipEvent_t& e : te.ev) {
+            if (!e && hipEventCreate(&e) != hipSuccess) {
+                (void)hipGetLastError();
+                return nullptr;
+            }
+        }
+        te.ok = true;
+    }
+    return te.ev;
+}
+
 int count_exact_impl(const slr_net* net, const slr_property* prop, const double* lo,
                      const double* hi, const slr_exact_opts* o, const Workspace& w,
                      slr_count_result* out) {
@@ -943,24 +968,28 @@ int count_exact_impl(const slr_net* net, const slr_property* prop, const double*
     HIP_TRY(hipMemcpyAsync(w.hi[0], root.data() + d, sizeof(float) * d, hipMemcpyHostToDevice, s), "count_exact: root");
     HIP_TRY(hipMemcpyAsync(w.path[0], &one, sizeof one, hipMemcpyHostToDevice, s), "count_exact: root");
 
-    hipEvent_t ev0 = nullptr, ev1 = nullptr;
-    if (o->timing) {
-        HIP_TRY(hipEventCreate(&ev0), "count_exact: event");
-        HIP_TRY(hipEventCreate(&ev1), "count_exact: event");
-    }
+    // timing events (thread-local, created once): the bound launches of a level, and two
+    // alternating pairs around split launches (a split is counted once its level continues)
+    hipEvent_t* tev = o->timing ? timing_events() : nullptr;
+    if (o->timing && !tev) return fail(SLR_EHIP, "count_exact: cannot create timing events");
+    hipEvent_t ev0 = tev && (o->timing & 1) ? tev[0] : nullptr;
+    hipEvent_t ev1 = tev && (o->timing & 1) ? tev[1] : nullptr;
+    const bool time_split = tev && (o->timing & 2);
+    auto sev = [&](int t, int k) { return tev[2 + 2 * (t & 1) + k]; };
+    int split_pending = -1;    // level whose timed split has not been read yet
+    double split_ms = 0.0;
+    int64_t split_bytes = 0;
     hipEvent_t evr = nullptr;   // marks the end of a level's read-back
     if (hipEventCreateWithFlags(&evr, hipEventDisableTiming) != hipSuccess) {
         (void)hipGetLastError();
         evr = nullptr;
     }
     struct EventGuard {
-        hipEvent_t a, b, c;
+        hipEvent_t e;
         ~EventGuard() {
-            if (a) (void)hipEventDestroy(a);
-            if (b) (void)hipEventDestroy(b);
-            if (c) (void)hipEventDestroy(c);
+            if (e) (void)hipEventDestroy(e);
         }
-    } guard{ev0, ev1, evr};
+    } guard{evr};
     double bound_ms = 0.0, alpha_ms = 0.0;
     int64_t launches = 0, alpha_boxes = 0, alpha_decided = 0, alpha_und_before = 0;
     int64_t n = 1, resolved = 0, bounded = 0, tcount = 0;
@@ -1080,12 +1109,21 @@ int count_exact_impl(const slr_net* net, const slr_property* prop, const double*
         const bool spec = t < D && pin && evr && resolved + 2 * n <= M;
         if (spec) {
             HIP_TRY(hipEventRecord(evr, s), "count_exact: event");
+            if (time_split) HIP_TRY(hipEventRecord(sev(t, 0), s), "count_exact: event");
             HIP_TRY(launch_split(n, d, w.cls, w.tile_und, w.lo[cur], w.hi[cur], w.path[cur],
                                  w.lo[cur ^ 1], w.hi[cur ^ 1], w.path[cur ^ 1], w.err + t, M, s),
                     "count_exact: split kernel");
+            if (time_split) HIP_TRY(hipEventRecord(sev(t, 1), s), "count_exact: event");
             HIP_TRY(hipEventSynchronize(evr), "count_exact: sync");
         } else {
             HIP_TRY(hipStreamSynchronize(s), "count_exact: sync");
+        }
+        if (split_pending >= 0) {   // the previous level's split has completed (stream order)
+            float ms = 0.f;
+            HIP_TRY(hipEventElapsedTime(&ms, sev(split_pending, 0), sev(split_pending, 1)),
+                    "count_exact: event");
+            split_ms += ms;
+            split_pending = -1;
         }
         if (pin) hs = *pin;
         if (ev0 && o->alpha_steps <= 0) {
@@ -1111,10 +1149,18 @@ int count_exact_impl(const slr_net* net, const slr_property* prop, const double*
             status = SLR_BUDGET;
             break;
         }
-        if (!spec)
+        if (!spec) {
+            if (time_split) HIP_TRY(hipEventRecord(sev(t, 0), s), "count_exact: event");
             HIP_TRY(launch_split(n, d, w.cls, w.tile_und, w.lo[cur], w.hi[cur], w.path[cur],
                                  w.lo[cur ^ 1], w.hi[cur ^ 1], w.path[cur ^ 1], w.err + t, M, s),
                     "count_exact: split kernel");
+            if (time_split) HIP_TRY(hipEventRecord(sev(t, 1), s), "count_exact: event");
+        }
+        if (time_split) split_pending = t;
+        // algorithmic bytes of the split: every class, the undecided parents' corners and paths,
+        // two children each, and the per-tile counts
+        split_bytes += n + und * (int64_t)(2 * d * sizeof(float) + 8) * 3 +
+                       (int64_t)level_tiles(n) * 4;
         n = 2 * und;
         cur ^= 1;
     }
@@ -1148,6 +1194,8 @@ int count_exact_impl(const slr_net* net, const slr_property* prop, const double*
     out->n_alpha_boxes = alpha_boxes;
     out->n_alpha_decided = alpha_decided;
     out->alpha_ms = alpha_ms;
+    out->split_ms = split_ms;
+    out->split_bytes = split_bytes;
     out->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     return status;
 }

@@ -50,7 +50,8 @@ class CountResult(C.Structure):
                 ("depth_reached", C.c_int32), ("status", C.c_int32), ("seconds", C.c_double),
                 ("trace_count", C.c_int64), ("bound_ms", C.c_double),
                 ("bound_launches", C.c_int64), ("n_alpha_boxes", C.c_int64),
-                ("n_alpha_decided", C.c_int64), ("alpha_ms", C.c_double)]
+                ("n_alpha_decided", C.c_int64), ("alpha_ms", C.c_double),
+                ("split_ms", C.c_double), ("split_bytes", C.c_int64)]
 
 
 class AlphaOpts(C.Structure):
@@ -294,7 +295,7 @@ def _exact_opts(net, prop, max_depth, max_leaves, chunk, workspace, stream, samp
     o.workspace_bytes = workspace.numel() * workspace.element_size()
     o.stream = _stream(stream)
     o.trace_capacity = int(trace_capacity)
-    o.timing = int(bool(timing))
+    o.timing = int(timing)
     o.alpha_steps = int(alpha_steps)
     o.alpha_lr = float(alpha_lr)
     o.alpha_min_depth = int(alpha_min_depth)
@@ -304,11 +305,13 @@ def _exact_opts(net, prop, max_depth, max_leaves, chunk, workspace, stream, samp
 
 def count_exact(net: Net, prop: Property, lo, hi, max_depth: int, max_leaves: int,
                 chunk: int = 0, workspace=None, stream=None, trace: bool = False,
-                trace_capacity: Optional[int] = None, timing: bool = False,
+                trace_capacity: Optional[int] = None, timing: int = 0,
                 alpha_steps: int = 0, alpha_lr: float = 0.1, alpha_min_depth: int = 0,
                 alpha_chunk: int = 0) -> dict:
     """Alg. 1 on the device; returns the bracket, counts and (optionally) a per-box trace.
 
+    ``timing``: bit 0 times the bound-kernel launches (``bound_ms``), bit 1 the split launches
+    (``split_ms``, with their algorithmic ``split_bytes``); True means 1.
     With ``alpha_steps`` > 0 the boxes the plain bounds leave undecided (from depth
     ``alpha_min_depth`` on) are re-bounded with optimized lower slopes before they are split."""
     lo = np.ascontiguousarray(lo, np.float64)
