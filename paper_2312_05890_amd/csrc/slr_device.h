@@ -69,6 +69,20 @@ __device__ __forceinline__ f32x4 mfma_bf16_quad(uint64_t a, f32x4 b, f32x4 c) {
     return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bf16_up4(b), c, 0, 0, 0);
 }
 
+// Raw buffer loads (bounds-checked against the byte count; loads past it read 0).  Unlike plain
+// loads they are not merged across a loop's back edge, so a load issued one iteration ahead
+// stays ahead.
+typedef __amdgpu_buffer_rsrc_t BufRsrc;
+
+__device__ __forceinline__ BufRsrc buf_rsrc(const void* base, uint32_t bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes,
+                                             0x00020000);
+}
+
+__device__ __forceinline__ float buf_f32(BufRsrc r, uint32_t off) {
+    return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
+}
+
 // Scalars of the epilogue: zero margins and no rounding-up in the unwidened mode.
 struct EpiConst {
     float kconc, krelu, lamfac;
@@ -512,37 +526,50 @@ __device__ __forceinline__ double relu64(double* st, int ncol, double eps, doubl
 
 // NCC consecutive columns of one neuron's pre-activation state (x = the layer input's state
 // from the first of those columns, row stride ncol): dot products over the n_in inputs in k
-// order, with the weights of 16 K-steps loaded before they are used.  RAD: the last column is the
+// order.  The weights are column j of the transposed [n_in][n_out] array wt, read 16 K-steps at a
+// time through raw buffer loads (reads past the array return 0) into two alternating register
+// sets, so the next 16 weights are in flight while these 16 are used.  RAD: the last column is the
 // radius, multiplied by |w|; ROW: A_row also sums |w| (in the same k order).
 template <int NCC, bool RAD, bool ROW>
-__device__ __forceinline__ void recheck_chunk(const float* __restrict__ wcol, int n_out, int n_in,
+__device__ __forceinline__ void recheck_chunk(const float* wt, int j, int n_out, int n_in,
                                               const double* x, int ncol, double* st,
                                               double& A_row) {
+    const BufRsrc wr = buf_rsrc(wt, (uint32_t)n_in * (uint32_t)n_out * 4u);
     double acc[NCC];
 #pragma unroll
     for (int v = 0; v < NCC; ++v) acc[v] = 0.0;
+    auto load = [&](float (&w)[16], int k0) {
+#pragma unroll
+        for (int u = 0; u < 16; ++u) w[u] = buf_f32(wr, ((uint32_t)(k0 + u) * n_out + j) * 4u);
+    };
     auto step = [&](float wf, const double* xr) {
         const double w = wf;
 #pragma unroll
         for (int v = 0; v < NCC; ++v) acc[v] = fma(RAD && v == NCC - 1 ? fabs(w) : w, xr[v], acc[v]);
         if (ROW) A_row += fabs(w);
     };
-    int k0 = 0;
-    for (; k0 + 16 <= n_in; k0 += 16) {
-        float wk[16];
-#pragma unroll
-        for (int u = 0; u < 16; ++u) wk[u] = wcol[(size_t)(k0 + u) * n_out];
-#pragma unroll
-        for (int u = 0; u < 16; ++u) step(wk[u], x + (k0 + u) * ncol);
-    }
-    if (k0 < n_in) {   // remainder: loads at clamped indices, uses guarded
-        float wk[16];
-#pragma unroll
-        for (int u = 0; u < 16; ++u) wk[u] = wcol[(size_t)min(k0 + u, n_in - 1) * n_out];
+    auto use = [&](const float (&w)[16], int k0) {
         const int kn = n_in - k0;
+        if (kn >= 16) {
 #pragma unroll
-        for (int u = 0; u < 16; ++u)
-            if (u < kn) step(wk[u], x + (k0 + u) * ncol);
+            for (int u = 0; u < 16; ++u) step(w[u], x + (k0 + u) * ncol);
+        } else {
+#pragma unroll
+            for (int u = 0; u < 16; ++u)
+                if (u < kn) step(w[u], x + (k0 + u) * ncol);
+        }
+    };
+    float wa[16], wb[16];
+    load(wa, 0);
+    for (int k0 = 0;;) {
+        load(wb, k0 + 16);
+        use(wa, k0);
+        k0 += 16;
+        if (k0 >= n_in) break;
+        load(wa, k0 + 16);
+        use(wb, k0);
+        k0 += 16;
+        if (k0 >= n_in) break;
     }
 #pragma unroll
     for (int v = 0; v < NCC; ++v) st[v] = acc[v];
@@ -595,20 +622,22 @@ __device__ __forceinline__ void recheck_box(const NetDev& net, const PropDev& pr
             double A_row = 0.0;
             // columns in chunks of at most 8 register accumulators; the chunk holding column
             // ncol-1 (the radius) multiplies it by |w|, the first one also sums |w|
-            const float* wcol = L->wt + j;
             for (int c0 = 0; c0 < ncol; c0 += 8) {
                 const double* x = in + c0;
                 if (c0 + 8 < ncol) {
                     if (c0 == 0)
-                        recheck_chunk<8, false, true>(wcol, L->n_out, L->n_in, x, ncol, st, A_row);
+                        recheck_chunk<8, false, true>(L->wt, j, L->n_out, L->n_in, x, ncol, st,
+                                                      A_row);
                     else
-                        recheck_chunk<8, false, false>(wcol, L->n_out, L->n_in, x, ncol, st + c0,
-                                                       A_row);
+                        recheck_chunk<8, false, false>(L->wt, j, L->n_out, L->n_in, x, ncol,
+                                                       st + c0, A_row);
                     continue;
                 }
                 switch ((ncol - c0) + (c0 == 0 ? 8 : 0)) {
 #define SLR_RC(NC, ROW, K) \
-    case K: recheck_chunk<NC, true, ROW>(wcol, L->n_out, L->n_in, x, ncol, st + c0, A_row); break;
+    case K:                                                                                     \
+        recheck_chunk<NC, true, ROW>(L->wt, j, L->n_out, L->n_in, x, ncol, st + c0, A_row);     \
+        break;
                     SLR_RC(1, false, 1) SLR_RC(2, false, 2) SLR_RC(3, false, 3)
                     SLR_RC(4, false, 4) SLR_RC(5, false, 5) SLR_RC(6, false, 6)
                     SLR_RC(7, false, 7) SLR_RC(8, false, 8) SLR_RC(1, true, 9)
