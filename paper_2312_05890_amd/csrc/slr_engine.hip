@@ -920,27 +920,39 @@ LevelStats* pinned_stats() {
     return ps.p;
 }
 
-// Timing events of count_exact, created once per thread and reused (creating them on every call
-// would add their cost to every timed step).
+// Timing events of count_exact, created once per thread and device and reused (creating them on
+// every call would add their cost to every timed step).  An event belongs to the device that was
+// current when it was created, so the set is rebuilt when the thread's current device changes.
 struct TimingEvents {
     hipEvent_t ev[6] = {};
-    bool ok = false;
-    ~TimingEvents() {
-        for (hipEvent_t e : ev)
+    int device = -1;
+    void release() {
+        for (hipEvent_t& e : ev) {
             if (e) (void)hipEventDestroy(e);
+            e = nullptr;
+        }
+        device = -1;
     }
+    ~TimingEvents() { release(); }
 };
 
 hipEvent_t* timing_events() {
     thread_local TimingEvents te;
-    if (!te.ok) {
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess) {
+        (void)hipGetLastError();
+        return nullptr;
+    }
+    if (te.device != dev) {
+        te.release();
         for (hipEvent_t& e : te.ev) {
-            if (!e && hipEventCreate(&e) != hipSuccess) {
+            if (hipEventCreate(&e) != hipSuccess) {
                 (void)hipGetLastError();
+                te.release();
                 return nullptr;
             }
         }
-        te.ok = true;
+        te.device = dev;
     }
     return te.ev;
 }
