@@ -257,6 +257,32 @@ def test_count_exact_deterministic_and_budget():
     assert z["n_boxes_bounded"] == 1 and z["depth_reached"] == 0
 
 
+def test_count_exact_timing_flags():
+    """Timing changes no result; bit 0 times the bound launches, bit 1 the split launches, whose
+    algorithmic bytes follow from the per-level counts (from the trace): every class byte, the
+    undecided parents' corners and paths and two children each, and one 4-byte count per
+    1024-box tile, for each level the search continued from."""
+    inst = synth.tiny2d(3)
+    net, prop = load(inst)
+    D, M = 14, 1 << 12
+    base = E().count_exact(net, prop, inst.lo, inst.hi, D, M, trace=True)
+    keys = ("unsafe", "safe", "undecided", "n_unsafe", "n_safe", "n_undecided", "n_boxes_bounded",
+            "n_recheck64", "depth_reached", "status")
+    for flag in (0, 1, 2, 3):
+        r = E().count_exact(net, prop, inst.lo, inst.hi, D, M, timing=flag)
+        assert all(r[k] == base[k] for k in keys)
+        assert (r["bound_ms"] > 0) == bool(flag & 1)
+        assert (r["split_ms"] > 0) == bool(flag & 2)
+    d = inst.lo.shape[0]
+    depth, cls = base["trace_depth"], base["trace_cls"]
+    expect = 0
+    for t in range(int(depth.max())):          # levels with a next level
+        n_t = int((depth == t).sum())
+        und = int(((depth == t) & (cls == 0)).sum())
+        expect += n_t + und * (2 * d * 4 + 8) * 3 + -(-n_t // 1024) * 4
+    assert r["split_bytes"] == expect
+
+
 def test_count_exact_rejects_bad_input():
     inst = synth.tiny2d(0)
     net, prop = load(inst)
