@@ -199,7 +199,7 @@ def compare_counts(inst, D, M, chunk=0):
     return g, o, diverge
 
 
-@pytest.mark.parametrize("seed", range(12))
+@pytest.mark.parametrize("seed", range(100))
 def test_count_exact_tiny2d(seed, cvariant):
     inst = synth.tiny2d(seed)
     g, o, div = compare_counts(inst, inst.max_depth, inst.max_leaves)
@@ -211,6 +211,13 @@ def test_count_exact_acas_small_budget(seed, cvariant):
     need(cvariant, synth.acas(seed))
     inst = synth.acas(seed)
     compare_counts(inst, 40, 1 << 12, chunk=1000)
+
+
+@pytest.mark.parametrize("seed", range(2, 10))
+def test_count_exact_acas_seeds(seed):
+    """The 5-50x6-5 workload over its parity seeds, default kernel, ragged launch chunks."""
+    inst = synth.acas(seed)
+    compare_counts(inst, 40, 1 << 12, chunk=3000)
 
 
 def test_count_exact_closed_forms(cvariant):
