@@ -302,8 +302,8 @@ def alpha_section(E, torch, seed, cpu):
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--cpu-leaves", type=int, default=1 << 15)
     ap.add_argument("--no-cpu-baseline", action="store_true")

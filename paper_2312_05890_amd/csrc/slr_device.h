@@ -193,6 +193,46 @@ __device__ __forceinline__ void k_quads(f32x4 (&acc)[NCOL], const float* __restr
     }
 }
 
+// Straight-line quads for nq <= MAXQ (the largest K-quad count a tile shape can meet: its units
+// per workgroup bound the layers' tiles), a loop otherwise.
+template <int NCOL, int MAXQ>
+__device__ __forceinline__ void k_quads_any(f32x4 (&acc)[NCOL], const float* __restrict__ wf,
+                                            const uint64_t* __restrict__ qf, const float* sb,
+                                            int colstride, int nq, int nqa) {
+    switch (nq) {
+        case 1: k_quads<NCOL, 1>(acc, wf, qf, sb, colstride, nq, nqa); return;
+        case 2: k_quads<NCOL, 2>(acc, wf, qf, sb, colstride, nq, nqa); return;
+        case 3: k_quads<NCOL, 3>(acc, wf, qf, sb, colstride, nq, nqa); return;
+        case 4: k_quads<NCOL, 4>(acc, wf, qf, sb, colstride, nq, nqa); return;
+        case 5:
+            if constexpr (MAXQ >= 5) {
+                k_quads<NCOL, 5>(acc, wf, qf, sb, colstride, nq, nqa);
+                return;
+            }
+            break;
+        case 6:
+            if constexpr (MAXQ >= 6) {
+                k_quads<NCOL, 6>(acc, wf, qf, sb, colstride, nq, nqa);
+                return;
+            }
+            break;
+        case 7:
+            if constexpr (MAXQ >= 7) {
+                k_quads<NCOL, 7>(acc, wf, qf, sb, colstride, nq, nqa);
+                return;
+            }
+            break;
+        case 8:
+            if constexpr (MAXQ >= 8) {
+                k_quads<NCOL, 8>(acc, wf, qf, sb, colstride, nq, nqa);
+                return;
+            }
+            break;
+        default: break;
+    }
+    k_quads<NCOL, 0>(acc, wf, qf, sb, colstride, nq, nqa);
+}
+
 template <int NCOL, int NT, int UW, int NW>
 __device__ __forceinline__ void bound_tile(
     const NetDev& net, const PropDev& prop, int64_t n, int64_t box0,
@@ -302,13 +342,8 @@ __device__ __forceinline__ void bound_tile(
                 const int nq = ks >> 2;
                 const int nqa = L->ks_alloc >> 2;
                 const uint64_t* qf = L->qfrag + (size_t)mt * nqa * 64 + lane;
-                switch (nq) {   // straight-line quads for the common widths, else a loop
-                    case 1: k_quads<NCOL, 1>(acc, wf, qf, sb, colstride, nq, nqa); break;
-                    case 2: k_quads<NCOL, 2>(acc, wf, qf, sb, colstride, nq, nqa); break;
-                    case 3: k_quads<NCOL, 3>(acc, wf, qf, sb, colstride, nq, nqa); break;
-                    case 4: k_quads<NCOL, 4>(acc, wf, qf, sb, colstride, nq, nqa); break;
-                    default: k_quads<NCOL, 0>(acc, wf, qf, sb, colstride, nq, nqa); break;
-                }
+                constexpr int kMaxQ = (UW * NW) / NT >= 8 ? 8 : 4;
+                k_quads_any<NCOL, kMaxQ>(acc, wf, qf, sb, colstride, nq, nqa);
                 // the last K-steps (ks % 4 of them) one at a time, B read as scalars: a plain
                 // loop keeps the accumulators in place (no per-step selects of the whole set);
                 // the margin column takes the whole partial quad in one bf16 MFMA (its A is
