@@ -1,6 +1,8 @@
 """The FP64 oracle against its pins (CPU only), and mutation tests proving the pins bite."""
 from __future__ import annotations
 
+from fractions import Fraction
+
 import numpy as np
 import pytest
 
@@ -96,6 +98,33 @@ def test_count_approx_lower_bound_closed_form():
                            seed=3, leaf_depth=12, leaf_leaves=1 << 12, resolve_tol=0.05)
     assert 0.0 < r["lower_bound"] <= 0.5
     assert all(e >= 0 for e in r["estimates"])
+
+
+@pytest.mark.parametrize("weights,bias,d,vr", [
+    ([1, 1], -1.0, 2, Fraction(1, 2)),          # x0 + x1 > 1 on the unit square
+    ([1, 1, 1], -2.0, 3, Fraction(1, 6)),       # the corner simplex x0 + x1 + x2 > 2
+])
+def test_count_approx_estimates_are_unbiased(weights, bias, d, vr):
+    """Each trial's estimate 2^s v f is, in expectation over the random halves kept, the
+    violation rate (per split: a f_low + (1 - a) f_high = f_parent, whatever the split point a);
+    with the leaf's unsafe and unsafe+undecided fractions it brackets the exact rate trial by
+    trial.  Over 256 seeded trials the rate must lie within 4 standard errors of the two means;
+    the same trials evaluated with a volume factor of 1/2 per split, or without the 2^s, miss
+    it on both nets."""
+    net = [(np.array([weights], np.float32), np.array([bias], np.float32))]
+    r = count.count_approx(net, [[1.0]], [0.0], np.zeros(d), np.ones(d), trials=256,
+                           samples=200, seed=5, leaf_depth=8, leaf_leaves=1 << 6,
+                           resolve_tol=0.02)
+    lo = np.array([2.0 ** t["splits"] * t["volume"] * float(t["leaf"]["unsafe_exact"])
+                   for t in r["trials"]])
+    hi = np.array([2.0 ** t["splits"] * t["volume"] *
+                   float(t["leaf"]["unsafe_exact"] + t["leaf"]["undecided_exact"])
+                   for t in r["trials"]])
+    assert np.allclose(lo, r["estimates"])
+    assert max(t["splits"] for t in r["trials"]) >= 2
+    se_lo = lo.std() / np.sqrt(lo.size)
+    se_hi = hi.std() / np.sqrt(hi.size)
+    assert lo.mean() - 4 * se_lo <= float(vr) <= hi.mean() + 4 * se_hi
 
 
 # ---------------------------------------------------------------------------------------
