@@ -27,6 +27,7 @@ sys.path.insert(0, ROOT)
 METRIC = "boxes bounded/s + time-to-exact unsafe volume, plain vs batched+α on 1 GPU"
 PEAK_FP32_MFMA = 157.3      # TFLOP/s, MI355X dense FP32 matrix
 PEAK_HBM = 8000.0           # GB/s
+ALPHA_SELECT = 0.2          # alpha only on boxes within 20% of their bound width from a decision
 
 
 def flops_per_box(sizes, rows):
@@ -157,13 +158,13 @@ def bench_alpha_optimize(E, torch, inst, n, steps, seed, reps=3):
             "decided": int((cls != 0).sum())}
 
 
-def bench_count(E, torch, inst, D, M, alpha_steps=0, min_depth=0, reps=1):
+def bench_count(E, torch, inst, D, M, alpha_steps=0, min_depth=0, reps=1, select=0.0):
     net = E.Net(inst.net)
     prop = E.Property(net, inst.C, inst.dvec)
     achunk = 16384 if alpha_steps else 0
     ws = torch.empty(E.workspace_size(net, prop, M, 0, achunk), dtype=torch.uint8, device="cuda")
     kw = dict(workspace=ws, alpha_steps=alpha_steps, alpha_min_depth=min_depth,
-              alpha_chunk=achunk)
+              alpha_chunk=achunk, alpha_select=select)
     E.count_exact(net, prop, inst.lo, inst.hi, D, M, **kw)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -291,8 +292,12 @@ def alpha_section(E, torch, seed, cpu):
         "wide20_optimize": bench_alpha_optimize(E, torch, b5, 4096, 20, seed),
         "acas_count_plain": bench_count(E, torch, a5, a5.max_depth, a5.max_leaves),
         "acas_count_alpha": bench_count(E, torch, a5, a5.max_depth, a5.max_leaves, 20, 16),
+        "acas_count_alpha_near": bench_count(E, torch, a5, a5.max_depth, a5.max_leaves, 20, 16,
+                                             select=ALPHA_SELECT),
         "wide20_count_plain": bench_count(E, torch, b5, b5.max_depth, 1 << 14),
         "wide20_count_alpha": bench_count(E, torch, b5, b5.max_depth, 1 << 14, 20, 8),
+        "wide20_count_alpha_near": bench_count(E, torch, b5, b5.max_depth, 1 << 14, 20, 8,
+                                               select=ALPHA_SELECT),
     }
     if cpu:
         out["cpu_baseline"] = cpu_alpha_baseline(a5, 32, 20, seed)

@@ -137,6 +137,13 @@ typedef struct {
     float alpha_lr;         /* Adam step size (0 = 0.1) */
     int32_t alpha_min_depth;
     int32_t alpha_chunk;
+    /* 0: the alpha pass takes every box the plain bounds leave undecided; > 0: only those
+       whose plain bounds are near a decision: for each property row the distance of the
+       deciding bound from zero relative to the row's bound width, (-g_lo) / (g_hi - g_lo) for
+       proving unsafe (the largest over the rows with g_lo <= 0) and g_hi / (g_hi - g_lo) for
+       proving safe (the smallest over the rows); a box is taken when the smaller of the two
+       is at most alpha_select.  Must be finite and >= 0. */
+    float alpha_select;
 } slr_exact_opts;
 
 typedef struct {

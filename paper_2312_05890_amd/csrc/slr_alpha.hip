@@ -922,11 +922,33 @@ __global__ __launch_bounds__(256) void center_obj_kernel(NetDev net, PropDev pro
 }
 
 // Indices of the undecided boxes (class 0) of a level, appended with one atomic per wavefront.
+// Distance of an undecided box from a decision, relative to its bound widths: the smaller of
+// the unsafe distance (the largest (-g_lo)/(g_hi - g_lo) over rows with g_lo <= 0) and the safe
+// distance (the smallest g_hi/(g_hi - g_lo) over the rows).
+__device__ __forceinline__ float decision_distance(const float* glo, const float* ghi, int rows) {
+    float du = 0.f, ds = INFINITY;
+    for (int r = 0; r < rows; ++r) {
+        const float w = ghi[r] - glo[r];
+        if (!(w > 0.f)) continue;
+        if (glo[r] <= 0.f) du = fmaxf(du, -glo[r] / w);
+        ds = fminf(ds, ghi[r] / w);
+    }
+    return fminf(du, ds);
+}
+
 __global__ __launch_bounds__(256) void collect_kernel(int64_t n, const int8_t* __restrict__ cls,
                                                      unsigned* __restrict__ list,
-                                                     unsigned* __restrict__ count) {
+                                                     unsigned* __restrict__ count,
+                                                     const float* __restrict__ g_lo,
+                                                     const float* __restrict__ g_hi, int rows,
+                                                     float select, unsigned* __restrict__ total) {
     const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    const bool und = i < n && cls[i] == 0;
+    bool und = i < n && cls[i] == 0;
+    if (total) {   // every undecided box, selected or not
+        const unsigned long long all = __ballot(und);
+        if ((threadIdx.x & 63) == 0 && all) atomicAdd(total, (unsigned)__popcll(all));
+    }
+    if (und && g_lo) und = decision_distance(g_lo + i * rows, g_hi + i * rows, rows) <= select;
     const unsigned long long mask = __ballot(und);
     const int lane = threadIdx.x & 63;
     unsigned base = 0;
@@ -1124,11 +1146,12 @@ hipError_t launch_center_objective(const NetDev& net, const PropDev& prop, int64
 }
 
 hipError_t launch_collect_undecided(int64_t n, const int8_t* cls, unsigned* list, unsigned* count,
-                                    hipStream_t stream) {
+                                    hipStream_t stream, const float* g_lo, const float* g_hi,
+                                    int rows, float select, unsigned* total) {
     if (n <= 0) return hipSuccess;
     (void)hipGetLastError();
     hipLaunchKernelGGL(collect_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream, n,
-                       cls, list, count);
+                       cls, list, count, g_lo, g_hi, rows, select, total);
     return hipGetLastError();
 }
 

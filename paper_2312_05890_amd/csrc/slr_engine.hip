@@ -529,6 +529,7 @@ struct Workspace {
     int64_t achunk;
     float *alo, *ahi;            // [achunk][d] gathered undecided boxes
     float *best_lo, *best_hi;    // [achunk][rows]
+    float *glo, *ghi;            // [cap][rows] plain bounds of a level (alpha candidate selection)
     int8_t* acls;                // [achunk]
     char* aws;                   // alpha_optimize workspace for achunk boxes
     size_t aws_bytes;
@@ -588,7 +589,7 @@ Workspace layout_ws(char* base, const NetDev& nd, const PropDev& pd, int64_t cap
     }
     w.cls = (int8_t*)take(cap);
     w.amb_list = (unsigned*)take(sizeof(unsigned) * cap);
-    w.amb_count = (unsigned*)take(sizeof(unsigned));
+    w.amb_count = (unsigned*)take(2 * sizeof(unsigned));   // [1]: all undecided (alpha pass)
     w.tile_und = (unsigned*)take(sizeof(unsigned) * level_tiles(cap));
     w.stats = (LevelStats*)take(sizeof(LevelStats) * kMaxLevels);
     w.vol = (double*)take(sizeof(double) * 3);
@@ -612,6 +613,8 @@ Workspace layout_ws(char* base, const NetDev& nd, const PropDev& pd, int64_t cap
         w.ahi = (float*)take(sizeof(float) * d * achunk);
         w.best_lo = (float*)take(sizeof(float) * pd.rows * achunk);
         w.best_hi = (float*)take(sizeof(float) * pd.rows * achunk);
+        w.glo = (float*)take(sizeof(float) * pd.rows * cap);
+        w.ghi = (float*)take(sizeof(float) * pd.rows * cap);
         w.acls = (int8_t*)take(achunk);
         w.aws_bytes = layout_alpha(nullptr, nd, pd, achunk).bytes;
         w.aws = take(w.aws_bytes);
@@ -1027,6 +1030,14 @@ int count_exact_impl(const slr_net* net, const slr_property* prop, const double*
                 a.g_hi = w.whi;
                 a.cls = w.cls + off;
                 HIP_TRY(launch_alpha_forward(net->dev, prop->dev, a, s), "count_exact: bound kernel");
+                if (o->alpha_steps > 0 && t >= o->alpha_min_depth && o->alpha_select > 0.f) {
+                    // an alpha level that selects its candidates keeps the plain bounds
+                    const size_t gb = sizeof(float) * prop->dev.rows * m;
+                    HIP_TRY(hipMemcpyAsync(w.glo + off * prop->dev.rows, w.wlo, gb,
+                                           hipMemcpyDeviceToDevice, s), "count_exact: bounds");
+                    HIP_TRY(hipMemcpyAsync(w.ghi + off * prop->dev.rows, w.whi, gb,
+                                           hipMemcpyDeviceToDevice, s), "count_exact: bounds");
+                }
                 a.raw = 1;
                 a.g_lo = w.rlo;
                 a.g_hi = w.rhi;
@@ -1038,11 +1049,15 @@ int count_exact_impl(const slr_net* net, const slr_property* prop, const double*
                 launches += 2;
             }
         } else {
+            // an alpha level that selects its candidates keeps the plain bounds
+            const bool keep_g = o->alpha_steps > 0 && t >= o->alpha_min_depth && o->alpha_select > 0.f;
+            const int rows = prop->dev.rows;
             for (int64_t off = 0; off < n; off += chunk) {
                 const int64_t m = std::min(chunk, n - off);
                 HIP_TRY(launch_bound_f32(net->dev, prop->dev, m, w.lo[cur] + off * d, w.hi[cur] + off * d,
-                                         nullptr, nullptr, w.cls + off, 0, s, &unsup, w.amb_list,
-                                         w.amb_count, (unsigned)off),
+                                         keep_g ? w.glo + off * rows : nullptr,
+                                         keep_g ? w.ghi + off * rows : nullptr, w.cls + off, 0, s,
+                                         &unsup, w.amb_list, w.amb_count, (unsigned)off),
                         "count_exact: bound kernel");
                 if (unsup) return fail(SLR_EUNSUPPORTED, "count_exact: shape not supported");
                 ++launches;
@@ -1062,11 +1077,16 @@ int count_exact_impl(const slr_net* net, const slr_property* prop, const double*
                 "count_exact: recheck kernel");
         if (o->alpha_steps > 0 && t >= o->alpha_min_depth) {
             if (ev0) HIP_TRY(hipEventRecord(ev0, s), "count_exact: event");
-            HIP_TRY(hipMemsetAsync(w.amb_count, 0, sizeof(unsigned), s), "count_exact: clear");
-            HIP_TRY(launch_collect_undecided(n, w.cls, w.amb_list, w.amb_count, s), "count_exact: collect kernel");
-            unsigned und_cnt = 0;
-            HIP_TRY(hipMemcpyAsync(&und_cnt, w.amb_count, sizeof und_cnt, hipMemcpyDeviceToHost, s), "count_exact: readback");
+            HIP_TRY(hipMemsetAsync(w.amb_count, 0, 2 * sizeof(unsigned), s), "count_exact: clear");
+            const bool sel = o->alpha_select > 0.f;
+            HIP_TRY(launch_collect_undecided(n, w.cls, w.amb_list, w.amb_count, s,
+                                             sel ? w.glo : nullptr, sel ? w.ghi : nullptr,
+                                             prop->dev.rows, o->alpha_select, w.amb_count + 1),
+                    "count_exact: collect kernel");
+            unsigned cnt2[2] = {0, 0};   // boxes given the alpha pass, all undecided boxes
+            HIP_TRY(hipMemcpyAsync(cnt2, w.amb_count, sizeof cnt2, hipMemcpyDeviceToHost, s), "count_exact: readback");
             HIP_TRY(hipStreamSynchronize(s), "count_exact: sync");
+            const unsigned und_cnt = cnt2[0];
             slr_alpha_opts ao{};
             ao.steps = o->alpha_steps;
             ao.lr = o->alpha_lr > 0.f ? o->alpha_lr : 0.1f;
@@ -1083,7 +1103,7 @@ int count_exact_impl(const slr_net* net, const slr_property* prop, const double*
                 HIP_TRY(launch_scatter_classes(m, w.amb_list + off, w.acls, w.cls, s), "count_exact: scatter kernel");
             }
             alpha_boxes += und_cnt;
-            alpha_und_before += und_cnt;
+            alpha_und_before += cnt2[1];   // decided by alpha = undecided before - after
             if (ev1) {
                 HIP_TRY(hipEventRecord(ev1, s), "count_exact: event");
                 HIP_TRY(hipEventSynchronize(ev1), "count_exact: event");
@@ -1226,6 +1246,8 @@ int check_exact_opts(const slr_net* net, const slr_property* prop, const slr_exa
         return fail(SLR_EINVAL, "%s: alpha mode needs alpha_chunk >= 1 (and a workspace sized for it)", who);
     if (!(o->alpha_lr >= 0.f) || o->alpha_min_depth < 0)
         return fail(SLR_EINVAL, "%s: alpha_lr and alpha_min_depth must be >= 0", who);
+    if (!(o->alpha_select >= 0.f) || !std::isfinite(o->alpha_select))
+        return fail(SLR_EINVAL, "%s: alpha_select must be finite and >= 0", who);
     const int64_t achunk = o->alpha_steps > 0 ? o->alpha_chunk : 0;
     const size_t need = layout_ws(nullptr, net->dev, prop->dev, o->max_leaves, samples, achunk).bytes;
     if (!o->workspace || o->workspace_bytes < need)

@@ -191,8 +191,13 @@ hipError_t launch_alpha_backward(const NetDev& net, const PropDev& prop, const A
                                  hipStream_t stream);
 // obj[b][0] = 1 if every property row is > 0 at the box center, obj[b][1] = argmin row there
 // Level helpers of the alpha pass inside the exact count.
+// Undecided boxes (cls 0) into list; with g_lo/g_hi ([n][rows]) only those whose decision
+// distance (see slr_exact_opts.alpha_select) is at most select; total (if given) counts every
+// undecided box.
 hipError_t launch_collect_undecided(int64_t n, const int8_t* cls, unsigned* list, unsigned* count,
-                                    hipStream_t stream);
+                                    hipStream_t stream, const float* g_lo = nullptr,
+                                    const float* g_hi = nullptr, int rows = 0, float select = 0.f,
+                                    unsigned* total = nullptr);
 hipError_t launch_gather_boxes(int64_t m, int d, const unsigned* list, const float* lo,
                                const float* hi, float* lo2, float* hi2, hipStream_t stream);
 hipError_t launch_scatter_classes(int64_t m, const unsigned* list, const int8_t* cls2, int8_t* cls,

@@ -40,7 +40,8 @@ class ExactOpts(C.Structure):
                 ("trace_depth", C.POINTER(C.c_int32)), ("trace_path", C.POINTER(C.c_uint64)),
                 ("trace_cls", C.POINTER(C.c_int8)), ("timing", C.c_int32),
                 ("alpha_steps", C.c_int32), ("alpha_lr", C.c_float),
-                ("alpha_min_depth", C.c_int32), ("alpha_chunk", C.c_int32)]
+                ("alpha_min_depth", C.c_int32), ("alpha_chunk", C.c_int32),
+                ("alpha_select", C.c_float)]
 
 
 class CountResult(C.Structure):
@@ -279,7 +280,7 @@ def workspace_size(net: Net, prop: Property, max_leaves: int, samples: int = 0,
 
 def _exact_opts(net, prop, max_depth, max_leaves, chunk, workspace, stream, samples,
                 trace_capacity=0, timing=False, alpha_steps=0, alpha_lr=0.0, alpha_min_depth=0,
-                alpha_chunk=0):
+                alpha_chunk=0, alpha_select=0.0):
     import torch
     if alpha_steps > 0 and alpha_chunk <= 0:
         alpha_chunk = 16384
@@ -300,6 +301,7 @@ def _exact_opts(net, prop, max_depth, max_leaves, chunk, workspace, stream, samp
     o.alpha_lr = float(alpha_lr)
     o.alpha_min_depth = int(alpha_min_depth)
     o.alpha_chunk = int(alpha_chunk)
+    o.alpha_select = float(alpha_select)
     return o, workspace
 
 
@@ -307,20 +309,22 @@ def count_exact(net: Net, prop: Property, lo, hi, max_depth: int, max_leaves: in
                 chunk: int = 0, workspace=None, stream=None, trace: bool = False,
                 trace_capacity: Optional[int] = None, timing: int = 0,
                 alpha_steps: int = 0, alpha_lr: float = 0.1, alpha_min_depth: int = 0,
-                alpha_chunk: int = 0) -> dict:
+                alpha_chunk: int = 0, alpha_select: float = 0.0) -> dict:
     """Alg. 1 on the device; returns the bracket, counts and (optionally) a per-box trace.
 
     ``timing``: bit 0 times the bound-kernel launches (``bound_ms``), bit 1 the split launches
     (``split_ms``, with their algorithmic ``split_bytes``); True means 1.
     With ``alpha_steps`` > 0 the boxes the plain bounds leave undecided (from depth
-    ``alpha_min_depth`` on) are re-bounded with optimized lower slopes before they are split."""
+    ``alpha_min_depth`` on) are re-bounded with optimized lower slopes before they are split;
+    ``alpha_select`` > 0 limits that to boxes whose plain bounds are within that fraction of
+    their width from a decision (see ``slr_exact_opts.alpha_select``)."""
     lo = np.ascontiguousarray(lo, np.float64)
     hi = np.ascontiguousarray(hi, np.float64)
     cap = 0
     if trace:
         cap = int(trace_capacity if trace_capacity is not None else 4 * max_leaves + 64)
     o, ws = _exact_opts(net, prop, max_depth, max_leaves, chunk, workspace, stream, 0, cap, timing,
-                        alpha_steps, alpha_lr, alpha_min_depth, alpha_chunk)
+                        alpha_steps, alpha_lr, alpha_min_depth, alpha_chunk, alpha_select)
     if trace:
         t_depth = np.zeros(cap, np.int32)
         t_path = np.zeros(cap, np.uint64)

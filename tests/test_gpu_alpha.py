@@ -253,11 +253,13 @@ def test_rejects_small_tape():
 
 
 @pytest.mark.parametrize("seed", [0, 1, 2])
-def test_count_exact_alpha_bracket_inside_plain(seed):
+@pytest.mark.parametrize("select", [0.0, 0.2])
+def test_count_exact_alpha_bracket_inside_plain(seed, select):
     inst = synth.tiny2d(seed)
     net, prop = load(inst)
     D = 10
-    r = E().count_exact(net, prop, inst.lo, inst.hi, D, 1 << 16, alpha_steps=20, alpha_chunk=256)
+    r = E().count_exact(net, prop, inst.lo, inst.hi, D, 1 << 16, alpha_steps=20, alpha_chunk=256,
+                        alpha_select=select)
     o = count.count_exact(inst.net, inst.C, inst.dvec, inst.lo, inst.hi, D, 1 << 16)
     assert abs(r["unsafe"] + r["safe"] + r["undecided"] - 1.0) == 0.0
     assert r["unsafe"] >= o["unsafe"] - 1e-12
@@ -280,6 +282,13 @@ def test_count_exact_alpha_acas():
     assert a["unsafe"] + a["safe"] + a["undecided"] == 1.0
     assert a["n_alpha_decided"] > 0
     assert a["n_boxes_bounded"] <= p["n_boxes_bounded"]
+    # only the boxes near a decision: far fewer alpha boxes, still decisions, still inside plain
+    s = eng.count_exact(net, prop, inst.lo, inst.hi, D, M, alpha_steps=20, alpha_chunk=16384,
+                        alpha_min_depth=16, alpha_select=0.2)
+    assert s["n_alpha_boxes"] < a["n_alpha_boxes"] / 3
+    assert s["n_alpha_decided"] > 0
+    assert s["unsafe"] >= p["unsafe"] and s["safe"] >= p["safe"]
+    assert s["unsafe"] + s["safe"] + s["undecided"] == 1.0
 
 
 def test_state_placement_variants_agree():

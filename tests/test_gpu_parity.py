@@ -308,6 +308,11 @@ def test_count_exact_rejects_bad_input():
     p_other = eng.Property(other, inst.C, inst.dvec)
     with pytest.raises(eng.SlrError):
         eng.count_exact(net, p_other, inst.lo, inst.hi, 5, 10)
+    for bad in (-0.5, float("nan"), float("inf")):
+        with pytest.raises(eng.SlrError) as e:
+            eng.count_exact(net, prop, inst.lo, inst.hi, 5, 10, alpha_steps=2, alpha_chunk=64,
+                            alpha_select=bad)
+        assert e.value.code == -1
 
 
 def reconstruct(lo, hi, depth, path):
