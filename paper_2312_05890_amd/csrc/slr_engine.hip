@@ -6,12 +6,15 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
+#include <thread>
 #include <vector>
 
 namespace {
@@ -1285,6 +1288,147 @@ static double snap_split(double med, double a, double b, double A, double B, int
     return A + k * h;
 }
 
+namespace {
+
+// One trial of the approximate count: halve the subdomain until count_exact resolves it (or the
+// split cap or the grid stops it); returns the trial's estimate 2^s v f in *E.  Every draw is a
+// Philox4x32-10 block keyed by the seed with counters (point/dimension, split, trial, tag), so a
+// trial's result does not depend on which thread or stream runs it.
+int approx_trial(const slr_net* net, const slr_property* prop, const double* lo, const double* hi,
+                 const slr_approx_opts& o, const slr_exact_opts& leaf, const Workspace& w, int t,
+                 double* E, int32_t* n_splits) {
+    const int d = net->dev.d;
+    const uint32_t key[2] = {(uint32_t)(o.seed & 0xFFFFFFFFu), (uint32_t)(o.seed >> 32)};
+    hipStream_t s = (hipStream_t)leaf.stream;
+    std::vector<double> slo(lo, lo + d), shi(hi, hi + d), coords;
+    std::vector<float> pts((size_t)o.samples * d);
+    std::vector<int8_t> viol(o.samples);
+    int splits = 0;
+    slr_count_result r;
+    while (true) {
+        memset(&r, 0, sizeof r);
+        const int rc = count_exact_impl(net, prop, slo.data(), shi.data(), &leaf, w, &r);
+        if (rc < 0) return rc;
+        if (r.undecided <= o.resolve_tol || splits >= o.max_splits) break;
+        // uniform samples of the subdomain (float64 arithmetic, rounded to float32)
+        for (int p = 0; p < o.samples; ++p)
+            for (int k = 0; k < d; ++k) {
+                const uint64_t q = (uint64_t)p * d + k;
+                const uint32_t ctr[4] = {(uint32_t)(q >> 1), (uint32_t)splits, (uint32_t)t, kTagSample};
+                uint32_t wv[4];
+                Philox::block(ctr, key, wv);
+                const double u = (q & 1) ? Philox::u53(wv[2], wv[3]) : Philox::u53(wv[0], wv[1]);
+                pts[(size_t)p * d + k] = (float)(slo[k] + u * (shi[k] - slo[k]));
+            }
+        HIP_TRY(hipMemcpyAsync(w.samples, pts.data(), pts.size() * sizeof(float), hipMemcpyHostToDevice, s), "count_approx: samples");
+        HIP_TRY(launch_sample_forward(net->dev, prop->dev, o.samples, w.samples, w.viol, s), "count_approx: sample kernel");
+        HIP_TRY(hipMemcpyAsync(viol.data(), w.viol, o.samples, hipMemcpyDeviceToHost, s), "count_approx: readback");
+        HIP_TRY(hipStreamSynchronize(s), "count_approx: sync");
+        const uint32_t sctr[4] = {0u, (uint32_t)splits, (uint32_t)t, kTagSplit};
+        uint32_t sw[4];
+        Philox::block(sctr, key, sw);
+        const int dim = (int)(((uint64_t)sw[0] * (uint64_t)d) >> 32);
+        const int side = (int)(sw[1] & 1u);
+        // a side as narrow as two grid steps is not split further: the trial stops here (the
+        // bound holds for any stopping rule; this keeps every leaf bisection exact in float32)
+        if (shi[dim] - slo[dim] < 2.0 * (hi[dim] - lo[dim]) * std::ldexp(1.0, -o.grid_bits)) break;
+        coords.clear();
+        for (int p = 0; p < o.samples; ++p)
+            if (viol[p]) coords.push_back(pts[(size_t)p * d + dim]);
+        if (coords.empty())
+            for (int p = 0; p < o.samples; ++p) coords.push_back(pts[(size_t)p * d + dim]);
+        std::sort(coords.begin(), coords.end());
+        const double med = coords[(coords.size() - 1) / 2];
+        const double m = snap_split(med, slo[dim], shi[dim], lo[dim], hi[dim], o.grid_bits);
+        if ((double)(float)m != m) return fail(SLR_EINTERNAL, "count_approx: split point not exact in float32");
+        if (side == 0) shi[dim] = m; else slo[dim] = m;
+        ++splits;
+    }
+    double v = 1.0;
+    for (int k = 0; k < d; ++k)
+        if (hi[k] > lo[k]) v *= (shi[k] - slo[k]) / (hi[k] - lo[k]);
+    *E = std::ldexp(v * r.unsafe, splits);
+    *n_splits = splits;
+    return SLR_OK;
+}
+
+// Trials on `conc` slots at once: slot 0 on the calling thread and opts->leaf.stream, slot k > 0
+// on a worker thread with a stream of its own (default priority) that first waits for the work
+// already queued on opts->leaf.stream.  Slot k uses bytes [k per, (k + 1) per) of the workspace.
+// Trials are taken in order from a shared counter; the first error stops the other slots after
+// their current trial and is reported with its message.
+int approx_concurrent(const slr_net* net, const slr_property* prop, const double* lo,
+                      const double* hi, const slr_approx_opts& o, int conc, size_t per,
+                      slr_approx_result* out) {
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev), "count_approx: device");
+    hipStream_t s0 = (hipStream_t)o.leaf.stream;
+    hipEvent_t ready = nullptr;
+    HIP_TRY(hipEventCreateWithFlags(&ready, hipEventDisableTiming), "count_approx: event");
+    std::vector<hipStream_t> streams(conc, nullptr);
+    streams[0] = s0;
+    int rc = SLR_OK;
+    hipError_t e = hipEventRecord(ready, s0);
+    for (int k = 1; k < conc && e == hipSuccess; ++k) {
+        e = hipStreamCreateWithFlags(&streams[k], hipStreamNonBlocking);
+        if (e == hipSuccess) e = hipStreamWaitEvent(streams[k], ready, 0);
+    }
+    if (e != hipSuccess) rc = hip_fail(e, "count_approx: streams");
+    std::atomic<int> next{0};
+    std::atomic<int> err{SLR_OK};
+    std::mutex mu;
+    std::string msg;
+    auto slot = [&](int k) {
+        if (k > 0 && hipSetDevice(dev) != hipSuccess) {
+            std::lock_guard<std::mutex> g(mu);
+            if (err.load() == SLR_OK) {
+                msg = "count_approx: worker thread could not select the device";
+                err.store(SLR_EHIP);
+            }
+            return;
+        }
+        slr_exact_opts leaf = o.leaf;
+        leaf.workspace = (char*)o.leaf.workspace + (size_t)k * per;
+        leaf.workspace_bytes = per;
+        leaf.stream = streams[k];
+        Workspace w;
+        int r = check_exact_opts(net, prop, &leaf, o.samples, &w, "count_approx");
+        while (r == SLR_OK && err.load() == SLR_OK) {
+            const int t = next.fetch_add(1);
+            if (t >= o.trials) break;
+            r = approx_trial(net, prop, lo, hi, o, leaf, w, t, &out->estimate[t], &out->splits[t]);
+        }
+        if (r < 0) {
+            (void)hipStreamSynchronize(streams[k]);
+            std::lock_guard<std::mutex> g(mu);
+            if (err.load() == SLR_OK) {
+                msg = g_err;
+                err.store(r);
+            }
+        }
+    };
+    if (rc == SLR_OK) {
+        std::vector<std::thread> workers;
+        for (int k = 1; k < conc; ++k) workers.emplace_back(slot, k);
+        slot(0);
+        for (auto& th : workers) th.join();
+    }
+    for (int k = 1; k < conc; ++k)
+        if (streams[k]) {
+            (void)hipStreamSynchronize(streams[k]);
+            (void)hipStreamDestroy(streams[k]);
+        }
+    (void)hipEventDestroy(ready);
+    if (rc != SLR_OK) return rc;
+    if (err.load() != SLR_OK) {
+        g_err = msg;
+        return err.load();
+    }
+    return SLR_OK;
+}
+
+}  // namespace
+
 extern "C" int count_approx(const slr_net* net, const slr_property* prop, const double* lo,
                             const double* hi, const slr_approx_opts* opts, slr_approx_result* out) {
     g_err.clear();
@@ -1292,79 +1436,37 @@ extern "C" int count_approx(const slr_net* net, const slr_property* prop, const 
     if (rc) return rc;
     if (!out || !opts) return fail(SLR_EINVAL, "count_approx: NULL argument");
     if ((rc = check_box(net, lo, hi, "count_approx"))) return rc;
-    const slr_approx_opts& o = *opts;
+    const slr_approx_opts o = *opts;
     if (o.trials < 1 || o.trials > 64) return fail(SLR_EINVAL, "count_approx: trials must be in [1, 64]");
     if (o.samples < 1 || o.samples > 65536) return fail(SLR_EINVAL, "count_approx: samples must be in [1, 65536]");
     if (!(o.confidence > 0.0 && o.confidence < 1.0)) return fail(SLR_EINVAL, "count_approx: confidence must be in (0, 1)");
     if (o.max_splits < 0 || o.max_splits > 1000) return fail(SLR_EINVAL, "count_approx: max_splits must be in [0, 1000]");
     if (o.grid_bits < 1 || o.grid_bits > 20) return fail(SLR_EINVAL, "count_approx: grid_bits must be in [1, 20]");
     if (!(o.resolve_tol >= 0.0)) return fail(SLR_EINVAL, "count_approx: resolve_tol must be >= 0");
+    if (o.concurrency < 0 || o.concurrency > 64) return fail(SLR_EINVAL, "count_approx: concurrency must be in [0, 64]");
+    const int conc = std::max(1, std::min(o.concurrency, o.trials));
+    if (conc > 1 && o.leaf.trace_capacity > 0)
+        return fail(SLR_EINVAL, "count_approx: a leaf trace needs concurrency <= 1");
     Workspace w;
     if ((rc = check_exact_opts(net, prop, &o.leaf, o.samples, &w, "count_approx"))) return rc;
+    const int64_t achunk = o.leaf.alpha_steps > 0 ? o.leaf.alpha_chunk : 0;
+    const size_t per = (layout_ws(nullptr, net->dev, prop->dev, o.leaf.max_leaves, o.samples, achunk).bytes + 255) &
+                       ~(size_t)255;
+    if (conc > 1 && o.leaf.workspace_bytes < per * (size_t)conc)
+        return fail(SLR_ENOMEM, "count_approx: workspace of %zu bytes is smaller than the %zu required for "
+                    "%d concurrent trials", o.leaf.workspace_bytes, per * (size_t)conc, conc);
     memset(out, 0, sizeof *out);
     const auto t0 = std::chrono::steady_clock::now();
-    const int d = net->dev.d;
-    const double beta = std::log2(1.0 / (1.0 - o.confidence)) / o.trials;
-    const uint32_t key[2] = {(uint32_t)(o.seed & 0xFFFFFFFFu), (uint32_t)(o.seed >> 32)};
-    hipStream_t s = (hipStream_t)o.leaf.stream;
-    std::vector<double> slo(d), shi(d), coords;
-    std::vector<float> pts((size_t)o.samples * d);
-    std::vector<int8_t> viol(o.samples);
-    double best = INFINITY;
-    for (int t = 0; t < o.trials; ++t) {
-        for (int k = 0; k < d; ++k) {
-            slo[k] = lo[k];
-            shi[k] = hi[k];
-        }
-        int splits = 0;
-        slr_count_result r;
-        while (true) {
-            memset(&r, 0, sizeof r);
-            rc = count_exact_impl(net, prop, slo.data(), shi.data(), &o.leaf, w, &r);
-            if (rc < 0) return rc;
-            if (r.undecided <= o.resolve_tol || splits >= o.max_splits) break;
-            // uniform samples of the subdomain (float64 arithmetic, rounded to float32)
-            for (int p = 0; p < o.samples; ++p)
-                for (int k = 0; k < d; ++k) {
-                    const uint64_t q = (uint64_t)p * d + k;
-                    const uint32_t ctr[4] = {(uint32_t)(q >> 1), (uint32_t)splits, (uint32_t)t, kTagSample};
-                    uint32_t wv[4];
-                    Philox::block(ctr, key, wv);
-                    const double u = (q & 1) ? Philox::u53(wv[2], wv[3]) : Philox::u53(wv[0], wv[1]);
-                    pts[(size_t)p * d + k] = (float)(slo[k] + u * (shi[k] - slo[k]));
-                }
-            HIP_TRY(hipMemcpyAsync(w.samples, pts.data(), pts.size() * sizeof(float), hipMemcpyHostToDevice, s), "count_approx: samples");
-            HIP_TRY(launch_sample_forward(net->dev, prop->dev, o.samples, w.samples, w.viol, s), "count_approx: sample kernel");
-            HIP_TRY(hipMemcpyAsync(viol.data(), w.viol, o.samples, hipMemcpyDeviceToHost, s), "count_approx: readback");
-            HIP_TRY(hipStreamSynchronize(s), "count_approx: sync");
-            const uint32_t sctr[4] = {0u, (uint32_t)splits, (uint32_t)t, kTagSplit};
-            uint32_t sw[4];
-            Philox::block(sctr, key, sw);
-            const int dim = (int)(((uint64_t)sw[0] * (uint64_t)d) >> 32);
-            const int side = (int)(sw[1] & 1u);
-            // a side as narrow as two grid steps is not split further: the trial stops here (the
-            // bound holds for any stopping rule; this keeps every leaf bisection exact in float32)
-            if (shi[dim] - slo[dim] < 2.0 * (hi[dim] - lo[dim]) * std::ldexp(1.0, -o.grid_bits)) break;
-            coords.clear();
-            for (int p = 0; p < o.samples; ++p)
-                if (viol[p]) coords.push_back(pts[(size_t)p * d + dim]);
-            if (coords.empty())
-                for (int p = 0; p < o.samples; ++p) coords.push_back(pts[(size_t)p * d + dim]);
-            std::sort(coords.begin(), coords.end());
-            const double med = coords[(coords.size() - 1) / 2];
-            const double m = snap_split(med, slo[dim], shi[dim], lo[dim], hi[dim], o.grid_bits);
-            if ((double)(float)m != m) return fail(SLR_EINTERNAL, "count_approx: split point not exact in float32");
-            if (side == 0) shi[dim] = m; else slo[dim] = m;
-            ++splits;
-        }
-        double v = 1.0;
-        for (int k = 0; k < d; ++k)
-            if (hi[k] > lo[k]) v *= (shi[k] - slo[k]) / (hi[k] - lo[k]);
-        const double E = std::ldexp(v * r.unsafe, splits);
-        out->estimate[t] = E;
-        out->splits[t] = splits;
-        best = std::min(best, E);
+    if (conc == 1) {
+        for (int t = 0; t < o.trials; ++t)
+            if ((rc = approx_trial(net, prop, lo, hi, o, o.leaf, w, t, &out->estimate[t], &out->splits[t])) < 0)
+                return rc;
+    } else if ((rc = approx_concurrent(net, prop, lo, hi, o, conc, per, out)) < 0) {
+        return rc;
     }
+    double best = INFINITY;
+    for (int t = 0; t < o.trials; ++t) best = std::min(best, out->estimate[t]);
+    const double beta = std::log2(1.0 / (1.0 - o.confidence)) / o.trials;
     out->trials = o.trials;
     out->lower_bound = std::exp2(-beta) * best;
     out->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();

@@ -3,6 +3,8 @@
 // kernel and the sample forward pass; launch and shape-class selection.
 #include "slr_device.h"
 
+#include <atomic>
+
 namespace {
 
 template <int NCOL, int NT, int UW, int NW>
@@ -418,19 +420,18 @@ hipError_t launch_ncol(TileShape t, const NetDev& net, const PropDev& prop, int6
     return hipErrorInvalidValue;
 }
 
-int g_num_cu = 0;
-
+// Compute units of the device current at the first call (a function-local static: its
+// initialization is thread-safe, so concurrent callers see one value).
 int num_cu() {
-    if (g_num_cu == 0) {
+    static const int cu_count = [] {
         int dev = 0, cu = 0;
-        if (hipGetDevice(&dev) == hipSuccess &&
-            hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && cu > 0)
-            g_num_cu = cu;
-        else
-            g_num_cu = 256;
+        const bool ok = hipGetDevice(&dev) == hipSuccess &&
+                        hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
+                        cu > 0;
         (void)hipGetLastError();
-    }
-    return g_num_cu;
+        return ok ? cu : 256;
+    }();
+    return cu_count;
 }
 
 size_t reg_lds_bytes(const NetDev& net, const PropDev& prop, int ncol) {
@@ -451,15 +452,17 @@ hipError_t launch_reg(const NetDev& net, const PropDev& prop, int64_t n, const f
     hipError_t e = allow_lds((const void*)kern, lds);
     if (e != hipSuccess) return e;
     // persistent grid: as many workgroups as can be resident at once
-    static int per_cu = 0;
-    if (per_cu == 0) {
+    static std::atomic<int> per_cu{0};
+    int pc = per_cu.load(std::memory_order_relaxed);
+    if (pc == 0) {
         int nb = 0;
         if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, (const void*)kern, 256, lds) != hipSuccess || nb < 1)
             nb = 1;
         (void)hipGetLastError();
-        per_cu = nb;
+        pc = nb;
+        per_cu.store(pc, std::memory_order_relaxed);
     }
-    const int64_t cap = (int64_t)num_cu() * per_cu;
+    const int64_t cap = (int64_t)num_cu() * pc;
     if (blocks > cap) blocks = cap;
     (void)hipGetLastError();
     hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(256), lds, stream, net, prop, n, lo, hi,

@@ -63,7 +63,7 @@ class AlphaOpts(C.Structure):
 class ApproxOpts(C.Structure):
     _fields_ = [("trials", C.c_int32), ("samples", C.c_int32), ("confidence", C.c_double),
                 ("seed", C.c_uint64), ("max_splits", C.c_int32), ("grid_bits", C.c_int32),
-                ("resolve_tol", C.c_double), ("leaf", ExactOpts)]
+                ("resolve_tol", C.c_double), ("concurrency", C.c_int32), ("leaf", ExactOpts)]
 
 
 class ApproxResult(C.Structure):
@@ -351,11 +351,19 @@ def count_approx(net: Net, prop: Property, lo, hi, trials: int = 20, samples: in
                  confidence: float = 0.99, seed: int = 0, max_splits: int = 300,
                  grid_bits: int = 16, resolve_tol: float = 0.01, leaf_depth: int = 48,
                  leaf_leaves: int = 1 << 16, chunk: int = 0, workspace=None,
-                 stream=None) -> dict:
+                 stream=None, concurrency: int = 1) -> dict:
+    """CountingProVe with count_exact as the leaf count; ``concurrency`` trials run at once,
+    each on its own stream and workspace slice (the results do not depend on it)."""
+    import torch
     lo = np.ascontiguousarray(lo, np.float64)
     hi = np.ascontiguousarray(hi, np.float64)
+    k = max(1, min(int(concurrency), int(trials)))
+    if workspace is None and k > 1:
+        per = (workspace_size(net, prop, leaf_leaves, samples, 0) + 255) // 256 * 256
+        workspace = torch.empty(k * per, dtype=torch.uint8, device="cuda")
     leaf, ws = _exact_opts(net, prop, leaf_depth, leaf_leaves, chunk, workspace, stream, samples)
     o = ApproxOpts()
+    o.concurrency = int(concurrency)
     o.trials = int(trials)
     o.samples = int(samples)
     o.confidence = float(confidence)

@@ -386,6 +386,40 @@ def test_count_approx_matches_oracle_draws():
     assert g["lower_bound"] <= 1.0 / 6.0       # true volume of {sum x > 2} is 1/6
 
 
+@pytest.mark.parametrize("conc", [2, 5, 8])
+def test_count_approx_concurrent_trials_equal_sequential(conc):
+    """Trials on several streams and threads at once give the sequential run's splits, estimates
+    and bound bit for bit (each trial's draws depend only on the seed, trial and split)."""
+    inst = synth.nav22(0)
+    net, prop = load(inst)
+    kw = dict(trials=8, samples=500, seed=5, max_splits=40, grid_bits=16, resolve_tol=0.02,
+              leaf_depth=36, leaf_leaves=1 << 10)
+    eng = E()
+    a = eng.count_approx(net, prop, inst.lo, inst.hi, **kw)
+    b = eng.count_approx(net, prop, inst.lo, inst.hi, concurrency=conc, **kw)
+    assert a["splits"] == b["splits"]
+    assert a["estimates"] == b["estimates"]
+    assert a["lower_bound"] == b["lower_bound"]
+    assert max(a["splits"]) > 0
+
+
+def test_count_approx_concurrency_rejects_bad_input():
+    import torch
+    inst = synth.nav22(0)
+    net, prop = load(inst)
+    eng = E()
+    kw = dict(trials=4, samples=100, max_splits=2, leaf_depth=8, leaf_leaves=1 << 6)
+    for c in (-1, 65):
+        with pytest.raises(eng.SlrError):
+            eng.count_approx(net, prop, inst.lo, inst.hi, concurrency=c, **kw)
+    # a workspace for one slot is too small for two
+    one = eng.workspace_size(net, prop, 1 << 6, 100, 0)
+    ws = torch.empty(one, dtype=torch.uint8, device="cuda")
+    with pytest.raises(eng.SlrError, match="concurrent"):
+        eng.count_approx(net, prop, inst.lo, inst.hi, concurrency=2, workspace=ws, **kw)
+    eng.count_approx(net, prop, inst.lo, inst.hi, concurrency=1, workspace=ws, **kw)
+
+
 def test_variants_agree_on_bounds_and_classes():
     """Both kernels on the same boxes: raw bounds within float32 rounding, and identical classes
     away from the decision thresholds.  (Their rounding-margin columns differ in precision -- the
