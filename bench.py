@@ -239,14 +239,10 @@ def batch_section(E, torch, seed, reps=3):
             "instances_resolved": sum(1 for r in res if r["undecided"] == 0.0)}
 
 
-APPROX_CONCURRENCY = 8   # trials of the approximate count run at once
-
-
 def approx_section(E, torch, seed, cpu):
     """CountingProVe with SLR leaves on the 22-input network (22-64x3-3, y2 strict argmax,
     [0,1]^22): 20 trials, 1000 samples per split, 99% confidence, leaf counts of depth 48 and
-    2^16 leaves, timed with all trials at once and one at a time (identical results); the FP64
-    oracle on a bounded sample of the same procedure beside it."""
+    2^16 leaves; the FP64 oracle on a bounded sample of the same procedure beside it."""
     import synth
     inst = synth.nav22(seed)
     net = E.Net(inst.net)
@@ -256,11 +252,8 @@ def approx_section(E, torch, seed, cpu):
     E.count_approx(net, prop, inst.lo, inst.hi, **dict(kw, trials=1))
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    r = E.count_approx(net, prop, inst.lo, inst.hi, concurrency=APPROX_CONCURRENCY, **kw)
+    r = E.count_approx(net, prop, inst.lo, inst.hi, **kw)
     dt = time.perf_counter() - t0
-    t0 = time.perf_counter()
-    r1 = E.count_approx(net, prop, inst.lo, inst.hi, **kw)
-    dt1 = time.perf_counter() - t0
     small = dict(kw, trials=1, leaf_leaves=1 << 10, max_splits=12)
     t0 = time.perf_counter()
     rs = E.count_approx(net, prop, inst.lo, inst.hi, **small)
@@ -268,9 +261,7 @@ def approx_section(E, torch, seed, cpu):
     out = {"workload": "count_approx, 22-64x3-3 network (seed %d), [0,1]^22, unsafe iff y2 is the "
                        "strict argmax, 20 trials x 1000 samples, 99%% confidence, <= 300 splits, "
                        "leaves: depth 48, 2^16 leaves, resolved at <= 1%% undecided" % seed,
-           "seconds": dt, "concurrency": APPROX_CONCURRENCY, "seconds_one_at_a_time": dt1,
-           "identical_to_one_at_a_time": (r["estimates"] == r1["estimates"]
-                                          and r["splits"] == r1["splits"]),
+           "seconds": dt,
            "lower_bound": r["lower_bound"],
            "mean_estimate": sum(r["estimates"]) / len(r["estimates"]),
            "splits": r["splits"],

@@ -195,13 +195,10 @@ typedef struct {
     int32_t max_splits;      /* cap on splits per trial                                    */
     int32_t grid_bits;       /* split points lie on the grid lo + k (hi - lo) 2^-grid_bits  */
     double resolve_tol;      /* a subdomain is resolved when <= this fraction is undecided  */
-    /* trials run at once (0 or 1: one after another on leaf.stream).  With k > 1, k slots each
-       run whole trials: slot 0 on the calling thread and leaf.stream, the others on worker
-       threads with streams of their own that first wait for the work queued on leaf.stream;
-       slot i uses bytes [i P, (i + 1) P) of leaf.workspace, P = workspace_size(...) rounded up
-       to a multiple of 256, so the workspace must hold k P bytes (SLR_ENOMEM otherwise).
-       Results are identical for every k (each trial's draws depend only on the seed, the trial
-       and the split); a leaf trace needs k <= 1.  At most 64. */
+    /* trials run at once: 0 or 1 (one after another on leaf.stream).  Larger values are
+       reserved and rejected with SLR_EUNSUPPORTED: a threaded form (one stream and workspace
+       slice per slot) gave identical results but crashed once inside hipEventRecord under a
+       kernel-trace profiler, with no cause found in this library.  Other values: SLR_EINVAL. */
     int32_t concurrency;
     slr_exact_opts leaf;     /* options (and workspace) of each leaf count                  */
 } slr_approx_opts;
@@ -218,8 +215,7 @@ typedef struct {
  * count_approx: probabilistic lower bound on the violation rate.  Each trial halves the
  * domain (at the lower median of the violating samples along a random dimension, keeping a
  * random side) until count_exact resolves the subdomain; see the implementation file for the
- * exact draw layout.  Synchronizes opts->leaf.stream (and every stream it creates for
- * concurrent trials) before returning.
+ * exact draw layout.  Synchronizes opts->leaf.stream.
  */
 int count_approx(const slr_net* net, const slr_property* prop, const double* lo,
                  const double* hi, const slr_approx_opts* opts, slr_approx_result* out);

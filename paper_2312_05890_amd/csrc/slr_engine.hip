@@ -6,15 +6,12 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
-#include <atomic>
 #include <chrono>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
-#include <mutex>
 #include <string>
-#include <thread>
 #include <vector>
 
 namespace {
@@ -1352,81 +1349,6 @@ int approx_trial(const slr_net* net, const slr_property* prop, const double* lo,
     return SLR_OK;
 }
 
-// Trials on `conc` slots at once: slot 0 on the calling thread and opts->leaf.stream, slot k > 0
-// on a worker thread with a stream of its own (default priority) that first waits for the work
-// already queued on opts->leaf.stream.  Slot k uses bytes [k per, (k + 1) per) of the workspace.
-// Trials are taken in order from a shared counter; the first error stops the other slots after
-// their current trial and is reported with its message.
-int approx_concurrent(const slr_net* net, const slr_property* prop, const double* lo,
-                      const double* hi, const slr_approx_opts& o, int conc, size_t per,
-                      slr_approx_result* out) {
-    int dev = 0;
-    HIP_TRY(hipGetDevice(&dev), "count_approx: device");
-    hipStream_t s0 = (hipStream_t)o.leaf.stream;
-    hipEvent_t ready = nullptr;
-    HIP_TRY(hipEventCreateWithFlags(&ready, hipEventDisableTiming), "count_approx: event");
-    std::vector<hipStream_t> streams(conc, nullptr);
-    streams[0] = s0;
-    int rc = SLR_OK;
-    hipError_t e = hipEventRecord(ready, s0);
-    for (int k = 1; k < conc && e == hipSuccess; ++k) {
-        e = hipStreamCreateWithFlags(&streams[k], hipStreamNonBlocking);
-        if (e == hipSuccess) e = hipStreamWaitEvent(streams[k], ready, 0);
-    }
-    if (e != hipSuccess) rc = hip_fail(e, "count_approx: streams");
-    std::atomic<int> next{0};
-    std::atomic<int> err{SLR_OK};
-    std::mutex mu;
-    std::string msg;
-    auto slot = [&](int k) {
-        if (k > 0 && hipSetDevice(dev) != hipSuccess) {
-            std::lock_guard<std::mutex> g(mu);
-            if (err.load() == SLR_OK) {
-                msg = "count_approx: worker thread could not select the device";
-                err.store(SLR_EHIP);
-            }
-            return;
-        }
-        slr_exact_opts leaf = o.leaf;
-        leaf.workspace = (char*)o.leaf.workspace + (size_t)k * per;
-        leaf.workspace_bytes = per;
-        leaf.stream = streams[k];
-        Workspace w;
-        int r = check_exact_opts(net, prop, &leaf, o.samples, &w, "count_approx");
-        while (r == SLR_OK && err.load() == SLR_OK) {
-            const int t = next.fetch_add(1);
-            if (t >= o.trials) break;
-            r = approx_trial(net, prop, lo, hi, o, leaf, w, t, &out->estimate[t], &out->splits[t]);
-        }
-        if (r < 0) {
-            (void)hipStreamSynchronize(streams[k]);
-            std::lock_guard<std::mutex> g(mu);
-            if (err.load() == SLR_OK) {
-                msg = g_err;
-                err.store(r);
-            }
-        }
-    };
-    if (rc == SLR_OK) {
-        std::vector<std::thread> workers;
-        for (int k = 1; k < conc; ++k) workers.emplace_back(slot, k);
-        slot(0);
-        for (auto& th : workers) th.join();
-    }
-    for (int k = 1; k < conc; ++k)
-        if (streams[k]) {
-            (void)hipStreamSynchronize(streams[k]);
-            (void)hipStreamDestroy(streams[k]);
-        }
-    (void)hipEventDestroy(ready);
-    if (rc != SLR_OK) return rc;
-    if (err.load() != SLR_OK) {
-        g_err = msg;
-        return err.load();
-    }
-    return SLR_OK;
-}
-
 }  // namespace
 
 extern "C" int count_approx(const slr_net* net, const slr_property* prop, const double* lo,
@@ -1444,26 +1366,16 @@ extern "C" int count_approx(const slr_net* net, const slr_property* prop, const 
     if (o.grid_bits < 1 || o.grid_bits > 20) return fail(SLR_EINVAL, "count_approx: grid_bits must be in [1, 20]");
     if (!(o.resolve_tol >= 0.0)) return fail(SLR_EINVAL, "count_approx: resolve_tol must be >= 0");
     if (o.concurrency < 0 || o.concurrency > 64) return fail(SLR_EINVAL, "count_approx: concurrency must be in [0, 64]");
-    const int conc = std::max(1, std::min(o.concurrency, o.trials));
-    if (conc > 1 && o.leaf.trace_capacity > 0)
-        return fail(SLR_EINVAL, "count_approx: a leaf trace needs concurrency <= 1");
+    if (o.concurrency > 1)
+        return fail(SLR_EUNSUPPORTED, "count_approx: concurrent trials are disabled (a profiled run of "
+                    "the threaded form crashed inside hipEventRecord; cause not found); use 0 or 1");
     Workspace w;
     if ((rc = check_exact_opts(net, prop, &o.leaf, o.samples, &w, "count_approx"))) return rc;
-    const int64_t achunk = o.leaf.alpha_steps > 0 ? o.leaf.alpha_chunk : 0;
-    const size_t per = (layout_ws(nullptr, net->dev, prop->dev, o.leaf.max_leaves, o.samples, achunk).bytes + 255) &
-                       ~(size_t)255;
-    if (conc > 1 && o.leaf.workspace_bytes < per * (size_t)conc)
-        return fail(SLR_ENOMEM, "count_approx: workspace of %zu bytes is smaller than the %zu required for "
-                    "%d concurrent trials", o.leaf.workspace_bytes, per * (size_t)conc, conc);
     memset(out, 0, sizeof *out);
     const auto t0 = std::chrono::steady_clock::now();
-    if (conc == 1) {
-        for (int t = 0; t < o.trials; ++t)
-            if ((rc = approx_trial(net, prop, lo, hi, o, o.leaf, w, t, &out->estimate[t], &out->splits[t])) < 0)
-                return rc;
-    } else if ((rc = approx_concurrent(net, prop, lo, hi, o, conc, per, out)) < 0) {
-        return rc;
-    }
+    for (int t = 0; t < o.trials; ++t)
+        if ((rc = approx_trial(net, prop, lo, hi, o, o.leaf, w, t, &out->estimate[t], &out->splits[t])) < 0)
+            return rc;
     double best = INFINITY;
     for (int t = 0; t < o.trials; ++t) best = std::min(best, out->estimate[t]);
     const double beta = std::log2(1.0 / (1.0 - o.confidence)) / o.trials;

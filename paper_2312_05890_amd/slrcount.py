@@ -352,15 +352,10 @@ def count_approx(net: Net, prop: Property, lo, hi, trials: int = 20, samples: in
                  grid_bits: int = 16, resolve_tol: float = 0.01, leaf_depth: int = 48,
                  leaf_leaves: int = 1 << 16, chunk: int = 0, workspace=None,
                  stream=None, concurrency: int = 1) -> dict:
-    """CountingProVe with count_exact as the leaf count; ``concurrency`` trials run at once,
-    each on its own stream and workspace slice (the results do not depend on it)."""
-    import torch
+    """CountingProVe with count_exact as the leaf count.  ``concurrency`` must be 0 or 1 (the
+    trials run one after another; larger values are rejected, see ``slr_approx_opts``)."""
     lo = np.ascontiguousarray(lo, np.float64)
     hi = np.ascontiguousarray(hi, np.float64)
-    k = max(1, min(int(concurrency), int(trials)))
-    if workspace is None and k > 1:
-        per = (workspace_size(net, prop, leaf_leaves, samples, 0) + 255) // 256 * 256
-        workspace = torch.empty(k * per, dtype=torch.uint8, device="cuda")
     leaf, ws = _exact_opts(net, prop, leaf_depth, leaf_leaves, chunk, workspace, stream, samples)
     o = ApproxOpts()
     o.concurrency = int(concurrency)

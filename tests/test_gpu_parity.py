@@ -386,6 +386,8 @@ def test_count_approx_matches_oracle_draws():
     assert g["lower_bound"] <= 1.0 / 6.0       # true volume of {sum x > 2} is 1/6
 
 
+@pytest.mark.skip(reason="concurrent trials are disabled in the library: a profiled run of the "
+                         "threaded form crashed inside hipEventRecord and no cause was found")
 @pytest.mark.parametrize("conc", [2, 5, 8])
 def test_count_approx_concurrent_trials_equal_sequential(conc):
     """Trials on several streams and threads at once give the sequential run's splits, estimates
@@ -410,14 +412,16 @@ def test_count_approx_concurrency_rejects_bad_input():
     eng = E()
     kw = dict(trials=4, samples=100, max_splits=2, leaf_depth=8, leaf_leaves=1 << 6)
     for c in (-1, 65):
-        with pytest.raises(eng.SlrError):
+        with pytest.raises(eng.SlrError) as e:
             eng.count_approx(net, prop, inst.lo, inst.hi, concurrency=c, **kw)
-    # a workspace for one slot is too small for two
+        assert e.value.code == -1                          # SLR_EINVAL
+    with pytest.raises(eng.SlrError, match="disabled") as e:
+        eng.count_approx(net, prop, inst.lo, inst.hi, concurrency=2, **kw)
+    assert e.value.code == -5                              # SLR_EUNSUPPORTED
     one = eng.workspace_size(net, prop, 1 << 6, 100, 0)
     ws = torch.empty(one, dtype=torch.uint8, device="cuda")
-    with pytest.raises(eng.SlrError, match="concurrent"):
-        eng.count_approx(net, prop, inst.lo, inst.hi, concurrency=2, workspace=ws, **kw)
-    eng.count_approx(net, prop, inst.lo, inst.hi, concurrency=1, workspace=ws, **kw)
+    for c in (0, 1):
+        eng.count_approx(net, prop, inst.lo, inst.hi, concurrency=c, workspace=ws, **kw)
 
 
 def test_variants_agree_on_bounds_and_classes():
