@@ -876,14 +876,23 @@ __device__ __forceinline__ void split_tile_impl(int64_t n, int d, const int8_t* 
         const int p = pidx[r];
         const float* l = rlo + p * d;
         const float* h = rhi + p * d;
+        // widest side, lowest index on ties; widths are loaded eight at a time (indices clamped
+        // into the row, so every load is in bounds and none waits on the comparison before it)
         int js = 0;
         float wbest = h[0] - l[0];
-        for (int k = 1; k < d; ++k) {
-            const float w = h[k] - l[k];
-            if (w > wbest) {
-                wbest = w;
-                js = k;
+        for (int k0 = 1; k0 < d; k0 += 8) {
+            float wv[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int kk = min(k0 + u, d - 1);
+                wv[u] = h[kk] - l[kk];
             }
+#pragma unroll
+            for (int u = 0; u < 8; ++u)
+                if (k0 + u < d && wv[u] > wbest) {
+                    wbest = wv[u];
+                    js = k0 + u;
+                }
         }
         const float m = 0.5f * (l[js] + h[js]);
         if (!(m - l[js] == h[js] - m && l[js] < m && m < h[js])) atomicOr(err, 1u);
@@ -900,15 +909,33 @@ __device__ __forceinline__ void split_tile_impl(int64_t n, int d, const int8_t* 
     float* olo = lo2 + 2 * base_out * d;
     float* ohi = hi2 + 2 * base_out * d;
     const int m = 2 * npairs * d;
-    for (int e = tid; e < m; e += 256) {
-        const int c = e / d, k = e - c * d;
-        const int r = c >> 1, side = c & 1;
-        const int p = pidx[r];
-        const bool cut = k == jsel[r];
-        const float mv = mval[r];
-        const float lv = rlo[p * d + k], hv = rhi[p * d + k];
-        olo[e] = cut && side ? mv : lv;
-        ohi[e] = cut && !side ? mv : hv;
+    // four elements per thread and pass, all loads before the stores (indices clamped into the
+    // run, so every load is in bounds); without staging the parents' corners come from global
+    // memory and a load-store chain per element would wait out one memory latency each
+    for (int e0 = tid; e0 < m; e0 += 256 * 4) {
+        float lv[4], hv[4], mv[4];
+        bool cl[4], ch[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int e = min(e0 + 256 * u, m - 1);
+            const int c = e / d, k = e - c * d;
+            const int r = c >> 1, side = c & 1;
+            const int p = pidx[r];
+            const bool cut = k == jsel[r];
+            mv[u] = mval[r];
+            cl[u] = cut && side;
+            ch[u] = cut && !side;
+            lv[u] = rlo[p * d + k];
+            hv[u] = rhi[p * d + k];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int e = e0 + 256 * u;
+            if (e < m) {
+                olo[e] = cl[u] ? mv[u] : lv[u];
+                ohi[e] = ch[u] ? mv[u] : hv[u];
+            }
+        }
     }
 }
 
