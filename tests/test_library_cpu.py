@@ -96,3 +96,35 @@ def test_tile_shape_validation_and_cache_roundtrip(tmp_path):
     autotune.save([{"key": "d5_mt4", "d": 5, "mt_max": 4, "best": [1, 1, 8]}], str(p))
     assert autotune.load(str(p)) == 1
     E.bound_tile_shape(5, 4, 0, 0, 0)
+
+
+@pytest.mark.parametrize("cname,pyname", [("slr_exact_opts", "ExactOpts"),
+                                          ("slr_count_result", "CountResult"),
+                                          ("slr_alpha_opts", "AlphaOpts"),
+                                          ("slr_approx_opts", "ApproxOpts"),
+                                          ("slr_approx_result", "ApproxResult")])
+def test_binding_structs_match_the_header_layout(tmp_path, cname, pyname):
+    """Every option and result struct of the binding has the header's size and field offsets
+    (a probe compiled against include/slrcount.h with the host C compiler)."""
+    import shutil
+    import subprocess
+    from paper_2312_05890_amd import slrcount
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no host C compiler")
+    py = getattr(slrcount, pyname)
+    fields = [f[0] for f in py._fields_]
+    lines = ['#include <stddef.h>', '#include <stdio.h>', '#include "slrcount.h"', 'int main(void) {',
+             '    printf("size %%zu\\n", sizeof(%s));' % cname]
+    lines += ['    printf("%s %%zu\\n", offsetof(%s, %s));' % (f, cname, f) for f in fields]
+    lines += ['    return 0;', '}']
+    src = tmp_path / "probe.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "probe"
+    subprocess.run([cc, "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)],
+                   check=True, capture_output=True)
+    out = dict(line.split() for line in subprocess.run([str(exe)], check=True, capture_output=True,
+                                                        text=True).stdout.splitlines())
+    assert int(out["size"]) == C.sizeof(py)
+    for f in fields:
+        assert int(out[f]) == getattr(py, f).offset, f
