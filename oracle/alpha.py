@@ -136,6 +136,22 @@ def objective(net, C, dvec, lo, hi, alpha):
     return np.where(mode == 1, -g_lo.min(axis=1), g_hi[np.arange(g_hi.shape[0]), row])
 
 
+def adam_step(a, g, m, v, t, lr, betas, eps):
+    """One projected Adam step (Kingma and Ba, Algorithm 1) on ``a`` in place.
+
+    First and second moment estimates with bias correction 1 - beta^t (t counts from 1),
+    step lr * m_hat / (sqrt(v_hat) + eps) against the gradient, then projection onto [0, 1].
+    Returns the new moments.
+    """
+    m = betas[0] * m + (1 - betas[0]) * g
+    v = betas[1] * v + (1 - betas[1]) * g * g
+    mh = m / (1 - betas[0] ** t)
+    vh = v / (1 - betas[1] ** t)
+    a -= lr * mh / (vh.sqrt() + eps)
+    a.clamp_(0.0, 1.0)
+    return m, v
+
+
 def optimize(net, C, dvec, lo, hi, steps=20, lr=0.1, betas=(0.9, 0.999), eps=1e-8):
     """Projected Adam from alpha = lam; returns (best alpha, best J) per box."""
     torch = _torch()
@@ -154,13 +170,7 @@ def optimize(net, C, dvec, lo, hi, steps=20, lr=0.1, betas=(0.9, 0.999), eps=1e-
         a.grad = None
         J.sum().backward()
         with torch.no_grad():
-            g = a.grad
-            m = betas[0] * m + (1 - betas[0]) * g
-            v = betas[1] * v + (1 - betas[1]) * g * g
-            mh = m / (1 - betas[0] ** t)
-            vh = v / (1 - betas[1] ** t)
-            a -= lr * mh / (vh.sqrt() + eps)
-            a.clamp_(0.0, 1.0)
+            m, v = adam_step(a, a.grad, m, v, t, lr, betas, eps)
     g_lo, g_hi = forward_torch(net, C, dvec, lo, hi, a)
     J = objective_torch(g_lo, g_hi, mode, row).detach()
     better = J < best_j

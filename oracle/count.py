@@ -140,7 +140,7 @@ def snap_split(med: float, a: float, b: float, A: float, B: float, grid_bits: in
     steps is bisected at its midpoint instead.
     """
     h = (B - A) * 2.0 ** -grid_bits
-    if b - a < 2.0 * h:
+    if b - a < 2.0 * h or h <= 0.0:
         return 0.5 * (a + b)
     k = math.floor((med - A) / h + 0.5)
     k_lo = math.floor((a - A) / h + 0.5) + 1
@@ -171,8 +171,10 @@ def count_approx(net, C, dvec, lo, hi, trials: int = 20, samples: int = 1000,
             pts = (slo + u * (shi - slo)).astype(np.float32).astype(np.float64)
             viol = np.all(slr.property_values(net, C, dvec, pts) > 0.0, axis=1)
             dim, side = philox.split_choice(seed, t, s, d)
-            # the drawn side is already as narrow as two grid steps: the trial stops here
-            if float(shi[dim]) - float(slo[dim]) < 2.0 * (float(hi[dim]) - float(lo[dim])) * 2.0 ** -grid_bits:
+            # the drawn side is already as narrow as two grid steps (or has no width at all,
+            # a degenerate side of the domain): the trial stops here
+            side_w = float(shi[dim]) - float(slo[dim])
+            if side_w < 2.0 * (float(hi[dim]) - float(lo[dim])) * 2.0 ** -grid_bits or side_w <= 0.0:
                 break
             vals = pts[viol, dim] if viol.any() else pts[:, dim]
             med = float(np.sort(vals)[(vals.shape[0] - 1) // 2])

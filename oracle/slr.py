@@ -210,6 +210,21 @@ def classify(g_lo: np.ndarray, g_hi: np.ndarray) -> np.ndarray:
     return cls
 
 
+def decision_margin(g_lo: np.ndarray, g_hi: np.ndarray) -> np.ndarray:
+    """How far each box's bounds are from changing its ``classify`` decision.
+
+    Unsafe: the smallest row lower bound (it must not reach 0).  Safe: the most negative row
+    upper bound, negated (the deciding row must stay <= 0).  Undecided: the smaller of the
+    largest negated row lower bound (every row's lower bound must pass 0 to become unsafe)
+    and the smallest row upper bound (one row's upper bound reaching 0 makes it safe).
+    """
+    cls = classify(g_lo, g_hi)
+    m_unsafe = g_lo.min(axis=1)
+    m_safe = (-g_hi).max(axis=1)
+    m_und = np.minimum((-g_lo).max(axis=1), g_hi.min(axis=1))
+    return np.where(cls == 1, m_unsafe, np.where(cls == 2, m_safe, m_und))
+
+
 def forward(net, x: np.ndarray) -> np.ndarray:
     """Concrete FP64 forward pass; ``x`` [N, d] -> outputs [N, n_out]."""
     h = np.asarray(x, np.float64)

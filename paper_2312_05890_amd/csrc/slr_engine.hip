@@ -1277,7 +1277,7 @@ extern "C" int count_exact(const slr_net* net, const slr_property* prop, const d
 // intervals narrower than two steps are bisected at the midpoint.
 static double snap_split(double med, double a, double b, double A, double B, int bits) {
     const double h = (B - A) * std::ldexp(1.0, -bits);
-    if (b - a < 2.0 * h) return 0.5 * (a + b);
+    if (b - a < 2.0 * h || h <= 0.0) return 0.5 * (a + b);
     double k = std::floor((med - A) / h + 0.5);
     const double k_lo = std::floor((a - A) / h + 0.5) + 1;
     const double k_hi = std::floor((b - A) / h + 0.5) - 1;
@@ -1328,7 +1328,9 @@ int approx_trial(const slr_net* net, const slr_property* prop, const double* lo,
         const int side = (int)(sw[1] & 1u);
         // a side as narrow as two grid steps is not split further: the trial stops here (the
         // bound holds for any stopping rule; this keeps every leaf bisection exact in float32)
-        if (shi[dim] - slo[dim] < 2.0 * (hi[dim] - lo[dim]) * std::ldexp(1.0, -o.grid_bits)) break;
+        // (a side of zero width, a degenerate side of the domain, stops it too)
+        const double side_w = shi[dim] - slo[dim];
+        if (side_w < 2.0 * (hi[dim] - lo[dim]) * std::ldexp(1.0, -o.grid_bits) || side_w <= 0.0) break;
         coords.clear();
         for (int p = 0; p < o.samples; ++p)
             if (viol[p]) coords.push_back(pts[(size_t)p * d + dim]);

@@ -225,5 +225,68 @@ def pin_accounting(seed=1):
             assert np.all(lev["path"] >> np.uint64(t) == 1)
 
 
+def scaled_relu_net(w_out):
+    """x in [-1, 1] -> z = x -> y = w_out * ReLU(z) (one crossing neuron, lam = 1/2)."""
+    return [(_f32([[1.0]]), _f32([0.0])), (_f32([[w_out]]), _f32([0.0]))]
+
+
+def pin_alpha_adam_closed_form():
+    """Alpha optimizer on one crossing neuron, derived by hand.
+
+    With y = -2 ReLU(x) on [-1, 1] and the row g = y - 0.1, the centre value is -0.1 (not
+    unsafe), so the objective is g_hi.  The lower line alpha*x of the ReLU meets the negative
+    output weight, so g_hi = max_x(-2 alpha x) - 0.1 = 2 alpha - 0.1: dJ/dalpha = 2 for every
+    alpha > 0.  With a constant gradient Adam's bias-corrected moments are m_hat = 2 and
+    v_hat = 4 at every step, so each step moves alpha by lr * 2 / (2 + eps) against the
+    gradient: from lam = 1/2, three steps of lr = 0.1 end at alpha = 0.2, J = 0.3.
+    The mirrored case y = +2 ReLU(x), g = y + 0.1 has an unsafe centre (0.1 > 0), objective
+    -g_lo = -(min_x 2 alpha x + 0.1) = 2 alpha - 0.1, and the same trajectory.
+    """
+    from oracle import alpha as A
+    step = 0.1 * 2.0 / (2.0 + 1e-8)
+    for w_out, dv, mode in ((-2.0, -0.1, 0), (2.0, 0.1, 1)):
+        net = scaled_relu_net(w_out)
+        lo, hi = np.array([[-1.0]]), np.array([[1.0]])
+        m, r = A.objective_weights(net, [[1.0]], [dv], lo, hi)
+        assert m[0] == mode and r[0] == 0
+        assert abs(A.plain_lambda(net, [[1.0]], [dv], lo, hi)[0, 0] - 0.5) < 1e-15
+        g = A.gradient(net, [[1.0]], [dv], lo, hi, np.array([[0.5]]))
+        assert abs(g[0, 0] - 2.0) < 1e-12
+        for steps in (1, 3):
+            best, jb = A.optimize(net, [[1.0]], [dv], lo, hi, steps=steps, lr=0.1)
+            assert abs(best[0, 0] - (0.5 - steps * step)) < 1e-12, (steps, best)
+            assert abs(jb[0] - (2.0 * (0.5 - steps * step) - 0.1)) < 1e-12, (steps, jb)
+        # past alpha = 0 the projection holds it there: J = -0.1 is the least objective
+        best, jb = A.optimize(net, [[1.0]], [dv], lo, hi, steps=8, lr=0.1)
+        assert best[0, 0] == 0.0 and abs(jb[0] + 0.1) < 1e-12
+
+
+def pin_alpha_objective_row():
+    """The objective row is the property row with the smallest centre value.
+
+    y = ReLU(x) on [-1, 1] with rows g0 = y + 0.5 and g1 = -y - 0.5: at the centre g0 = 0.5
+    and g1 = -0.5, so the box is not unsafe there and the objective is g1_hi.  g1's upper
+    bound uses the ReLU's lower line: g1_hi = max_x(-alpha x) - 0.5 = alpha - 0.5, gradient 1,
+    while g0_hi = 1.5 does not depend on alpha.  Three Adam steps of lr = 0.1 from lam = 1/2
+    give alpha = 0.2; optimizing row 0 (or the unsafe-mode objective, whose min over rows is
+    g1_lo = -1.5 for every alpha) would leave alpha at 1/2.
+    """
+    from oracle import alpha as A
+    net = scaled_relu_net(1.0)
+    C = [[1.0], [-1.0]]
+    dv = [0.5, -0.5]
+    lo, hi = np.array([[-1.0]]), np.array([[1.0]])
+    m, r = A.objective_weights(net, C, dv, lo, hi)
+    assert m[0] == 0 and r[0] == 1
+    best, jb = A.optimize(net, C, dv, lo, hi, steps=3, lr=0.1)
+    step = 0.1 / (1.0 + 1e-8)
+    assert abs(best[0, 0] - (0.5 - 3 * step)) < 1e-12, best
+    assert abs(jb[0] - (0.5 - 3 * step - 0.5)) < 1e-12, jb
+    # both rows positive at the centre: unsafe mode, J = -min_r g_lo_r
+    m, r = A.objective_weights(net, C, [0.5, 0.5], lo, hi)
+    assert m[0] == 1
+
+
 ALL_PINS = [pin_eq1_single_relu, pin_two_neurons, pin_linear_regime, pin_soundness,
-            pin_irwin_hall, pin_abs_closed_form, pin_dense_grid, pin_accounting]
+            pin_irwin_hall, pin_abs_closed_form, pin_dense_grid, pin_accounting,
+            pin_alpha_adam_closed_form, pin_alpha_objective_row]

@@ -221,8 +221,32 @@ def test_optimize_close_to_oracle_adam():
     j_plain = oalpha.objective(inst.net, inst.C, inst.dvec, lo, hi, lam)
     gain_ref = j_plain - j_ref
     gain_gpu = j_plain - j_gpu
+    assert gain_ref.sum() > 0 and np.sum(gain_ref > 0) >= 4
     assert np.all(gain_gpu >= -1e-4 * np.maximum(1, np.abs(j_plain)))
     assert gain_gpu.sum() >= 0.5 * gain_ref.sum()
+
+
+@pytest.mark.parametrize("w_out,dv,rows", [(-2.0, [-0.1], [[1.0]]), (2.0, [0.1], [[1.0]]),
+                                           (1.0, [0.5, -0.5], [[1.0], [-1.0]])],
+                         ids=["safe-mode", "unsafe-mode", "two-rows"])
+@pytest.mark.parametrize("steps", [1, 3, 8])
+def test_optimize_hand_derived_trajectory(w_out, dv, rows, steps):
+    """One crossing neuron y = w ReLU(x) on [-1, 1] (lam = 1/2) with an objective whose
+    gradient in alpha is the constant |w| (the oracle pins derive it): every bias-corrected Adam
+    step moves alpha by lr against the gradient, projected onto [0, 1], so the last slope is
+    max(0, 1/2 - 0.1 steps); the float64 reference Adam lands on the same slope."""
+    from tests import oracle_pins as P
+    net_l = P.scaled_relu_net(w_out)
+    eng = E()
+    net = eng.Net(net_l)
+    prop = eng.Property(net, np.asarray(rows, np.float32), np.asarray(dv, np.float32))
+    lo, hi = np.array([[-1.0]]), np.array([[1.0]])
+    r = eng.alpha_optimize(net, prop, dev(lo), dev(hi), steps=steps, raw=True)
+    a_gpu = float(r["alpha"].cpu().numpy()[0, 0])
+    a_ref, _ = oalpha.optimize(net_l, rows, dv, lo, hi, steps=steps)
+    expect = max(0.0, 0.5 - 0.1 * steps)
+    assert abs(a_gpu - expect) <= 1e-6, (a_gpu, expect)
+    assert abs(a_ref[0, 0] - expect) <= 1e-7
 
 
 @pytest.mark.parametrize("n", [0, 1, 17, 33])

@@ -8,6 +8,8 @@ unrelated device work and synchronizations between the replays.
 """
 from __future__ import annotations
 
+import dataclasses
+
 import numpy as np
 import pytest
 
@@ -75,6 +77,51 @@ def test_batch_graph_replays_agree():
         assert same(r, q)
 
 
+def _one_per_shape(side_log2):
+    """The first instance of the 256-instance generator (seed 0) for every pair (inputs d,
+    hidden width), 6 x 4 = 24 instances covering every column class and width of the batch.
+    Each is restricted to a dyadic sub-box of side 2^-side_log2 at a corner drawn from
+    default_rng(instance index): on the whole unit cube these deep random networks decide no
+    box within a small leaf budget, on such sub-boxes they decide unsafe and safe boxes."""
+    seen = {}
+    for i, inst in enumerate(synth.batch(0)):
+        seen.setdefault((inst.sizes[0], inst.sizes[1]), (i, inst))
+    out = []
+    for k in sorted(seen):
+        i, inst = seen[k]
+        d = inst.sizes[0]
+        c = np.floor(np.random.default_rng(i).uniform(0, 1, size=d) * 2 ** side_log2)
+        c = c / 2 ** side_log2
+        out.append(dataclasses.replace(inst, name=f"batch{i}-d{d}w{inst.sizes[1]}",
+                                       lo=c, hi=c + 2.0 ** -side_log2))
+    return out
+
+
+@pytest.mark.parametrize("side_log2", [4, 5])
+def test_batch_of_all_shapes_equals_oracle(side_log2):
+    """Every (inputs, width) shape of the batch workload, on a 2^-4 and a 2^-5 sub-box, at depth
+    4 d with a 2^11-leaf budget: ``count_exact`` is compared box by box with the oracle
+    (matched on depth and path id, classes equal wherever the oracle's margin exceeds 1e-5,
+    identical leaf counts and volumes unless such a box explains the difference), and the same
+    instances run as one batch give the oracle's counts and volumes exactly (or differ in unsafe
+    volume by at most the volume of the boxes that explain a difference)."""
+    from tests.test_gpu_parity import compare_counts
+    insts = _one_per_shape(side_log2)
+    items = items_of(insts, leaves=1 << 11)
+    res = E().Batch(items).run()
+    decided = 0
+    for inst, it, r in zip(insts, items, res):
+        _, o, diverge = compare_counts(inst, it[4], it[5])
+        decided += o["n_unsafe"] + o["n_safe"]
+        if not diverge:
+            for k in ("n_unsafe", "n_safe", "n_undecided", "n_boxes_bounded", "depth_reached",
+                      "status", "unsafe", "safe", "undecided"):
+                assert r[k] == o[k], (inst.name, k, r[k], o[k])
+        else:
+            assert abs(r["unsafe"] - o["unsafe"]) <= sum(2.0 ** -k[0] for k in diverge)
+    assert decided > 1000
+
+
 def test_batch_mixed_shapes_and_budgets_against_oracle():
     insts = [synth.tiny2d(0), synth.tiny2d(3), synth.acas(1)] + synth.batch(2, count=3)
     depth = [12, 10, 30, 12, 14, 16]
@@ -85,13 +132,16 @@ def test_batch_mixed_shapes_and_budgets_against_oracle():
         net = eng.Net(inst.net)
         items.append((net, eng.Property(net, inst.C, inst.dvec), inst.lo, inst.hi, D, M))
     res = eng.Batch(items).run()
+    from tests.test_gpu_parity import compare_counts
     for inst, it, r in zip(insts, items, res):
         assert same(r, single(it))
-        o = count.count_exact(inst.net, inst.C, inst.dvec, inst.lo, inst.hi, it[4], it[5])
-        # the single-instance path equals the oracle unless a box within 1e-5 of a decision
-        # is classified differently (checked box by box in the parity tests); here: brackets
-        assert abs(r["unsafe"] - o["unsafe"]) <= 2.0 ** -8
-        assert r["depth_reached"] <= it[4]
+        _, o, diverge = compare_counts(inst, it[4], it[5])
+        if not diverge:
+            for k in ("n_unsafe", "n_safe", "n_undecided", "n_boxes_bounded", "unsafe",
+                      "safe", "undecided", "depth_reached", "status"):
+                assert r[k] == o[k], (inst.name, k, r[k], o[k])
+        else:
+            assert abs(r["unsafe"] - o["unsafe"]) <= sum(2.0 ** -k[0] for k in diverge)
 
 
 def test_batch_full_config_counts():

@@ -7,6 +7,7 @@ import numpy as np
 import pytest
 
 import synth
+from oracle import alpha as alpha_oracle
 from oracle import count, philox, slr
 from tests import oracle_pins as P
 
@@ -100,6 +101,23 @@ def test_count_approx_lower_bound_closed_form():
     assert all(e >= 0 for e in r["estimates"])
 
 
+def test_count_approx_zero_width_side():
+    """A domain with one side of zero width (x2 = 1/2 fixed): the rate is that of the 2-d
+    slice, x0 + x1 > 3/2, i.e. 1/8.  A trial that draws the fixed side cannot split it and
+    stops there (a grid step of zero would divide by zero); the others split as usual."""
+    net = [(np.eye(3, dtype=np.float32), np.zeros(3, np.float32)),
+           (np.array([[1, 1, 1]], np.float32), np.array([-2.0], np.float32))]
+    lo, hi = np.array([0.0, 0.0, 0.5]), np.array([1.0, 1.0, 0.5])
+    r = count.count_approx(net, [[1.0]], [0.0], lo, hi, trials=8, samples=200, seed=11,
+                           leaf_depth=14, leaf_leaves=1 << 10, resolve_tol=0.0, max_splits=20)
+    assert 0.0 <= r["lower_bound"] <= 0.125
+    assert all(np.isfinite(r["estimates"]))
+    # every trial ends before its split cap: on the first draw of the fixed side
+    assert max(r["splits"]) < 20 and len(set(r["splits"])) > 1
+    for t in r["trials"]:
+        assert t["lo"][2] == 0.5 and t["hi"][2] == 0.5
+
+
 @pytest.mark.parametrize("weights,bias,d,vr", [
     ([1, 1], -1.0, 2, Fraction(1, 2)),          # x0 + x1 > 1 on the unit square
     ([1, 1, 1], -2.0, 3, Fraction(1, 6)),       # the corner simplex x0 + x1 + x2 > 2
@@ -190,6 +208,35 @@ def _exact_sum_off_by_one(hist):
     return sum((Fraction(int(n), 1 << (t + 1)) for t, n in enumerate(hist)), Fraction(0))
 
 
+def _adam_step_ascends(a, g, m, v, t, lr, betas, eps):
+    """Adam step taken along the gradient instead of against it."""
+    m = betas[0] * m + (1 - betas[0]) * g
+    v = betas[1] * v + (1 - betas[1]) * g * g
+    a += lr * (m / (1 - betas[0] ** t)) / ((v / (1 - betas[1] ** t)).sqrt() + eps)
+    a.clamp_(0.0, 1.0)
+    return m, v
+
+
+def _adam_step_no_bias_correction(a, g, m, v, t, lr, betas, eps):
+    m = betas[0] * m + (1 - betas[0]) * g
+    v = betas[1] * v + (1 - betas[1]) * g * g
+    a -= lr * m / (v.sqrt() + eps)
+    a.clamp_(0.0, 1.0)
+    return m, v
+
+
+def _objective_row_argmax(net, C, dvec, lo, hi):
+    center = 0.5 * (np.asarray(lo, np.float64) + np.asarray(hi, np.float64))
+    gc = slr.property_values(net, C, dvec, center)
+    return np.all(gc > 0, axis=1).astype(np.int64), np.argmax(gc, axis=1)
+
+
+def _objective_mode_any(net, C, dvec, lo, hi):
+    center = 0.5 * (np.asarray(lo, np.float64) + np.asarray(hi, np.float64))
+    gc = slr.property_values(net, C, dvec, center)
+    return np.any(gc > 0, axis=1).astype(np.int64), np.argmin(gc, axis=1)
+
+
 ORIG_AFFINE = slr.affine
 ORIG_RELU = slr.relu_relax
 ORIG_CLASSIFY = slr.classify
@@ -203,6 +250,10 @@ MUTANTS = [
     ("safe test on the lower bound", slr, "classify", _classify_safe_on_lower),
     ("bisects the narrowest side", count, "bisect", _bisect_narrowest),
     ("volume of depth t taken as 2^-(t+1)", count, "_exact_sum", _exact_sum_off_by_one),
+    ("alpha Adam steps along the gradient", alpha_oracle, "adam_step", _adam_step_ascends),
+    ("alpha Adam without bias correction", alpha_oracle, "adam_step", _adam_step_no_bias_correction),
+    ("alpha objective row is the argmax", alpha_oracle, "objective_weights", _objective_row_argmax),
+    ("alpha unsafe mode when any row is positive", alpha_oracle, "objective_weights", _objective_mode_any),
 ]
 
 
