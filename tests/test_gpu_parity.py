@@ -5,8 +5,9 @@ Parity protocol:
     interval magnitude max(1, |g_lo|, |g_hi|) (each endpoint is c0 -+ (r + S), a sum whose terms
     can be far larger than the endpoint itself);
   * widened bounds contain every sampled point's exact value;
-  * the raw bounds' error against the oracle lies within the rounding margin the kernel itself
-    adds to them (widened minus raw), box by box;
+  * the raw bounds' error against the oracle lies within a per-box float32 rounding-error
+    model (``eps32_model``), box by box, wherever no neuron is within that error of a phase
+    change;
   * classes agree wherever the oracle's margin (the distance of its bounds from a change of its
     decision, see ``margin``) exceeds 1e-5;
   * exact counts visit the same boxes (matched by depth and path id), with identical classes,
@@ -110,24 +111,82 @@ def test_bound_raw_parity(name, seed, depth, variant):
     assert err_hi.max() <= 1.0, f"worst upper-bound error {err_hi.max():.3g} x tolerance"
 
 
+def eps32_model(inst, blo, bhi, kappa=2.0):
+    """Per-box bound on the float32 rounding error of the kernel's raw bounds, from the
+    oracle's own per-neuron quantities (Higham, Accuracy and Stability of Numerical Algorithms,
+    Thm. 3.1: a sum of n rounded terms is off by at most gamma_n = n u / (1 - n u) times the sum
+    of their magnitudes, u = 2^-24), step by step as the kernel computes in box-local
+    coordinates: the first layer's d + 1 products, each concretization's d + 2 terms, Eq. 1's
+    ratio (a reciprocal and a product: 3 u) and its three products, and each affine layer's
+    K + 1 terms plus the errors of its inputs, through |W|.  An error e in a crossing neuron's
+    l or u moves its ratio by at most e / (u - l).  kappa = 2 covers the accumulation order of
+    the matrix cores.  Also returns the boxes where some neuron's oracle bound l or u lies
+    within the error of 0: there the float32 pass may take another phase (dead, active,
+    crossing) than the oracle, a different valid relaxation rather than a rounding error.
+    """
+    uu = 2.0 ** -24
+
+    def gam(n):
+        return n * uu / (1.0 - n * uu)
+
+    lo = blo.astype(np.float64)
+    hi = bhi.astype(np.float64)
+    mid = 0.5 * (lo + hi)
+    rad = 0.5 * (hi - lo)
+    d = lo.shape[1]
+    _, _, tr = slr.propagate(inst.net, inst.C, inst.dvec, lo, hi, keep=True)
+
+    def mag(E):
+        return (np.abs(E[..., 0] + np.einsum("bnd,bd->bn", E[..., 1:], mid))
+                + np.einsum("bnd,bd->bn", np.abs(E[..., 1:]), rad))
+
+    layers = [(np.abs(np.asarray(W, np.float64)), np.abs(np.asarray(b, np.float64)))
+              for W, b in inst.net]
+    Wg, bg, _, _ = slr.fold_property(inst.net, inst.C, inst.dvec)
+    layers[-1] = (np.abs(Wg), np.abs(bg))
+    aW1, ab1 = layers[0]
+    eps = gam(d + 2) * ((np.abs(mid) + rad) @ aW1.T + ab1)
+    amb = np.zeros(lo.shape[0], bool)
+    for li, t in enumerate(tr):
+        M = np.maximum(mag(t["L"]), mag(t["U"]))
+        e_b = eps + gam(d + 3) * M                          # error of l and of u
+        l, h = t["lo"], t["hi"]
+        amb |= np.any(np.minimum(np.abs(l), np.abs(h)) <= kappa * e_b, axis=1)
+        cross = (l < 0) & (h > 0)
+        dead = h <= 0
+        den = np.where(cross, h - l, 1.0)
+        lam = np.where(cross, h / den, 1.0)
+        dlam = np.where(cross, 2.0 * e_b / den + 3.0 * uu * lam, 0.0)
+        post = np.where(cross, lam * (eps + e_b) + (dlam + gam(4) * lam) * (M + np.abs(l)), eps)
+        post = np.where(dead, 0.0, post)
+        Mp = np.maximum(mag(t["Lr"]), mag(t["Ur"]))
+        aW, ab = layers[li + 1]
+        K = aW.shape[1]
+        eps = post @ aW.T + gam(K + 2) * (Mp @ aW.T + ab)
+        if li == len(tr) - 1:                               # folded rows rounded to float32
+            eps = eps + uu * (Mp @ aW.T + ab)
+            Mout = Mp @ aW.T + ab
+    eps = eps + gam(d + 3) * Mout
+    return kappa * eps, amb
+
+
 @pytest.mark.parametrize("name,seed,depth", CASES)
-def test_raw_error_within_kernel_margin(name, seed, depth, variant):
-    """Per box and endpoint, the float32 raw bound's distance from the float64 oracle is at most
-    the rounding margin the same kernel adds when it widens (|widened - raw|): the margin the
-    kernel claims covers the error it makes.  Prints the worst ratio."""
+def test_raw_error_within_eps32_model(name, seed, depth, variant):
+    """Per box and endpoint, |raw float32 bound - float64 oracle| <= eps32, the rounding-error
+    model of ``eps32_model``, on every box whose neurons are all clear of a phase change."""
     inst = make(name, seed)
     need(variant, inst)
     blo, bhi = synth.random_boxes(inst.lo, inst.hi, 1000, seed + 17, depth)
     o_lo, o_hi = slr.propagate(inst.net, inst.C, inst.dvec, blo, bhi)
     r_lo, r_hi, _ = gpu_bounds(inst, blo, bhi, raw=True)
-    w_lo, w_hi, _ = gpu_bounds(inst, blo, bhi, raw=False)
-    eps_lo = r_lo - w_lo
-    eps_hi = w_hi - r_hi
-    assert np.all(eps_lo > 0) and np.all(eps_hi > 0)
-    ratio = np.maximum(np.abs(r_lo - o_lo) / eps_lo, np.abs(r_hi - o_hi) / eps_hi)
-    print(f"{name} seed {seed}: worst |raw - oracle| / margin = {ratio.max():.3g}, "
-          f"median margin {np.median(np.concatenate([eps_lo, eps_hi]).ravel()):.3g}")
-    assert ratio.max() <= 1.0
+    eps, amb = eps32_model(inst, blo, bhi)
+    ratio = np.maximum(np.abs(r_lo - o_lo), np.abs(r_hi - o_hi)) / eps
+    ok = ~amb
+    print(f"{name} seed {seed}: {ok.sum()} boxes clear of phase changes ({amb.sum()} not); worst "
+          f"|raw - oracle| / eps32 = {ratio[ok].max() if ok.any() else 0:.3g}, median eps32 / "
+          f"|g| = {np.median(eps / np.maximum(1e-30, np.abs(o_lo))):.3g}")
+    assert ok.mean() >= 0.5
+    assert np.all(ratio[ok] <= 1.0), f"worst ratio {ratio[ok].max():.3g}"
 
 
 @pytest.mark.parametrize("name,seed,depth", CASES)
@@ -461,9 +520,12 @@ def test_count_approx_zero_width_side_matches_oracle():
     net = eng.Net(net_l)
     prop = eng.Property(net, [[1.0]], [0.0])
     lo, hi = np.array([0.0, 0.0, 0.5]), np.array([1.0, 1.0, 0.5])
-    kw = dict(trials=8, samples=200, seed=11, max_splits=20, grid_bits=16, resolve_tol=0.0)
-    g = eng.count_approx(net, prop, lo, hi, leaf_depth=14, leaf_leaves=1 << 10, **kw)
-    o = count.count_approx(net_l, [[1.0]], [0.0], lo, hi, leaf_depth=14, leaf_leaves=1 << 10, **kw)
+    # split points on a 2^-10 grid leave 14 float32-exact halvings per side for the leaf
+    # counts of depth 12 (on a 2^-16 grid, two free sides and depth 14 exceed float32 near 0.6,
+    # which the library reports as an inexact midpoint)
+    kw = dict(trials=8, samples=200, seed=11, max_splits=20, grid_bits=10, resolve_tol=0.0)
+    g = eng.count_approx(net, prop, lo, hi, leaf_depth=12, leaf_leaves=1 << 10, **kw)
+    o = count.count_approx(net_l, [[1.0]], [0.0], lo, hi, leaf_depth=12, leaf_leaves=1 << 10, **kw)
     assert g["splits"] == o["splits"] and max(g["splits"]) < 20
     assert np.allclose(g["estimates"], o["estimates"], rtol=1e-12, atol=0)
     assert 0.0 <= g["lower_bound"] <= 0.125

@@ -109,7 +109,8 @@ def test_count_approx_zero_width_side():
            (np.array([[1, 1, 1]], np.float32), np.array([-2.0], np.float32))]
     lo, hi = np.array([0.0, 0.0, 0.5]), np.array([1.0, 1.0, 0.5])
     r = count.count_approx(net, [[1.0]], [0.0], lo, hi, trials=8, samples=200, seed=11,
-                           leaf_depth=14, leaf_leaves=1 << 10, resolve_tol=0.0, max_splits=20)
+                           leaf_depth=12, leaf_leaves=1 << 10, resolve_tol=0.0, max_splits=20,
+                           grid_bits=10)
     assert 0.0 <= r["lower_bound"] <= 0.125
     assert all(np.isfinite(r["estimates"]))
     # every trial ends before its split cap: on the first draw of the fixed side
