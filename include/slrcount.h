@@ -186,6 +186,28 @@ int workspace_size(const slr_net* net, const slr_property* prop, int64_t max_lea
 int count_exact(const slr_net* net, const slr_property* prop, const double* lo, const double* hi,
                 const slr_exact_opts* opts, slr_count_result* out);
 
+/*
+ * count_exact_noalloc: count_exact for callers that cannot allocate memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc).  It makes no device or host
+ * allocation, creates no event and uses no pinned staging: its workspace is a static device
+ * array of count_exact_noalloc_max_bytes() bytes (64 MiB) inside the library, one copy per GPU,
+ * held from the library's first use on that GPU until the process ends, whose device address is
+ * looked up once per GPU on the first call there.  Arguments and results are those of
+ * count_exact, except:
+ *   opts->workspace must be NULL and opts->workspace_bytes 0;
+ *   opts->trace_capacity and opts->timing must be 0 (SLR_EINVAL otherwise);
+ *   a count whose workspace_size() (with samples = 0) exceeds the static array fails with
+ *   SLR_ENOMEM before any GPU work (e.g. the 5-input 6x50 network fits up to 2^19 leaves);
+ *   the level counts are read back into stack memory, so each split waits for that read-back.
+ * Every call on one GPU shares that GPU's array (the call re-initializes what it reads), so calls
+ * that overlap on one GPU, from several threads or streams, race and must not be made.
+ */
+int count_exact_noalloc(const slr_net* net, const slr_property* prop, const double* lo,
+                        const double* hi, const slr_exact_opts* opts, slr_count_result* out);
+
+/* count_exact_noalloc_max_bytes: size of count_exact_noalloc's static workspace in bytes. */
+size_t count_exact_noalloc_max_bytes(void);
+
 /* Options of the approximate count (CountingProVe with count_exact as leaf backend, §2.3). */
 typedef struct {
     int32_t trials;          /* independent trials T (1..64)                                */

@@ -11,6 +11,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -960,9 +961,11 @@ hipEvent_t* timing_events() {
     return te.ev;
 }
 
+// no_alloc: the call makes no allocation of any kind (no pinned staging buffer, no event, no
+// host heap): level counts are read back into stack memory and the split waits for them.
 int count_exact_impl(const slr_net* net, const slr_property* prop, const double* lo,
                      const double* hi, const slr_exact_opts* o, const Workspace& w,
-                     slr_count_result* out) {
+                     slr_count_result* out, bool no_alloc = false) {
     const auto t0 = std::chrono::steady_clock::now();
     hipStream_t s = (hipStream_t)o->stream;
     const int d = net->dev.d;
@@ -973,14 +976,14 @@ int count_exact_impl(const slr_net* net, const slr_property* prop, const double*
     HIP_TRY(hipMemsetAsync(w.stats, 0, sizeof(LevelStats) * kMaxLevels, s), "count_exact: clear");
     HIP_TRY(hipMemsetAsync(w.rechecks, 0, sizeof(unsigned long long), s), "count_exact: clear");
     HIP_TRY(hipMemsetAsync(w.err, 0, sizeof(unsigned) * (kMaxLevels + 1), s), "count_exact: clear");
-    std::vector<float> root(2 * d);
+    float root[2 * SLR_MAX_D];   // d <= SLR_MAX_D (load_net)
     for (int k = 0; k < d; ++k) {
         root[k] = (float)lo[k];
         root[d + k] = (float)hi[k];
     }
     const unsigned long long one = 1;
-    HIP_TRY(hipMemcpyAsync(w.lo[0], root.data(), sizeof(float) * d, hipMemcpyHostToDevice, s), "count_exact: root");
-    HIP_TRY(hipMemcpyAsync(w.hi[0], root.data() + d, sizeof(float) * d, hipMemcpyHostToDevice, s), "count_exact: root");
+    HIP_TRY(hipMemcpyAsync(w.lo[0], root, sizeof(float) * d, hipMemcpyHostToDevice, s), "count_exact: root");
+    HIP_TRY(hipMemcpyAsync(w.hi[0], root + d, sizeof(float) * d, hipMemcpyHostToDevice, s), "count_exact: root");
     HIP_TRY(hipMemcpyAsync(w.path[0], &one, sizeof one, hipMemcpyHostToDevice, s), "count_exact: root");
 
     // timing events (thread-local, created once): the bound launches of a level, and two
@@ -995,7 +998,7 @@ int count_exact_impl(const slr_net* net, const slr_property* prop, const double*
     double split_ms = 0.0;
     int64_t split_bytes = 0;
     hipEvent_t evr = nullptr;   // marks the end of a level's read-back
-    if (hipEventCreateWithFlags(&evr, hipEventDisableTiming) != hipSuccess) {
+    if (!no_alloc && hipEventCreateWithFlags(&evr, hipEventDisableTiming) != hipSuccess) {
         (void)hipGetLastError();
         evr = nullptr;
     }
@@ -1117,7 +1120,7 @@ int count_exact_impl(const slr_net* net, const slr_property* prop, const double*
         // read-back travels); if the level turns out to be the last one its output is unused,
         // children beyond the buffers are not written and its error slot is ignored
         LevelStats hs;
-        LevelStats* pin = pinned_stats();
+        LevelStats* pin = no_alloc ? nullptr : pinned_stats();
         HIP_TRY(hipMemcpyAsync(pin ? pin : &hs, w.stats + t, sizeof hs, hipMemcpyDeviceToHost, s),
                 "count_exact: readback");
         if (o->trace_capacity > 0 && o->trace_path && o->trace_cls && o->trace_depth && tcount < o->trace_capacity) {
@@ -1233,7 +1236,7 @@ int count_exact_impl(const slr_net* net, const slr_property* prop, const double*
 }
 
 int check_exact_opts(const slr_net* net, const slr_property* prop, const slr_exact_opts* o,
-                     int samples, Workspace* w, const char* who) {
+                     int samples, Workspace* w, const char* who, bool check_device = true) {
     if (!o) return fail(SLR_EINVAL, "%s: opts is NULL", who);
     if (o->max_depth < 0 || o->max_depth > kMaxLevels - 1)
         return fail(SLR_EINVAL, "%s: max_depth must be in [0, %d]", who, kMaxLevels - 1);
@@ -1253,7 +1256,7 @@ int check_exact_opts(const slr_net* net, const slr_property* prop, const slr_exa
     if (!o->workspace || o->workspace_bytes < need)
         return fail(SLR_ENOMEM, "%s: workspace of %zu bytes is smaller than the %zu required", who,
                     o->workspace_bytes, need);
-    if (!is_device_ptr(o->workspace)) return fail(SLR_EINVAL, "%s: workspace must be device memory", who);
+    if (check_device && !is_device_ptr(o->workspace)) return fail(SLR_EINVAL, "%s: workspace must be device memory", who);
     *w = layout_ws((char*)o->workspace, net->dev, prop->dev, o->max_leaves, samples, achunk);
     return SLR_OK;
 }
@@ -1271,6 +1274,75 @@ extern "C" int count_exact(const slr_net* net, const slr_property* prop, const d
     if ((rc = check_exact_opts(net, prop, opts, 0, &w, "count_exact"))) return rc;
     memset(out, 0, sizeof *out);
     return count_exact_impl(net, prop, lo, hi, opts, w, out);
+}
+
+// ------------------------------------------------------------------------------------------
+// Allocation-free exact count: the workspace is a file-scope device array
+// ------------------------------------------------------------------------------------------
+namespace {
+
+constexpr size_t kScratchBytes = size_t(64) << 20;
+constexpr int kMaxDevices = 64;
+
+// One copy per GPU, held from the library's first use on that GPU until the process ends.
+// Host code never passes this name to a kernel: it is a host-side stand-in, and the device
+// address of each GPU's copy comes from hipGetSymbolAddress (scratch_address).
+__device__ __align__(256) char scratch[kScratchBytes];
+
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of the current GPU's scratch copy, looked up once per device.
+int scratch_address(void** out, const char* who) {
+    int dev = -1;
+    HIP_TRY(hipGetDevice(&dev), "scratch: hipGetDevice");
+    if (dev < 0 || dev >= kMaxDevices) return fail(SLR_EUNSUPPORTED, "%s: device %d beyond %d", who, dev, kMaxDevices);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) {
+            (void)hipGetLastError();
+            return fail(SLR_EHIP, "%s: hipGetSymbolAddress(scratch) failed on device %d: %s", who, dev,
+                        hipGetErrorString(e));
+        }
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return SLR_OK;
+}
+
+}  // namespace
+
+extern "C" size_t count_exact_noalloc_max_bytes(void) { return kScratchBytes; }
+
+extern "C" int count_exact_noalloc(const slr_net* net, const slr_property* prop, const double* lo,
+                                   const double* hi, const slr_exact_opts* opts, slr_count_result* out) {
+    g_err.clear();
+    int rc = check_pair(net, prop, "count_exact_noalloc");
+    if (rc) return rc;
+    if (!out || !opts) return fail(SLR_EINVAL, "count_exact_noalloc: NULL argument");
+    if ((rc = check_box(net, lo, hi, "count_exact_noalloc"))) return rc;
+    if (opts->workspace || opts->workspace_bytes)
+        return fail(SLR_EINVAL, "count_exact_noalloc: the workspace is the library's own; pass workspace = NULL, 0 bytes");
+    if (opts->trace_capacity || opts->timing)
+        return fail(SLR_EINVAL, "count_exact_noalloc: traces and timing are not available (they need host buffers and events)");
+    const int64_t achunk = opts->alpha_steps > 0 ? opts->alpha_chunk : 0;
+    if (opts->max_leaves >= 1 && achunk >= 0) {
+        const size_t need = layout_ws(nullptr, net->dev, prop->dev, opts->max_leaves, 0, achunk).bytes;
+        if (need > kScratchBytes)
+            return fail(SLR_ENOMEM, "count_exact_noalloc: this count needs %zu bytes of workspace, more than the "
+                        "%zu-byte static scratch (lower max_leaves or alpha_chunk, or use count_exact)", need, kScratchBytes);
+    }
+    void* base = nullptr;
+    if ((rc = scratch_address(&base, "count_exact_noalloc"))) return rc;
+    slr_exact_opts o = *opts;
+    o.workspace = base;
+    o.workspace_bytes = kScratchBytes;
+    Workspace w;
+    if ((rc = check_exact_opts(net, prop, &o, 0, &w, "count_exact_noalloc", /*check_device=*/false))) return rc;
+    memset(out, 0, sizeof *out);
+    return count_exact_impl(net, prop, lo, hi, &o, w, out, /*no_alloc=*/true);
 }
 
 // Split point for [a, b] near med on the grid A + k (B - A) 2^-bits, kept one step inside (a, b);

@@ -24,7 +24,7 @@ EXPORTS = ("load_net", "free_net", "load_property", "free_property", "bound_boxe
            "bound_kernel_variant", "alpha_size", "alpha_tape_size", "bound_boxes_alpha",
            "bound_boxes_backward", "alpha_workspace_size", "alpha_optimize", "batch_create",
            "batch_run", "batch_free", "count_exact_batch", "bound_tile_shape",
-           "alpha_state_variant")
+           "alpha_state_variant", "count_exact_noalloc", "count_exact_noalloc_max_bytes")
 
 
 class SlrError(RuntimeError):
@@ -104,6 +104,11 @@ def lib() -> C.CDLL:
         L.count_exact.argtypes = [vp, vp, C.POINTER(C.c_double), C.POINTER(C.c_double),
                                   C.POINTER(ExactOpts), C.POINTER(CountResult)]
         L.count_exact.restype = C.c_int
+        L.count_exact_noalloc.argtypes = [vp, vp, C.POINTER(C.c_double), C.POINTER(C.c_double),
+                                          C.POINTER(ExactOpts), C.POINTER(CountResult)]
+        L.count_exact_noalloc.restype = C.c_int
+        L.count_exact_noalloc_max_bytes.argtypes = []
+        L.count_exact_noalloc_max_bytes.restype = C.c_size_t
         L.count_approx.argtypes = [vp, vp, C.POINTER(C.c_double), C.POINTER(C.c_double),
                                    C.POINTER(ApproxOpts), C.POINTER(ApproxResult)]
         L.count_approx.restype = C.c_int
@@ -345,6 +350,40 @@ def count_exact(net: Net, prop: Property, lo, hi, max_depth: int, max_leaves: in
         out["trace_path"] = t_path[:k].copy()
         out["trace_cls"] = t_cls[:k].copy()
     return out
+
+
+def count_exact_noalloc(net: Net, prop: Property, lo, hi, max_depth: int, max_leaves: int,
+                        chunk: int = 0, stream=None, alpha_steps: int = 0, alpha_lr: float = 0.1,
+                        alpha_min_depth: int = 0, alpha_chunk: int = 0,
+                        alpha_select: float = 0.0) -> dict:
+    """``count_exact`` on the library's static workspace (no allocation by the library or here:
+    only the host option and result structs)."""
+    lo = np.ascontiguousarray(lo, np.float64)
+    hi = np.ascontiguousarray(hi, np.float64)
+    if alpha_steps > 0 and alpha_chunk <= 0:
+        alpha_chunk = 16384
+    o = ExactOpts()
+    o.max_depth = int(max_depth)
+    o.max_leaves = int(max_leaves)
+    o.chunk = int(chunk)
+    o.stream = _stream(stream)
+    o.alpha_steps = int(alpha_steps)
+    o.alpha_lr = float(alpha_lr)
+    o.alpha_min_depth = int(alpha_min_depth)
+    o.alpha_chunk = int(alpha_chunk)
+    o.alpha_select = float(alpha_select)
+    r = CountResult()
+    rc = _check(lib().count_exact_noalloc(net.handle, prop.handle,
+                                          lo.ctypes.data_as(C.POINTER(C.c_double)),
+                                          hi.ctypes.data_as(C.POINTER(C.c_double)), C.byref(o),
+                                          C.byref(r)))
+    out = {f: getattr(r, f) for f, _ in CountResult._fields_}
+    out["rc"] = rc
+    return out
+
+
+def count_exact_noalloc_max_bytes() -> int:
+    return int(lib().count_exact_noalloc_max_bytes())
 
 
 def count_approx(net: Net, prop: Property, lo, hi, trials: int = 20, samples: int = 1000,
