@@ -208,6 +208,56 @@ int count_exact_noalloc(const slr_net* net, const slr_property* prop, const doub
 /* count_exact_noalloc_max_bytes: size of count_exact_noalloc's static workspace in bytes. */
 size_t count_exact_noalloc_max_bytes(void);
 
+/* ------------------------------------------------------------------------------------------
+ * Depth-first stack count: Alg. 1 without a leaf budget, in bounded memory.
+ *
+ * The paper's exact counter keeps whole branch-and-bound levels and spills partial results to
+ * disk once they outgrow memory (§4).  count_exact_stack keeps the undecided boxes on a stack
+ * ordered by depth (shallowest at the bottom) and repeatedly bounds the top `chunk` boxes
+ * (§3's independent per-box bounding, one launch), counts their classes per depth and pushes
+ * the children of the undecided ones; so the deepest work is done first and the stack holds
+ * about (max_depth + 2) * 2 * chunk boxes at most, whatever the number of leaves.  When the
+ * device part of the stack would exceed `device_boxes`, its bottom half moves to the caller's
+ * host buffer (out of core) and comes back once the device part has drained.  The boxes bounded
+ * are exactly those of count_exact with the same max_depth and an unlimited leaf budget, so the
+ * counts and exact volumes are identical; only the order differs.
+ * ------------------------------------------------------------------------------------------ */
+typedef struct {
+    int32_t max_depth;       /* undecided boxes at this depth are not split (0..62)           */
+    int32_t chunk;           /* boxes per bound launch (1..65536; 0 = 65536)                  */
+    int64_t max_boxes;       /* 0: no cap; else the count stops (SLR_BUDGET) before a chunk
+                                would take the boxes bounded beyond it, and every box left on
+                                the stack counts as undecided at its depth                  */
+    int64_t device_boxes;    /* device stack capacity in boxes (>= 4 * chunk; 0 = the bound
+                                2 * (max_depth + 2) * chunk, which never spills)             */
+    void* host_spill;        /* host memory for the stack's bottom (pinned for speed), or NULL */
+    size_t host_spill_bytes; /* holds host_spill_bytes / (8 d + 8) boxes                      */
+    void* workspace;         /* device memory of at least stack_workspace_size() bytes        */
+    size_t workspace_bytes;
+    void* stream;            /* hipStream_t used for all work of the call                     */
+    /* optional per-box trace (host arrays, NULL to disable): depth, path id and final class of
+       every bounded box, in the order bounded (not level order) */
+    int64_t trace_capacity;
+    int32_t* trace_depth;
+    uint64_t* trace_path;
+    int8_t* trace_cls;
+} slr_stack_opts;
+
+/* stack_workspace_size: device workspace of count_exact_stack for these options (max_depth,
+   chunk and device_boxes are read). */
+int stack_workspace_size(const slr_net* net, const slr_property* prop, const slr_stack_opts* opts,
+                         size_t* bytes);
+
+/*
+ * count_exact_stack: see above.  lo, hi as for count_exact.  out as for count_exact
+ * (trace_count, n_boxes_bounded, n_recheck64, depth_reached, status; the timing and alpha
+ * fields are 0).  Returns SLR_OK when nothing is left undecided, SLR_BUDGET otherwise, and
+ * SLR_ENOMEM when the stack outgrows device_boxes plus the host buffer.  Synchronizes `stream`
+ * before returning.
+ */
+int count_exact_stack(const slr_net* net, const slr_property* prop, const double* lo,
+                      const double* hi, const slr_stack_opts* opts, slr_count_result* out);
+
 /* Options of the approximate count (CountingProVe with count_exact as leaf backend, §2.3). */
 typedef struct {
     int32_t trials;          /* independent trials T (1..64)                                */

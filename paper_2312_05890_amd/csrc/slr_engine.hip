@@ -1345,6 +1345,279 @@ extern "C" int count_exact_noalloc(const slr_net* net, const slr_property* prop,
     return count_exact_impl(net, prop, lo, hi, &o, w, out, /*no_alloc=*/true);
 }
 
+// ------------------------------------------------------------------------------------------
+// Depth-first stack count (bounded memory, optional host spill)
+// ------------------------------------------------------------------------------------------
+namespace {
+
+struct StackWs {
+    float *lo, *hi;                  // [cap][d] the stack, shallowest boxes at the bottom
+    unsigned long long* path;        // [cap]
+    float *clo, *chi;                // [2 chunk][d] children of the chunk just bounded
+    unsigned long long* cpath;       // [2 chunk]
+    int8_t* cls;                     // [chunk]
+    unsigned* amb_list;              // [chunk]
+    unsigned* amb_count;
+    unsigned* tile_und;
+    unsigned* split_total;
+    LevelStats* stats;               // [kMaxLevels]
+    double* vol;
+    unsigned long long *counts, *rechecks;
+    unsigned* err;
+    int64_t cap, chunk;
+    size_t bytes;
+};
+
+int64_t stack_chunk(const slr_stack_opts& o) { return o.chunk > 0 ? o.chunk : 65536; }
+
+int64_t stack_device_boxes(const slr_stack_opts& o) {
+    return o.device_boxes > 0 ? o.device_boxes : 2 * (int64_t)(o.max_depth + 2) * stack_chunk(o);
+}
+
+StackWs layout_stack(char* base, const NetDev& nd, int64_t cap, int64_t chunk) {
+    const int d = nd.d;
+    StackWs w{};
+    size_t o = 0;
+    auto take = [&](size_t bytes) {
+        char* p = base ? base + o : nullptr;
+        o += align256(bytes);
+        return p;
+    };
+    w.cap = cap;
+    w.chunk = chunk;
+    w.lo = (float*)take(sizeof(float) * d * cap);
+    w.hi = (float*)take(sizeof(float) * d * cap);
+    w.path = (unsigned long long*)take(sizeof(unsigned long long) * cap);
+    w.clo = (float*)take(sizeof(float) * d * 2 * chunk);
+    w.chi = (float*)take(sizeof(float) * d * 2 * chunk);
+    w.cpath = (unsigned long long*)take(sizeof(unsigned long long) * 2 * chunk);
+    w.cls = (int8_t*)take(chunk);
+    w.amb_list = (unsigned*)take(sizeof(unsigned) * chunk);
+    w.amb_count = (unsigned*)take(2 * sizeof(unsigned));
+    w.tile_und = (unsigned*)take(sizeof(unsigned) * level_tiles(chunk));
+    w.split_total = (unsigned*)take(sizeof(unsigned));
+    w.stats = (LevelStats*)take(sizeof(LevelStats) * kMaxLevels);
+    w.vol = (double*)take(sizeof(double) * 3);
+    w.counts = (unsigned long long*)take(sizeof(unsigned long long) * 3);
+    w.rechecks = (unsigned long long*)take(sizeof(unsigned long long));
+    w.err = (unsigned*)take(sizeof(unsigned));
+    w.bytes = o;
+    return w;
+}
+
+int check_stack_opts(const slr_net* net, const slr_stack_opts* o, const char* who) {
+    if (!o) return fail(SLR_EINVAL, "%s: opts is NULL", who);
+    if (o->max_depth < 0 || o->max_depth > kMaxLevels - 1)
+        return fail(SLR_EINVAL, "%s: max_depth must be in [0, %d]", who, kMaxLevels - 1);
+    if (o->chunk < 0 || o->chunk > 65536) return fail(SLR_EINVAL, "%s: chunk must be in [0, 65536]", who);
+    if (o->max_boxes < 0) return fail(SLR_EINVAL, "%s: max_boxes must be >= 0", who);
+    if (o->device_boxes < 0 || (o->device_boxes > 0 && o->device_boxes < 4 * stack_chunk(*o)))
+        return fail(SLR_EINVAL, "%s: device_boxes must be 0 or >= 4 * chunk", who);
+    if (o->trace_capacity < 0) return fail(SLR_EINVAL, "%s: trace_capacity must be >= 0", who);
+    if (o->host_spill_bytes > 0 && !o->host_spill) return fail(SLR_EINVAL, "%s: host_spill is NULL", who);
+    (void)net;
+    return SLR_OK;
+}
+
+// The whole count; see the header.  Invariant: stack depths are non-decreasing from the bottom
+// to the top (children, in parent order, are deeper than every box left below them), so the
+// top chunk holds the deepest boxes and the host part the shallowest.
+int count_stack_impl(const slr_net* net, const slr_property* prop, const double* lo,
+                     const double* hi, const slr_stack_opts& o, const StackWs& w,
+                     slr_count_result* out) {
+    const auto t0 = std::chrono::steady_clock::now();
+    hipStream_t s = (hipStream_t)o.stream;
+    const int d = net->dev.d;
+    const int D = o.max_depth;
+    const int64_t chunk = w.chunk, cap = w.cap;
+    const size_t rec_host = sizeof(float) * 2 * d + sizeof(unsigned long long);
+    const int64_t hcap = o.host_spill ? (int64_t)(o.host_spill_bytes / rec_host) : 0;
+    float* h_lo = (float*)o.host_spill;
+    float* h_hi = h_lo ? h_lo + (size_t)d * hcap : nullptr;
+    unsigned long long* h_path = h_lo ? (unsigned long long*)(h_hi + (size_t)d * hcap) : nullptr;
+
+    HIP_TRY(hipMemsetAsync(w.stats, 0, sizeof(LevelStats) * kMaxLevels, s), "count_exact_stack: clear");
+    HIP_TRY(hipMemsetAsync(w.rechecks, 0, sizeof(unsigned long long), s), "count_exact_stack: clear");
+    HIP_TRY(hipMemsetAsync(w.err, 0, sizeof(unsigned), s), "count_exact_stack: clear");
+    float root[2 * SLR_MAX_D];
+    for (int k = 0; k < d; ++k) {
+        root[k] = (float)lo[k];
+        root[d + k] = (float)hi[k];
+    }
+    const unsigned long long one = 1;
+    HIP_TRY(hipMemcpyAsync(w.lo, root, sizeof(float) * d, hipMemcpyHostToDevice, s), "count_exact_stack: root");
+    HIP_TRY(hipMemcpyAsync(w.hi, root + d, sizeof(float) * d, hipMemcpyHostToDevice, s), "count_exact_stack: root");
+    HIP_TRY(hipMemcpyAsync(w.path, &one, sizeof one, hipMemcpyHostToDevice, s), "count_exact_stack: root");
+
+    LevelStats* pin = pinned_stats();      // pinned read-back slot (the split total goes here)
+    unsigned nsplit_host = 0;
+    int64_t top = 1, host_cnt = 0, bounded = 0, tcount = 0;
+    int status = SLR_OK;
+    std::vector<unsigned long long> hpath;
+    std::vector<int8_t> hcls;
+    auto copy3 = [&](float* dlo, float* dhi, unsigned long long* dpath, const float* slo,
+                     const float* shi, const unsigned long long* spath, int64_t m, hipMemcpyKind k) {
+        hipError_t e = hipMemcpyAsync(dlo, slo, sizeof(float) * d * m, k, s);
+        if (e == hipSuccess) e = hipMemcpyAsync(dhi, shi, sizeof(float) * d * m, k, s);
+        if (e == hipSuccess) e = hipMemcpyAsync(dpath, spath, sizeof(unsigned long long) * m, k, s);
+        return e;
+    };
+    while (top > 0 || host_cnt > 0) {
+        if (top == 0) {   // the device part has drained: bring back the deepest host boxes
+            const int64_t k = std::min(host_cnt, cap / 2);
+            const int64_t from = host_cnt - k;
+            HIP_TRY(copy3(w.lo, w.hi, w.path, h_lo + from * d, h_hi + from * d, h_path + from, k,
+                          hipMemcpyHostToDevice), "count_exact_stack: refill");
+            host_cnt = from;
+            top = k;
+        }
+        const int64_t m = std::min(chunk, top);
+        if (o.max_boxes > 0 && bounded + m > o.max_boxes) {
+            status = SLR_BUDGET;
+            break;
+        }
+        const int64_t base = top - m;
+        float* blo = w.lo + base * d;
+        float* bhi = w.hi + base * d;
+        unsigned long long* bpath = w.path + base;
+        int unsup = 0;
+        HIP_TRY(hipMemsetAsync(w.amb_count, 0, sizeof(unsigned), s), "count_exact_stack: clear");
+        HIP_TRY(hipMemsetAsync(w.split_total, 0, sizeof(unsigned), s), "count_exact_stack: clear");
+        HIP_TRY(launch_bound_f32(net->dev, prop->dev, m, blo, bhi, nullptr, nullptr, w.cls, 0, s, &unsup,
+                                 w.amb_list, w.amb_count, 0u),
+                "count_exact_stack: bound kernel");
+        if (unsup) return fail(SLR_EUNSUPPORTED, "count_exact_stack: network shape exceeds the LDS bound kernel");
+        HIP_TRY(launch_recheck64(net->dev, prop->dev, m, blo, bhi, nullptr, nullptr, w.cls, w.rechecks,
+                                 w.amb_list, w.amb_count, s),
+                "count_exact_stack: recheck kernel");
+        HIP_TRY(launch_stack_count(m, w.cls, bpath, D, 0, w.tile_und, w.stats, w.split_total, s),
+                "count_exact_stack: count kernel");
+        HIP_TRY(launch_split(m, d, w.cls, w.tile_und, blo, bhi, bpath, w.clo, w.chi, w.cpath, w.err,
+                             2 * chunk, s),
+                "count_exact_stack: split kernel");
+        unsigned* dst = pin ? (unsigned*)pin : &nsplit_host;
+        HIP_TRY(hipMemcpyAsync(dst, w.split_total, sizeof(unsigned), hipMemcpyDeviceToHost, s),
+                "count_exact_stack: readback");
+        if (o.trace_capacity > 0 && o.trace_path && o.trace_cls && o.trace_depth && tcount < o.trace_capacity) {
+            const int64_t k = std::min<int64_t>(m, o.trace_capacity - tcount);
+            hpath.resize(k);
+            hcls.resize(k);
+            HIP_TRY(hipMemcpyAsync(hpath.data(), bpath, k * sizeof(unsigned long long), hipMemcpyDeviceToHost, s),
+                    "count_exact_stack: trace");
+            HIP_TRY(hipMemcpyAsync(hcls.data(), w.cls, k, hipMemcpyDeviceToHost, s), "count_exact_stack: trace");
+            HIP_TRY(hipStreamSynchronize(s), "count_exact_stack: sync");
+            for (int64_t i = 0; i < k; ++i) {
+                int dep = 0;
+                for (unsigned long long p = hpath[i]; p > 1; p >>= 1) ++dep;
+                o.trace_depth[tcount + i] = dep;
+                o.trace_path[tcount + i] = hpath[i];
+                o.trace_cls[tcount + i] = hcls[i] == 4 ? 0 : hcls[i];
+            }
+            tcount += k;
+        }
+        HIP_TRY(hipStreamSynchronize(s), "count_exact_stack: sync");
+        const int64_t nsplit = pin ? (int64_t)*(unsigned*)pin : (int64_t)nsplit_host;
+        bounded += m;
+        int64_t b = base;
+        const int64_t need = b + 2 * nsplit - cap;
+        if (need > 0) {   // spill the stack's bottom (its shallowest boxes) to the host
+            const int64_t h = std::max(need, (b + 1) / 2);
+            if (host_cnt + h > hcap)
+                return fail(SLR_ENOMEM, "count_exact_stack: the stack needs more than %lld device and %lld host boxes",
+                            (long long)cap, (long long)hcap);
+            HIP_TRY(copy3(h_lo + host_cnt * d, h_hi + host_cnt * d, h_path + host_cnt, w.lo, w.hi, w.path, h,
+                          hipMemcpyDeviceToHost), "count_exact_stack: spill");
+            // [h, b) moves down to [0, b - h); b - h <= h, so source and destination do not overlap
+            HIP_TRY(copy3(w.lo, w.hi, w.path, w.lo + h * d, w.hi + h * d, w.path + h, b - h,
+                          hipMemcpyDeviceToDevice), "count_exact_stack: spill");
+            HIP_TRY(hipStreamSynchronize(s), "count_exact_stack: sync");
+            host_cnt += h;
+            b -= h;
+        }
+        if (nsplit > 0)
+            HIP_TRY(copy3(w.lo + b * d, w.hi + b * d, w.path + b, w.clo, w.chi, w.cpath, 2 * nsplit,
+                          hipMemcpyDeviceToDevice), "count_exact_stack: push");
+        top = b + 2 * nsplit;
+    }
+    if (status == SLR_BUDGET) {
+        // every box still on the stack is undecided at its depth
+        HIP_TRY(launch_stack_count(top, nullptr, w.path, D, 1, nullptr, w.stats, w.split_total, s),
+                "count_exact_stack: count kernel");
+        for (int64_t done = 0; done < host_cnt;) {
+            const int64_t k = std::min<int64_t>(host_cnt - done, 2 * chunk);
+            HIP_TRY(hipMemcpyAsync(w.cpath, h_path + done, sizeof(unsigned long long) * k, hipMemcpyHostToDevice, s),
+                    "count_exact_stack: refill");
+            HIP_TRY(launch_stack_count(k, nullptr, w.cpath, D, 1, nullptr, w.stats, w.split_total, s),
+                    "count_exact_stack: count kernel");
+            HIP_TRY(hipStreamSynchronize(s), "count_exact_stack: sync");
+            done += k;
+        }
+    }
+    LevelStats st[kMaxLevels];
+    HIP_TRY(hipMemcpyAsync(st, w.stats, sizeof st, hipMemcpyDeviceToHost, s), "count_exact_stack: readback");
+    HIP_TRY(hipStreamSynchronize(s), "count_exact_stack: sync");
+    int levels = 1;
+    for (int t = 0; t < kMaxLevels; ++t)
+        if (st[t].unsafe_cnt + st[t].safe_cnt + st[t].undecided_cnt > 0) levels = t + 1;
+    HIP_TRY(launch_stack_volume(w.stats, levels, w.vol, w.counts, w.err, s), "count_exact_stack: volume kernel");
+    double vol[3];
+    unsigned long long counts[3], rechecks = 0;
+    unsigned err = 0;
+    HIP_TRY(hipMemcpyAsync(vol, w.vol, sizeof vol, hipMemcpyDeviceToHost, s), "count_exact_stack: readback");
+    HIP_TRY(hipMemcpyAsync(counts, w.counts, sizeof counts, hipMemcpyDeviceToHost, s), "count_exact_stack: readback");
+    HIP_TRY(hipMemcpyAsync(&rechecks, w.rechecks, sizeof rechecks, hipMemcpyDeviceToHost, s), "count_exact_stack: readback");
+    HIP_TRY(hipMemcpyAsync(&err, w.err, sizeof err, hipMemcpyDeviceToHost, s), "count_exact_stack: readback");
+    HIP_TRY(hipStreamSynchronize(s), "count_exact_stack: sync");
+    if (err & 1u) return fail(SLR_EINTERNAL, "count_exact_stack: a bisection midpoint is not exact in float32 (box too deep for its coordinates)");
+    if (err & 2u) return fail(SLR_EINTERNAL, "count_exact_stack: leaf volumes do not sum to the box volume");
+    memset(out, 0, sizeof *out);
+    out->unsafe = vol[0];
+    out->safe = vol[1];
+    out->undecided = vol[2];
+    out->n_unsafe = (int64_t)counts[0];
+    out->n_safe = (int64_t)counts[1];
+    out->n_undecided = (int64_t)counts[2];
+    out->n_boxes_bounded = bounded;
+    out->n_recheck64 = (int64_t)rechecks;
+    out->depth_reached = levels - 1;
+    out->trace_count = tcount;
+    if (counts[2] > 0 && status == SLR_OK) status = SLR_BUDGET;
+    out->status = status;
+    out->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    return status;
+}
+
+}  // namespace
+
+extern "C" int stack_workspace_size(const slr_net* net, const slr_property* prop, const slr_stack_opts* opts,
+                                    size_t* bytes) {
+    g_err.clear();
+    if (!bytes) return fail(SLR_EINVAL, "stack_workspace_size: bytes is NULL");
+    int rc = check_pair(net, prop, "stack_workspace_size");
+    if (rc) return rc;
+    if ((rc = check_stack_opts(net, opts, "stack_workspace_size"))) return rc;
+    *bytes = layout_stack(nullptr, net->dev, stack_device_boxes(*opts), stack_chunk(*opts)).bytes;
+    return SLR_OK;
+}
+
+extern "C" int count_exact_stack(const slr_net* net, const slr_property* prop, const double* lo,
+                                 const double* hi, const slr_stack_opts* opts, slr_count_result* out) {
+    g_err.clear();
+    int rc = check_pair(net, prop, "count_exact_stack", /*need_lds=*/true);
+    if (rc) return rc;
+    if (!out) return fail(SLR_EINVAL, "count_exact_stack: out is NULL");
+    if ((rc = check_box(net, lo, hi, "count_exact_stack"))) return rc;
+    if ((rc = check_stack_opts(net, opts, "count_exact_stack"))) return rc;
+    const int64_t cap = stack_device_boxes(*opts), chunk = stack_chunk(*opts);
+    const size_t need = layout_stack(nullptr, net->dev, cap, chunk).bytes;
+    if (!opts->workspace || opts->workspace_bytes < need)
+        return fail(SLR_ENOMEM, "count_exact_stack: workspace of %zu bytes is smaller than the %zu required",
+                    opts->workspace_bytes, need);
+    if (!is_device_ptr(opts->workspace)) return fail(SLR_EINVAL, "count_exact_stack: workspace must be device memory");
+    const StackWs w = layout_stack((char*)opts->workspace, net->dev, cap, chunk);
+    return count_stack_impl(net, prop, lo, hi, *opts, w, out);
+}
+
 // Split point for [a, b] near med on the grid A + k (B - A) 2^-bits, kept one step inside (a, b);
 // intervals narrower than two steps are bisected at the midpoint.
 static double snap_split(double med, double a, double b, double A, double B, int bits) {

@@ -121,6 +121,16 @@ hipError_t launch_split(int64_t n, int d, const int8_t* cls, const unsigned int*
                         const float* lo, const float* hi, const unsigned long long* path,
                         float* lo2, float* hi2, unsigned long long* path2, unsigned int* err,
                         int64_t cap, hipStream_t stream);
+// Depth-first stack count (count_exact_stack): per-depth class counts of a chunk of mixed-depth
+// boxes (depth from the path id), class 4 for undecided boxes at max_depth, per-tile and total
+// counts of the boxes to split; all_undecided counts every box as undecided at its depth.
+constexpr int kMaxDepthLevels = 63;
+hipError_t launch_stack_count(int64_t n, int8_t* cls, const unsigned long long* path, int max_depth,
+                              int all_undecided, unsigned* tile_und, LevelStats* stats,
+                              unsigned* split_total, hipStream_t stream);
+// Exact volumes summed over every level and class (undecided leaves at any depth).
+hipError_t launch_stack_volume(const LevelStats* stats, int levels, double* out3,
+                               unsigned long long* out_counts, unsigned* err, hipStream_t stream);
 hipError_t launch_volume(const LevelStats* stats, int levels, int stop_level, int stopped,
                          double* out3, unsigned long long* out_counts, unsigned int* err,
                          hipStream_t stream);

@@ -72,6 +72,82 @@ __global__ __launch_bounds__(256) void split_kernel(int64_t n, int d, const int8
                d <= kSplitStageD ? split_stage : nullptr);
 }
 
+// Depth-first stack count, one chunk of boxes of mixed depths (the depth of a box is the position
+// of its path id's leading 1 bit: root 1, children 2p and 2p + 1).  Unsafe and safe boxes add to
+// their depth's counters; an undecided box at max_depth (or every box, with all_undecided) adds
+// to the undecided counter of its depth and, unless all_undecided, gets class 4 so the split
+// leaves it; the remaining undecided boxes are counted per 1024-box tile (for the split's
+// offsets) and in *split_total.  Per-depth counts go through an LDS histogram, then one 64-bit
+// atomic per non-zero entry.
+__global__ __launch_bounds__(256) void stack_count_kernel(int64_t n, int8_t* __restrict__ cls,
+                                                          const unsigned long long* __restrict__ path,
+                                                          int max_depth, int all_undecided,
+                                                          unsigned* __restrict__ tile_und,
+                                                          LevelStats* stats, unsigned* split_total) {
+    __shared__ unsigned hist[kMaxDepthLevels * 3];
+    __shared__ unsigned red[4];
+    const int tid = threadIdx.x;
+    for (int e = tid; e < kMaxDepthLevels * 3; e += 256) hist[e] = 0;
+    __syncthreads();
+    const int64_t base = (int64_t)blockIdx.x * kTile + tid * 4;
+    unsigned nsplit = 0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int64_t i = base + q;
+        if (i < n) {
+            const int depth = 63 - __clzll(path[i]);
+            const int8_t c = all_undecided ? 0 : cls[i];
+            if (c == 1) {
+                atomicAdd(&hist[depth * 3 + 0], 1u);
+            } else if (c == 2) {
+                atomicAdd(&hist[depth * 3 + 1], 1u);
+            } else if (c == 0) {
+                if (all_undecided || depth >= max_depth) {
+                    atomicAdd(&hist[depth * 3 + 2], 1u);
+                    if (!all_undecided) cls[i] = 4;
+                } else {
+                    ++nsplit;
+                }
+            }
+        }
+    }
+    __syncthreads();
+    for (int e = tid; e < kMaxDepthLevels * 3; e += 256) {
+        const unsigned h = hist[e];
+        if (h) {
+            unsigned long long* f = reinterpret_cast<unsigned long long*>(stats + e / 3) + (e % 3);
+            atomicAdd(f, (unsigned long long)h);
+        }
+    }
+    nsplit = block_sum256(nsplit, red);
+    if (tid == 0) {
+        if (tile_und) tile_und[blockIdx.x] = nsplit;
+        if (nsplit) atomicAdd(split_total, nsplit);
+    }
+}
+
+// Exact volumes of a count whose undecided leaves may lie at any depth: sum_t n_t 2^(Dm - t)
+// over every level for each class in 64-bit integers (they must partition 2^Dm exactly), then
+// one conversion to float64 each.
+__global__ void stack_volume_kernel(const LevelStats* stats, int levels, double* out3,
+                                    unsigned long long* out_counts, unsigned* err) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    const int Dm = levels - 1;
+    unsigned long long s[3] = {0, 0, 0}, c[3] = {0, 0, 0};
+    for (int t = 0; t < levels; ++t) {
+        const unsigned long long v[3] = {stats[t].unsafe_cnt, stats[t].safe_cnt, stats[t].undecided_cnt};
+        for (int k = 0; k < 3; ++k) {
+            s[k] += v[k] << (Dm - t);
+            c[k] += v[k];
+        }
+    }
+    if (s[0] + s[1] + s[2] != (1ull << Dm)) atomicOr(err, 2u);
+    for (int k = 0; k < 3; ++k) {
+        out3[k] = ldexp((double)s[k], -Dm);
+        out_counts[k] = c[k];
+    }
+}
+
 __global__ void volume_kernel(const LevelStats* stats, int levels, int stop_level, int stopped,
                               double* out3, unsigned long long* out_counts, unsigned* err) {
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
@@ -639,6 +715,24 @@ hipError_t launch_split(int64_t n, int d, const int8_t* cls, const unsigned* til
     const size_t lds = d <= kSplitStageD ? 2 * sizeof(float) * kTile * d : 0;
     hipLaunchKernelGGL(split_kernel, dim3((unsigned)level_tiles(n)), dim3(256), lds, stream, n, d,
                        cls, tile_und, lo, hi, path, lo2, hi2, path2, err, cap);
+    return hipGetLastError();
+}
+
+hipError_t launch_stack_count(int64_t n, int8_t* cls, const unsigned long long* path, int max_depth,
+                              int all_undecided, unsigned* tile_und, LevelStats* stats,
+                              unsigned* split_total, hipStream_t stream) {
+    if (n <= 0) return hipSuccess;
+    (void)hipGetLastError();
+    hipLaunchKernelGGL(stack_count_kernel, dim3((unsigned)level_tiles(n)), dim3(256), 0, stream, n,
+                       cls, path, max_depth, all_undecided, tile_und, stats, split_total);
+    return hipGetLastError();
+}
+
+hipError_t launch_stack_volume(const LevelStats* stats, int levels, double* out3,
+                               unsigned long long* out_counts, unsigned* err, hipStream_t stream) {
+    (void)hipGetLastError();
+    hipLaunchKernelGGL(stack_volume_kernel, dim3(1), dim3(64), 0, stream, stats, levels, out3,
+                       out_counts, err);
     return hipGetLastError();
 }
 

@@ -24,7 +24,8 @@ EXPORTS = ("load_net", "free_net", "load_property", "free_property", "bound_boxe
            "bound_kernel_variant", "alpha_size", "alpha_tape_size", "bound_boxes_alpha",
            "bound_boxes_backward", "alpha_workspace_size", "alpha_optimize", "batch_create",
            "batch_run", "batch_free", "count_exact_batch", "bound_tile_shape",
-           "alpha_state_variant", "count_exact_noalloc", "count_exact_noalloc_max_bytes")
+           "alpha_state_variant", "count_exact_noalloc", "count_exact_noalloc_max_bytes",
+           "stack_workspace_size", "count_exact_stack")
 
 
 class SlrError(RuntimeError):
@@ -53,6 +54,15 @@ class CountResult(C.Structure):
                 ("bound_launches", C.c_int64), ("n_alpha_boxes", C.c_int64),
                 ("n_alpha_decided", C.c_int64), ("alpha_ms", C.c_double),
                 ("split_ms", C.c_double), ("split_bytes", C.c_int64)]
+
+
+class StackOpts(C.Structure):
+    _fields_ = [("max_depth", C.c_int32), ("chunk", C.c_int32), ("max_boxes", C.c_int64),
+                ("device_boxes", C.c_int64), ("host_spill", C.c_void_p),
+                ("host_spill_bytes", C.c_size_t), ("workspace", C.c_void_p),
+                ("workspace_bytes", C.c_size_t), ("stream", C.c_void_p),
+                ("trace_capacity", C.c_int64), ("trace_depth", C.POINTER(C.c_int32)),
+                ("trace_path", C.POINTER(C.c_uint64)), ("trace_cls", C.POINTER(C.c_int8))]
 
 
 class AlphaOpts(C.Structure):
@@ -109,6 +119,11 @@ def lib() -> C.CDLL:
         L.count_exact_noalloc.restype = C.c_int
         L.count_exact_noalloc_max_bytes.argtypes = []
         L.count_exact_noalloc_max_bytes.restype = C.c_size_t
+        L.stack_workspace_size.argtypes = [vp, vp, C.POINTER(StackOpts), C.POINTER(C.c_size_t)]
+        L.stack_workspace_size.restype = C.c_int
+        L.count_exact_stack.argtypes = [vp, vp, C.POINTER(C.c_double), C.POINTER(C.c_double),
+                                        C.POINTER(StackOpts), C.POINTER(CountResult)]
+        L.count_exact_stack.restype = C.c_int
         L.count_approx.argtypes = [vp, vp, C.POINTER(C.c_double), C.POINTER(C.c_double),
                                    C.POINTER(ApproxOpts), C.POINTER(ApproxResult)]
         L.count_approx.restype = C.c_int
@@ -384,6 +399,66 @@ def count_exact_noalloc(net: Net, prop: Property, lo, hi, max_depth: int, max_le
 
 def count_exact_noalloc_max_bytes() -> int:
     return int(lib().count_exact_noalloc_max_bytes())
+
+
+def _stack_opts(max_depth, chunk, max_boxes, device_boxes, host_spill, stream):
+    o = StackOpts()
+    o.max_depth = int(max_depth)
+    o.chunk = int(chunk)
+    o.max_boxes = int(max_boxes)
+    o.device_boxes = int(device_boxes)
+    if host_spill is not None:
+        o.host_spill = host_spill.data_ptr()
+        o.host_spill_bytes = host_spill.numel() * host_spill.element_size()
+    o.stream = _stream(stream)
+    return o
+
+
+def stack_workspace_size(net: Net, prop: Property, max_depth: int, chunk: int = 0,
+                         device_boxes: int = 0) -> int:
+    o = _stack_opts(max_depth, chunk, 0, device_boxes, None, None)
+    out = C.c_size_t()
+    _check(lib().stack_workspace_size(net.handle, prop.handle, C.byref(o), C.byref(out)))
+    return out.value
+
+
+def count_exact_stack(net: Net, prop: Property, lo, hi, max_depth: int, chunk: int = 0,
+                      max_boxes: int = 0, device_boxes: int = 0, host_spill=None, workspace=None,
+                      stream=None, trace: bool = False, trace_capacity: int = 0) -> dict:
+    """Alg. 1 without a leaf budget in bounded memory (depth-first over chunks of the frontier,
+    optional spill of the stack's bottom to ``host_spill``, a pinned uint8 tensor); results
+    equal ``count_exact`` with the same depth and an unlimited leaf budget."""
+    import torch
+    lo = np.ascontiguousarray(lo, np.float64)
+    hi = np.ascontiguousarray(hi, np.float64)
+    o = _stack_opts(max_depth, chunk, max_boxes, device_boxes, host_spill, stream)
+    need = stack_workspace_size(net, prop, max_depth, chunk, device_boxes)
+    if workspace is None:
+        workspace = torch.empty(need, dtype=torch.uint8, device="cuda")
+    o.workspace = workspace.data_ptr()
+    o.workspace_bytes = workspace.numel() * workspace.element_size()
+    if trace:
+        cap = int(trace_capacity)
+        t_depth = np.zeros(cap, np.int32)
+        t_path = np.zeros(cap, np.uint64)
+        t_cls = np.zeros(cap, np.int8)
+        o.trace_capacity = cap
+        o.trace_depth = t_depth.ctypes.data_as(C.POINTER(C.c_int32))
+        o.trace_path = t_path.ctypes.data_as(C.POINTER(C.c_uint64))
+        o.trace_cls = t_cls.ctypes.data_as(C.POINTER(C.c_int8))
+    r = CountResult()
+    rc = _check(lib().count_exact_stack(net.handle, prop.handle,
+                                        lo.ctypes.data_as(C.POINTER(C.c_double)),
+                                        hi.ctypes.data_as(C.POINTER(C.c_double)), C.byref(o),
+                                        C.byref(r)))
+    out = {f: getattr(r, f) for f, _ in CountResult._fields_}
+    out["rc"] = rc
+    if trace:
+        k = r.trace_count
+        out["trace_depth"] = t_depth[:k].copy()
+        out["trace_path"] = t_path[:k].copy()
+        out["trace_cls"] = t_cls[:k].copy()
+    return out
 
 
 def count_approx(net: Net, prop: Property, lo, hi, trials: int = 20, samples: int = 1000,
