@@ -316,6 +316,13 @@ int sample_violations(const slr_net* net, const slr_property* prop, int64_t n, c
    more resident workgroups).  Tape sizes depend on it: query alpha_tape_size after setting it. */
 int alpha_state_variant(int32_t variant);
 
+/* alpha_kernel_variant: process-wide launch structure of alpha_optimize and of the alpha pass of
+   the exact count: 0 (default) one launch per forward and per adjoint pass; 1 one fused launch
+   per optimization, every 16-box tile running its initial forward pass and all steps (adjoint
+   with the Adam step, forward) in one workgroup (the batched alpha pass always uses this form).
+   Both compute the same values. */
+int alpha_kernel_variant(int32_t variant);
+
 /* alpha_size: nh, the slopes per box. */
 int alpha_size(const slr_net* net, int64_t* nh);
 
@@ -396,10 +403,34 @@ int batch_create(int32_t n_inst, const slr_net* const* nets, const slr_property*
                  const double* const* lo, const double* const* hi, const int32_t* max_depth,
                  const int64_t* max_leaves, int32_t use_graph, slr_batch** out);
 
+/* Options of batch_create_opts.  With alpha_steps > 0 every level of every instance from depth
+   alpha_min_depth on gets the alpha pass of slr_exact_opts inside the batch's launch sequence:
+   the boxes its plain bounds leave undecided (all of them, or with alpha_select > 0 only those
+   near a decision, as in slr_exact_opts) are optimized for alpha_steps projected-Adam steps and
+   the boxes the optimized bounds decide take that class.  Instances share the alpha kernels of
+   their template class; each class optimizes at most alpha_chunk boxes per level (0 = 8192),
+   taken instance by instance in batch order and box by box in level order (the rest keep their
+   plain class).  While no class runs out of room, every instance's result equals count_exact
+   with the same alpha options. */
+typedef struct {
+    int32_t use_graph;       /* 1 = capture the launch sequence in a graph (as batch_create)   */
+    int32_t alpha_steps;     /* 0 = plain counts                                              */
+    float alpha_lr;          /* Adam step size (0 = 0.1)                                      */
+    int32_t alpha_min_depth;
+    float alpha_select;      /* finite, >= 0                                                  */
+    int32_t alpha_chunk;     /* boxes per alpha class and level (0 = 8192)                    */
+} slr_batch_opts;
+
+/* batch_create_opts: batch_create with options (NULL opts: SLR_EINVAL). */
+int batch_create_opts(int32_t n_inst, const slr_net* const* nets, const slr_property* const* props,
+                      const double* const* lo, const double* const* hi, const int32_t* max_depth,
+                      const int64_t* max_leaves, const slr_batch_opts* opts, slr_batch** out);
+
 /*
  * batch_run: one complete count of every instance on `stream` (graph replay or the same
  * launches issued directly), then one read-back; results[i] (host, [n_inst]) as from
- * count_exact (bound_ms, trace and alpha fields are 0; seconds is the batch's wall time).
+ * count_exact (bound_ms, trace and timing fields are 0; n_alpha_boxes and n_alpha_decided as in count_exact;
+ * seconds is the batch's wall time).
  * Returns SLR_BUDGET if any instance stopped on its depth or leaf budget.  Calls on one batch
  * must not overlap.
  */

@@ -43,6 +43,11 @@ __device__ __forceinline__ bool row_valid(int mt, int g, int v, int tiles, int r
 
 __device__ __forceinline__ float sgn(float x) { return x > 0.f ? 1.f : (x < 0.f ? -1.f : 0.f); }
 
+// Projected Adam step constants: step size, moment decays, eps, bias corrections 1/(1 - beta^t).
+struct AdamK {
+    float lr, beta1, beta2, eps, c1, c2;
+};
+
 // Column groups of one contraction unit: for 2 NC <= 16 one unit takes every column (center
 // columns with W, radius columns with |W|); otherwise units take CG columns of one half.
 template <int NC> struct Groups;
@@ -410,7 +415,7 @@ __device__ __forceinline__ void bwd_relu_core(PT pre, GetD getd, PS dpre, int mt
                                               const bool (&valid)[4], float* __restrict__ arow,
                                               float* __restrict__ drow, float* __restrict__ mrow,
                                               float* __restrict__ vrow,
-                                              const int* __restrict__ rowmap, const AlphaArgs& A,
+                                              const int* __restrict__ rowmap, const AdamK& A,
                                               const EpiK& k) {
     auto at = [&](int c) { return (size_t)(c * mtS + mt) * 64 + lane; };
     const int g = lane >> 4;
@@ -494,7 +499,7 @@ __device__ __forceinline__ void bwd_relu(PT pre, PS dpost, PS dpre, int mtS, int
                                          const bool (&valid)[4], float* __restrict__ arow,
                                          float* __restrict__ drow, float* __restrict__ mrow,
                                          float* __restrict__ vrow, const int* __restrict__ rowmap,
-                                         const AlphaArgs& A, const EpiK& k) {
+                                         const AdamK& A, const EpiK& k) {
     auto getd = [&](int c) { return dpost[(size_t)(c * mtS + mt) * 64 + lane]; };
     bwd_relu_core<NC, bwd_unroll<NC>()>(pre, getd, dpre, mtS, mt, lane, valid, arow, drow, mrow,
                                         vrow, rowmap, A, k);
@@ -506,7 +511,7 @@ __device__ __forceinline__ void bwd_relu_reg(const f32x4 (&dp)[2 * NC], PT pre, 
                                              int mt, int lane, const bool (&valid)[4],
                                              float* __restrict__ arow, float* __restrict__ drow,
                                              float* __restrict__ mrow, float* __restrict__ vrow,
-                                             const int* __restrict__ rowmap, const AlphaArgs& A,
+                                             const int* __restrict__ rowmap, const AdamK& A,
                                              const EpiK& k) {
     auto getd = [&](int c) { return dp[c]; };
     bwd_relu_core<NC, NC>(pre, getd, dpre, mtS, mt, lane, valid, arow, drow, mrow, vrow, rowmap,
@@ -525,21 +530,23 @@ __device__ __forceinline__ int hidden_rem(const NetDev& net, int h) {
 // ---------------------------------------------------------------------------------------------
 // RP: every layer's columns fit one contraction unit and its tiles one unit per wavefront, so
 // contraction results stay in registers across the barrier and the epilogue reads no tape.
+// The forward pass of 16-box tile `tile` (one workgroup of kNW wavefronts).
 template <int NC, bool GS, bool RP>
-__global__ __launch_bounds__(kNW * 64, 2) void alpha_fwd_kernel(NetDev net, PropDev prop,
-                                                             AlphaArgs A, int slots) {
+__device__ __forceinline__ void alpha_fwd_tile(const NetDev& net, const PropDev& prop,
+                                               const AlphaArgs& A, int slots, int64_t tile,
+                                               int init) {
     extern __shared__ float lds[];
     using G = Groups<NC>;
     constexpr int NC2 = 2 * NC;
     constexpr int NCT = 2 * NC + 2;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, g = lane >> 4, j = lane & 15;
-    const int64_t b = (int64_t)blockIdx.x * 16 + j;
+    const int64_t b = tile * 16 + j;
     const bool bval = b < A.n;
     const int mtS = net.mt_max;
     const size_t slot = (size_t)NCT * mtS * 64;   // float4 per slot
     const int H = net.n_affine - 1;
     const int d = net.d;
-    f32x4* tape = reinterpret_cast<f32x4*>(A.tape) + (size_t)blockIdx.x * slots * slot;
+    f32x4* tape = reinterpret_cast<f32x4*>(A.tape) + (size_t)tile * slots * slot;
     const EpiK k = epi_k(net, A.raw);
     float* part;
     f32x4* S;
@@ -603,13 +610,13 @@ __global__ __launch_bounds__(kNW * 64, 2) void alpha_fwd_kernel(NetDev net, Prop
                 for (int c = NC; c < NC2; ++c) cols[c] = f32x4{0.f, 0.f, 0.f, 0.f};
                 emax = fwd_relu_reg<NC>(cols, A.fwd_only ? nullptr : pre, S, mtS, mt, lane, eps,
                                         valid, arow ? arow + net.hoff[0] : nullptr, net.rowmap[0],
-                                        A.init, k);
+                                        init, k);
             } else {
                 pre[at(0)] = f32x4{c0[0], c0[1], c0[2], c0[3]};
 #pragma unroll
                 for (int c = NC; c < NC2; ++c) pre[at(c)] = f32x4{0.f, 0.f, 0.f, 0.f};
                 emax = fwd_relu<NC>(pre, S, mtS, mt, lane, eps, valid,
-                                    arow ? arow + net.hoff[0] : nullptr, net.rowmap[0], A.init, k);
+                                    arow ? arow + net.hoff[0] : nullptr, net.rowmap[0], init, k);
             }
             emax = fmaxf(emax, __shfl_xor(emax, 16));
             emax = fmaxf(emax, __shfl_xor(emax, 32));
@@ -650,11 +657,11 @@ __global__ __launch_bounds__(kNW * 64, 2) void alpha_fwd_kernel(NetDev net, Prop
                 for (int v = 0; v < 4; ++v) acc[0][v] += L.bias[16 * mt + 4 * g + v];
                 emax = fwd_relu_reg<NC>(acc, A.fwd_only ? nullptr : pre, S, mtS, mt, lane, eps,
                                         valid, arow ? arow + net.hoff[l + 1] : nullptr,
-                                        net.rowmap[l + 1], A.init, k);
+                                        net.rowmap[l + 1], init, k);
             } else {
                 emax = fwd_relu<NC>(pre, S, mtS, mt, lane, eps, valid,
                                     arow ? arow + net.hoff[l + 1] : nullptr, net.rowmap[l + 1],
-                                    A.init, k);
+                                    init, k);
             }
             emax = fmaxf(emax, __shfl_xor(emax, 16));
             emax = fmaxf(emax, __shfl_xor(emax, 32));
@@ -707,7 +714,7 @@ __global__ __launch_bounds__(kNW * 64, 2) void alpha_fwd_kernel(NetDev net, Prop
                 if (A.g_hi) A.g_hi[o] = HI[v];
                 float blo = LO[v], bhi = HI[v];
                 if (A.best_lo) {
-                    if (!A.init) {
+                    if (!init) {
                         blo = fmaxf(blo, A.best_lo[o]);
                         bhi = fminf(bhi, A.best_hi[o]);
                     }
@@ -734,20 +741,22 @@ __global__ __launch_bounds__(kNW * 64, 2) void alpha_fwd_kernel(NetDev net, Prop
 // Adjoint pass: d J / d alpha through the property rows, the transposed contractions W^T, |W|^T
 // on MFMA and every alpha epilogue, from the tape of the forward pass with the same slopes.
 // ---------------------------------------------------------------------------------------------
+// The adjoint pass (with the fused projected Adam step when A.adam_m is set) of tile `tile`.
 template <int NC, bool GS, bool RP>
-__global__ __launch_bounds__(kNW * 64, 2) void alpha_bwd_kernel(NetDev net, PropDev prop,
-                                                             AlphaArgs A, int slots) {
+__device__ __forceinline__ void alpha_bwd_tile(const NetDev& net, const PropDev& prop,
+                                               const AlphaArgs& A, int slots, int64_t tile,
+                                               const AdamK& ak) {
     extern __shared__ float lds[];
     using G = Groups<NC>;
     constexpr int NC2 = 2 * NC;
     constexpr int NCT = 2 * NC + 2;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, g = lane >> 4, j = lane & 15;
-    const int64_t b = (int64_t)blockIdx.x * 16 + j;
+    const int64_t b = tile * 16 + j;
     const bool bval = b < A.n;
     const int mtS = net.mt_max;
     const size_t slot = (size_t)NCT * mtS * 64;
     const int H = net.n_affine - 1;
-    f32x4* tape = reinterpret_cast<f32x4*>(A.tape) + (size_t)blockIdx.x * slots * slot;
+    f32x4* tape = reinterpret_cast<f32x4*>(A.tape) + (size_t)tile * slots * slot;
     const EpiK k = epi_k(net, A.raw);
     f32x4 *dA, *dB;   // dA: adjoint of a pre-activation, dB: of a post-activation
     if constexpr (GS) {
@@ -831,7 +840,7 @@ __global__ __launch_bounds__(kNW * 64, 2) void alpha_bwd_kernel(NetDev net, Prop
                 bwd_relu_reg<NC>(acc, tape + (size_t)h * slot, dA, mtS, wave, lane, valid,
                                  arow ? arow + off : nullptr, drow ? drow + off : nullptr,
                                  mrow ? mrow + off : nullptr, vrow ? vrow + off : nullptr,
-                                 net.rowmap[h], A, k);
+                                 net.rowmap[h], ak, k);
             }
             if (h == 0) break;
             __syncthreads();
@@ -858,7 +867,7 @@ __global__ __launch_bounds__(kNW * 64, 2) void alpha_bwd_kernel(NetDev net, Prop
             for (int v = 0; v < 4; ++v) valid[v] = row_valid(mt, g, v, tiles, rem);
             bwd_relu<NC>(pre, dB, dA, mtS, mt, lane, valid, arow ? arow + off : nullptr,
                          drow ? drow + off : nullptr, mrow ? mrow + off : nullptr,
-                         vrow ? vrow + off : nullptr, net.rowmap[h], A, k);
+                         vrow ? vrow + off : nullptr, net.rowmap[h], ak, k);
         }
         if (h == 0) break;
         __syncthreads();
@@ -868,56 +877,189 @@ __global__ __launch_bounds__(kNW * 64, 2) void alpha_bwd_kernel(NetDev net, Prop
     }
 }
 
+template <int NC, bool GS, bool RP>
+__global__ __launch_bounds__(kNW * 64, 2) void alpha_fwd_kernel(NetDev net, PropDev prop,
+                                                             AlphaArgs A, int slots) {
+    alpha_fwd_tile<NC, GS, RP>(net, prop, A, slots, blockIdx.x, A.init);
+}
+
+template <int NC, bool GS, bool RP>
+__global__ __launch_bounds__(kNW * 64, 2) void alpha_bwd_kernel(NetDev net, PropDev prop,
+                                                             AlphaArgs A, int slots) {
+    const AdamK ak{A.lr, A.beta1, A.beta2, A.eps, A.c1, A.c2};
+    alpha_bwd_tile<NC, GS, RP>(net, prop, A, slots, blockIdx.x, ak);
+}
+
+// A whole optimization of one tile: the forward pass that writes the plain ratios (init), then
+// `steps` pairs (adjoint with the projected Adam step, forward).  Adam's bias corrections
+// 1 / (1 - beta^t) are formed in float64 and rounded once, as a host loop would.  The tile's
+// moments are cleared first.  Between passes the workgroup barrier orders the tape, LDS and
+// per-box buffers, which only this workgroup touches.
+template <int NC, bool GS, bool RPF, bool RPB>
+__device__ __forceinline__ void alpha_opt_tile(const NetDev& net, const PropDev& prop,
+                                               const AlphaArgs& A, int slots, int steps,
+                                               int64_t tile) {
+    {
+        const int64_t b0 = tile * 16;
+        const int64_t nb = min((int64_t)16, A.n - b0);
+        const int64_t cnt = nb > 0 ? nb * net.nh : 0;
+        for (int64_t e = threadIdx.x; e < cnt; e += blockDim.x) {
+            A.adam_m[b0 * net.nh + e] = 0.f;
+            A.adam_v[b0 * net.nh + e] = 0.f;
+        }
+    }
+    alpha_fwd_tile<NC, GS, RPF>(net, prop, A, slots, tile, 1);
+    double p1 = 1.0, p2 = 1.0;
+    for (int t = 1; t <= steps; ++t) {
+        p1 *= (double)A.beta1;
+        p2 *= (double)A.beta2;
+        const AdamK ak{A.lr, A.beta1, A.beta2, A.eps, (float)(1.0 / (1.0 - p1)), (float)(1.0 / (1.0 - p2))};
+        __syncthreads();
+        alpha_bwd_tile<NC, GS, RPB>(net, prop, A, slots, tile, ak);
+        __syncthreads();
+        alpha_fwd_tile<NC, GS, RPF>(net, prop, A, slots, tile, 0);
+    }
+}
+
+template <int NC, bool GS, bool RPF, bool RPB>
+__global__ __launch_bounds__(kNW * 64, 2) void alpha_opt_kernel(NetDev net, PropDev prop,
+                                                             AlphaArgs A, int slots, int steps) {
+    alpha_opt_tile<NC, GS, RPF, RPB>(net, prop, A, slots, steps, blockIdx.x);
+}
+
 // ---------------------------------------------------------------------------------------------
 // Objective of each box from a float32 forward pass at its center: obj = (all rows > 0, argmin).
 // ---------------------------------------------------------------------------------------------
+// The objective of one box (the whole workgroup): a float32 forward pass at the box center;
+// obj[0] = 1 if every property row is > 0 there, obj[1] = the row with the smallest value.
+__device__ __forceinline__ void center_obj_box(const NetDev& net, const PropDev& prop,
+                                               const float* __restrict__ lo,
+                                               const float* __restrict__ hi,
+                                               int8_t* __restrict__ obj, float* h0, float* h1,
+                                               float* gv) {
+    const int tid = threadIdx.x;
+    const int d = net.d;
+    if (tid < d) h1[tid] = 0.5f * (lo[tid] + hi[tid]);
+    __syncthreads();
+    if (tid < net.n1) {
+        float s = net.b1[tid];
+        for (int kk = 0; kk < d; ++kk) s = fmaf(net.w1[tid * d + kk], h1[kk], s);
+        h0[tid] = fmaxf(s, 0.f);
+    }
+    __syncthreads();
+    float* in = h0;
+    float* out = h1;
+    for (int l = 0; l < net.n_affine - 2; ++l) {
+        const MidLayer& L = net.mid[l];
+        if (tid < L.n_out) {
+            float s = L.b[tid];
+            const float* wr = L.w + (size_t)tid * L.n_in;
+            for (int kk = 0; kk < L.n_in; ++kk) s = fmaf(wr[kk], in[kk], s);
+            out[tid] = fmaxf(s, 0.f);
+        }
+        __syncthreads();
+        float* t = in;
+        in = out;
+        out = t;
+    }
+    if (tid < prop.rows) {
+        float s = prop.bg[tid];
+        for (int kk = 0; kk < prop.n_last; ++kk) s = fmaf(prop.wg[tid * prop.n_last + kk], in[kk], s);
+        gv[tid] = s;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        int all = 1, arg = 0;
+        for (int r = 0; r < prop.rows; ++r) {
+            all &= gv[r] > 0.f;
+            if (gv[r] < gv[arg]) arg = r;
+        }
+        obj[0] = (int8_t)all;
+        obj[1] = (int8_t)arg;
+    }
+    __syncthreads();
+}
+
 __global__ __launch_bounds__(256) void center_obj_kernel(NetDev net, PropDev prop, int64_t n,
                                                          const float* __restrict__ lo,
                                                          const float* __restrict__ hi,
                                                          int8_t* __restrict__ obj) {
     __shared__ float h0[SLR_MAX_WIDTH], h1[SLR_MAX_WIDTH], gv[SLR_MAX_ROWS];
-    const int tid = threadIdx.x;
     const int d = net.d;
-    for (int64_t p = blockIdx.x; p < n; p += gridDim.x) {
-        if (tid < d) h1[tid] = 0.5f * (lo[p * d + tid] + hi[p * d + tid]);
-        __syncthreads();
-        if (tid < net.n1) {
-            float s = net.b1[tid];
-            for (int kk = 0; kk < d; ++kk) s = fmaf(net.w1[tid * d + kk], h1[kk], s);
-            h0[tid] = fmaxf(s, 0.f);
+    for (int64_t p = blockIdx.x; p < n; p += gridDim.x)
+        center_obj_box(net, prop, lo + p * d, hi + p * d, obj + 2 * p, h0, h1, gv);
+}
+
+// ---------------------------------------------------------------------------------------------
+// Batched alpha pass: per alpha class, each instance's candidates occupy a 16-aligned segment
+// of the class buffers (laid out by the plan kernel); a box or tile finds its instance by the
+// segment starts.
+// ---------------------------------------------------------------------------------------------
+// Largest k with seg[k] <= q (seg non-decreasing, seg[0] = 0).
+__device__ __forceinline__ int seg_owner(const unsigned* __restrict__ seg, int n, unsigned q) {
+    int a = 0, b = n - 1;
+    while (a < b) {
+        const int m = (a + b + 1) >> 1;
+        if (seg[m] <= q) a = m;
+        else b = m - 1;
+    }
+    return a;
+}
+
+__global__ __launch_bounds__(256) void batch_center_kernel(const BatchInst* insts, const BatchCtl* ctl,
+                                                           int c, BatchAlphaBuf B) {
+    __shared__ float h0[SLR_MAX_WIDTH], h1[SLR_MAX_WIDTH], gv[SLR_MAX_ROWS];
+    const unsigned nb = ctl->antiles[c] * 16;
+    for (unsigned q = blockIdx.x; q < nb; q += gridDim.x) {
+        const int k = seg_owner(B.seg, B.ninst, q);
+        const BatchInst& I = insts[B.inst[k]];
+        const unsigned pos = q - I.aseg;
+        if (pos >= I.alen) continue;   // padding of a segment (uniform)
+        const size_t o = (size_t)I.aseg * B.dmax + (size_t)pos * I.d;
+        center_obj_box(I.net, I.prop, B.lo + o, B.hi + o, B.obj + 2 * (size_t)q, h0, h1, gv);
+    }
+}
+
+template <int NC, bool GS, bool RPF, bool RPB>
+__global__ __launch_bounds__(kNW * 64, 2) void batch_alpha_opt_kernel(const BatchInst* insts,
+                                                                   const BatchCtl* ctl, int c,
+                                                                   BatchAlphaBuf B, AlphaArgs base,
+                                                                   int steps) {
+    const unsigned t = blockIdx.x;
+    if (t >= ctl->antiles[c]) return;
+    const int k = seg_owner(B.seg, B.ninst, 16 * t);
+    const BatchInst& I = insts[B.inst[k]];
+    const unsigned s0 = I.aseg;
+    AlphaArgs A = base;
+    A.n = I.alen;
+    A.lo = B.lo + (size_t)s0 * B.dmax;
+    A.hi = B.hi + (size_t)s0 * B.dmax;
+    A.alpha = B.alpha + (size_t)s0 * B.nhmax;
+    A.adam_m = B.m + (size_t)s0 * B.nhmax;
+    A.adam_v = B.v + (size_t)s0 * B.nhmax;
+    A.g_lo = B.glo + (size_t)s0 * B.rowsmax;
+    A.g_hi = B.ghi + (size_t)s0 * B.rowsmax;
+    A.best_lo = B.blo + (size_t)s0 * B.rowsmax;
+    A.best_hi = B.bhi + (size_t)s0 * B.rowsmax;
+    A.cls = B.cls + s0;
+    A.obj = B.obj + 2 * (size_t)s0;
+    A.tape = B.tape + I.atape;
+    alpha_opt_tile<NC, GS, RPF, RPB>(I.net, I.prop, A, I.aslots, steps, (int64_t)(t - s0 / 16));
+}
+
+// Boxes the optimized bounds decided take their class back into the instance's level.
+__global__ __launch_bounds__(256) void batch_scatter_kernel(BatchInst* insts, const BatchCtl* ctl,
+                                                            int c, BatchAlphaBuf B) {
+    const unsigned nb = ctl->antiles[c] * 16;
+    for (unsigned q = blockIdx.x * 256 + threadIdx.x; q < nb; q += gridDim.x * 256) {
+        const int k = seg_owner(B.seg, B.ninst, q);
+        BatchInst& I = insts[B.inst[k]];
+        if (q - I.aseg >= I.alen) continue;
+        const int8_t v = B.cls[q];
+        if (v != 0) {
+            I.cls[B.list[q]] = v;
+            atomicAdd((unsigned long long*)&I.n_alpha_decided, 1ull);
         }
-        __syncthreads();
-        float* in = h0;
-        float* out = h1;
-        for (int l = 0; l < net.n_affine - 2; ++l) {
-            const MidLayer& L = net.mid[l];
-            if (tid < L.n_out) {
-                float s = L.b[tid];
-                const float* wr = L.w + (size_t)tid * L.n_in;
-                for (int kk = 0; kk < L.n_in; ++kk) s = fmaf(wr[kk], in[kk], s);
-                out[tid] = fmaxf(s, 0.f);
-            }
-            __syncthreads();
-            float* t = in;
-            in = out;
-            out = t;
-        }
-        if (tid < prop.rows) {
-            float s = prop.bg[tid];
-            for (int kk = 0; kk < prop.n_last; ++kk) s = fmaf(prop.wg[tid * prop.n_last + kk], in[kk], s);
-            gv[tid] = s;
-        }
-        __syncthreads();
-        if (tid == 0) {
-            int all = 1, arg = 0;
-            for (int r = 0; r < prop.rows; ++r) {
-                all &= gv[r] > 0.f;
-                if (gv[r] < gv[arg]) arg = r;
-            }
-            obj[2 * p] = (int8_t)all;
-            obj[2 * p + 1] = (int8_t)arg;
-        }
-        __syncthreads();
     }
 }
 
@@ -1072,11 +1214,57 @@ hipError_t launch_bwd_nc(const NetDev& net, const PropDev& prop, const AlphaArgs
     return hipGetLastError();
 }
 
+template <int NC>
+hipError_t launch_opt_nc(const NetDev& net, const PropDev& prop, const AlphaArgs& a, int steps,
+                         const AlphaShape& sh, hipStream_t stream) {
+    const int64_t blocks = (a.n + 15) / 16;
+    (void)hipGetLastError();
+    if (sh.global_state) {
+        auto kern = alpha_opt_kernel<NC, true, false, false>;
+        const size_t lds = sh.lds_fwd > sh.lds_bwd ? sh.lds_fwd : sh.lds_bwd;
+        hipError_t e = allow_lds_a((const void*)kern, lds);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(kNW * 64), lds, stream, net, prop, a,
+                           sh.slots, steps);
+    } else {
+        if constexpr (NC <= 11) {
+            auto kern = alpha_opt_kernel<NC, false, false, false>;
+            if constexpr (Groups<NC>::NG == 1) {
+                if (sh.reg_path) kern = alpha_opt_kernel<NC, false, true, false>;
+                if constexpr (NC <= 6) {
+                    if (sh.reg_path_bwd) kern = alpha_opt_kernel<NC, false, true, true>;
+                }
+            }
+            const size_t lds = sh.lds_fwd > sh.lds_bwd ? sh.lds_fwd : sh.lds_bwd;
+            hipError_t e = allow_lds_a((const void*)kern, lds);
+            if (e != hipSuccess) return e;
+            hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(kNW * 64), lds, stream, net, prop,
+                               a, sh.slots, steps);
+        } else {
+            return hipErrorInvalidValue;
+        }
+    }
+    return hipGetLastError();
+}
+
 }  // namespace
 
 namespace {
 int g_alpha_state = 0;   // 0 automatic, 1 LDS where it fits, 2 always the tape's global slots
+// 0 (default): one launch per pass; 1: one launch per optimization (alpha_opt_kernel).  With
+// 65536 acas boxes the per-pass launches took 30.7 ms and the fused one 34.6 ms (the fused
+// kernel spills: its step loop holds both passes' live values); the fused form pays where the
+// passes are small, in the batched alpha pass.
+int g_alpha_fused = 0;
 }  // namespace
+
+int set_alpha_fused(int v) {
+    if (v != 0 && v != 1) return -1;
+    g_alpha_fused = v;
+    return 0;
+}
+
+int alpha_fused() { return g_alpha_fused; }
 
 int set_alpha_state_variant(int v) {
     if (v < 0 || v > 2) return -1;
@@ -1134,6 +1322,18 @@ hipError_t launch_alpha_backward(const NetDev& net, const PropDev& prop, const A
     }
 }
 
+hipError_t launch_alpha_optimize(const NetDev& net, const PropDev& prop, const AlphaArgs& a,
+                                 int steps, hipStream_t stream) {
+    if (a.n <= 0) return hipSuccess;
+    const AlphaShape sh = alpha_shape(net, prop);
+    switch (sh.nc) {
+#define SLR_O(C) case C: return launch_opt_nc<C>(net, prop, a, steps, sh, stream);
+        SLR_ALPHA_NC(SLR_O)
+#undef SLR_O
+        default: return hipErrorInvalidValue;
+    }
+}
+
 hipError_t launch_center_objective(const NetDev& net, const PropDev& prop, int64_t n,
                                    const float* lo, const float* hi, int8_t* obj,
                                    hipStream_t stream) {
@@ -1180,5 +1380,65 @@ hipError_t launch_ambiguity(int64_t n, int rows, const float* wlo, const float* 
     (void)hipGetLastError();
     hipLaunchKernelGGL(ambiguity_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream, n,
                        rows, wlo, whi, rlo, rhi, cls, amb_list, amb_count, base);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------------------------
+// Batched alpha pass: kernel templates per alpha class
+// ---------------------------------------------------------------------------------------------
+int batch_alpha_key(const NetDev& net, const PropDev& prop, size_t* lds) {
+    const AlphaShape sh = alpha_shape(net, prop);
+    if (sh.nc < 0 || sh.nc > 14) return -1;
+    const int gs = sh.global_state;
+    const int rpf = (!gs && sh.nc <= 8 && sh.reg_path) ? 1 : 0;
+    const int rpb = (rpf && sh.nc <= 6 && sh.reg_path_bwd) ? 1 : 0;
+    if (!gs && sh.nc > 11) return -1;
+    *lds = sh.lds_fwd > sh.lds_bwd ? sh.lds_fwd : sh.lds_bwd;
+    return ((sh.nc * 2 + gs) * 2 + rpf) * 2 + rpb;
+}
+
+namespace {
+const void* batch_opt_ptr(int key) {
+#define SLR_K(NC, GS, RPF, RPB)                                                          \
+    if (key == (((NC) * 2 + (GS)) * 2 + (RPF)) * 2 + (RPB))                              \
+        return (const void*)batch_alpha_opt_kernel<NC, (GS) != 0, (RPF) != 0, (RPB) != 0>;
+    SLR_K(3, 1, 0, 0) SLR_K(3, 0, 0, 0) SLR_K(3, 0, 1, 0) SLR_K(3, 0, 1, 1)
+    SLR_K(4, 1, 0, 0) SLR_K(4, 0, 0, 0) SLR_K(4, 0, 1, 0) SLR_K(4, 0, 1, 1)
+    SLR_K(6, 1, 0, 0) SLR_K(6, 0, 0, 0) SLR_K(6, 0, 1, 0) SLR_K(6, 0, 1, 1)
+    SLR_K(8, 1, 0, 0) SLR_K(8, 0, 0, 0) SLR_K(8, 0, 1, 0)
+    SLR_K(11, 1, 0, 0) SLR_K(11, 0, 0, 0)
+    SLR_K(14, 1, 0, 0)
+#undef SLR_K
+    return nullptr;
+}
+}  // namespace
+
+hipError_t batch_alpha_prepare(int key, size_t lds) {
+    const void* k = batch_opt_ptr(key);
+    if (!k) return hipErrorInvalidValue;
+    return allow_lds_a(k, lds);
+}
+
+hipError_t launch_batch_alpha_class(int key, size_t lds, BatchInst* insts, BatchCtl* ctl, int c,
+                                    const BatchAlphaBuf& buf, const AlphaArgs& base, int steps,
+                                    hipStream_t stream) {
+    const void* k = batch_opt_ptr(key);
+    if (!k) return hipErrorInvalidValue;
+    const unsigned tiles = buf.cap / 16;
+    (void)hipGetLastError();
+    hipLaunchKernelGGL(batch_center_kernel, dim3(tiles * 16 < 4096 ? tiles * 16 : 4096), dim3(256), 0,
+                       stream, (const BatchInst*)insts, (const BatchCtl*)ctl, c, buf);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const BatchInst* ci = insts;
+    const BatchCtl* cc = ctl;
+    BatchAlphaBuf b = buf;
+    AlphaArgs a = base;
+    int st = steps;
+    void* args[] = {(void*)&ci, (void*)&cc, &c, &b, &a, &st};
+    e = hipLaunchKernel(k, dim3(tiles), dim3(kNW * 64), args, lds, stream);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(batch_scatter_kernel, dim3(tiles * 16 / 256 + 1), dim3(256), 0, stream, insts,
+                       (const BatchCtl*)ctl, c, buf);
     return hipGetLastError();
 }

@@ -62,6 +62,12 @@ __global__ __launch_bounds__(256) void batch_init_kernel(BatchInst* insts, int n
         I.levels = 0;
         I.rechecks = 0;
         I.err = 0;
+        I.acand = 0;
+        I.aseg = 0;
+        I.alen = 0;
+        I.atape = 0;
+        I.n_alpha_boxes = 0;
+        I.n_alpha_decided = 0;
     }
 }
 
@@ -112,9 +118,9 @@ __global__ __launch_bounds__(NW * 64) void batch_bound_kernel(BatchInst* insts, 
         const int i = find_owner(bpre, cbeg, cend, t);
         const BatchInst& I = insts[i];
         const int64_t box0 = (int64_t)(t - bpre[i]) * (NT * 16);
-        bound_tile<NCOL, NT, UW, NW>(I.net, I.prop, I.n, box0, I.lo[I.cur], I.hi[I.cur], nullptr,
-                                 nullptr, I.cls, 0, I.sp, amb_list, &ctl->amb_count,
-                                 (unsigned)i << 22);
+        bound_tile<NCOL, NT, UW, NW>(I.net, I.prop, I.n, box0, I.lo[I.cur], I.hi[I.cur], I.glo,
+                                     I.ghi, I.cls, 0, I.sp, amb_list, &ctl->amb_count,
+                                     (unsigned)i << 22);
         __syncthreads();   // the tile's LDS is reused by the next tile
     }
 }
@@ -185,6 +191,134 @@ __global__ __launch_bounds__(256) void batch_split_kernel(BatchInst* insts, int 
         split_tile(I.n, I.d, I.cls, I.tile_und, I.lo[c], I.hi[c], I.path[c], I.lo[c ^ 1],
                    I.hi[c ^ 1], I.path[c ^ 1], &I.err, I.max_leaves, (int64_t)(t - cpre[i]),
                    split_stage);
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------------------------
+// Alpha pass of a level (batches with alpha options)
+// ---------------------------------------------------------------------------------------------
+// An instance takes part at this level when it has an alpha class, is active and has reached its
+// first alpha depth; a box is a candidate when it is undecided and (select > 0) its plain bounds
+// lie within select of a decision.
+__device__ __forceinline__ bool alpha_level(const BatchInst& I) {
+    return I.acls_id >= 0 && I.active && I.level >= I.alpha_min_depth;
+}
+
+__device__ __forceinline__ bool alpha_candidate(const BatchInst& I, int64_t b, float select) {
+    if (b >= I.n || I.cls[b] != 0) return false;
+    if (select <= 0.f) return true;
+    const int rows = I.prop.rows;
+    return slr_decision_distance(I.glo + b * rows, I.ghi + b * rows, rows) <= select;
+}
+
+// Candidates per 1024-box bookkeeping tile, and per instance.
+__global__ __launch_bounds__(256) void batch_alpha_cand_kernel(BatchInst* insts, int n_inst,
+                                                               BatchCtl* ctl,
+                                                               const unsigned* __restrict__ cpre,
+                                                               unsigned* __restrict__ tile_cand,
+                                                               float select) {
+    __shared__ unsigned red[4];
+    const unsigned total = ctl->ctiles;
+    for (unsigned t = blockIdx.x; t < total; t += gridDim.x) {
+        const int i = find_owner(cpre, 0, n_inst, t);
+        BatchInst& I = insts[i];
+        unsigned cnt = 0;
+        if (alpha_level(I)) {
+            const int64_t b0 = (int64_t)(t - cpre[i]) * kTile + threadIdx.x * 4;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) cnt += alpha_candidate(I, b0 + q, select) ? 1u : 0u;
+        }
+        cnt = block_sum256(cnt, red);
+        if (threadIdx.x == 0) {
+            tile_cand[t] = cnt;
+            if (cnt) atomicAdd(&I.acand, cnt);
+        }
+        __syncthreads();
+    }
+}
+
+// Segments: per alpha class (one thread each), its instances in order take min(candidates,
+// room) boxes at 16-aligned offsets of the class buffers, and tape room for their tiles.
+__global__ void batch_alpha_plan_kernel(BatchInst* insts, BatchCtl* ctl, const BatchAlphaBuf* bufs,
+                                        int n_acls) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= n_acls) return;
+    const BatchAlphaBuf& B = bufs[c];
+    unsigned used = 0;
+    unsigned long long tape = 0;
+    for (int k = 0; k < B.ninst; ++k) {
+        BatchInst& I = insts[B.inst[k]];
+        const unsigned room = B.cap - used;
+        const unsigned len = min(I.acand, room);
+        I.aseg = used;
+        I.alen = len;
+        I.atape = tape;
+        I.n_alpha_boxes += len;
+        I.acand = 0;
+        B.seg[k] = used;
+        const unsigned tiles = (len + 15) / 16;
+        used += 16 * tiles;
+        tape += (unsigned long long)tiles * I.atile_floats;
+    }
+    ctl->antiles[c] = used / 16;
+}
+
+// The candidates of one bookkeeping tile go, in box order, to their instance's segment (those
+// beyond its length stay undecided with their plain bounds).
+__global__ __launch_bounds__(256) void batch_alpha_gather_kernel(BatchInst* insts, int n_inst,
+                                                                 BatchCtl* ctl,
+                                                                 const unsigned* __restrict__ cpre,
+                                                                 const unsigned* __restrict__ tile_cand,
+                                                                 const BatchAlphaBuf* bufs,
+                                                                 float select) {
+    __shared__ unsigned red[4];
+    __shared__ unsigned wpre[4];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const unsigned total = ctl->ctiles;
+    for (unsigned t = blockIdx.x; t < total; t += gridDim.x) {
+        const int i = find_owner(cpre, 0, n_inst, t);
+        const BatchInst& I = insts[i];
+        if (!alpha_level(I) || I.alen == 0 || tile_cand[t] == 0) continue;   // uniform
+        // candidates of the instance's earlier tiles
+        unsigned pre = 0;
+        for (unsigned k = cpre[i] + tid; k < t; k += 256) pre += tile_cand[k];
+        const unsigned base = block_sum256(pre, red);
+        const int64_t b0 = (int64_t)(t - cpre[i]) * kTile + tid * 4;
+        unsigned flags = 0, cnt = 0;
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+            if (alpha_candidate(I, b0 + q, select)) {
+                flags |= 1u << q;
+                ++cnt;
+            }
+        unsigned incl = cnt;
+        for (int o = 1; o < 64; o <<= 1) {
+            const unsigned x = __shfl_up(incl, o);
+            if (lane >= o) incl += x;
+        }
+        if (lane == 63) wpre[wave] = incl;
+        __syncthreads();
+        unsigned rank = base + incl - cnt;
+        for (int w = 0; w < wave; ++w) rank += wpre[w];
+        const BatchAlphaBuf& B = bufs[I.acls_id];
+        const int d = I.d;
+        const float* lo = I.lo[I.cur];
+        const float* hi = I.hi[I.cur];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            if (!(flags & (1u << q))) continue;
+            if (rank < I.alen) {
+                const int64_t b = b0 + q;
+                const size_t o = (size_t)I.aseg * B.dmax + (size_t)rank * d;
+                for (int k = 0; k < d; ++k) {
+                    B.lo[o + k] = lo[b * d + k];
+                    B.hi[o + k] = hi[b * d + k];
+                }
+                B.list[I.aseg + rank] = (unsigned)b;
+            }
+            ++rank;
+        }
         __syncthreads();
     }
 }
@@ -357,6 +491,30 @@ hipError_t launch_batch_split(BatchInst* insts, int n_inst, BatchCtl* ctl, const
     (void)hipGetLastError();
     hipLaunchKernelGGL(batch_split_kernel, dim3(2048), dim3(256),
                        2 * sizeof(float) * kTile * kSplitStageD, stream, insts, n_inst, ctl, cpre);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_alpha_cand(BatchInst* insts, int n_inst, BatchCtl* ctl, const unsigned* cpre,
+                                   unsigned* tile_cand, float select, hipStream_t stream) {
+    (void)hipGetLastError();
+    hipLaunchKernelGGL(batch_alpha_cand_kernel, dim3(2048), dim3(256), 0, stream, insts, n_inst, ctl,
+                       cpre, tile_cand, select);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_alpha_plan(BatchInst* insts, BatchCtl* ctl, const BatchAlphaBuf* bufs,
+                                   int n_acls, hipStream_t stream) {
+    (void)hipGetLastError();
+    hipLaunchKernelGGL(batch_alpha_plan_kernel, dim3(1), dim3(64), 0, stream, insts, ctl, bufs, n_acls);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_alpha_gather(BatchInst* insts, int n_inst, BatchCtl* ctl, const unsigned* cpre,
+                                     const unsigned* tile_cand, const BatchAlphaBuf* bufs, float select,
+                                     hipStream_t stream) {
+    (void)hipGetLastError();
+    hipLaunchKernelGGL(batch_alpha_gather_kernel, dim3(2048), dim3(256), 0, stream, insts, n_inst,
+                       ctl, cpre, tile_cand, bufs, select);
     return hipGetLastError();
 }
 

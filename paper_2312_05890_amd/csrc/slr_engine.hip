@@ -748,8 +748,6 @@ int alpha_run(const slr_net* net, const slr_property* prop, int64_t n, const flo
     const NetDev& nd = net->dev;
     const PropDev& pd = prop->dev;
     HIP_TRY(launch_center_objective(nd, pd, n, lo, hi, w.obj, s), "alpha: center kernel");
-    HIP_TRY(hipMemsetAsync(w.m, 0, sizeof(float) * (size_t)n * nd.nh, s), "alpha: clear");
-    HIP_TRY(hipMemsetAsync(w.v, 0, sizeof(float) * (size_t)n * nd.nh, s), "alpha: clear");
     AlphaArgs a{};
     a.n = n;
     a.lo = lo;
@@ -762,9 +760,6 @@ int alpha_run(const slr_net* net, const slr_property* prop, int64_t n, const flo
     a.cls = cls;
     a.tape = w.tape;
     a.raw = o.raw;
-    a.init = 1;
-    HIP_TRY(launch_alpha_forward(nd, pd, a, s), "alpha: forward kernel");
-    a.init = 0;
     a.obj = w.obj;
     a.adam_m = w.m;
     a.adam_v = w.v;
@@ -772,6 +767,19 @@ int alpha_run(const slr_net* net, const slr_property* prop, int64_t n, const flo
     a.beta1 = o.beta1;
     a.beta2 = o.beta2;
     a.eps = o.eps;
+    if (alpha_fused()) {
+        // every tile runs its whole optimization in one launch (init forward, then the steps)
+        HIP_TRY(launch_alpha_optimize(nd, pd, a, o.steps, s), "alpha: optimizer kernel");
+        return SLR_OK;
+    }
+    HIP_TRY(hipMemsetAsync(w.m, 0, sizeof(float) * (size_t)n * nd.nh, s), "alpha: clear");
+    HIP_TRY(hipMemsetAsync(w.v, 0, sizeof(float) * (size_t)n * nd.nh, s), "alpha: clear");
+    a.init = 1;
+    AlphaArgs a0 = a;
+    a0.obj = nullptr;
+    a0.adam_m = a0.adam_v = nullptr;
+    HIP_TRY(launch_alpha_forward(nd, pd, a0, s), "alpha: forward kernel");
+    a.init = 0;
     double p1 = 1.0, p2 = 1.0;
     for (int t = 1; t <= o.steps; ++t) {
         p1 *= o.beta1;
@@ -785,6 +793,13 @@ int alpha_run(const slr_net* net, const slr_property* prop, int64_t n, const flo
 }
 
 }  // namespace
+
+extern "C" int alpha_kernel_variant(int32_t variant) {
+    g_err.clear();
+    if (variant != 0 && variant != 1) return fail(SLR_EINVAL, "alpha_kernel_variant: must be 0 or 1");
+    set_alpha_fused(variant);
+    return SLR_OK;
+}
 
 extern "C" int alpha_size(const slr_net* net, int64_t* nh) {
     g_err.clear();
@@ -1749,6 +1764,17 @@ struct slr_batch {
         size_t lds;
     };
     std::vector<Cls> cls;
+    // alpha pass (batch_create_opts with alpha_steps > 0)
+    struct ACls {
+        int key;
+        size_t lds;
+        BatchAlphaBuf buf;
+    };
+    std::vector<ACls> acls;
+    BatchAlphaBuf* abufs = nullptr;   // device copy of the classes' buffers
+    unsigned* tile_cand = nullptr;
+    int alpha_steps = 0;
+    float alpha_lr = 0.1f, alpha_select = 0.f;
     int nrow = 0, ncol_max = 0;
     hipStream_t cap = nullptr;
     hipGraph_t graph = nullptr;
@@ -1771,6 +1797,23 @@ int batch_enqueue(const slr_batch* b, hipStream_t s) {
                     "batch: bound kernel");
         }
         HIP_TRY(launch_batch_recheck(b->insts, b->ctl, b->amb, b->nrow, b->ncol_max, s), "batch: recheck kernel");
+        if (!b->acls.empty()) {
+            HIP_TRY(launch_batch_alpha_cand(b->insts, b->n_inst, b->ctl, b->cpre, b->tile_cand,
+                                            b->alpha_select, s), "batch: alpha candidate kernel");
+            HIP_TRY(launch_batch_alpha_plan(b->insts, b->ctl, b->abufs, (int)b->acls.size(), s),
+                    "batch: alpha plan kernel");
+            HIP_TRY(launch_batch_alpha_gather(b->insts, b->n_inst, b->ctl, b->cpre, b->tile_cand,
+                                              b->abufs, b->alpha_select, s), "batch: alpha gather kernel");
+            AlphaArgs base{};
+            base.lr = b->alpha_lr;
+            base.beta1 = 0.9f;
+            base.beta2 = 0.999f;
+            base.eps = 1e-8f;
+            for (size_t c = 0; c < b->acls.size(); ++c)
+                HIP_TRY(launch_batch_alpha_class(b->acls[c].key, b->acls[c].lds, b->insts, b->ctl, (int)c,
+                                                 b->acls[c].buf, base, b->alpha_steps, s),
+                        "batch: alpha kernels");
+        }
         HIP_TRY(launch_batch_count(b->insts, b->n_inst, b->ctl, b->cpre, s), "batch: count kernel");
         HIP_TRY(launch_batch_advance(b->insts, b->n_inst, s), "batch: advance kernel");
         HIP_TRY(launch_batch_split(b->insts, b->n_inst, b->ctl, b->cpre, s), "batch: split kernel");
@@ -1794,9 +1837,27 @@ extern "C" int batch_create(int32_t n_inst, const slr_net* const* nets,
                             const slr_property* const* props, const double* const* lo,
                             const double* const* hi, const int32_t* max_depth,
                             const int64_t* max_leaves, int32_t use_graph, slr_batch** out) {
+    slr_batch_opts o{};
+    o.use_graph = use_graph;
+    return batch_create_opts(n_inst, nets, props, lo, hi, max_depth, max_leaves, &o, out);
+}
+
+extern "C" int batch_create_opts(int32_t n_inst, const slr_net* const* nets,
+                                 const slr_property* const* props, const double* const* lo,
+                                 const double* const* hi, const int32_t* max_depth,
+                                 const int64_t* max_leaves, const slr_batch_opts* opts,
+                                 slr_batch** out) {
     g_err.clear();
     if (!out) return fail(SLR_EINVAL, "batch_create: out is NULL");
     *out = nullptr;
+    if (!opts) return fail(SLR_EINVAL, "batch_create: opts is NULL");
+    const int32_t use_graph = opts->use_graph;
+    if (opts->alpha_steps < 0 || opts->alpha_steps > 1000)
+        return fail(SLR_EINVAL, "batch_create: alpha_steps must be in [0, 1000]");
+    if (!(opts->alpha_lr >= 0.f) || opts->alpha_min_depth < 0 || opts->alpha_chunk < 0)
+        return fail(SLR_EINVAL, "batch_create: alpha_lr, alpha_min_depth and alpha_chunk must be >= 0");
+    if (!(opts->alpha_select >= 0.f) || !std::isfinite(opts->alpha_select))
+        return fail(SLR_EINVAL, "batch_create: alpha_select must be finite and >= 0");
     if (n_inst < 1 || n_inst > SLR_MAX_BATCH)
         return fail(SLR_EINVAL, "batch_create: n_inst must be in [1, %d]", SLR_MAX_BATCH);
     if (!nets || !props || !lo || !hi || !max_depth || !max_leaves)
@@ -1877,6 +1938,83 @@ extern "C" int batch_create(int32_t n_inst, const slr_net* const* nets,
         r.stats = take(sizeof(LevelStats) * SLR_MAX_LEVELS);
         r.root = take(sizeof(float) * 2 * d);
     }
+    // alpha pass: classes by kernel template, plain bounds per instance, class buffers
+    const bool use_alpha = opts->alpha_steps > 0;
+    std::vector<int> akey(n_inst, -1), acls_of(n_inst, -1);
+    std::vector<size_t> aglo(n_inst, 0), aghi(n_inst, 0);
+    std::vector<std::vector<int>> ainst;
+    struct ARegs {
+        size_t lo, hi, alpha, m, v, glo, ghi, blo, bhi, cls, obj, list, seg, inst, tape;
+    };
+    std::vector<ARegs> areg;
+    size_t o_abufs = 0, o_tcand = 0;
+    if (use_alpha) {
+        b->alpha_steps = opts->alpha_steps;
+        b->alpha_lr = opts->alpha_lr > 0.f ? opts->alpha_lr : 0.1f;
+        b->alpha_select = opts->alpha_select;
+        const unsigned cap = (unsigned)(((opts->alpha_chunk > 0 ? opts->alpha_chunk : 8192) + 15) / 16 * 16);
+        size_t ctiles = 0;
+        for (int p = 0; p < n_inst; ++p) {
+            const int i = b->order[p];
+            size_t lds = 0;
+            akey[p] = batch_alpha_key(nets[i]->dev, props[i]->dev, &lds);
+            if (akey[p] < 0) {
+                batch_free(b);
+                return fail(SLR_EUNSUPPORTED, "batch_create: instance %d has no alpha kernel", i);
+            }
+            int c = -1;
+            for (size_t k = 0; k < b->acls.size(); ++k)
+                if (b->acls[k].key == akey[p]) c = (int)k;
+            if (c < 0) {
+                if ((int)b->acls.size() == SLR_MAX_CLASSES) {
+                    batch_free(b);
+                    return fail(SLR_EINTERNAL, "batch_create: too many alpha classes");
+                }
+                b->acls.push_back({akey[p], 0, BatchAlphaBuf{}});
+                ainst.emplace_back();
+                c = (int)b->acls.size() - 1;
+                b->acls[c].buf.cap = cap;
+            }
+            acls_of[p] = c;
+            ainst[c].push_back(p);
+            auto& A = b->acls[c];
+            A.lds = std::max(A.lds, lds);
+            A.buf.dmax = std::max(A.buf.dmax, nets[i]->dev.d);
+            A.buf.nhmax = std::max(A.buf.nhmax, nets[i]->dev.nh);
+            A.buf.rowsmax = std::max(A.buf.rowsmax, props[i]->dev.rows);
+            aglo[p] = take(sizeof(float) * props[i]->dev.rows * (size_t)max_leaves[i]);
+            aghi[p] = take(sizeof(float) * props[i]->dev.rows * (size_t)max_leaves[i]);
+            ctiles += level_tiles(max_leaves[i]);
+        }
+        o_tcand = take(sizeof(unsigned) * ctiles);
+        o_abufs = take(sizeof(BatchAlphaBuf) * b->acls.size());
+        areg.resize(b->acls.size());
+        for (size_t c = 0; c < b->acls.size(); ++c) {
+            const BatchAlphaBuf& B = b->acls[c].buf;
+            size_t tile_floats = 0;
+            for (int p : ainst[c]) {
+                const int i = b->order[p];
+                const AlphaShape sh = alpha_shape(nets[i]->dev, props[i]->dev);
+                tile_floats = std::max(tile_floats, (size_t)sh.slots * sh.slot_floats);
+            }
+            ARegs& r = areg[c];
+            r.lo = take(sizeof(float) * B.cap * B.dmax);
+            r.hi = take(sizeof(float) * B.cap * B.dmax);
+            r.alpha = take(sizeof(float) * B.cap * B.nhmax);
+            r.m = take(sizeof(float) * B.cap * B.nhmax);
+            r.v = take(sizeof(float) * B.cap * B.nhmax);
+            r.glo = take(sizeof(float) * B.cap * B.rowsmax);
+            r.ghi = take(sizeof(float) * B.cap * B.rowsmax);
+            r.blo = take(sizeof(float) * B.cap * B.rowsmax);
+            r.bhi = take(sizeof(float) * B.cap * B.rowsmax);
+            r.cls = take(B.cap);
+            r.obj = take(2 * (size_t)B.cap);
+            r.list = take(sizeof(unsigned) * B.cap);
+            r.seg = take(sizeof(unsigned) * ainst[c].size());
+            r.inst = take(sizeof(int) * ainst[c].size());
+            r.tape = take(sizeof(float) * (B.cap / 16) * tile_floats);
+        }
+    }
     hipError_t e = hipMalloc(&b->mem, o);
     if (e != hipSuccess) {
         delete b;
@@ -1888,6 +2026,47 @@ extern "C" int batch_create(int32_t n_inst, const slr_net* const* nets,
     b->bpre = (unsigned*)(base + o_bpre);
     b->cpre = (unsigned*)(base + o_cpre);
     b->amb = (unsigned*)(base + o_amb);
+    if (use_alpha) {
+        b->tile_cand = (unsigned*)(base + o_tcand);
+        b->abufs = (BatchAlphaBuf*)(base + o_abufs);
+        for (size_t c = 0; c < b->acls.size(); ++c) {
+            BatchAlphaBuf& B = b->acls[c].buf;
+            const ARegs& r = areg[c];
+            B.lo = (float*)(base + r.lo);
+            B.hi = (float*)(base + r.hi);
+            B.alpha = (float*)(base + r.alpha);
+            B.m = (float*)(base + r.m);
+            B.v = (float*)(base + r.v);
+            B.glo = (float*)(base + r.glo);
+            B.ghi = (float*)(base + r.ghi);
+            B.blo = (float*)(base + r.blo);
+            B.bhi = (float*)(base + r.bhi);
+            B.cls = (int8_t*)(base + r.cls);
+            B.obj = (int8_t*)(base + r.obj);
+            B.list = (unsigned*)(base + r.list);
+            B.seg = (unsigned*)(base + r.seg);
+            B.tape = (float*)(base + r.tape);
+            B.inst = (const int*)(base + r.inst);
+            B.ninst = (int)ainst[c].size();
+            e = hipMemcpy(base + r.inst, ainst[c].data(), sizeof(int) * ainst[c].size(), hipMemcpyHostToDevice);
+            if (e != hipSuccess) {
+                batch_free(b);
+                return hip_fail(e, "batch_create: upload");
+            }
+            e = batch_alpha_prepare(b->acls[c].key, b->acls[c].lds);
+            if (e != hipSuccess) {
+                batch_free(b);
+                return hip_fail(e, "batch_create: alpha kernel");
+            }
+        }
+        std::vector<BatchAlphaBuf> hb;
+        for (auto& a : b->acls) hb.push_back(a.buf);
+        e = hipMemcpy(b->abufs, hb.data(), sizeof(BatchAlphaBuf) * hb.size(), hipMemcpyHostToDevice);
+        if (e != hipSuccess) {
+            batch_free(b);
+            return hip_fail(e, "batch_create: upload");
+        }
+    }
     b->host.assign(n_inst, BatchInst{});
     int levels = 0;
     for (int p = 0; p < n_inst; ++p) {
@@ -1910,6 +2089,16 @@ extern "C" int batch_create(int32_t n_inst, const slr_net* const* nets,
         I.max_leaves = max_leaves[i];
         I.cls_id = cls_of[p];
         I.sp = 4 * I.net.mt_max + ((I.net.mt_max & 1) ? 0 : 4);
+        I.acls_id = -1;
+        if (use_alpha) {
+            const AlphaShape sh = alpha_shape(I.net, I.prop);
+            I.glo = (float*)(base + aglo[p]);
+            I.ghi = (float*)(base + aghi[p]);
+            I.acls_id = acls_of[p];
+            I.alpha_min_depth = opts->alpha_min_depth;
+            I.aslots = sh.slots;
+            I.atile_floats = (unsigned long long)sh.slots * sh.slot_floats;
+        }
         levels = std::max(levels, max_depth[i] + 1);
         std::vector<float> root(2 * I.d);
         for (int k = 0; k < I.d; ++k) {
@@ -2015,6 +2204,8 @@ extern "C" int batch_run(slr_batch* b, void* stream, slr_count_result* results) 
         r.depth_reached = I.levels - 1;
         r.status = I.status;
         r.seconds = secs;
+        r.n_alpha_boxes = I.n_alpha_boxes;
+        r.n_alpha_decided = I.n_alpha_decided;
         if (I.status == SLR_BUDGET) worst = SLR_BUDGET;
     }
     return worst;

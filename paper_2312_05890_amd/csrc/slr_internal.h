@@ -199,6 +199,15 @@ hipError_t launch_alpha_forward(const NetDev& net, const PropDev& prop, const Al
                                 hipStream_t stream);
 hipError_t launch_alpha_backward(const NetDev& net, const PropDev& prop, const AlphaArgs& a,
                                  hipStream_t stream);
+// 0 (default): single-instance alpha optimizations run one launch per forward/adjoint pass;
+// 1: one fused launch.  Both compute the same values.  Returns -1 for an unknown value.
+int set_alpha_fused(int v);
+int alpha_fused();
+// A whole optimization per tile in one launch: forward with init, then `steps` (adjoint with the
+// projected Adam step, forward); a.obj, a.adam_m and a.adam_v must be set (the moments are
+// cleared by the kernel), a.init and a.c1/a.c2 are ignored.
+hipError_t launch_alpha_optimize(const NetDev& net, const PropDev& prop, const AlphaArgs& a,
+                                 int steps, hipStream_t stream);
 // obj[b][0] = 1 if every property row is > 0 at the box center, obj[b][1] = argmin row there
 // Level helpers of the alpha pass inside the exact count.
 // Undecided boxes (cls 0) into list; with g_lo/g_hi ([n][rows]) only those whose decision
@@ -246,7 +255,49 @@ struct BatchInst {
     unsigned pad;
     double vol[3];
     unsigned long long counts[3];
+    // alpha pass of batches with alpha options (acls_id < 0: none for this instance)
+    float* glo;                  // [max_leaves][rows] widened plain bounds of the level
+    float* ghi;
+    int acls_id, alpha_min_depth;
+    int aslots;                  // tape slots per 16-box tile
+    unsigned acand;              // candidates at this level (summed by the candidate kernel)
+    unsigned aseg, alen;         // segment of the alpha class's buffers: first box (16-aligned), boxes
+    unsigned long long atile_floats;   // tape floats per tile
+    unsigned long long atape;    // first tape float of the segment
+    long long n_alpha_boxes, n_alpha_decided;
 };
+
+// Buffers of one alpha class of a batch (instances whose alpha kernels share a template): every
+// instance optimized at a level owns a segment of cap boxes; per-box rows use the class's largest
+// stride (d, nh, rows) as the segment base and the instance's own stride inside it.
+struct BatchAlphaBuf {
+    float *lo, *hi;              // [cap][dmax]
+    float *alpha, *m, *v;        // [cap][nhmax]
+    float *glo, *ghi, *blo, *bhi;   // [cap][rowsmax]
+    int8_t* cls;                 // [cap]
+    int8_t* obj;                 // [cap][2]
+    unsigned* list;              // [cap] instance-local box index
+    unsigned* seg;               // [ninst] segment start of each instance of the class (plan)
+    float* tape;
+    int dmax, nhmax, rowsmax;
+    unsigned cap;
+    const int* inst;             // [ninst] instance positions
+    int ninst;
+};
+
+// Device-side decision distance of a box (see slr_exact_opts.alpha_select): the smaller of the
+// unsafe distance (largest (-g_lo)/(g_hi - g_lo) over rows with g_lo <= 0) and the safe distance
+// (smallest g_hi/(g_hi - g_lo) over the rows).
+__device__ __forceinline__ float slr_decision_distance(const float* glo, const float* ghi, int rows) {
+    float du = 0.f, ds = INFINITY;
+    for (int r = 0; r < rows; ++r) {
+        const float w = ghi[r] - glo[r];
+        if (!(w > 0.f)) continue;
+        if (glo[r] <= 0.f) du = fmaxf(du, -glo[r] / w);
+        ds = fminf(ds, ghi[r] / w);
+    }
+    return fminf(du, ds);
+}
 
 struct BatchCtl {
     unsigned head[SLR_MAX_CLASSES];     // bound work-queue heads (one queue per kernel class)
@@ -254,6 +305,7 @@ struct BatchCtl {
     int tbox[SLR_MAX_CLASSES];          // boxes per bound tile of each class
     unsigned amb_count;                 // boxes listed for the FP64 re-decision
     unsigned ctiles;                    // 1024-box bookkeeping tiles at the current level
+    unsigned antiles[SLR_MAX_CLASSES];  // alpha tiles per alpha class at the current level
 };
 
 // Kernel class of the batch bound kernel: NCOL and the tile shape of the LDS-staged tile.
@@ -276,4 +328,21 @@ hipError_t launch_batch_advance(BatchInst* insts, int n_inst, hipStream_t stream
 hipError_t launch_batch_split(BatchInst* insts, int n_inst, BatchCtl* ctl, const unsigned* cpre,
                               hipStream_t stream);
 hipError_t launch_batch_volume(BatchInst* insts, int n_inst, hipStream_t stream);
+// Alpha pass of a batch level (after the FP64 re-decision, before the count): candidates per
+// bookkeeping tile and instance, segments per alpha class, gathered boxes; then per alpha class
+// the centre objective, the fused optimizer and the scatter of decided classes.
+hipError_t launch_batch_alpha_cand(BatchInst* insts, int n_inst, BatchCtl* ctl, const unsigned* cpre,
+                                   unsigned* tile_cand, float select, hipStream_t stream);
+hipError_t launch_batch_alpha_plan(BatchInst* insts, BatchCtl* ctl, const BatchAlphaBuf* bufs,
+                                   int n_acls, hipStream_t stream);
+hipError_t launch_batch_alpha_gather(BatchInst* insts, int n_inst, BatchCtl* ctl, const unsigned* cpre,
+                                     const unsigned* tile_cand, const BatchAlphaBuf* bufs, float select,
+                                     hipStream_t stream);
+// Kernel template of an instance's alpha pass (nc class, global state, register paths) and the
+// LDS of its fused optimizer; key packs the template.
+int batch_alpha_key(const NetDev& net, const PropDev& prop, size_t* lds);
+hipError_t batch_alpha_prepare(int key, size_t lds);
+hipError_t launch_batch_alpha_class(int key, size_t lds, BatchInst* insts, BatchCtl* ctl, int c,
+                                    const BatchAlphaBuf& buf, const AlphaArgs& base, int steps,
+                                    hipStream_t stream);
 int batch_num_cu();

@@ -25,7 +25,8 @@ EXPORTS = ("load_net", "free_net", "load_property", "free_property", "bound_boxe
            "bound_boxes_backward", "alpha_workspace_size", "alpha_optimize", "batch_create",
            "batch_run", "batch_free", "count_exact_batch", "bound_tile_shape",
            "alpha_state_variant", "count_exact_noalloc", "count_exact_noalloc_max_bytes",
-           "stack_workspace_size", "count_exact_stack")
+           "stack_workspace_size", "count_exact_stack", "alpha_kernel_variant",
+           "batch_create_opts")
 
 
 class SlrError(RuntimeError):
@@ -63,6 +64,12 @@ class StackOpts(C.Structure):
                 ("workspace_bytes", C.c_size_t), ("stream", C.c_void_p),
                 ("trace_capacity", C.c_int64), ("trace_depth", C.POINTER(C.c_int32)),
                 ("trace_path", C.POINTER(C.c_uint64)), ("trace_cls", C.POINTER(C.c_int8))]
+
+
+class BatchOpts(C.Structure):
+    _fields_ = [("use_graph", C.c_int32), ("alpha_steps", C.c_int32), ("alpha_lr", C.c_float),
+                ("alpha_min_depth", C.c_int32), ("alpha_select", C.c_float),
+                ("alpha_chunk", C.c_int32)]
 
 
 class AlphaOpts(C.Structure):
@@ -150,6 +157,10 @@ def lib() -> C.CDLL:
                                    C.POINTER(vp), C.POINTER(C.c_int32), C.POINTER(C.c_int64),
                                    i32, C.POINTER(vp)]
         L.batch_create.restype = C.c_int
+        L.batch_create_opts.argtypes = [i32, C.POINTER(vp), C.POINTER(vp), C.POINTER(vp),
+                                        C.POINTER(vp), C.POINTER(C.c_int32), C.POINTER(C.c_int64),
+                                        C.POINTER(BatchOpts), C.POINTER(vp)]
+        L.batch_create_opts.restype = C.c_int
         L.batch_run.argtypes = [vp, vp, C.POINTER(CountResult)]
         L.batch_run.restype = C.c_int
         L.batch_free.argtypes = [vp]
@@ -158,6 +169,8 @@ def lib() -> C.CDLL:
                                         C.POINTER(vp), C.POINTER(C.c_int32),
                                         C.POINTER(C.c_int64), vp, C.POINTER(CountResult)]
         L.count_exact_batch.restype = C.c_int
+        L.alpha_kernel_variant.argtypes = [i32]
+        L.alpha_kernel_variant.restype = C.c_int
         L.alpha_state_variant.argtypes = [i32]
         L.alpha_state_variant.restype = C.c_int
         L.bound_tile_shape.argtypes = [i32, i32, i32, i32, i32]
@@ -508,6 +521,11 @@ def alpha_state_variant(variant: int) -> None:
     _check(lib().alpha_state_variant(int(variant)))
 
 
+def alpha_kernel_variant(variant: int) -> None:
+    """0: one launch per alpha pass (default); 1: one fused launch per optimization."""
+    _check(lib().alpha_kernel_variant(int(variant)))
+
+
 def alpha_size(net: Net) -> int:
     """Slopes per box: the sum of the hidden widths."""
     out = C.c_int64()
@@ -676,13 +694,17 @@ class Batch:
     """Many exact counts advanced together on the device (``batch_create``); ``run()`` replays
     the captured graph (or issues the same launches) and returns one result dict per instance."""
 
-    def __init__(self, items, use_graph: bool = True):
+    def __init__(self, items, use_graph: bool = True, alpha_steps: int = 0,
+                 alpha_lr: float = 0.1, alpha_min_depth: int = 0, alpha_select: float = 0.0,
+                 alpha_chunk: int = 0):
         self.items = list(items)   # keeps nets and properties alive
         self.n = len(self.items)
         nets, props, lo, hi, depth, leaves, self._keep = _batch_arrays(self.items)
         h = C.c_void_p()
-        _check(lib().batch_create(self.n, nets, props, lo, hi, depth, leaves,
-                                  int(bool(use_graph)), C.byref(h)))
+        o = BatchOpts(int(bool(use_graph)), int(alpha_steps), float(alpha_lr),
+                      int(alpha_min_depth), float(alpha_select), int(alpha_chunk))
+        _check(lib().batch_create_opts(self.n, nets, props, lo, hi, depth, leaves, C.byref(o),
+                                       C.byref(h)))
         self.handle = h
 
     def run(self, stream=None):

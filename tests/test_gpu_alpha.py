@@ -249,6 +249,28 @@ def test_optimize_hand_derived_trajectory(w_out, dv, rows, steps):
     assert abs(a_ref[0, 0] - expect) <= 1e-7
 
 
+@pytest.mark.parametrize("name,n,scale", [("tiny2d", 37, 0.5), ("acas", 100, 0.2),
+                                          ("nav22", 21, 0.05), ("wide20", 20, 0.02)],
+                         ids=["tiny2d", "acas", "nav22", "wide20"])
+@pytest.mark.parametrize("raw", [0, 1])
+def test_fused_optimizer_equals_per_pass_launches(name, n, scale, raw):
+    """The fused optimizer (each tile runs its init pass and all Adam steps in one workgroup)
+    gives the per-pass launches' slopes, intersected bounds and classes bit for bit."""
+    inst, lo, hi = make(name, n, scale, seed=21)
+    net, prop = load(inst)
+    eng = E()
+    out = []
+    try:
+        for v in (0, 1):
+            eng.alpha_kernel_variant(v)
+            r = eng.alpha_optimize(net, prop, dev(lo), dev(hi), steps=7, raw=bool(raw))
+            out.append({k: t.cpu().numpy() for k, t in r.items()})
+    finally:
+        eng.alpha_kernel_variant(0)
+    for k in ("alpha", "best_lo", "best_hi", "cls"):
+        assert np.array_equal(out[0][k], out[1][k]), k
+
+
 @pytest.mark.parametrize("n", [0, 1, 17, 33])
 def test_ragged_batches(n):
     inst, lo, hi = make("acas", max(n, 1), 0.2, seed=13)

@@ -169,3 +169,84 @@ def test_batch_rejects_bad_input():
     inst = synth.tiny2d(0)
     with pytest.raises(eng.SlrError):
         eng.count_exact_batch(items_of([inst], leaves=(1 << 22) + 1))
+
+
+ALPHA_KEYS = KEYS + ("n_alpha_boxes", "n_alpha_decided")
+
+
+def _alpha_items():
+    """Mixed shapes with decisions: tiny2d seeds 0-3 (depth 12), the 5-input 6x50 network
+    (seed 1, depth 30, 2^12 leaves) and every (inputs, width) shape of the batch workload on
+    its 2^-4 sub-box (depth 4 d, 2^11 leaves)."""
+    insts = [synth.tiny2d(s) for s in range(4)] + [synth.acas(1)] + _one_per_shape(4)
+    depth = [12] * 4 + [30] + [i.max_depth for i in insts[5:]]
+    leaves = [1 << 12] * 5 + [1 << 11] * (len(insts) - 5)
+    eng = E()
+    items = []
+    for inst, D, M in zip(insts, depth, leaves):
+        net = eng.Net(inst.net)
+        items.append((net, eng.Property(net, inst.C, inst.dvec), inst.lo, inst.hi, D, M))
+    return insts, items
+
+
+@pytest.mark.parametrize("select", [0.0, 0.2])
+def test_batch_alpha_equals_count_exact_alpha(select):
+    """The batched alpha pass (fused optimizer per tile, segments per alpha class) gives every
+    instance exactly the counts, volumes, alpha boxes and alpha decisions of count_exact with the
+    same alpha options, and a bracket inside the plain count's."""
+    insts, items = _alpha_items()
+    kw = dict(alpha_steps=5, alpha_min_depth=3, alpha_select=select)
+    res = E().Batch(items, alpha_chunk=1 << 16, **kw).run()
+    decided = 0
+    for it, r in zip(items, res):
+        net, prop, lo, hi, D, M = it
+        s = E().count_exact(net, prop, lo, hi, D, M, alpha_chunk=1 << 16, **kw)
+        for k in ALPHA_KEYS:
+            assert r[k] == s[k], (k, r[k], s[k])
+        p = single(it)
+        assert r["unsafe"] >= p["unsafe"] and r["safe"] >= p["safe"]
+        decided += r["n_alpha_decided"]
+    assert decided > 0
+
+
+def test_batch_alpha_graph_replays_and_small_chunk():
+    """Graph replays equal direct launches; with room for only 16 boxes per class and level the
+    counts stay sound: brackets inside the plain ones, containing the full-room alpha ones."""
+    insts, items = _alpha_items()
+    kw = dict(alpha_steps=4, alpha_min_depth=2, alpha_select=0.2)
+    g = E().Batch(items, use_graph=True, alpha_chunk=1 << 16, **kw)
+    ref = E().Batch(items, use_graph=False, alpha_chunk=1 << 16, **kw).run()
+    x = torch.randn(1 << 18, device="cuda")
+    for rep in range(3):
+        for r, q in zip(g.run(), ref):
+            assert all(r[k] == q[k] for k in ALPHA_KEYS), rep
+        x = x.cos()
+        torch.cuda.synchronize()
+    small = E().Batch(items, alpha_chunk=16, **kw).run()
+    for it, r, q in zip(items, small, ref):
+        p = single(it)
+        assert r["unsafe"] + r["safe"] + r["undecided"] == 1.0
+        assert r["unsafe"] >= p["unsafe"] and r["safe"] >= p["safe"]
+        assert r["n_alpha_boxes"] <= q["n_alpha_boxes"]
+
+
+def test_batch_alpha_brackets_inside_oracle_plain():
+    """Alpha brackets lie inside the FP64 oracle's plain bracket (up to boxes within 1e-5 of a
+    decision, which the parity tests enumerate)."""
+    insts, items = _alpha_items()
+    res = E().Batch(items, alpha_steps=5, alpha_min_depth=3, alpha_select=0.2,
+                    alpha_chunk=1 << 16).run()
+    for inst, it, r in zip(insts[:5], items[:5], res[:5]):
+        o = count.count_exact(inst.net, inst.C, inst.dvec, inst.lo, inst.hi, it[4], it[5])
+        assert r["unsafe"] >= o["unsafe"] - 2.0 ** -it[4]
+        assert r["unsafe"] + r["undecided"] <= o["unsafe"] + o["undecided"] + 2.0 ** -it[4]
+
+
+def test_batch_rejects_bad_alpha_options():
+    insts, items = _alpha_items()
+    eng = E()
+    for bad in (dict(alpha_steps=-1), dict(alpha_steps=2, alpha_select=float("nan")),
+                dict(alpha_steps=2, alpha_min_depth=-1), dict(alpha_steps=2, alpha_chunk=-5)):
+        with pytest.raises(eng.SlrError) as e:
+            eng.Batch(items[:2], **bad)
+        assert e.value.code == -1

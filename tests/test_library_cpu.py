@@ -103,7 +103,8 @@ def test_tile_shape_validation_and_cache_roundtrip(tmp_path):
                                           ("slr_alpha_opts", "AlphaOpts"),
                                           ("slr_approx_opts", "ApproxOpts"),
                                           ("slr_approx_result", "ApproxResult"),
-                                          ("slr_stack_opts", "StackOpts")])
+                                          ("slr_stack_opts", "StackOpts"),
+                                          ("slr_batch_opts", "BatchOpts")])
 def test_binding_structs_match_the_header_layout(tmp_path, cname, pyname):
     """Every option and result struct of the binding has the header's size and field offsets
     (a probe compiled against include/slrcount.h with the host C compiler)."""
