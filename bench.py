@@ -28,6 +28,7 @@ METRIC = "boxes bounded/s + time-to-exact unsafe volume, plain vs batched+α on 
 PEAK_FP32_MFMA = 157.3      # TFLOP/s, MI355X dense FP32 matrix
 PEAK_HBM = 8000.0           # GB/s
 ALPHA_SELECT = 0.2          # alpha only on boxes within 20% of their bound width from a decision
+ALPHA_MIN_DEPTH_BATCH = 8   # first alpha level of the batched-plus-alpha count
 
 
 def flops_per_box(sizes, rows):
@@ -111,23 +112,32 @@ def split_report(res):
 
 
 def cpu_baseline(seed, leaves):
-    """The FP64 oracle, untuned, on the same network with a smaller leaf budget."""
+    """The FP64 oracle, untuned, on the same network with a smaller leaf budget: once with the
+    BLAS thread pool at its default (all the threads it takes on this host; os.cpu_count() is
+    recorded beside it) and once on one thread."""
     from oracle import count
     import synth
-    try:
-        from threadpoolctl import threadpool_info
-        cores = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
-    except Exception:
-        cores = os.cpu_count()
+    from threadpoolctl import threadpool_info, threadpool_limits
+    cores = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
     inst = synth.acas(seed)
-    t0 = time.perf_counter()
-    r = count.count_exact(inst.net, inst.C, inst.dvec, inst.lo, inst.hi, inst.max_depth, leaves)
-    dt = time.perf_counter() - t0
+
+    def run():
+        t0 = time.perf_counter()
+        r = count.count_exact(inst.net, inst.C, inst.dvec, inst.lo, inst.hi, inst.max_depth,
+                              leaves)
+        return r, time.perf_counter() - t0
+
+    r, dt = run()
+    with threadpool_limits(limits=1):
+        r1, dt1 = run()
     return {"value": r["n_boxes_bounded"] / dt, "unit": "boxes/s", "cores": cores,
             "kind": "oracle",
             "sample": f"FP64 NumPy oracle count_exact on the same network and property with a "
                       f"{leaves}-leaf budget ({r['n_boxes_bounded']} boxes, levels 0-"
-                      f"{r['depth_reached']}), {dt:.1f} s"}
+                      f"{r['depth_reached']}), {dt:.1f} s",
+            "host_cpu_count": os.cpu_count(),
+            "one_core": {"value": r1["n_boxes_bounded"] / dt1, "unit": "boxes/s", "cores": 1,
+                         "seconds": dt1}}
 
 
 def bench_alpha_optimize(E, torch, inst, n, steps, seed, reps=3):
@@ -228,6 +238,34 @@ def batch_section(E, torch, seed, reps=3):
                 for r, inst in zip(res, insts))
     agree = all(r[k] == q[k] for r, q in zip(res, seq)
                 for k in ("unsafe", "safe", "undecided", "n_boxes_bounded"))
+    # batched plus alpha (near-decision selection, 20 Adam steps) in the same graph
+    ba = E.Batch(items, use_graph=True, alpha_steps=20, alpha_min_depth=ALPHA_MIN_DEPTH_BATCH,
+                 alpha_select=ALPHA_SELECT, alpha_chunk=8192)
+    ra = ba.run()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        ra = ba.run()
+    t_alpha = (time.perf_counter() - t0) / reps
+    inside = all(a["unsafe"] >= q["unsafe"] and a["safe"] >= q["safe"] for a, q in zip(ra, seq))
+    # time to a bracket inside the plain one: the same batch plus alpha with smaller leaf
+    # budgets, counting the instances whose bracket lies inside their plain 2^16-leaf bracket
+    smaller = []
+    for shift in (1, 2, 3):
+        its = [it[:5] + (it[5] >> shift,) for it in items]
+        bs = E.Batch(its, use_graph=True, alpha_steps=20, alpha_min_depth=ALPHA_MIN_DEPTH_BATCH,
+                     alpha_select=ALPHA_SELECT, alpha_chunk=8192)
+        rs = bs.run()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rs = bs.run()
+        ts = time.perf_counter() - t0
+        smaller.append({"leaves": items[0][5] >> shift, "graph_ms": ts * 1e3,
+                        "instances_inside_plain": sum(1 for a, q in zip(rs, seq)
+                                                      if a["unsafe"] >= q["unsafe"]
+                                                      and a["safe"] >= q["safe"]),
+                        "speedup_vs_sequential_plain": t_seq / ts})
+        del bs
     return {"workload": "256 instances: d 5..10, 3..6 hidden layers of 32/64/96/128, 2..5 "
                         "outputs, c ~ N(0,1), [0,1]^d, depth 4d, 2^16 leaves each (seed %d)" % seed,
             "boxes_per_batch": boxes, "graph_ms": t_graph * 1e3, "direct_ms": t_direct * 1e3,
@@ -236,7 +274,43 @@ def batch_section(E, torch, seed, reps=3):
             "speedup_vs_sequential": t_seq / t_graph,
             "achieved_tflops_graph": flops / t_graph / 1e12,
             "results_equal_sequential": agree,
-            "instances_resolved": sum(1 for r in res if r["undecided"] == 0.0)}
+            "instances_resolved": sum(1 for r in res if r["undecided"] == 0.0),
+            "batched_alpha": {
+                "options": "20 Adam steps from depth %d on boxes within %.1f of a decision, "
+                           "8192 boxes per alpha class and level" % (ALPHA_MIN_DEPTH_BATCH,
+                                                                      ALPHA_SELECT),
+                "graph_ms": t_alpha * 1e3,
+                "speedup_vs_sequential_plain": t_seq / t_alpha,
+                "brackets_inside_plain": inside,
+                "alpha_boxes": sum(r["n_alpha_boxes"] for r in ra),
+                "alpha_decided": sum(r["n_alpha_decided"] for r in ra),
+                "unsafe_volume_sum": sum(r["unsafe"] for r in ra),
+                "unsafe_volume_sum_plain": sum(r["unsafe"] for r in seq),
+                "safe_volume_sum": sum(r["safe"] for r in ra),
+                "safe_volume_sum_plain": sum(r["safe"] for r in seq),
+                "smaller_budgets": smaller}}
+
+
+def stack_section(E, torch, seed, depth=24, reps=2):
+    """count_exact_stack (depth-first chunks, no leaf budget) on the same network past the
+    2^20-leaf budget of the headline count."""
+    import synth
+    inst = synth.acas(seed)
+    net = E.Net(inst.net)
+    prop = E.Property(net, inst.C, inst.dvec)
+    ws = torch.empty(E.stack_workspace_size(net, prop, depth), dtype=torch.uint8, device="cuda")
+    E.count_exact_stack(net, prop, inst.lo, inst.hi, depth, workspace=ws)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        r = E.count_exact_stack(net, prop, inst.lo, inst.hi, depth, workspace=ws)
+    dt = (time.perf_counter() - t0) / reps
+    return {"workload": "count_exact_stack, 5-50x6-5 network (seed %d), [0,1]^5, depth %d, "
+                        "no leaf budget, 65536-box chunks" % (seed, depth),
+            "time_to_bracket_ms": dt * 1e3, "boxes_bounded": r["n_boxes_bounded"],
+            "boxes_per_s": r["n_boxes_bounded"] / dt,
+            "bracket": [r["unsafe"], r["unsafe"] + r["undecided"]],
+            "workspace_mb": ws.numel() / 1e6}
 
 
 def approx_section(E, torch, seed, cpu):
@@ -319,6 +393,8 @@ def main():
                     help="skip the batched-instances measurement")
     ap.add_argument("--no-approx", action="store_true",
                     help="skip the approximate-count measurement")
+    ap.add_argument("--no-stack", action="store_true",
+                    help="skip the depth-first stack count past the leaf budget")
     ap.add_argument("--no-tile-cache", action="store_true",
                     help="ignore the autotuner's tile-shape cache (default shapes)")
     ap.add_argument("--variant", type=int, default=0,
@@ -409,6 +485,8 @@ def main():
     }
     if not args.no_batch:
         line["batch"] = batch_section(E, torch, args.seed)
+    if not args.no_stack:
+        line["stack"] = stack_section(E, torch, args.seed)
     if not args.no_approx:
         line["approx"] = approx_section(E, torch, args.seed, not args.no_cpu_baseline)
     if not args.no_alpha:

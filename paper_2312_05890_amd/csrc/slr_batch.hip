@@ -71,17 +71,41 @@ __global__ __launch_bounds__(256) void batch_init_kernel(BatchInst* insts, int n
     }
 }
 
-__global__ void batch_plan_kernel(BatchInst* insts, int n_inst, BatchCtl* ctl,
-                                  unsigned* __restrict__ bpre, unsigned* __restrict__ cpre,
-                                  int n_classes) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    for (int c = 0; c < n_classes; ++c) {
-        ctl->ntiles[c] = 0;
-        ctl->head[c] = 0;
+// One workgroup of 1024 threads, thread i = instance i (instances are sorted by kernel class,
+// so each class is a contiguous run): applies the pending split, then two exclusive scans over
+// the instances, of their bound tiles (bpre: offset inside the instance's class) and of their
+// 1024-box bookkeeping tiles (cpre).
+__device__ __forceinline__ unsigned block_exclusive_scan1024(unsigned v, unsigned* wtot, unsigned* total) {
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    unsigned incl = v;
+    for (int o = 1; o < 64; o <<= 1) {
+        const unsigned x = __shfl_up(incl, o);
+        if (lane >= o) incl += x;
     }
-    ctl->amb_count = 0;
-    unsigned ctot = 0;
-    for (int i = 0; i < n_inst; ++i) {
+    if (lane == 63) wtot[wave] = incl;
+    __syncthreads();
+    unsigned pre = 0, all = 0;
+    for (int w = 0; w < 16; ++w) {
+        if (w < wave) pre += wtot[w];
+        all += wtot[w];
+    }
+    *total = all;
+    __syncthreads();
+    return pre + incl - v;
+}
+
+__global__ __launch_bounds__(1024) void batch_plan_kernel(BatchInst* insts, int n_inst, BatchCtl* ctl,
+                                                          unsigned* __restrict__ bpre,
+                                                          unsigned* __restrict__ cpre,
+                                                          int n_classes) {
+    __shared__ unsigned wtot[16];
+    __shared__ unsigned pstart[SLR_MAX_CLASSES];
+    const int i = threadIdx.x;
+    if (i < n_classes) ctl->head[i] = 0;
+    if (i == 0) ctl->amb_count = 0;
+    unsigned tb = 0, tc = 0;
+    int cid = -1;
+    if (i < n_inst) {
         BatchInst& I = insts[i];
         if (I.split_pending) {
             I.n = I.n_next;
@@ -90,18 +114,35 @@ __global__ void batch_plan_kernel(BatchInst* insts, int n_inst, BatchCtl* ctl,
             I.split_pending = 0;
         }
         const long long n = I.active ? I.n : 0;
-        const int T = ctl->tbox[I.cls_id];
-        bpre[i] = ctl->ntiles[I.cls_id];
-        ctl->ntiles[I.cls_id] += (unsigned)((n + T - 1) / T);
-        cpre[i] = ctot;
-        ctot += (unsigned)((n + kTile - 1) / kTile);
+        cid = I.cls_id;
+        const int T = ctl->tbox[cid];
+        tb = (unsigned)((n + T - 1) / T);
+        tc = (unsigned)((n + kTile - 1) / kTile);
     }
-    cpre[n_inst] = ctot;
-    ctl->ctiles = ctot;
+    unsigned tot_b, tot_c;
+    const unsigned pb = block_exclusive_scan1024(tb, wtot, &tot_b);
+    const unsigned pc = block_exclusive_scan1024(tc, wtot, &tot_c);
+    // the first instance of each class publishes its scan value
+    const bool first = i < n_inst && (i == 0 || insts[i - 1].cls_id != cid);
+    if (first) pstart[cid] = pb;
+    __syncthreads();
+    if (i < n_inst) {
+        bpre[i] = pb - pstart[cid];
+        cpre[i] = pc;
+        const bool last = i == n_inst - 1 || insts[i + 1].cls_id != cid;
+        if (last) ctl->ntiles[cid] = pb + tb - pstart[cid];
+    }
+    if (i == 0) {
+        cpre[n_inst] = tot_c;
+        ctl->ctiles = tot_c;
+    }
 }
 
+// insts is read-only here and aliases nothing the kernel writes, so descriptor loads need not be
+// repeated after the tile's stores.
 template <int NCOL, int NT, int UW, int NW>
-__global__ __launch_bounds__(NW * 64) void batch_bound_kernel(BatchInst* insts, BatchCtl* ctl,
+__global__ __launch_bounds__(NW * 64) void batch_bound_kernel(const BatchInst* __restrict__ insts,
+                                                              BatchCtl* ctl,
                                                               const unsigned* __restrict__ bpre,
                                                               int cbeg, int cend, int c,
                                                               unsigned* __restrict__ amb_list) {
@@ -425,7 +466,7 @@ hipError_t launch_batch_init(BatchInst* insts, int n_inst, hipStream_t stream) {
 hipError_t launch_batch_plan(BatchInst* insts, int n_inst, BatchCtl* ctl, unsigned* bpre,
                              unsigned* cpre, int n_classes, hipStream_t stream) {
     (void)hipGetLastError();
-    hipLaunchKernelGGL(batch_plan_kernel, dim3(1), dim3(64), 0, stream, insts, n_inst, ctl, bpre,
+    hipLaunchKernelGGL(batch_plan_kernel, dim3(1), dim3(1024), 0, stream, insts, n_inst, ctl, bpre,
                        cpre, n_classes);
     return hipGetLastError();
 }
