@@ -141,13 +141,86 @@ def relu_relax(L, U, lo_b, hi_b, xmag, alpha=None):
     return Ln, Un
 
 
-def propagate(net, C, dvec, lo, hi, alpha: Optional[np.ndarray] = None, keep: bool = False):
+def activation_of(net) -> str:
+    """'relu' (the paper's networks), or 'tanh' / 'sigmoid' for a net that carries ``act``."""
+    return getattr(net, "act", "relu")
+
+
+def act_fn(act: str, z):
+    """The activation itself, in float64."""
+    z = np.asarray(z, np.float64)
+    if act == "relu":
+        return np.maximum(z, 0.0)
+    if act == "tanh":
+        return np.tanh(z)
+    if act == "sigmoid":
+        return 1.0 / (1.0 + np.exp(-z))
+    raise ValueError(act)
+
+
+def act_critical(act: str, lam):
+    """The z >= 0 where the derivative of tanh (1 - tanh^2 z) or of the sigmoid (s (1 - s))
+    equals lam; the derivative is even and has one maximum at 0, so +-z are the only points
+    with that slope (none when lam exceeds the maximum, which a chord slope never does)."""
+    lam = np.asarray(lam, np.float64)
+    if act == "tanh":
+        t = np.sqrt(np.clip(1.0 - lam, 0.0, 1.0))
+        return np.arctanh(np.minimum(t, 1.0 - 1e-16))
+    s = np.sqrt(np.clip(1.0 - 4.0 * lam, 0.0, 1.0))
+    p = np.minimum(0.5 * (1.0 + s), 1.0 - 1e-16)
+    return np.log(p / (1.0 - p))
+
+
+def act_relax(L, U, lo_b, hi_b, xmag, act):
+    """Tanh or sigmoid on the equations, by two parallel lines (the extension of Eq. 1 the paper
+    leaves to future work, §3).
+
+    On [l, u] take the chord slope lam = (s(u) - s(l)) / (u - l) (the derivative at l for a
+    point); h(z) = s(z) - lam z then has its extrema over [l, u] at l, u or at the points +-z*
+    where s'(z) = lam, so lam z + min h <= s(z) <= lam z + max h on [l, u].  With lam > 0 and
+    L <= z <= U: L' = lam L + min h, U' = lam U + max h, plus rounding margins.
+    """
+    l = np.asarray(lo_b, np.float64)
+    u = np.asarray(hi_b, np.float64)
+    w = u - l
+    fl, fu = act_fn(act, l), act_fn(act, u)
+    if act == "tanh":
+        dl = 1.0 - np.tanh(l) ** 2
+    else:
+        dl = fl * (1.0 - fl)
+    lam = np.where(w > 0.0, (fu - fl) / np.where(w > 0.0, w, 1.0), dl)
+    zc = act_critical(act, lam)
+    hl, hu = fl - lam * l, fu - lam * u
+    bl = np.minimum(hl, hu)
+    bh = np.maximum(hl, hu)
+    for z in (zc, -zc):
+        inside = (z > l) & (z < u)
+        hz = act_fn(act, z) - lam * z
+        bl = np.where(inside, np.minimum(bl, hz), bl)
+        bh = np.where(inside, np.maximum(bh, hz), bh)
+    # rounding of the few evaluations above (library tanh/exp within a few ulp)
+    m = 16.0 * UNIT * (1.0 + np.abs(lam) * (np.abs(l) + np.abs(u)))
+    bl = bl - m
+    bh = bh + m
+    magL = magnitude(L, xmag)
+    magU = magnitude(U, xmag)
+    Ln = lam[..., None] * L
+    Un = lam[..., None] * U
+    Ln[..., 0] += bl - gamma(3) * lam * magL
+    Un[..., 0] += bh + gamma(3) * lam * magU
+    return Ln, Un
+
+
+def propagate(net, C, dvec, lo, hi, alpha: Optional[np.ndarray] = None, keep: bool = False,
+              equations: bool = False):
     """Output-property bounds for a batch of boxes.
 
     ``lo``/``hi``: [B, d] box corners.  ``alpha``: optional [B, sum of hidden widths] lower
     slopes in [0, 1] (replacing lam for crossing neurons).  Returns ``(g_lo, g_hi)`` of shape
     [B, rows]; with ``keep`` also a list with, per hidden layer, the pre-activation
-    equations and bounds and the post-activation equations (for soundness checks).
+    equations and bounds and the post-activation equations (for soundness checks); with
+    ``equations`` also the property rows' lower and upper equations ``(L, U)`` [B, rows, d+1]
+    (last, after the trace if both are asked for).
     """
     layers = _as64(net)
     lo = np.atleast_2d(np.asarray(lo, np.float64))
@@ -181,7 +254,12 @@ def propagate(net, C, dvec, lo, hi, alpha: Optional[np.ndarray] = None, keep: bo
             n = L.shape[1]
             a = np.asarray(alpha, np.float64)[:, a_off:a_off + n]
             a_off += n
-        Lr, Ur = relu_relax(L, U, lo_b, hi_b, xmag, a)
+        act = activation_of(net)
+        if act == "relu":
+            Lr, Ur = relu_relax(L, U, lo_b, hi_b, xmag, a)
+        else:
+            assert alpha is None, "alpha slopes are defined for ReLU networks only"
+            Lr, Ur = act_relax(L, U, lo_b, hi_b, xmag, act)
         if keep:
             trace.append(dict(L=L, U=U, lo=lo_b, hi=hi_b, Lr=Lr, Ur=Ur))
         if li == len(layers) - 1:
@@ -191,9 +269,12 @@ def propagate(net, C, dvec, lo, hi, alpha: Optional[np.ndarray] = None, keep: bo
             L, U = affine(Lr, Ur, W, b, xmag)
     g_lo = concretize_lower(L, lo, hi, xmag)
     g_hi = concretize_upper(U, lo, hi, xmag)
+    out = (g_lo, g_hi)
     if keep:
-        return g_lo, g_hi, trace
-    return g_lo, g_hi
+        out = out + (trace,)
+    if equations:
+        out = out + ((L, U),)
+    return out
 
 
 def classify(g_lo: np.ndarray, g_hi: np.ndarray) -> np.ndarray:
@@ -229,10 +310,11 @@ def forward(net, x: np.ndarray) -> np.ndarray:
     """Concrete FP64 forward pass; ``x`` [N, d] -> outputs [N, n_out]."""
     h = np.asarray(x, np.float64)
     layers = _as64(net)
+    act = activation_of(net)
     for i, (W, b) in enumerate(layers):
         h = h @ W.T + b
         if i < len(layers) - 1:
-            h = np.maximum(h, 0.0)
+            h = act_fn(act, h)
     return h
 
 
@@ -241,10 +323,11 @@ def preactivations(net, x: np.ndarray) -> List[np.ndarray]:
     h = np.asarray(x, np.float64)
     out = []
     layers = _as64(net)
+    act = activation_of(net)
     for W, b in layers[:-1]:
         z = h @ W.T + b
         out.append(z)
-        h = np.maximum(z, 0.0)
+        h = act_fn(act, z)
     return out
 
 

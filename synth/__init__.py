@@ -37,6 +37,35 @@ import numpy as np
 Net = List[Tuple[np.ndarray, np.ndarray]]
 
 
+class ActNet(list):
+    """A network (list of (W, b) layers) whose hidden activation is ``act`` ('tanh' or
+    'sigmoid') instead of ReLU."""
+
+    def __init__(self, layers, act: str):
+        super().__init__(layers)
+        self.act = act
+
+
+def with_activation(net, act: str):
+    """The same layers with another hidden activation."""
+    return ActNet(list(net), act)
+
+
+def tanh2d(seed: int, act: str = "tanh") -> "Instance":
+    """tiny2d's shape with a smooth activation: 2-16-16-1, [-1, 1]^2, y > 0, depth 16."""
+    base = tiny2d(seed)
+    return dataclasses.replace(base, name=f"{act}2d", net=with_activation(base.net, act))
+
+
+def smooth5(seed: int, act: str = "tanh", max_depth: int = 30,
+            max_leaves: int = 1 << 16) -> "Instance":
+    """A 5-input 3x32 network with a smooth activation, [0, 1]^5, y0 - y1 > 0."""
+    net = with_activation(make_net([5, 32, 32, 32, 5], seed), act)
+    lo, hi = _box(0.0, 1.0, 5)
+    C = np.array([[1.0, -1.0, 0.0, 0.0, 0.0]], np.float32)
+    return Instance(f"{act}5", net, lo, hi, C, np.zeros(1, np.float32), max_depth, max_leaves)
+
+
 @dataclasses.dataclass
 class Instance:
     """One verification instance: network, input box, property and search limits."""

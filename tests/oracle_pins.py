@@ -92,12 +92,14 @@ def _eval_eq(E, x):
     return E[..., 0] + np.einsum("ni,pi->pn", E[..., 1:], x) if E.ndim == 2 else None
 
 
-def pin_soundness(seed=0, n_boxes=6, n_points=4000, alpha=False):
+def pin_soundness(seed=0, n_boxes=6, n_points=4000, alpha=False, act="relu"):
     """Brute force: every sampled point (and every vertex) lies inside every bound."""
     rng = np.random.default_rng(seed)
     shapes = ([2, 16, 16, 1], [3, 8, 8, 2], [4, 10, 10, 10, 3])
     for si, sizes in enumerate(shapes):
         net = synth.make_net(sizes, seed * 10 + si)
+        if act != "relu":
+            net = synth.with_activation(net, act)
         n_out = sizes[-1]
         C = rng.normal(size=(min(2, n_out), n_out)).astype(np.float32)
         dv = rng.normal(scale=0.1, size=C.shape[0]).astype(np.float32)
@@ -118,7 +120,7 @@ def pin_soundness(seed=0, n_boxes=6, n_points=4000, alpha=False):
                 assert np.all(z <= Ux + 1e-12 * (1 + np.abs(z)))
                 assert np.all(t["lo"][b] <= z.min(axis=0))
                 assert np.all(z.max(axis=0) <= t["hi"][b])
-                a = np.maximum(z, 0.0)
+                a = slr.act_fn(act, z)
                 Lr = t["Lr"][b, :, 0] + x @ t["Lr"][b, :, 1:].T
                 Ur = t["Ur"][b, :, 0] + x @ t["Ur"][b, :, 1:].T
                 assert np.all(Lr <= a + 1e-12 * (1 + a))
@@ -176,9 +178,9 @@ def pin_abs_closed_form():
                 assert a >= 0.25 and b <= 0.75
 
 
-def pin_dense_grid(seed=0, cells=1024):
+def pin_dense_grid(seed=0, cells=1024, act="relu"):
     """tiny2d: leaves classify every point of an aligned grid correctly (no tolerance)."""
-    inst = synth.tiny2d(seed)
+    inst = synth.tiny2d(seed) if act == "relu" else synth.tanh2d(seed, act)
     r = count.count_exact(inst.net, inst.C, inst.dvec, inst.lo, inst.hi, inst.max_depth,
                           inst.max_leaves, trace=True)
     h = 2.0 / cells
@@ -287,6 +289,52 @@ def pin_alpha_objective_row():
     assert m[0] == 1
 
 
+def act_neuron_net(act):
+    """x -> z = x -> y = s(z) for s = tanh or the sigmoid."""
+    return synth.with_activation([(_f32([[1.0]]), _f32([0.0])), (_f32([[1.0]]), _f32([0.0]))], act)
+
+
+def pin_act_single_neuron_bruteforce():
+    """One tanh / sigmoid neuron on intervals left of, right of, around and far around 0: the
+    output bounds equal lam a + min h and lam b + max h, with lam the chord slope over [a, b]
+    and min / max of h(z) = s(z) - lam z found by brute force on 2e6 grid points (the exact
+    extrema lie within (step)^2 of the grid's), so a wrong critical point or a missing
+    candidate shows.  Left of 0 both functions are convex, so the chord is the upper line and
+    the upper bound at b is s(b) itself; right of 0 they are concave and the lower bound at a
+    is s(a)."""
+    for act in ("tanh", "sigmoid"):
+        f = (lambda z: np.tanh(z)) if act == "tanh" else (lambda z: 1.0 / (1.0 + np.exp(-z)))
+        net = act_neuron_net(act)
+        for a, b in ((-3.0, -1.0), (0.5, 2.5), (-1.0, 1.0), (-0.25, 4.0), (-20.0, 20.0),
+                     (-6.0, 0.125)):
+            g_lo, g_hi = slr.propagate(net, [[1.0]], [0.0], [[a]], [[b]])
+            lam = (f(b) - f(a)) / (b - a)
+            z = np.linspace(a, b, 2_000_001)
+            h = f(z) - lam * z
+            step = (b - a) / 2e6
+            assert g_lo[0, 0] <= lam * a + h.min() + 1e-12
+            assert g_lo[0, 0] >= lam * a + h.min() - step ** 2 - 1e-12, (act, a, b)
+            assert g_hi[0, 0] >= lam * b + h.max() - 1e-12
+            assert g_hi[0, 0] <= lam * b + h.max() + step ** 2 + 1e-12, (act, a, b)
+            if b <= 0.0:                       # convex piece: the chord lies above s
+                assert abs(g_hi[0, 0] - f(b)) < 1e-12
+            if a >= 0.0:                       # concave piece: the chord lies below s
+                assert abs(g_lo[0, 0] - f(a)) < 1e-12
+
+
+def pin_act_soundness():
+    """Random tanh and sigmoid networks: every sampled point lies inside every bound."""
+    for act in ("tanh", "sigmoid"):
+        pin_soundness(seed=3, n_boxes=4, n_points=2000, act=act)
+
+
+def pin_act_dense_grid():
+    """tanh and sigmoid versions of tiny2d: leaves classify an aligned grid correctly."""
+    for act in ("tanh", "sigmoid"):
+        pin_dense_grid(seed=1, cells=512, act=act)
+
+
 ALL_PINS = [pin_eq1_single_relu, pin_two_neurons, pin_linear_regime, pin_soundness,
             pin_irwin_hall, pin_abs_closed_form, pin_dense_grid, pin_accounting,
-            pin_alpha_adam_closed_form, pin_alpha_objective_row]
+            pin_alpha_adam_closed_form, pin_alpha_objective_row,
+            pin_act_single_neuron_bruteforce, pin_act_soundness, pin_act_dense_grid]

@@ -238,10 +238,39 @@ def _objective_mode_any(net, C, dvec, lo, hi):
     return np.any(gc > 0, axis=1).astype(np.int64), np.argmin(gc, axis=1)
 
 
+def _act_critical_no_sqrt(act, lam):
+    """Critical point from 1 - lam instead of its square root (tanh) / 1 - 4 lam (sigmoid)."""
+    lam = np.asarray(lam, np.float64)
+    if act == "tanh":
+        return np.arctanh(np.clip(1.0 - lam, 0.0, 1.0 - 1e-16))
+    p = np.minimum(0.5 * (1.0 + np.clip(1.0 - 4.0 * lam, 0.0, 1.0)), 1.0 - 1e-16)
+    return np.log(p / (1.0 - p))
+
+
+def _act_critical_halved(act, lam):
+    return 0.5 * ORIG_ACT_CRITICAL(act, lam)
+
+
+def _act_relax_endpoints_only(L, U, lo_b, hi_b, xmag, act):
+    """Parallel lines whose offsets look only at the interval's ends (no critical points)."""
+    l = np.asarray(lo_b, np.float64)
+    u = np.asarray(hi_b, np.float64)
+    w = u - l
+    fl, fu = slr.act_fn(act, l), slr.act_fn(act, u)
+    lam = np.where(w > 0.0, (fu - fl) / np.where(w > 0.0, w, 1.0), 0.0)
+    hl, hu = fl - lam * l, fu - lam * u
+    Ln = lam[..., None] * L
+    Un = lam[..., None] * U
+    Ln[..., 0] += np.minimum(hl, hu)
+    Un[..., 0] += np.maximum(hl, hu)
+    return Ln, Un
+
+
 ORIG_AFFINE = slr.affine
 ORIG_RELU = slr.relu_relax
 ORIG_CLASSIFY = slr.classify
 ORIG_BISECT = count.bisect
+ORIG_ACT_CRITICAL = slr.act_critical
 
 MUTANTS = [
     ("affine swaps W+ and W-", slr, "affine", _swap_wpm_affine),
@@ -255,6 +284,9 @@ MUTANTS = [
     ("alpha Adam without bias correction", alpha_oracle, "adam_step", _adam_step_no_bias_correction),
     ("alpha objective row is the argmax", alpha_oracle, "objective_weights", _objective_row_argmax),
     ("alpha unsafe mode when any row is positive", alpha_oracle, "objective_weights", _objective_mode_any),
+    ("smooth activation: critical point without the square root", slr, "act_critical", _act_critical_no_sqrt),
+    ("smooth activation: critical point halved", slr, "act_critical", _act_critical_halved),
+    ("smooth activation: offsets from the interval ends only", slr, "act_relax", _act_relax_endpoints_only),
 ]
 
 
