@@ -39,6 +39,9 @@ enum {
     SLR_EUNSUPPORTED = -5 /* valid input outside the sizes this build supports               */
 };
 
+/* Hidden activations of load_net_act (load_net: ReLU). */
+enum { SLR_ACT_RELU = 0, SLR_ACT_TANH = 1, SLR_ACT_SIGMOID = 2 };
+
 /* Box classes written by bound_boxes and recorded in traces. */
 enum { SLR_UNDECIDED = 0, SLR_UNSAFE = 1, SLR_SAFE = 2 };
 
@@ -58,6 +61,20 @@ typedef struct slr_property slr_property;  /* opaque; immutable after load_prope
  */
 int load_net(int32_t n_affine, const int32_t* sizes, const float* const* W,
              const float* const* b, slr_net** out);
+
+/*
+ * load_net_act: load_net with another hidden activation, SLR_ACT_TANH or SLR_ACT_SIGMOID
+ * (SLR_ACT_RELU is load_net).  The paper treats ReLU networks and names other activations as
+ * future work (§3); here a tanh or sigmoid neuron with pre-activation bounds [l, u] is enclosed
+ * by two parallel lines lam z + b_lo <= s(z) <= lam z + b_hi: lam is the chord slope over [l, u]
+ * and b_lo, b_hi bound s(z) - lam z over [l, u] (its extrema lie at l, u or where s'(z) = lam),
+ * moved outward by a rounding margin.  bound_boxes, count_exact, count_exact_stack,
+ * count_exact_noalloc, count_approx and plain batches accept such networks; the alpha calls,
+ * alpha options and the tape-state kernel (shapes beyond the LDS bound kernel) return
+ * SLR_EUNSUPPORTED.  Other act values: SLR_EINVAL.
+ */
+int load_net_act(int32_t n_affine, const int32_t* sizes, const float* const* W,
+                 const float* const* b, int32_t act, slr_net** out);
 void free_net(slr_net* net);
 
 /*

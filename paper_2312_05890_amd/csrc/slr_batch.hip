@@ -140,7 +140,7 @@ __global__ __launch_bounds__(1024) void batch_plan_kernel(BatchInst* insts, int 
 
 // insts is read-only here and aliases nothing the kernel writes, so descriptor loads need not be
 // repeated after the tile's stores.
-template <int NCOL, int NT, int UW, int NW>
+template <int NCOL, int NT, int UW, int NW, bool SMOOTH = false>
 __global__ __launch_bounds__(NW * 64) void batch_bound_kernel(const BatchInst* __restrict__ insts,
                                                               BatchCtl* ctl,
                                                               const unsigned* __restrict__ bpre,
@@ -159,7 +159,7 @@ __global__ __launch_bounds__(NW * 64) void batch_bound_kernel(const BatchInst* _
         const int i = find_owner(bpre, cbeg, cend, t);
         const BatchInst& I = insts[i];
         const int64_t box0 = (int64_t)(t - bpre[i]) * (NT * 16);
-        bound_tile<NCOL, NT, UW, NW>(I.net, I.prop, I.n, box0, I.lo[I.cur], I.hi[I.cur], I.glo,
+        bound_tile<NCOL, NT, UW, NW, SMOOTH>(I.net, I.prop, I.n, box0, I.lo[I.cur], I.hi[I.cur], I.glo,
                                      I.ghi, I.cls, 0, I.sp, amb_list, &ctl->amb_count,
                                      (unsigned)i << 22);
         __syncthreads();   // the tile's LDS is reused by the next tile
@@ -381,12 +381,26 @@ int ncol_class_b(int d) {
     return -1;
 }
 
-template <int NCOL, int NT, int UW, int NW>
+template <int NCOL, int NT, int UW, int NW, bool SMOOTH = false>
 const void* kern_ptr() {
-    return (const void*)batch_bound_kernel<NCOL, NT, UW, NW>;
+    return (const void*)batch_bound_kernel<NCOL, NT, UW, NW, SMOOTH>;
 }
 
+// nt < 0 selects the tanh / sigmoid kernels (default shapes only) of the shape (-nt, uw, nw).
 const void* class_kernel(int ncol, TileShape t) {
+    if (t.nt < 0) {
+#define SLR_S(C)                                                                           \
+        if (ncol == C) {                                                                   \
+            if (t.nt == -4 && t.uw == 1 && t.nw == 4) return kern_ptr<C, 4, 1, 4, true>(); \
+            if (t.nt == -2 && t.uw == 1 && t.nw == 4) return kern_ptr<C, 2, 1, 4, true>(); \
+            if (t.nt == -1 && t.uw == 1 && t.nw == 4) return kern_ptr<C, 1, 1, 4, true>(); \
+            if (t.nt == -1 && t.uw == 2 && t.nw == 4) return kern_ptr<C, 1, 2, 4, true>(); \
+            return nullptr;                                                                \
+        }
+        SLR_S(4) SLR_S(5) SLR_S(6) SLR_S(7) SLR_S(8) SLR_S(9) SLR_S(10) SLR_S(11) SLR_S(12) SLR_S(14)
+#undef SLR_S
+        return nullptr;
+    }
 #define SLR_T(C)                                                                    \
     if (ncol == C) {                                                                \
         if (t.nt == 4 && t.uw == 1 && t.nw == 4) return kern_ptr<C, 4, 1, 4>();     \
@@ -425,6 +439,13 @@ int batch_class_of(const NetDev& net, const PropDev& prop, int* ncol, TileShape*
     (void)prop;
     *ncol = ncol_class_b(net.d);
     if (*ncol < 0 || net.mt_max > 8) return -1;
+    if (net.act != SLR_ACT_RELU) {   // the smooth kernels: default shapes, marked by nt < 0
+        if (net.mt_max <= 1) *t = {-4, 1, 4};
+        else if (net.mt_max == 2) *t = {-2, 1, 4};
+        else if (net.mt_max <= 4) *t = {-1, 1, 4};
+        else *t = {-1, 2, 4};
+        return batch_class_supported(*ncol, *t) ? 0 : -1;
+    }
     // the tuned shape of this class when the batch kernels have it, else the default
     *t = tile_shape_for(net.d, net.mt_max);
     if (!batch_class_supported(*ncol, *t)) {
@@ -437,6 +458,7 @@ int batch_class_of(const NetDev& net, const PropDev& prop, int* ncol, TileShape*
 }
 
 size_t batch_bound_lds(int ncol, TileShape t, int mt_max, int rows) {
+    t.nt = t.nt < 0 ? -t.nt : t.nt;   // the smooth kernels' marker
     return bound_lds_bytes(ncol, t, mt_max, rows);
 }
 

@@ -83,13 +83,69 @@ __device__ __forceinline__ float buf_f32(BufRsrc r, uint32_t off) {
     return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
 }
 
+// Smooth activations (tanh, sigmoid) by two parallel lines: slope lam = the chord's over [l, u]
+// (the derivative at l for a point), offsets bl <= min h and bh >= max h of h(z) = s(z) - lam z
+// over [l, u].  Both functions are concave for z >= 0 and convex for z <= 0, so the tangent of h
+// at any point a of [max(l, 0), u] bounds h from above there and the tangent at any point b of
+// [l, min(u, 0)] from below; a and b are the points where s' = lam (clamped into their pieces),
+// which makes the tangents flat and the bounds tight, but any a, b keep them valid.  The ends
+// l, u complete the candidates.  widen: offsets moved outward by a rounding margin of the few
+// float32 evaluations (library tanhf/expf/logf/atanhf within a few ulp).
+__device__ __forceinline__ float act_eval(int act, float z) {
+    return act == SLR_ACT_TANH ? tanhf(z) : 1.f / (1.f + expf(-z));
+}
+
+__device__ __forceinline__ float act_slope(int act, float fz) {
+    return act == SLR_ACT_TANH ? 1.f - fz * fz : fz * (1.f - fz);
+}
+
+__device__ __forceinline__ void smooth_lines(int act, float l, float u, bool widen, float& lam,
+                                             float& bl, float& bh) {
+    const float fl = act_eval(act, l), fu = act_eval(act, u);
+    const float w = u - l;
+    lam = fmaxf(0.f, w > 0.f ? (fu - fl) / w : act_slope(act, fl));
+    float zc;
+    if (act == SLR_ACT_TANH) {
+        const float t = sqrtf(fmaxf(0.f, 1.f - lam));
+        zc = atanhf(fminf(t, 1.f - 0x1p-24f));
+    } else {
+        const float sq = sqrtf(fmaxf(0.f, 1.f - 4.f * lam));
+        const float pp = fminf(0.5f * (1.f + sq), 1.f - 0x1p-24f);
+        zc = logf(pp / (1.f - pp));
+    }
+    const float hl = fl - lam * l, hu = fu - lam * u;
+    bl = fminf(hl, hu);
+    bh = fmaxf(hl, hu);
+    if (u > 0.f) {   // concave piece
+        const float a0 = fmaxf(l, 0.f);
+        const float a = fminf(fmaxf(zc, a0), u);
+        const float fa = act_eval(act, a);
+        const float ha = fa - lam * a, da = act_slope(act, fa) - lam;
+        bh = fmaxf(bh, ha + fmaxf(da * (u - a), da * (a0 - a)));
+    }
+    if (l < 0.f) {   // convex piece
+        const float b0 = fminf(u, 0.f);
+        const float b = fmaxf(fminf(-zc, b0), l);
+        const float fb = act_eval(act, b);
+        const float hb = fb - lam * b, db = act_slope(act, fb) - lam;
+        bl = fminf(bl, hb + fminf(db * (l - b), db * (b0 - b)));
+    }
+    if (widen) {
+        const float m = 32.f * kU32 * (1.f + lam * (fabsf(l) + fabsf(u)));
+        bl -= m;
+        bh += m;
+    }
+}
+
 // Scalars of the epilogue: zero margins and no rounding-up in the unwidened mode.
 struct EpiConst {
     float kconc, krelu, lamfac;
+    int act;
 };
 
 __device__ __forceinline__ EpiConst epi_const(const NetDev& net, int raw) {
     EpiConst k;
+    k.act = net.act;
     k.kconc = raw ? 0.f : net.kconc;
     k.krelu = raw ? 0.f : net.krelu;
     // lam = hi * rcp(hi - lo): v_rcp_f32 is within 1 ulp, the product within 1/2 ulp, so a
@@ -103,7 +159,7 @@ __device__ __forceinline__ EpiConst epi_const(const NetDev& net, int raw) {
 // without branches.  In: a[c][v] = pre-activation center coefficients (c = 0..d, bias included),
 // the unwidened radius a[d+1][v] and margin part a[d+2][v]; eps[v] = rounding margin of the
 // affine step.  Out: post-activation state in place; returns max_v bound on |value| over the box.
-template <int NCOL>
+template <int NCOL, bool SMOOTH = false>
 __device__ __forceinline__ float relu_epilogue(float (&a)[NCOL][4], const float (&eps)[4],
                                                const bool (&valid)[4], const EpiConst& k) {
     constexpr int D = NCOL - 3;
@@ -120,6 +176,20 @@ __device__ __forceinline__ float relu_epilogue(float (&a)[NCOL][4], const float 
         const float delta = k.kconc * (fabsf(c0) + r + S);
         const float lo = (c0 - (r + S)) - delta;
         const float hi = (c0 + (r + S)) + delta;
+        if constexpr (SMOOTH) {   // tanh or sigmoid network (k.act)
+            float lam = 0.f, bl = 0.f, bh = 0.f;
+            if (valid[v]) smooth_lines(k.act, lo, hi, k.krelu != 0.f, lam, bl, bh);
+            const float er = k.krelu * lam * (fabsf(c0) + S + r);
+#pragma unroll
+            for (int c = 1; c <= D; ++c) a[c][v] *= lam;
+            const float c0n = fmaf(lam, c0, 0.5f * (bl + bh));
+            const float rn = fmaf(lam, r, 0.5f * (bh - bl)) + er;
+            a[0][v] = c0n;
+            a[R][v] = rn;
+            a[Q][v] = valid[v] ? fmaf(1.f + lam, q, delta + er) : 0.f;
+            emax = fmaxf(emax, (fabsf(c0n) + lam * S + rn) * (1.f + 4.f * kU32));
+            continue;
+        }
         const bool dead = !valid[v] || !(hi > 0.f);
         const bool act = !dead && lo >= 0.f;
         const bool cross = !dead && !act;
@@ -233,7 +303,7 @@ __device__ __forceinline__ void k_quads_any(f32x4 (&acc)[NCOL], const float* __r
     k_quads<NCOL, 0>(acc, wf, qf, sb, colstride, nq, nqa);
 }
 
-template <int NCOL, int NT, int UW, int NW>
+template <int NCOL, int NT, int UW, int NW, bool SMOOTH = false>
 __device__ __forceinline__ void bound_tile(
     const NetDev& net, const PropDev& prop, int64_t n, int64_t box0,
     const float* __restrict__ blo, const float* __restrict__ bhi, float* __restrict__ g_lo,
@@ -304,7 +374,7 @@ __device__ __forceinline__ void bound_tile(
                     a[NCOL - 1][v] = 0.f;
                     eps[v] = raw ? 0.f : net.kfirst * s + kEta;
                 }
-                float emax = relu_epilogue<NCOL>(a, eps, valid, ek);
+                float emax = relu_epilogue<NCOL, SMOOTH>(a, eps, valid, ek);
                 float* sb = S + ((nt * NCOL * 4 + g) * 16 + j) * SP + 4 * mt;
 #pragma unroll
                 for (int c = 0; c < NCOL; ++c) {
@@ -388,7 +458,7 @@ __device__ __forceinline__ void bound_tile(
                     a[0][v] += bb;
                     eps[v] = raw ? 0.f : L->kgam * (A * emax_in + fabsf(bb)) + kEta;
                 }
-                float emax = relu_epilogue<NCOL>(a, eps, valid, ek);
+                float emax = relu_epilogue<NCOL, SMOOTH>(a, eps, valid, ek);
                 float* sb = S + ((nt * NCOL * 4 + g) * 16 + j) * SP + 4 * mt;
 #pragma unroll
                 for (int c = 0; c < NCOL; ++c) {
@@ -529,8 +599,51 @@ __device__ __forceinline__ double wave_max(double v) {
     return v;
 }
 
+// Float64 twin of smooth_lines (always widened, margin 32 u64 per unit of magnitude).
+__device__ __forceinline__ double act_eval64(int act, double z) {
+    return act == SLR_ACT_TANH ? tanh(z) : 1.0 / (1.0 + exp(-z));
+}
+
+__device__ __forceinline__ double act_slope64(int act, double fz) {
+    return act == SLR_ACT_TANH ? 1.0 - fz * fz : fz * (1.0 - fz);
+}
+
+__device__ __forceinline__ void smooth_lines64(int act, double l, double u, double& lam, double& bl,
+                                               double& bh) {
+    const double fl = act_eval64(act, l), fu = act_eval64(act, u);
+    const double w = u - l;
+    lam = fmax(0.0, w > 0.0 ? (fu - fl) / w : act_slope64(act, fl));
+    double zc;
+    if (act == SLR_ACT_TANH) {
+        zc = atanh(fmin(sqrt(fmax(0.0, 1.0 - lam)), 1.0 - 0x1p-53));
+    } else {
+        const double pp = fmin(0.5 * (1.0 + sqrt(fmax(0.0, 1.0 - 4.0 * lam))), 1.0 - 0x1p-53);
+        zc = log(pp / (1.0 - pp));
+    }
+    const double hl = fl - lam * l, hu = fu - lam * u;
+    bl = fmin(hl, hu);
+    bh = fmax(hl, hu);
+    if (u > 0.0) {
+        const double a0 = fmax(l, 0.0);
+        const double a = fmin(fmax(zc, a0), u);
+        const double fa = act_eval64(act, a);
+        const double ha = fa - lam * a, da = act_slope64(act, fa) - lam;
+        bh = fmax(bh, ha + fmax(da * (u - a), da * (a0 - a)));
+    }
+    if (l < 0.0) {
+        const double b0 = fmin(u, 0.0);
+        const double b = fmax(fmin(-zc, b0), l);
+        const double fb = act_eval64(act, b);
+        const double hb = fb - lam * b, db = act_slope64(act, fb) - lam;
+        bl = fmin(bl, hb + fmin(db * (l - b), db * (b0 - b)));
+    }
+    const double m = 32.0 * kU64 * (1.0 + lam * (fabs(l) + fabs(u)));
+    bl -= m;
+    bh += m;
+}
+
 __device__ __forceinline__ double relu64(double* st, int ncol, double eps, double kconc,
-                                         double krelu) {
+                                         double krelu, int act = SLR_ACT_RELU) {
     // st: one neuron's row (center c_0..c_d, then the unwidened radius); returns |value| bound
     const int D = ncol - 2;
     double c0 = st[0];
@@ -540,6 +653,17 @@ __device__ __forceinline__ double relu64(double* st, int ncol, double eps, doubl
     const double delta = kconc * (fabs(c0) + r + S);
     const double lo = (c0 - (r + S)) - delta;
     const double hi = (c0 + (r + S)) + delta;
+    if (act != SLR_ACT_RELU) {
+        double lam, bl, bh;
+        smooth_lines64(act, lo, hi, lam, bl, bh);
+        const double er = krelu * lam * (fabs(c0) + S + r);
+        for (int c = 1; c <= D; ++c) st[c] *= lam;
+        c0 = fma(lam, c0, 0.5 * (bl + bh));
+        r = fma(lam, r, 0.5 * (bh - bl)) + er;
+        st[0] = c0;
+        st[ncol - 1] = r;
+        return (fabs(c0) + lam * S + r) * (1.0 + 4.0 * kU64);
+    }
     if (hi <= 0.0) {
         for (int c = 0; c < ncol; ++c) st[c] = 0.0;
         return 0.0;
@@ -643,7 +767,7 @@ __device__ __forceinline__ void recheck_box(const NetDev& net, const PropDev& pr
         }
         st[0] = c0;
         st[ncol - 1] = 0.0;
-        e = fmax(e, relu64(st, ncol, net.kfirst64 * s + kEta64, net.kconc64, net.krelu64));
+        e = fmax(e, relu64(st, ncol, net.kfirst64 * s + kEta64, net.kconc64, net.krelu64, net.act));
     }
     double emax = wave_max(e);
     wave_sync();
@@ -686,7 +810,7 @@ __device__ __forceinline__ void recheck_box(const NetDev& net, const PropDev& pr
             const double bb = L->b[j];
             st[0] += bb;
             const double eps = L->kgam64 * (A_row * (1.0 + 0x1p-40) * emax + fabs(bb)) + kEta64;
-            e = fmax(e, relu64(st, ncol, eps, net.kconc64, net.krelu64));
+            e = fmax(e, relu64(st, ncol, eps, net.kconc64, net.krelu64, net.act));
         }
         emax = wave_max(e);
         wave_sync();

@@ -197,9 +197,16 @@ extern "C" const char* last_error(void) { return g_err.c_str(); }
 
 extern "C" int load_net(int32_t n_affine, const int32_t* sizes, const float* const* W,
                         const float* const* b, slr_net** out) {
+    return load_net_act(n_affine, sizes, W, b, SLR_ACT_RELU, out);
+}
+
+extern "C" int load_net_act(int32_t n_affine, const int32_t* sizes, const float* const* W,
+                            const float* const* b, int32_t act, slr_net** out) {
     g_err.clear();
     if (!out) return fail(SLR_EINVAL, "load_net: out is NULL");
     *out = nullptr;
+    if (act != SLR_ACT_RELU && act != SLR_ACT_TANH && act != SLR_ACT_SIGMOID)
+        return fail(SLR_EINVAL, "load_net: unknown activation %d", act);
     if (n_affine < 2 || n_affine > SLR_MAX_AFFINE)
         return fail(SLR_EINVAL, "load_net: n_affine must be in [2, %d], got %d", SLR_MAX_AFFINE, n_affine);
     if (!sizes || !W || !b) return fail(SLR_EINVAL, "load_net: NULL array");
@@ -223,6 +230,7 @@ extern "C" int load_net(int32_t n_affine, const int32_t* sizes, const float* con
         return blobs.size() - 1;
     };
     NetDev nd{};
+    nd.act = act;
     nd.d = d;
     nd.n_affine = n_affine;
     nd.n1 = sizes[1];
@@ -736,6 +744,8 @@ int check_alpha_pair(const slr_net* net, const slr_property* prop, const char* w
     if (!prop) return fail(SLR_EINVAL, "%s: property is NULL", who);
     if (prop->net != net) return fail(SLR_EINVAL, "%s: property was loaded for another net", who);
     if (alpha_shape(net->dev, prop->dev).nc < 0) return fail(SLR_EUNSUPPORTED, "%s: input dimension too large", who);
+    if (net->dev.act != SLR_ACT_RELU)
+        return fail(SLR_EUNSUPPORTED, "%s: alpha slopes are defined for ReLU networks only", who);
     return SLR_OK;
 }
 
@@ -1266,6 +1276,12 @@ int check_exact_opts(const slr_net* net, const slr_property* prop, const slr_exa
         return fail(SLR_EINVAL, "%s: alpha_lr and alpha_min_depth must be >= 0", who);
     if (!(o->alpha_select >= 0.f) || !std::isfinite(o->alpha_select))
         return fail(SLR_EINVAL, "%s: alpha_select must be finite and >= 0", who);
+    if (net->dev.act != SLR_ACT_RELU) {
+        if (o->alpha_steps > 0)
+            return fail(SLR_EUNSUPPORTED, "%s: alpha slopes are defined for ReLU networks only", who);
+        if (!bound_f32_supported(net->dev, prop->dev) || bound_variant_for(net->dev, prop->dev) < 0)
+            return fail(SLR_EUNSUPPORTED, "%s: tanh and sigmoid networks need the LDS or register bound kernel", who);
+    }
     const int64_t achunk = o->alpha_steps > 0 ? o->alpha_chunk : 0;
     const size_t need = layout_ws(nullptr, net->dev, prop->dev, o->max_leaves, samples, achunk).bytes;
     if (!o->workspace || o->workspace_bytes < need)
@@ -1883,7 +1899,7 @@ extern "C" int batch_create_opts(int32_t n_inst, const slr_net* const* nets,
         if (batch_class_of(nets[i]->dev, props[i]->dev, &f.ncol, &f.t) != 0)
             return fail(SLR_EUNSUPPORTED, "%s: shape (d=%d, widths up to %d) outside the batch kernels "
                         "(d <= 11, widths <= 128)", who, nets[i]->dev.d, nets[i]->dev.n_max);
-        f.key = ((f.ncol * 8 + f.t.nt) * 8 + f.t.uw) * 16 + f.t.nw;
+        f.key = ((f.ncol * 16 + (f.t.nt + 8)) * 8 + f.t.uw) * 16 + f.t.nw;   // nt < 0: smooth kernels
     }
     slr_batch* b = new slr_batch;
     b->n_inst = n_inst;
@@ -1958,6 +1974,10 @@ extern "C" int batch_create_opts(int32_t n_inst, const slr_net* const* nets,
             const int i = b->order[p];
             size_t lds = 0;
             akey[p] = batch_alpha_key(nets[i]->dev, props[i]->dev, &lds);
+            if (nets[i]->dev.act != SLR_ACT_RELU) {
+                batch_free(b);
+                return fail(SLR_EUNSUPPORTED, "batch_create: instance %d: alpha slopes are defined for ReLU networks only", i);
+            }
             if (akey[p] < 0) {
                 batch_free(b);
                 return fail(SLR_EUNSUPPORTED, "batch_create: instance %d has no alpha kernel", i);
@@ -2119,7 +2139,7 @@ extern "C" int batch_create_opts(int32_t n_inst, const slr_net* const* nets,
     }
     b->levels = levels;
     BatchCtl hc{};
-    for (size_t c = 0; c < b->cls.size(); ++c) hc.tbox[c] = 16 * b->cls[c].t.nt;
+    for (size_t c = 0; c < b->cls.size(); ++c) hc.tbox[c] = 16 * std::abs(b->cls[c].t.nt);
     e = hipMemcpy(b->ctl, &hc, sizeof hc, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(b->insts, b->host.data(), sizeof(BatchInst) * n_inst, hipMemcpyHostToDevice);
     if (e != hipSuccess) {

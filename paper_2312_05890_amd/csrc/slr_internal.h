@@ -17,6 +17,7 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include "../../include/slrcount.h"
 #include <stdint.h>
 
 #define SLR_MAX_AFFINE 8
@@ -67,6 +68,7 @@ struct NetDev {
     const int* rowmap[SLR_MAX_AFFINE];
     int hoff[SLR_MAX_AFFINE];
     int nh;               // hidden neurons in total = alpha floats per box
+    int act;              // hidden activation: SLR_ACT_RELU, SLR_ACT_TANH or SLR_ACT_SIGMOID
     float kfirst, kconc, krelu;     // kappa*gamma_{d+2}, kappa*gamma_{d+3}, kappa*gamma_4
     double kfirst64, kconc64, krelu64;
 };

@@ -7,14 +7,16 @@
 
 namespace {
 
-template <int NCOL, int NT, int UW, int NW>
+// SMOOTH: tanh / sigmoid networks (parallel-line relaxation); a separate instantiation keeps the
+// ReLU kernels' registers and occupancy unchanged.
+template <int NCOL, int NT, int UW, int NW, bool SMOOTH = false>
 __global__ __launch_bounds__(NW * 64) void bound_f32_kernel(
     NetDev net, PropDev prop, int64_t n, const float* __restrict__ blo,
     const float* __restrict__ bhi, float* __restrict__ g_lo, float* __restrict__ g_hi,
     int8_t* __restrict__ cls, int raw, int SP, unsigned* __restrict__ amb_list,
     unsigned* __restrict__ amb_count, unsigned list_base) {
-    bound_tile<NCOL, NT, UW, NW>(net, prop, n, (int64_t)blockIdx.x * (NT * 16), blo, bhi, g_lo,
-                                 g_hi, cls, raw, SP, amb_list, amb_count, list_base);
+    bound_tile<NCOL, NT, UW, NW, SMOOTH>(net, prop, n, (int64_t)blockIdx.x * (NT * 16), blo, bhi,
+                                         g_lo, g_hi, cls, raw, SP, amb_list, amb_count, list_base);
 }
 
 __global__ __launch_bounds__(256) void recheck64_kernel(NetDev net, PropDev prop, int64_t n,
@@ -402,7 +404,7 @@ __global__ __launch_bounds__(256) void sample_forward_kernel(NetDev net, PropDev
         if (tid < net.n1) {
             float s = net.b1[tid];
             for (int k = 0; k < d; ++k) s = fmaf(net.w1[tid * d + k], h1[k], s);
-            h0[tid] = fmaxf(s, 0.f);
+            h0[tid] = net.act == SLR_ACT_RELU ? fmaxf(s, 0.f) : act_eval(net.act, s);
         }
         __syncthreads();
         float* in = h0;
@@ -413,7 +415,7 @@ __global__ __launch_bounds__(256) void sample_forward_kernel(NetDev net, PropDev
                 float s = L->b[tid];
                 const float* wr = L->w + (size_t)tid * L->n_in;
                 for (int k = 0; k < L->n_in; ++k) s = fmaf(wr[k], in[k], s);
-                out[tid] = fmaxf(s, 0.f);
+                out[tid] = net.act == SLR_ACT_RELU ? fmaxf(s, 0.f) : act_eval(net.act, s);
             }
             __syncthreads();
             float* t = in;
@@ -455,13 +457,13 @@ int ncol_class(int d) {
 
 int state_stride(int mt_max) { return 4 * mt_max + ((mt_max & 1) ? 0 : 4); }
 
-template <int NCOL, int NT, int UW, int NW>
+template <int NCOL, int NT, int UW, int NW, bool SMOOTH = false>
 hipError_t launch_inst(const NetDev& net, const PropDev& prop, int64_t n, const float* lo,
                        const float* hi, float* g_lo, float* g_hi, int8_t* cls, int raw,
                        hipStream_t stream, unsigned* amb_list, unsigned* amb_count,
                        unsigned list_base) {
     const size_t lds = bound_lds_bytes(NCOL, TileShape{NT, UW, NW}, net.mt_max, prop.rows);
-    auto kern = bound_f32_kernel<NCOL, NT, UW, NW>;
+    auto kern = bound_f32_kernel<NCOL, NT, UW, NW, SMOOTH>;
     hipError_t e = allow_lds((const void*)kern, lds);
     if (e != hipSuccess) return e;
     const int64_t blocks = (n + NT * 16 - 1) / (NT * 16);
@@ -477,6 +479,18 @@ template <int NCOL>
 hipError_t launch_ncol(TileShape t, const NetDev& net, const PropDev& prop, int64_t n,
                        const float* lo, const float* hi, float* g_lo, float* g_hi, int8_t* cls,
                        int raw, hipStream_t stream, unsigned* al, unsigned* ac, unsigned lb) {
+    if (net.act != SLR_ACT_RELU) {   // smooth networks: the default shapes only
+#define SLR_SMOOTH(A, B, C)                                                                      \
+        if (t.nt == A && t.uw == B && t.nw == C)                                                  \
+            return launch_inst<NCOL, A, B, C, true>(net, prop, n, lo, hi, g_lo, g_hi, cls, raw,   \
+                                                    stream, al, ac, lb);
+        SLR_SMOOTH(4, 1, 4) SLR_SMOOTH(2, 1, 4) SLR_SMOOTH(1, 1, 4) SLR_SMOOTH(1, 2, 4)
+        if constexpr (NCOL <= 18) {
+            SLR_SMOOTH(1, 4, 4)
+        }
+#undef SLR_SMOOTH
+        return hipErrorInvalidValue;
+    }
 #define SLR_SHAPE(A, B, C)                                                                       \
     if (t.nt == A && t.uw == B && t.nw == C)                                                      \
         return launch_inst<NCOL, A, B, C>(net, prop, n, lo, hi, g_lo, g_hi, cls, raw, stream, al, \
@@ -575,7 +589,7 @@ int set_bound_variant(int v) {
 }
 
 int bound_variant_for(const NetDev& net, const PropDev& prop) {
-    if (g_variant == 2) return reg_fits(net, prop) ? 2 : -1;
+    if (g_variant == 2) return reg_fits(net, prop) && net.act == SLR_ACT_RELU ? 2 : -1;
     if (g_variant == 3) return -1;   // the level driver then bounds with the tape-state kernel
     return 1;
 }
@@ -662,7 +676,7 @@ hipError_t launch_bound_f32(const NetDev& net, const PropDev& prop, int64_t n, c
             default: break;
         }
     }
-    const TileShape t = tile_shape_for(net.d, net.mt_max);
+    const TileShape t = net.act == SLR_ACT_RELU ? tile_shape_for(net.d, net.mt_max) : default_shape(net.mt_max);
     switch (ncol_class(net.d)) {
 #define SLR_CASE(C) \
     case C: return launch_ncol<C>(t, net, prop, n, lo, hi, g_lo, g_hi, cls, raw, stream, \

@@ -26,7 +26,7 @@ EXPORTS = ("load_net", "free_net", "load_property", "free_property", "bound_boxe
            "batch_run", "batch_free", "count_exact_batch", "bound_tile_shape",
            "alpha_state_variant", "count_exact_noalloc", "count_exact_noalloc_max_bytes",
            "stack_workspace_size", "count_exact_stack", "alpha_kernel_variant",
-           "batch_create_opts")
+           "batch_create_opts", "load_net_act")
 
 
 class SlrError(RuntimeError):
@@ -108,6 +108,9 @@ def lib() -> C.CDLL:
         vp, i32, i64 = C.c_void_p, C.c_int32, C.c_int64
         L.load_net.argtypes = [i32, C.POINTER(C.c_int32), C.POINTER(vp), C.POINTER(vp), C.POINTER(vp)]
         L.load_net.restype = C.c_int
+        L.load_net_act.argtypes = [i32, C.POINTER(C.c_int32), C.POINTER(vp), C.POINTER(vp), i32,
+                                   C.POINTER(vp)]
+        L.load_net_act.restype = C.c_int
         L.free_net.argtypes = [vp]
         L.free_net.restype = None
         L.load_property.argtypes = [vp, i32, vp, vp, C.POINTER(vp)]
@@ -198,10 +201,19 @@ def _stream(stream):
     return C.c_void_p(stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream))
 
 
-class Net:
-    """A ReLU network resident on the device (``load_net``)."""
+ACTIVATIONS = {"relu": 0, "tanh": 1, "sigmoid": 2}
 
-    def __init__(self, layers: Sequence[Tuple[np.ndarray, np.ndarray]]):
+
+class Net:
+    """A network resident on the device (``load_net_act``): ReLU hidden layers, or tanh /
+    sigmoid when ``act`` (or the ``act`` attribute of ``layers``) says so."""
+
+    def __init__(self, layers: Sequence[Tuple[np.ndarray, np.ndarray]], act: Optional[str] = None):
+        if act is None:
+            act = getattr(layers, "act", "relu")
+        if act not in ACTIVATIONS:
+            raise ValueError(f"unknown activation {act!r}")
+        self.act = act
         L = lib()
         self._keep = [(np.ascontiguousarray(W, np.float32), np.ascontiguousarray(b, np.float32))
                       for W, b in layers]
@@ -216,7 +228,7 @@ class Net:
         arr_w = (C.c_void_p * n)(*[W.ctypes.data for W, _ in self._keep])
         arr_b = (C.c_void_p * n)(*[b.ctypes.data for _, b in self._keep])
         h = C.c_void_p()
-        _check(L.load_net(n, arr_s, arr_w, arr_b, C.byref(h)))
+        _check(L.load_net_act(n, arr_s, arr_w, arr_b, ACTIVATIONS[act], C.byref(h)))
         self.handle = h
 
     def __del__(self):
