@@ -54,14 +54,15 @@ def bound_chunked(net, C, dvec, lo, hi, chunk=8192):
     return np.concatenate(g_lo), np.concatenate(g_hi)
 
 
-def bisect(lo: np.ndarray, hi: np.ndarray, paths: np.ndarray):
-    """Split every box at the midpoint of its widest side (lowest index on ties).
+def bisect(lo: np.ndarray, hi: np.ndarray, paths: np.ndarray, sides=None):
+    """Split every box at the midpoint of its widest side (lowest index on ties), or of the
+    given ``sides``.
 
     Children are emitted in parent order as [lower half, upper half]; the path id of a child
     is 2 * parent + side (the root is 1).
     """
     n, d = lo.shape
-    j = np.argmax(hi - lo, axis=1)
+    j = np.argmax(hi - lo, axis=1) if sides is None else np.asarray(sides)
     rows = np.arange(n)
     mid = 0.5 * (lo[rows, j] + hi[rows, j])
     lo2 = np.repeat(lo, 2, axis=0)
@@ -74,11 +75,64 @@ def bisect(lo: np.ndarray, hi: np.ndarray, paths: np.ndarray):
     return lo2, hi2, p2
 
 
+ASPECT_LOG2 = 6      # split candidates: sides at least 2^-6 of the box's widest side
+BAND = 1e-4          # crossing tests within BAND * (|c0| + S) of zero are uncertain
+TIE = 1e-5           # relative score gap below which a split choice is not robust
+
+
+def crossing_scores(lo, hi, tr, layers, band=0.0):
+    """Per box and input side j: the sum over the crossing neurons of the first ``layers``
+    hidden layers of |coefficient of x_j| x (hi_j - lo_j) in the neuron's pre-activation
+    equation (the part of the neuron's interval that side j contributes).  A neuron counts as
+    crossing when l < -band m and u > band m, m = |centre| + sum of the side terms; band < 0
+    counts the uncertain ones too."""
+    w = hi - lo
+    s = np.zeros_like(w)
+    for t in tr[:layers]:
+        C = 0.5 * (t["L"] + t["U"])
+        terms = np.abs(C[..., 1:]) * w[:, None, :]
+        centre = C[..., 0] + np.einsum("bkj,bj->bk", C[..., 1:], 0.5 * (lo + hi))
+        m = np.abs(centre) + 0.5 * terms.sum(-1)
+        cross = (t["lo"] < -band * m) & (t["hi"] > band * m)
+        s += np.einsum("bk,bkj->bj", cross.astype(np.float64), terms)
+    return s
+
+
+def split_sides(lo, hi, tr, layers):
+    """The side to bisect and whether that choice is robust.
+
+    layers = 0: the widest side, lowest index on ties (the reading of §2.2's refinement).
+    layers > 0: among the sides at least 2^-6 of the widest, the one with the largest
+    ``crossing_scores`` (lowest index on ties); the widest if no neuron crosses.  The choice is
+    robust unless another candidate's score could reach the chosen one's within TIE when
+    neurons within BAND of a phase change flip (a float32 evaluation may see them either way).
+    """
+    w = hi - lo
+    widest = np.argmax(w, axis=1)
+    if layers <= 0:
+        return widest, np.ones(w.shape[0], bool)
+    ok = w >= w.max(axis=1, keepdims=True) * 2.0 ** -ASPECT_LOG2
+    s = np.where(ok, crossing_scores(lo, hi, tr, layers), -1.0)
+    j = np.argmax(s, axis=1)
+    none = s.max(axis=1) <= 0.0
+    j = np.where(none, widest, j)
+    sure = np.where(ok, crossing_scores(lo, hi, tr, layers, BAND), -1.0)     # certain crossings
+    maybe = np.where(ok, crossing_scores(lo, hi, tr, layers, -BAND), -1.0)   # and uncertain
+    rows = np.arange(w.shape[0])
+    others = maybe.copy()
+    others[rows, j] = -np.inf
+    robust = sure[rows, j] * (1.0 - TIE) > others.max(axis=1)
+    robust = np.where(none, maybe.max(axis=1) <= 0.0, robust)
+    return j, robust
+
+
 def count_exact(net, C, dvec, lo, hi, max_depth: int, max_leaves: int, trace: bool = False,
-                chunk: int = 8192):
+                chunk: int = 8192, split_layers: int = 0):
     """Alg. 1, level by level.  Returns a dict with the bracket, counts and histograms.
 
-    With ``trace`` the dict also holds, per level, the boxes' path ids, classes and bounds.
+    With ``trace`` the dict also holds, per level, the boxes' path ids, classes and bounds,
+    and for the boxes that were split the side and whether that choice was robust.
+    ``split_layers``: the split rule of ``split_sides``.
     """
     lo = np.asarray(lo, np.float64).reshape(1, -1)
     hi = np.asarray(hi, np.float64).reshape(1, -1)
@@ -99,7 +153,10 @@ def count_exact(net, C, dvec, lo, hi, max_depth: int, max_leaves: int, trace: bo
         if lo.shape[0] == 0:
             break
         depth = t
-        g_lo, g_hi = bound_chunked(net, C, dvec, lo, hi, chunk)
+        if split_layers > 0:
+            g_lo, g_hi, tr = slr.propagate(net, C, dvec, lo, hi, keep=True)
+        else:
+            g_lo, g_hi = bound_chunked(net, C, dvec, lo, hi, chunk)
         cls = slr.classify(g_lo, g_hi)
         bounded += lo.shape[0]
         if trace:
@@ -117,7 +174,20 @@ def count_exact(net, C, dvec, lo, hi, max_depth: int, max_leaves: int, trace: bo
             h_undec[t] = n_und
             status = BUDGET
             break
-        lo, hi, paths = bisect(lo[und], hi[und], paths[und])
+        if split_layers > 0:
+            tru = [{k: v[und] for k, v in x.items()} for x in tr]
+            sides, robust = split_sides(lo[und], hi[und], tru, split_layers)
+        else:
+            sides, robust = None, None
+        if trace:
+            levels[-1]["side"] = np.full(cls.shape[0], -1, np.int64)
+            levels[-1]["robust"] = np.ones(cls.shape[0], bool)
+            if sides is not None:
+                levels[-1]["side"][und] = sides
+                levels[-1]["robust"][und] = robust
+            else:
+                levels[-1]["side"][und] = np.argmax(hi[und] - lo[und], axis=1)
+        lo, hi, paths = bisect(lo[und], hi[und], paths[und], sides)
 
     unsafe = _exact_sum(h_unsafe)
     safe = _exact_sum(h_safe)

@@ -334,7 +334,56 @@ def pin_act_dense_grid():
         pin_dense_grid(seed=1, cells=512, act=act)
 
 
+def pin_split_rule_hand():
+    """Crossing-score split (split_layers = 1), derived by hand.  On [0, 1]^2 with hidden
+    neurons z0 = x1 - 0.4 (crossing: l = -0.4, u = 0.6; it depends on x1 only) and
+    z1 = x0 + 5 (active), y = ReLU(z0) + ReLU(z1) - 5.2: the only crossing neuron scores side 1
+    with |1| * 1 and side 0 with 0, so the root is cut at x1 = 1/2, where widest-first (a tie of
+    two unit sides, lowest index) cuts x0.  Below: on x1 in [0, 1/2] z0 still crosses
+    (l = -0.4, u = 0.1) and side 1 (score 1/2) is cut again; on x1 in [1/2, 1] z0 is active,
+    no neuron crosses and the widest side, x0, is cut.  With x1 confined to [0, 2^-7] and
+    z0 = x1 - 2^-8 (crossing, so only side 1 scores) side 1 is narrower than 2^-6 of the
+    widest side, no candidate, and side 0 is cut."""
+    net = [(_f32([[0.0, 1.0], [1.0, 0.0]]), _f32([-0.4, 5.0])), (_f32([[1.0, 1.0]]), _f32([-5.2]))]
+    r = count.count_exact(net, [[1.0]], [0.0], [0.0, 0.0], [1.0, 1.0], 2, 1 << 10, trace=True,
+                          split_layers=1)
+    assert r["levels"][0]["side"][0] == 1 and r["levels"][0]["robust"][0]
+    lev1 = r["levels"][1]
+    assert lev1["cls"].tolist() == [0, 0]
+    assert lev1["hi"][0, 1] == 0.5 and lev1["lo"][1, 1] == 0.5
+    assert lev1["side"].tolist() == [1, 0] and lev1["robust"].all()
+    r = count.count_exact(net, [[1.0]], [0.0], [0.0, 0.0], [1.0, 1.0], 1, 1 << 10, trace=True)
+    assert r["levels"][0]["side"][0] == 0
+    net2 = [(_f32([[0.0, 1.0], [1.0, 0.0]]), _f32([-2.0 ** -8, 5.0])), net[1]]
+    r = count.count_exact(net2, [[1.0]], [0.0], [0.0, 0.0], [1.0, 2.0 ** -7], 1, 1 << 10,
+                          trace=True, split_layers=1)
+    assert r["levels"][0]["cls"][0] == 0 and r["levels"][0]["side"][0] == 0
+
+
+def pin_split_rule_grid():
+    """Dense-grid check and exact accounting with the crossing-score split on tiny2d."""
+    inst = synth.tiny2d(2)
+    r = count.count_exact(inst.net, inst.C, inst.dvec, inst.lo, inst.hi, 14, 1 << 20,
+                          trace=True, split_layers=2)
+    assert r["unsafe_exact"] + r["safe_exact"] + r["undecided_exact"] == 1
+    cells = 512
+    h = 2.0 / cells
+    centers = -1.0 + h * (np.arange(cells) + 0.5)
+    X, Y = np.meshgrid(centers, centers, indexing="ij")
+    G = (slr.property_values(inst.net, inst.C, inst.dvec,
+                             np.stack([X.ravel(), Y.ravel()], axis=1))[:, 0] > 0).reshape(cells, cells)
+    for lev in r["levels"]:
+        for i, c in enumerate(lev["cls"]):
+            if c == 0:
+                continue
+            i0, i1 = (int(round((lev["lo"][i, 0] + 1) / h)), int(round((lev["hi"][i, 0] + 1) / h)))
+            j0, j1 = (int(round((lev["lo"][i, 1] + 1) / h)), int(round((lev["hi"][i, 1] + 1) / h)))
+            block = G[i0:i1, j0:j1]
+            assert block.size > 0 and (block.all() if c == 1 else not block.any())
+
+
 ALL_PINS = [pin_eq1_single_relu, pin_two_neurons, pin_linear_regime, pin_soundness,
             pin_irwin_hall, pin_abs_closed_form, pin_dense_grid, pin_accounting,
             pin_alpha_adam_closed_form, pin_alpha_objective_row,
-            pin_act_single_neuron_bruteforce, pin_act_soundness, pin_act_dense_grid]
+            pin_act_single_neuron_bruteforce, pin_act_soundness, pin_act_dense_grid,
+            pin_split_rule_hand, pin_split_rule_grid]

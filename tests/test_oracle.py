@@ -266,11 +266,29 @@ def _act_relax_endpoints_only(L, U, lo_b, hi_b, xmag, act):
     return Ln, Un
 
 
+def _split_sides_argmin(lo, hi, tr, layers):
+    j, robust = ORIG_SPLIT_SIDES(lo, hi, tr, layers)
+    if layers <= 0:
+        return j, robust
+    w = hi - lo
+    s = np.where(w >= w.max(axis=1, keepdims=True) / 64, count.crossing_scores(lo, hi, tr, layers), np.inf)
+    return np.argmin(s, axis=1), robust
+
+
+def _split_sides_no_aspect_guard(lo, hi, tr, layers):
+    j, robust = ORIG_SPLIT_SIDES(lo, hi, tr, layers)
+    if layers <= 0:
+        return j, robust
+    s = count.crossing_scores(lo, hi, tr, layers)
+    return np.where(s.max(axis=1) > 0, np.argmax(s, axis=1), j), robust
+
+
 ORIG_AFFINE = slr.affine
 ORIG_RELU = slr.relu_relax
 ORIG_CLASSIFY = slr.classify
 ORIG_BISECT = count.bisect
 ORIG_ACT_CRITICAL = slr.act_critical
+ORIG_SPLIT_SIDES = count.split_sides
 
 MUTANTS = [
     ("affine swaps W+ and W-", slr, "affine", _swap_wpm_affine),
@@ -287,6 +305,8 @@ MUTANTS = [
     ("smooth activation: critical point without the square root", slr, "act_critical", _act_critical_no_sqrt),
     ("smooth activation: critical point halved", slr, "act_critical", _act_critical_halved),
     ("smooth activation: offsets from the interval ends only", slr, "act_relax", _act_relax_endpoints_only),
+    ("crossing-score split takes the smallest score", count, "split_sides", _split_sides_argmin),
+    ("crossing-score split without the aspect guard", count, "split_sides", _split_sides_no_aspect_guard),
 ]
 
 
