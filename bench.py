@@ -291,6 +291,29 @@ def batch_section(E, torch, seed, reps=3):
                 "smaller_budgets": smaller}}
 
 
+def split_section(E, torch, inst, reps=3):
+    """The headline count with the crossing-score split rule (first one and two hidden layers)
+    beside the widest-side rule: same leaf budget, brackets and time."""
+    net = E.Net(inst.net)
+    prop = E.Property(net, inst.C, inst.dvec)
+    ws = torch.empty(E.workspace_size(net, prop, inst.max_leaves), dtype=torch.uint8, device="cuda")
+    out = {}
+    for k in (0, 1, 2):
+        E.count_exact(net, prop, inst.lo, inst.hi, inst.max_depth, inst.max_leaves, chunk=65536,
+                      workspace=ws, split_layers=k)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            r = E.count_exact(net, prop, inst.lo, inst.hi, inst.max_depth, inst.max_leaves,
+                              chunk=65536, workspace=ws, split_layers=k)
+        dt = (time.perf_counter() - t0) / reps
+        out["split_layers_%d" % k] = {"time_to_bracket_ms": dt * 1e3,
+                                      "bracket": [r["unsafe"], r["unsafe"] + r["undecided"]],
+                                      "boxes_bounded": r["n_boxes_bounded"],
+                                      "depth_reached": r["depth_reached"]}
+    return out
+
+
 def stack_section(E, torch, seed, depth=24, reps=2):
     """count_exact_stack (depth-first chunks, no leaf budget) on the same network past the
     2^20-leaf budget of the headline count."""
@@ -487,6 +510,7 @@ def main():
         line["batch"] = batch_section(E, torch, args.seed)
     if not args.no_stack:
         line["stack"] = stack_section(E, torch, args.seed)
+        line["split_rule"] = split_section(E, torch, inst)
     if not args.no_approx:
         line["approx"] = approx_section(E, torch, args.seed, not args.no_cpu_baseline)
     if not args.no_alpha:

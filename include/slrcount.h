@@ -161,6 +161,17 @@ typedef struct {
        proving safe (the smallest over the rows); a box is taken when the smaller of the two
        is at most alpha_select.  Must be finite and >= 0. */
     float alpha_select;
+    /* which side of an undecided box to bisect (the paper's iterative refinement, §2.2,
+       leaves it open): 0 the widest (lowest index on ties); k in 1..8 the side, among those at
+       least 2^-6 of the widest, that contributes most to the intervals of the crossing neurons
+       of the first k hidden layers, sum over them of |coefficient of the side| x its width
+       (the widest when none crosses).  k > 0 needs a ReLU network on the LDS bound kernel with
+       at most 11 inputs (SLR_EUNSUPPORTED otherwise). */
+    int32_t split_layers;
+    /* optional trace of the side bisected per bounded box (host, trace_capacity entries, NULL
+       to disable): the side for undecided boxes (-2 when the widest side was taken by
+       split_layers = 0), -1 for decided ones */
+    int8_t* trace_dim;
 } slr_exact_opts;
 
 typedef struct {

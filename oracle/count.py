@@ -76,7 +76,10 @@ def bisect(lo: np.ndarray, hi: np.ndarray, paths: np.ndarray, sides=None):
 
 
 ASPECT_LOG2 = 6      # split candidates: sides at least 2^-6 of the box's widest side
-BAND = 1e-4          # crossing tests within BAND * (|c0| + S) of zero are uncertain
+# crossing tests within BAND[layer] * (|c0| + S) of zero are uncertain: the first layer's
+# bounds are exact affine images (a float32 pass is off by ~1e-6 relative); deeper layers
+# inherit a float32 pass's worst-case rounding margins, up to ~1e-3 relative
+BAND = (1e-4, 1e-2)
 TIE = 1e-5           # relative score gap below which a split choice is not robust
 
 
@@ -84,16 +87,18 @@ def crossing_scores(lo, hi, tr, layers, band=0.0):
     """Per box and input side j: the sum over the crossing neurons of the first ``layers``
     hidden layers of |coefficient of x_j| x (hi_j - lo_j) in the neuron's pre-activation
     equation (the part of the neuron's interval that side j contributes).  A neuron counts as
-    crossing when l < -band m and u > band m, m = |centre| + sum of the side terms; band < 0
-    counts the uncertain ones too."""
+    crossing when l < -b m and u > b m, m = |centre| + sum of the side terms and
+    b = band * BAND[layer]: band = 1 leaves the uncertain ones out, band = -1 counts them in,
+    band = 0 is the plain test."""
     w = hi - lo
     s = np.zeros_like(w)
-    for t in tr[:layers]:
+    for li, t in enumerate(tr[:layers]):
         C = 0.5 * (t["L"] + t["U"])
         terms = np.abs(C[..., 1:]) * w[:, None, :]
         centre = C[..., 0] + np.einsum("bkj,bj->bk", C[..., 1:], 0.5 * (lo + hi))
         m = np.abs(centre) + 0.5 * terms.sum(-1)
-        cross = (t["lo"] < -band * m) & (t["hi"] > band * m)
+        bl = band * BAND[min(li, len(BAND) - 1)]
+        cross = (t["lo"] < -bl * m) & (t["hi"] > bl * m)
         s += np.einsum("bk,bkj->bj", cross.astype(np.float64), terms)
     return s
 
@@ -105,7 +110,8 @@ def split_sides(lo, hi, tr, layers):
     layers > 0: among the sides at least 2^-6 of the widest, the one with the largest
     ``crossing_scores`` (lowest index on ties); the widest if no neuron crosses.  The choice is
     robust unless another candidate's score could reach the chosen one's within TIE when
-    neurons within BAND of a phase change flip (a float32 evaluation may see them either way).
+    neurons within the BAND of a phase change flip (a float32 evaluation may see them either
+    way).
     """
     w = hi - lo
     widest = np.argmax(w, axis=1)
@@ -116,8 +122,8 @@ def split_sides(lo, hi, tr, layers):
     j = np.argmax(s, axis=1)
     none = s.max(axis=1) <= 0.0
     j = np.where(none, widest, j)
-    sure = np.where(ok, crossing_scores(lo, hi, tr, layers, BAND), -1.0)     # certain crossings
-    maybe = np.where(ok, crossing_scores(lo, hi, tr, layers, -BAND), -1.0)   # and uncertain
+    sure = np.where(ok, crossing_scores(lo, hi, tr, layers, 1.0), -1.0)      # certain crossings
+    maybe = np.where(ok, crossing_scores(lo, hi, tr, layers, -1.0), -1.0)    # and uncertain
     rows = np.arange(w.shape[0])
     others = maybe.copy()
     others[rows, j] = -np.inf

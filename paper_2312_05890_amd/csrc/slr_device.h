@@ -159,9 +159,12 @@ __device__ __forceinline__ EpiConst epi_const(const NetDev& net, int raw) {
 // without branches.  In: a[c][v] = pre-activation center coefficients (c = 0..d, bias included),
 // the unwidened radius a[d+1][v] and margin part a[d+2][v]; eps[v] = rounding margin of the
 // affine step.  Out: post-activation state in place; returns max_v bound on |value| over the box.
-template <int NCOL, bool SMOOTH = false>
+// SCORE (crossing-score split rule): when `score` is set, the local coefficients |c_1..c_D| of
+// every crossing neuron are added to sc (per-lane sums for the side to bisect).
+template <int NCOL, bool SMOOTH = false, bool SCORE = false>
 __device__ __forceinline__ float relu_epilogue(float (&a)[NCOL][4], const float (&eps)[4],
-                                               const bool (&valid)[4], const EpiConst& k) {
+                                               const bool (&valid)[4], const EpiConst& k,
+                                               float* sc = nullptr, bool score = false) {
     constexpr int D = NCOL - 3;
     constexpr int R = NCOL - 2, Q = NCOL - 1;
     float emax = 0.f;
@@ -193,6 +196,12 @@ __device__ __forceinline__ float relu_epilogue(float (&a)[NCOL][4], const float 
         const bool dead = !valid[v] || !(hi > 0.f);
         const bool act = !dead && lo >= 0.f;
         const bool cross = !dead && !act;
+        if constexpr (SCORE) {
+            if (score && cross) {
+#pragma unroll
+                for (int c = 1; c <= D; ++c) sc[c - 1] += fabsf(a[c][v]);
+            }
+        }
         const float den = cross ? hi - lo : 1.f;
         const float lamc = fminf(1.f, hi * __builtin_amdgcn_rcpf(den) * k.lamfac);
         const float lam = dead ? 0.f : (act ? 1.f : lamc);
@@ -303,15 +312,24 @@ __device__ __forceinline__ void k_quads_any(f32x4 (&acc)[NCOL], const float* __r
     k_quads<NCOL, 0>(acc, wf, qf, sb, colstride, nq, nqa);
 }
 
-template <int NCOL, int NT, int UW, int NW, bool SMOOTH = false>
+template <int NCOL, int NT, int UW, int NW, bool SMOOTH = false, bool SCORE = false>
 __device__ __forceinline__ void bound_tile(
     const NetDev& net, const PropDev& prop, int64_t n, int64_t box0,
     const float* __restrict__ blo, const float* __restrict__ bhi, float* __restrict__ g_lo,
     float* __restrict__ g_hi, int8_t* __restrict__ cls, int raw, int SP,
-    unsigned* __restrict__ amb_list, unsigned* __restrict__ amb_count, unsigned list_base) {
+    unsigned* __restrict__ amb_list, unsigned* __restrict__ amb_count, unsigned list_base,
+    int8_t* __restrict__ dimsel = nullptr, int split_layers = 0) {
     extern __shared__ float lds[];
     constexpr int T = NT * 16;
     constexpr int D = NCOL - 3;
+    // SCORE: per-lane crossing scores of each unit's box (a unit keeps its 16-box column)
+    float scv[UW][D];
+    if constexpr (SCORE) {
+#pragma unroll
+        for (int i = 0; i < UW; ++i)
+#pragma unroll
+            for (int c = 0; c < D; ++c) scv[i][c] = 0.f;
+    }
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6, g = lane >> 4, j = lane & 15;
     const int d = net.d;
@@ -374,7 +392,8 @@ __device__ __forceinline__ void bound_tile(
                     a[NCOL - 1][v] = 0.f;
                     eps[v] = raw ? 0.f : net.kfirst * s + kEta;
                 }
-                float emax = relu_epilogue<NCOL, SMOOTH>(a, eps, valid, ek);
+                float emax = relu_epilogue<NCOL, SMOOTH, SCORE>(a, eps, valid, ek, scv[i],
+                                                                split_layers >= 1);
                 float* sb = S + ((nt * NCOL * 4 + g) * 16 + j) * SP + 4 * mt;
 #pragma unroll
                 for (int c = 0; c < NCOL; ++c) {
@@ -458,7 +477,8 @@ __device__ __forceinline__ void bound_tile(
                     a[0][v] += bb;
                     eps[v] = raw ? 0.f : L->kgam * (A * emax_in + fabsf(bb)) + kEta;
                 }
-                float emax = relu_epilogue<NCOL, SMOOTH>(a, eps, valid, ek);
+                float emax = relu_epilogue<NCOL, SMOOTH, SCORE>(a, eps, valid, ek, scv[i],
+                                                                l + 2 <= split_layers);
                 float* sb = S + ((nt * NCOL * 4 + g) * 16 + j) * SP + 4 * mt;
 #pragma unroll
                 for (int c = 0; c < NCOL; ++c) {
@@ -579,6 +599,58 @@ __device__ __forceinline__ void bound_tile(
             if (amb_list) amb_list[atomicAdd(amb_count, 1u)] = list_base + (unsigned)b;
         }
         if (cls) cls[b] = k;
+    }
+    if constexpr (SCORE) {
+        // side to bisect: per box, the scores summed in a fixed order (lanes g by xor 16, 32;
+        // units in ascending order), then the largest among the sides at least 2^-6 of the
+        // widest (lowest index on ties); the widest side when no neuron crossed
+        if (dimsel) {
+            float* scp = S;   // [NW * UW][16][D]; S is not read after the output contraction
+#pragma unroll
+            for (int i = 0; i < UW; ++i) {
+#pragma unroll
+                for (int c = 0; c < D; ++c) {
+                    float v = scv[i][c];
+                    v += __shfl_xor(v, 16);
+                    v += __shfl_xor(v, 32);
+                    if (g == 0) scp[((wave * UW + i) * 16 + j) * D + c] = v;
+                }
+            }
+            __syncthreads();
+            for (int bj = tid; bj < T; bj += NW * 64) {
+                const int64_t b = box0 + bj;
+                if (b >= n) continue;
+                const int nt = bj >> 4, jj = bj & 15;
+                float sc[D];
+#pragma unroll
+                for (int c = 0; c < D; ++c) sc[c] = 0.f;
+                for (int u = 0; u < NW * UW; ++u) {
+                    if (u % NT != nt) continue;
+                    const float* p = scp + (((u % NW) * UW + u / NW) * 16 + jj) * D;
+#pragma unroll
+                    for (int c = 0; c < D; ++c) sc[c] += p[c];
+                }
+                int widest = 0, best = -1;
+                float wmax = -1.f, sbest = 0.f;
+                for (int kk = 0; kk < d; ++kk) {
+                    const float w = bhi[b * d + kk] - blo[b * d + kk];
+                    if (w > wmax) {
+                        wmax = w;
+                        widest = kk;
+                    }
+                }
+#pragma unroll
+                for (int kk = 0; kk < D; ++kk) {
+                    if (kk >= d) break;
+                    const float w = bhi[b * d + kk] - blo[b * d + kk];
+                    if (w >= wmax * 0x1p-6f && sc[kk] > sbest) {
+                        sbest = sc[kk];
+                        best = kk;
+                    }
+                }
+                dimsel[b] = (int8_t)(best >= 0 ? best : widest);
+            }
+        }
     }
 }
 
@@ -931,7 +1003,7 @@ __device__ __forceinline__ void split_tile_impl(int64_t n, int d, const int8_t* 
                                                 float* __restrict__ lo2, float* __restrict__ hi2,
                                                 unsigned long long* __restrict__ path2,
                                                 unsigned* err, int64_t cap, int64_t tile,
-                                                float* stage) {
+                                                float* stage, const int8_t* __restrict__ dimsel) {
     __shared__ unsigned red[4];
     __shared__ unsigned wpre[4];
     __shared__ unsigned short pidx[kTile];   // tile-local box index of the parent of local rank
@@ -1004,7 +1076,8 @@ __device__ __forceinline__ void split_tile_impl(int64_t n, int d, const int8_t* 
         // into the row, so every load is in bounds and none waits on the comparison before it)
         int js = 0;
         float wbest = h[0] - l[0];
-        for (int k0 = 1; k0 < d; k0 += 8) {
+        if (dimsel) js = min(max((int)dimsel[t0 + p], 0), d - 1);   // chosen by the bound kernel
+        for (int k0 = 1; k0 < d && !dimsel; k0 += 8) {
             float wv[8];
 #pragma unroll
             for (int u = 0; u < 8; ++u) {
@@ -1072,13 +1145,13 @@ __device__ __forceinline__ void split_tile(int64_t n, int d, const int8_t* __res
                                            float* __restrict__ lo2, float* __restrict__ hi2,
                                            unsigned long long* __restrict__ path2,
                                            unsigned* err, int64_t cap, int64_t tile,
-                                           float* stage) {
+                                           float* stage, const int8_t* dimsel = nullptr) {
     if (stage && d <= kSplitStageD)
         split_tile_impl<true>(n, d, cls, tile_und, lo, hi, path, lo2, hi2, path2, err, cap, tile,
-                              stage);
+                              stage, dimsel);
     else
         split_tile_impl<false>(n, d, cls, tile_und, lo, hi, path, lo2, hi2, path2, err, cap, tile,
-                               nullptr);
+                               nullptr, dimsel);
 }
 
 // Exact leaf-volume sums: sum_t count_t 2^(Dm - t) in 64-bit integers (the totals partition

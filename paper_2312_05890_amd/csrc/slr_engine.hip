@@ -524,6 +524,7 @@ struct Workspace {
     float *lo[2], *hi[2];
     unsigned long long* path[2];
     int8_t* cls;
+    int8_t* dimsel;              // [cap] side to bisect (crossing-score split rule)
     unsigned* amb_list;          // [cap] boxes of the level that need the FP64 re-decision
     unsigned* amb_count;
     unsigned* tile_und;
@@ -597,6 +598,7 @@ Workspace layout_ws(char* base, const NetDev& nd, const PropDev& pd, int64_t cap
         w.path[s] = (unsigned long long*)take(sizeof(unsigned long long) * cap);
     }
     w.cls = (int8_t*)take(cap);
+    w.dimsel = (int8_t*)take(cap);
     w.amb_list = (unsigned*)take(sizeof(unsigned) * cap);
     w.amb_count = (unsigned*)take(2 * sizeof(unsigned));   // [1]: all undecided (alpha pass)
     w.tile_und = (unsigned*)take(sizeof(unsigned) * level_tiles(cap));
@@ -1038,7 +1040,7 @@ int count_exact_impl(const slr_net* net, const slr_property* prop, const double*
     int64_t n = 1, resolved = 0, bounded = 0, tcount = 0;
     int cur = 0, levels = 0, stop_level = 0, stopped = 0, status = SLR_OK;
     std::vector<unsigned long long> hpath;
-    std::vector<int8_t> hcls;
+    std::vector<int8_t> hcls, hdim;
     for (int t = 0; t <= D; ++t) {
         int unsup = 0;
         HIP_TRY(hipMemsetAsync(w.amb_count, 0, sizeof(unsigned), s), "count_exact: clear");
@@ -1085,7 +1087,8 @@ int count_exact_impl(const slr_net* net, const slr_property* prop, const double*
                 HIP_TRY(launch_bound_f32(net->dev, prop->dev, m, w.lo[cur] + off * d, w.hi[cur] + off * d,
                                          keep_g ? w.glo + off * rows : nullptr,
                                          keep_g ? w.ghi + off * rows : nullptr, w.cls + off, 0, s,
-                                         &unsup, w.amb_list, w.amb_count, (unsigned)off),
+                                         &unsup, w.amb_list, w.amb_count, (unsigned)off,
+                                         o->split_layers > 0 ? w.dimsel + off : nullptr, o->split_layers),
                         "count_exact: bound kernel");
                 if (unsup) return fail(SLR_EUNSUPPORTED, "count_exact: shape not supported");
                 ++launches;
@@ -1154,11 +1157,22 @@ int count_exact_impl(const slr_net* net, const slr_property* prop, const double*
             hcls.resize(m);
             HIP_TRY(hipMemcpyAsync(hpath.data(), w.path[cur], m * sizeof(unsigned long long), hipMemcpyDeviceToHost, s), "count_exact: trace");
             HIP_TRY(hipMemcpyAsync(hcls.data(), w.cls, m, hipMemcpyDeviceToHost, s), "count_exact: trace");
+            if (o->trace_dim) {
+                hdim.resize(m);
+                if (o->split_layers > 0)
+                    HIP_TRY(hipMemcpyAsync(hdim.data(), w.dimsel, m, hipMemcpyDeviceToHost, s), "count_exact: trace");
+            }
             HIP_TRY(hipStreamSynchronize(s), "count_exact: sync");
             for (int64_t i = 0; i < m; ++i) {
                 o->trace_depth[tcount + i] = t;
                 o->trace_path[tcount + i] = hpath[i];
                 o->trace_cls[tcount + i] = hcls[i];
+                if (o->trace_dim) {
+                    // the side bisected: chosen by the bound kernel, or the widest one
+                    int8_t side = -1;
+                    if (hcls[i] == 0) side = o->split_layers > 0 ? hdim[i] : (int8_t)-2;
+                    o->trace_dim[tcount + i] = side;
+                }
             }
             tcount += m;
         }
@@ -1171,7 +1185,8 @@ int count_exact_impl(const slr_net* net, const slr_property* prop, const double*
             HIP_TRY(hipEventRecord(evr, s), "count_exact: event");
             if (time_split) HIP_TRY(hipEventRecord(sev(t, 0), s), "count_exact: event");
             HIP_TRY(launch_split(n, d, w.cls, w.tile_und, w.lo[cur], w.hi[cur], w.path[cur],
-                                 w.lo[cur ^ 1], w.hi[cur ^ 1], w.path[cur ^ 1], w.err + t, M, s),
+                                 w.lo[cur ^ 1], w.hi[cur ^ 1], w.path[cur ^ 1], w.err + t, M, s,
+                                 o->split_layers > 0 ? w.dimsel : nullptr),
                     "count_exact: split kernel");
             if (time_split) HIP_TRY(hipEventRecord(sev(t, 1), s), "count_exact: event");
             HIP_TRY(hipEventSynchronize(evr), "count_exact: sync");
@@ -1212,7 +1227,8 @@ int count_exact_impl(const slr_net* net, const slr_property* prop, const double*
         if (!spec) {
             if (time_split) HIP_TRY(hipEventRecord(sev(t, 0), s), "count_exact: event");
             HIP_TRY(launch_split(n, d, w.cls, w.tile_und, w.lo[cur], w.hi[cur], w.path[cur],
-                                 w.lo[cur ^ 1], w.hi[cur ^ 1], w.path[cur ^ 1], w.err + t, M, s),
+                                 w.lo[cur ^ 1], w.hi[cur ^ 1], w.path[cur ^ 1], w.err + t, M, s,
+                                 o->split_layers > 0 ? w.dimsel : nullptr),
                     "count_exact: split kernel");
             if (time_split) HIP_TRY(hipEventRecord(sev(t, 1), s), "count_exact: event");
         }
@@ -1276,6 +1292,12 @@ int check_exact_opts(const slr_net* net, const slr_property* prop, const slr_exa
         return fail(SLR_EINVAL, "%s: alpha_lr and alpha_min_depth must be >= 0", who);
     if (!(o->alpha_select >= 0.f) || !std::isfinite(o->alpha_select))
         return fail(SLR_EINVAL, "%s: alpha_select must be finite and >= 0", who);
+    if (o->split_layers < 0 || o->split_layers > SLR_MAX_AFFINE)
+        return fail(SLR_EINVAL, "%s: split_layers must be in [0, %d]", who, SLR_MAX_AFFINE);
+    if (o->split_layers > 0 && (net->dev.act != SLR_ACT_RELU || !bound_f32_supported(net->dev, prop->dev) ||
+                                bound_variant_for(net->dev, prop->dev) < 0 || net->dev.d + 3 > 14))
+        return fail(SLR_EUNSUPPORTED, "%s: the crossing-score split needs a ReLU network on the LDS bound "
+                    "kernel with at most 11 inputs", who);
     if (net->dev.act != SLR_ACT_RELU) {
         if (o->alpha_steps > 0)
             return fail(SLR_EUNSUPPORTED, "%s: alpha slopes are defined for ReLU networks only", who);

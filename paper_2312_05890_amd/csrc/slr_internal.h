@@ -108,10 +108,13 @@ struct LevelStats {
 // Kernel launchers (slr_kernels.hip).  All are asynchronous on `stream`.
 // The bound kernel writes class 3 for boxes whose class could differ in exact arithmetic and,
 // if amb_list is given, appends list_base + (box index) to amb_list[atomicAdd(amb_count)].
+// dimsel (with split_layers > 0): the crossing-score split rule writes each box's side to
+// bisect (ReLU networks, input classes up to NCOL 14; otherwise *unsupported).
 hipError_t launch_bound_f32(const NetDev& net, const PropDev& prop, int64_t n, const float* lo,
                             const float* hi, float* g_lo, float* g_hi, int8_t* cls, int raw,
                             hipStream_t stream, int* unsupported, unsigned* amb_list,
-                            unsigned* amb_count, unsigned list_base);
+                            unsigned* amb_count, unsigned list_base, int8_t* dimsel = nullptr,
+                            int split_layers = 0);
 // FP64 re-decision of the boxes list[0 .. *list_count), or of every class-3 box if list is NULL.
 hipError_t launch_recheck64(const NetDev& net, const PropDev& prop, int64_t n, const float* lo,
                             const float* hi, float* g_lo, float* g_hi, int8_t* cls,
@@ -119,10 +122,11 @@ hipError_t launch_recheck64(const NetDev& net, const PropDev& prop, int64_t n, c
                             const unsigned* list_count, hipStream_t stream);
 hipError_t launch_level_count(int64_t n, const int8_t* cls, unsigned int* tile_und,
                               LevelStats* stats, hipStream_t stream);
+// dimsel: the side of each parent chosen by the bound kernel (NULL: the widest side).
 hipError_t launch_split(int64_t n, int d, const int8_t* cls, const unsigned int* tile_und,
                         const float* lo, const float* hi, const unsigned long long* path,
                         float* lo2, float* hi2, unsigned long long* path2, unsigned int* err,
-                        int64_t cap, hipStream_t stream);
+                        int64_t cap, hipStream_t stream, const int8_t* dimsel = nullptr);
 // Depth-first stack count (count_exact_stack): per-depth class counts of a chunk of mixed-depth
 // boxes (depth from the path id), class 4 for undecided boxes at max_depth, per-tile and total
 // counts of the boxes to split; all_undecided counts every box as undecided at its depth.

@@ -9,14 +9,17 @@ namespace {
 
 // SMOOTH: tanh / sigmoid networks (parallel-line relaxation); a separate instantiation keeps the
 // ReLU kernels' registers and occupancy unchanged.
-template <int NCOL, int NT, int UW, int NW, bool SMOOTH = false>
+// SCORE: the crossing-score split rule (the side to bisect per box into dimsel).
+template <int NCOL, int NT, int UW, int NW, bool SMOOTH = false, bool SCORE = false>
 __global__ __launch_bounds__(NW * 64) void bound_f32_kernel(
     NetDev net, PropDev prop, int64_t n, const float* __restrict__ blo,
     const float* __restrict__ bhi, float* __restrict__ g_lo, float* __restrict__ g_hi,
     int8_t* __restrict__ cls, int raw, int SP, unsigned* __restrict__ amb_list,
-    unsigned* __restrict__ amb_count, unsigned list_base) {
-    bound_tile<NCOL, NT, UW, NW, SMOOTH>(net, prop, n, (int64_t)blockIdx.x * (NT * 16), blo, bhi,
-                                         g_lo, g_hi, cls, raw, SP, amb_list, amb_count, list_base);
+    unsigned* __restrict__ amb_count, unsigned list_base, int8_t* __restrict__ dimsel,
+    int split_layers) {
+    bound_tile<NCOL, NT, UW, NW, SMOOTH, SCORE>(net, prop, n, (int64_t)blockIdx.x * (NT * 16), blo,
+                                                bhi, g_lo, g_hi, cls, raw, SP, amb_list, amb_count,
+                                                list_base, dimsel, split_layers);
 }
 
 __global__ __launch_bounds__(256) void recheck64_kernel(NetDev net, PropDev prop, int64_t n,
@@ -68,10 +71,11 @@ __global__ __launch_bounds__(256) void split_kernel(int64_t n, int d, const int8
                                                     const unsigned long long* __restrict__ path,
                                                     float* __restrict__ lo2, float* __restrict__ hi2,
                                                     unsigned long long* __restrict__ path2,
-                                                    unsigned* err, int64_t cap) {
+                                                    unsigned* err, int64_t cap,
+                                                    const int8_t* __restrict__ dimsel) {
     extern __shared__ float split_stage[];
     split_tile(n, d, cls, tile_und, lo, hi, path, lo2, hi2, path2, err, cap, blockIdx.x,
-               d <= kSplitStageD ? split_stage : nullptr);
+               d <= kSplitStageD ? split_stage : nullptr, dimsel);
 }
 
 // Depth-first stack count, one chunk of boxes of mixed depths (the depth of a box is the position
@@ -457,20 +461,20 @@ int ncol_class(int d) {
 
 int state_stride(int mt_max) { return 4 * mt_max + ((mt_max & 1) ? 0 : 4); }
 
-template <int NCOL, int NT, int UW, int NW, bool SMOOTH = false>
+template <int NCOL, int NT, int UW, int NW, bool SMOOTH = false, bool SCORE = false>
 hipError_t launch_inst(const NetDev& net, const PropDev& prop, int64_t n, const float* lo,
                        const float* hi, float* g_lo, float* g_hi, int8_t* cls, int raw,
                        hipStream_t stream, unsigned* amb_list, unsigned* amb_count,
-                       unsigned list_base) {
+                       unsigned list_base, int8_t* dimsel = nullptr, int split_layers = 0) {
     const size_t lds = bound_lds_bytes(NCOL, TileShape{NT, UW, NW}, net.mt_max, prop.rows);
-    auto kern = bound_f32_kernel<NCOL, NT, UW, NW, SMOOTH>;
+    auto kern = bound_f32_kernel<NCOL, NT, UW, NW, SMOOTH, SCORE>;
     hipError_t e = allow_lds((const void*)kern, lds);
     if (e != hipSuccess) return e;
     const int64_t blocks = (n + NT * 16 - 1) / (NT * 16);
     (void)hipGetLastError();
     hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(NW * 64), lds, stream, net, prop, n,
                        lo, hi, g_lo, g_hi, cls, raw, state_stride(net.mt_max), amb_list,
-                       amb_count, list_base);
+                       amb_count, list_base, dimsel, split_layers);
     return hipGetLastError();
 }
 
@@ -478,7 +482,20 @@ hipError_t launch_inst(const NetDev& net, const PropDev& prop, int64_t n, const 
 template <int NCOL>
 hipError_t launch_ncol(TileShape t, const NetDev& net, const PropDev& prop, int64_t n,
                        const float* lo, const float* hi, float* g_lo, float* g_hi, int8_t* cls,
-                       int raw, hipStream_t stream, unsigned* al, unsigned* ac, unsigned lb) {
+                       int raw, hipStream_t stream, unsigned* al, unsigned* ac, unsigned lb,
+                       int8_t* dimsel, int split_layers) {
+    if (dimsel && split_layers > 0) {   // crossing-score split: ReLU, the default shapes only
+        if constexpr (NCOL <= 14) {
+#define SLR_SCORE(A, B, C)                                                                       \
+            if (t.nt == A && t.uw == B && t.nw == C)                                              \
+                return launch_inst<NCOL, A, B, C, false, true>(net, prop, n, lo, hi, g_lo, g_hi, \
+                                                               cls, raw, stream, al, ac, lb,     \
+                                                               dimsel, split_layers);
+            SLR_SCORE(4, 1, 4) SLR_SCORE(2, 1, 4) SLR_SCORE(1, 1, 4) SLR_SCORE(1, 2, 4)
+#undef SLR_SCORE
+        }
+        return hipErrorInvalidValue;
+    }
     if (net.act != SLR_ACT_RELU) {   // smooth networks: the default shapes only
 #define SLR_SMOOTH(A, B, C)                                                                      \
         if (t.nt == A && t.uw == B && t.nw == C)                                                  \
@@ -659,14 +676,15 @@ int bound_f32_supported(const NetDev& net, const PropDev& prop) {
 hipError_t launch_bound_f32(const NetDev& net, const PropDev& prop, int64_t n, const float* lo,
                             const float* hi, float* g_lo, float* g_hi, int8_t* cls, int raw,
                             hipStream_t stream, int* unsupported, unsigned* amb_list,
-                            unsigned* amb_count, unsigned list_base) {
+                            unsigned* amb_count, unsigned list_base, int8_t* dimsel,
+                            int split_layers) {
     *unsupported = 0;
     if (n <= 0) return hipSuccess;
     if (!bound_f32_supported(net, prop)) {
         *unsupported = 1;
         return hipSuccess;
     }
-    if (bound_variant_for(net, prop) == 2) {
+    if (bound_variant_for(net, prop) == 2 && !(dimsel && split_layers > 0)) {
         switch (net.d + 3) {
 #define SLR_RCASE(C) \
     case C: return launch_reg_mt<C>(net, prop, n, lo, hi, g_lo, g_hi, cls, raw, stream, amb_list, \
@@ -676,11 +694,17 @@ hipError_t launch_bound_f32(const NetDev& net, const PropDev& prop, int64_t n, c
             default: break;
         }
     }
-    const TileShape t = net.act == SLR_ACT_RELU ? tile_shape_for(net.d, net.mt_max) : default_shape(net.mt_max);
+    const bool scored = dimsel && split_layers > 0;
+    if (scored && (net.act != SLR_ACT_RELU || ncol_class(net.d) > 14)) {
+        *unsupported = 1;
+        return hipSuccess;
+    }
+    const TileShape t = net.act == SLR_ACT_RELU && !scored ? tile_shape_for(net.d, net.mt_max)
+                                                           : default_shape(net.mt_max);
     switch (ncol_class(net.d)) {
 #define SLR_CASE(C) \
     case C: return launch_ncol<C>(t, net, prop, n, lo, hi, g_lo, g_hi, cls, raw, stream, \
-                                  amb_list, amb_count, list_base);
+                                  amb_list, amb_count, list_base, dimsel, split_layers);
         SLR_CASE(4) SLR_CASE(5) SLR_CASE(6) SLR_CASE(7) SLR_CASE(8) SLR_CASE(9)
         SLR_CASE(10) SLR_CASE(11) SLR_CASE(12) SLR_CASE(14) SLR_CASE(18) SLR_CASE(26) SLR_CASE(35)
 #undef SLR_CASE
@@ -723,12 +747,12 @@ hipError_t launch_level_count(int64_t n, const int8_t* cls, unsigned* tile_und, 
 hipError_t launch_split(int64_t n, int d, const int8_t* cls, const unsigned* tile_und,
                         const float* lo, const float* hi, const unsigned long long* path,
                         float* lo2, float* hi2, unsigned long long* path2, unsigned* err,
-                        int64_t cap, hipStream_t stream) {
+                        int64_t cap, hipStream_t stream, const int8_t* dimsel) {
     if (n <= 0) return hipSuccess;
     (void)hipGetLastError();
     const size_t lds = d <= kSplitStageD ? 2 * sizeof(float) * kTile * d : 0;
     hipLaunchKernelGGL(split_kernel, dim3((unsigned)level_tiles(n)), dim3(256), lds, stream, n, d,
-                       cls, tile_und, lo, hi, path, lo2, hi2, path2, err, cap);
+                       cls, tile_und, lo, hi, path, lo2, hi2, path2, err, cap, dimsel);
     return hipGetLastError();
 }
 

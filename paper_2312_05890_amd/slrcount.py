@@ -43,7 +43,8 @@ class ExactOpts(C.Structure):
                 ("trace_cls", C.POINTER(C.c_int8)), ("timing", C.c_int32),
                 ("alpha_steps", C.c_int32), ("alpha_lr", C.c_float),
                 ("alpha_min_depth", C.c_int32), ("alpha_chunk", C.c_int32),
-                ("alpha_select", C.c_float)]
+                ("alpha_select", C.c_float), ("split_layers", C.c_int32),
+                ("trace_dim", C.POINTER(C.c_int8))]
 
 
 class CountResult(C.Structure):
@@ -325,7 +326,7 @@ def workspace_size(net: Net, prop: Property, max_leaves: int, samples: int = 0,
 
 def _exact_opts(net, prop, max_depth, max_leaves, chunk, workspace, stream, samples,
                 trace_capacity=0, timing=False, alpha_steps=0, alpha_lr=0.0, alpha_min_depth=0,
-                alpha_chunk=0, alpha_select=0.0):
+                alpha_chunk=0, alpha_select=0.0, split_layers=0):
     import torch
     if alpha_steps > 0 and alpha_chunk <= 0:
         alpha_chunk = 16384
@@ -347,6 +348,7 @@ def _exact_opts(net, prop, max_depth, max_leaves, chunk, workspace, stream, samp
     o.alpha_min_depth = int(alpha_min_depth)
     o.alpha_chunk = int(alpha_chunk)
     o.alpha_select = float(alpha_select)
+    o.split_layers = int(split_layers)
     return o, workspace
 
 
@@ -354,8 +356,9 @@ def count_exact(net: Net, prop: Property, lo, hi, max_depth: int, max_leaves: in
                 chunk: int = 0, workspace=None, stream=None, trace: bool = False,
                 trace_capacity: Optional[int] = None, timing: int = 0,
                 alpha_steps: int = 0, alpha_lr: float = 0.1, alpha_min_depth: int = 0,
-                alpha_chunk: int = 0, alpha_select: float = 0.0) -> dict:
-    """Alg. 1 on the device; returns the bracket, counts and (optionally) a per-box trace.
+                alpha_chunk: int = 0, alpha_select: float = 0.0, split_layers: int = 0) -> dict:
+    """Alg. 1 on the device; returns the bracket, counts and (optionally) a per-box trace
+    (with the side bisected per box in ``trace_dim``).
 
     ``timing``: bit 0 times the bound-kernel launches (``bound_ms``), bit 1 the split launches
     (``split_ms``, with their algorithmic ``split_bytes``); True means 1.
@@ -369,14 +372,17 @@ def count_exact(net: Net, prop: Property, lo, hi, max_depth: int, max_leaves: in
     if trace:
         cap = int(trace_capacity if trace_capacity is not None else 4 * max_leaves + 64)
     o, ws = _exact_opts(net, prop, max_depth, max_leaves, chunk, workspace, stream, 0, cap, timing,
-                        alpha_steps, alpha_lr, alpha_min_depth, alpha_chunk, alpha_select)
+                        alpha_steps, alpha_lr, alpha_min_depth, alpha_chunk, alpha_select,
+                        split_layers)
     if trace:
         t_depth = np.zeros(cap, np.int32)
         t_path = np.zeros(cap, np.uint64)
         t_cls = np.zeros(cap, np.int8)
+        t_dim = np.zeros(cap, np.int8)
         o.trace_depth = t_depth.ctypes.data_as(C.POINTER(C.c_int32))
         o.trace_path = t_path.ctypes.data_as(C.POINTER(C.c_uint64))
         o.trace_cls = t_cls.ctypes.data_as(C.POINTER(C.c_int8))
+        o.trace_dim = t_dim.ctypes.data_as(C.POINTER(C.c_int8))
     r = CountResult()
     rc = _check(lib().count_exact(net.handle, prop.handle,
                                   lo.ctypes.data_as(C.POINTER(C.c_double)),
@@ -389,6 +395,7 @@ def count_exact(net: Net, prop: Property, lo, hi, max_depth: int, max_leaves: in
         out["trace_depth"] = t_depth[:k].copy()
         out["trace_path"] = t_path[:k].copy()
         out["trace_cls"] = t_cls[:k].copy()
+        out["trace_dim"] = t_dim[:k].copy()
     return out
 
 
