@@ -44,11 +44,11 @@ def _exact_sum(hist):
     return sum((Fraction(int(n), 1 << t) for t, n in enumerate(hist)), Fraction(0))
 
 
-def bound_chunked(net, C, dvec, lo, hi, chunk=8192):
+def bound_chunked(net, C, dvec, lo, hi, chunk=8192, relax="one"):
     g_lo = []
     g_hi = []
     for s in range(0, lo.shape[0], chunk):
-        a, b = slr.propagate(net, C, dvec, lo[s:s + chunk], hi[s:s + chunk])
+        a, b = slr.propagate(net, C, dvec, lo[s:s + chunk], hi[s:s + chunk], relax=relax)
         g_lo.append(a)
         g_hi.append(b)
     return np.concatenate(g_lo), np.concatenate(g_hi)
@@ -133,12 +133,13 @@ def split_sides(lo, hi, tr, layers):
 
 
 def count_exact(net, C, dvec, lo, hi, max_depth: int, max_leaves: int, trace: bool = False,
-                chunk: int = 8192, split_layers: int = 0):
+                chunk: int = 8192, split_layers: int = 0, relax: str = "one"):
     """Alg. 1, level by level.  Returns a dict with the bracket, counts and histograms.
 
     With ``trace`` the dict also holds, per level, the boxes' path ids, classes and bounds,
     and for the boxes that were split the side and whether that choice was robust.
-    ``split_layers``: the split rule of ``split_sides``.
+    ``split_layers``: the split rule of ``split_sides``.  ``relax``: the ReLU relaxation of
+    ``slr.propagate`` ("one": Eq. 1; "two": one ratio per equation).
     """
     lo = np.asarray(lo, np.float64).reshape(1, -1)
     hi = np.asarray(hi, np.float64).reshape(1, -1)
@@ -160,9 +161,9 @@ def count_exact(net, C, dvec, lo, hi, max_depth: int, max_leaves: int, trace: bo
             break
         depth = t
         if split_layers > 0:
-            g_lo, g_hi, tr = slr.propagate(net, C, dvec, lo, hi, keep=True)
+            g_lo, g_hi, tr = slr.propagate(net, C, dvec, lo, hi, keep=True, relax=relax)
         else:
-            g_lo, g_hi = bound_chunked(net, C, dvec, lo, hi, chunk)
+            g_lo, g_hi = bound_chunked(net, C, dvec, lo, hi, chunk, relax)
         cls = slr.classify(g_lo, g_hi)
         bounded += lo.shape[0]
         if trace:

@@ -141,6 +141,38 @@ def relu_relax(L, U, lo_b, hi_b, xmag, alpha=None):
     return Ln, Un
 
 
+def relu_relax_two(L, U, lo_b, hi_b, lU, uL, xmag):
+    """ReLU with two ratios, one per equation (the separate-ratio form Eq. 1 is derived from).
+
+    A neuron is dead when u = max U <= 0 and active when l = min L >= 0, as in Eq. 1.  When it
+    crosses, each equation gets the chord of its own range: the upper one, with range
+    [lU, u], becomes lamU (U - lU), lamU = u / (u - lU) rounded up (or stays U when lU >= 0:
+    then ReLU(z) <= ReLU(U) = U); the lower one, with range [l, uL], becomes lamL L,
+    lamL = uL / (uL - l) (or 0 when uL <= 0): any slope in [0, 1] gives ReLU(z) >= slope z >=
+    slope L.
+    """
+    dead = hi_b <= 0.0
+    cross = (lo_b < 0.0) & (hi_b > 0.0)
+    up_chord = cross & (lU < 0.0)
+    lamU = np.where(up_chord, hi_b / np.where(up_chord, hi_b - lU, 1.0), 1.0)
+    lamU = np.minimum(1.0, lamU * (1.0 + 4.0 * UNIT))
+    lo_zero = cross & (uL <= 0.0)
+    lo_chord = cross & (uL > 0.0)
+    lamL = np.where(lo_chord, uL / np.where(lo_chord, uL - lo_b, 1.0), 1.0)
+    lamL = np.where(lo_zero, 0.0, lamL)
+    magL = magnitude(L, xmag)
+    magU = magnitude(U, xmag)
+    Ln = np.where(cross[..., None], lamL[..., None] * L, L)
+    shifted = U.copy()
+    shifted[..., 0] -= np.where(up_chord, lU, 0.0)
+    Un = np.where(up_chord[..., None], lamU[..., None] * shifted, U)
+    Ln[..., 0] -= np.where(cross, gamma(3) * lamL * magL, 0.0)
+    Un[..., 0] += np.where(up_chord, gamma(3) * lamU * (magU + np.abs(lU)), 0.0)
+    Ln[dead] = 0.0
+    Un[dead] = 0.0
+    return Ln, Un
+
+
 def activation_of(net) -> str:
     """'relu' (the paper's networks), or 'tanh' / 'sigmoid' for a net that carries ``act``."""
     return getattr(net, "act", "relu")
@@ -212,7 +244,7 @@ def act_relax(L, U, lo_b, hi_b, xmag, act):
 
 
 def propagate(net, C, dvec, lo, hi, alpha: Optional[np.ndarray] = None, keep: bool = False,
-              equations: bool = False):
+              equations: bool = False, relax: str = "one"):
     """Output-property bounds for a batch of boxes.
 
     ``lo``/``hi``: [B, d] box corners.  ``alpha``: optional [B, sum of hidden widths] lower
@@ -220,7 +252,8 @@ def propagate(net, C, dvec, lo, hi, alpha: Optional[np.ndarray] = None, keep: bo
     [B, rows]; with ``keep`` also a list with, per hidden layer, the pre-activation
     equations and bounds and the post-activation equations (for soundness checks); with
     ``equations`` also the property rows' lower and upper equations ``(L, U)`` [B, rows, d+1]
-    (last, after the trace if both are asked for).
+    (last, after the trace if both are asked for).  ``relax``: "one" (Eq. 1, one ratio) or
+    "two" (``relu_relax_two``, ReLU networks without alpha).
     """
     layers = _as64(net)
     lo = np.atleast_2d(np.asarray(lo, np.float64))
@@ -255,7 +288,12 @@ def propagate(net, C, dvec, lo, hi, alpha: Optional[np.ndarray] = None, keep: bo
             a = np.asarray(alpha, np.float64)[:, a_off:a_off + n]
             a_off += n
         act = activation_of(net)
-        if act == "relu":
+        if act == "relu" and relax == "two":
+            assert alpha is None
+            lU = concretize_lower(U, lo, hi, xmag)
+            uL = concretize_upper(L, lo, hi, xmag)
+            Lr, Ur = relu_relax_two(L, U, lo_b, hi_b, lU, uL, xmag)
+        elif act == "relu":
             Lr, Ur = relu_relax(L, U, lo_b, hi_b, xmag, a)
         else:
             assert alpha is None, "alpha slopes are defined for ReLU networks only"

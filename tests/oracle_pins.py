@@ -382,8 +382,90 @@ def pin_split_rule_grid():
             assert block.size > 0 and (block.all() if c == 1 else not block.any())
 
 
+def pin_two_ratio_hand():
+    """Two ratios, derived by hand.  x in [-1, 1], h = ReLU(x), z = h - 1/4, y = ReLU(z).
+    The first neuron has L = U = x, so both forms give L = x/2, U = (x + 1)/2.  For z:
+    L = x/2 - 1/4 (range [-3/4, 1/4]) and U = x/2 + 1/4 (range [-1/4, 3/4]), so l = -3/4,
+    u = 3/4.  Eq. 1 (one ratio 1/2): L' = x/4 - 1/8, U' = (U + 3/4)/2 = x/4 + 1/2, bounds
+    [-3/8, 3/4].  Two ratios: lamU = (3/4)/(3/4 + 1/4) = 3/4, U' = 3/4 (U + 1/4) = 3x/8 + 3/8;
+    lamL = (1/4)/(1/4 + 3/4) = 1/4, L' = x/8 - 1/16; bounds [-3/16, 3/4]."""
+    net = [(_f32([[1.0]]), _f32([0.0])), (_f32([[1.0]]), _f32([-0.25])), (_f32([[1.0]]), _f32([0.0]))]
+    for relax, lo_exp, L2, U2 in (("one", -0.375, [-0.125, 0.25], [0.5, 0.25]),
+                                  ("two", -0.1875, [-0.0625, 0.125], [0.375, 0.375])):
+        g_lo, g_hi, tr = slr.propagate(net, [[1.0]], [0.0], [[-1.0]], [[1.0]], keep=True,
+                                       relax=relax)
+        assert np.allclose(tr[0]["Lr"][0, 0], [0.0, 0.5], atol=1e-12)
+        assert np.allclose(tr[0]["Ur"][0, 0], [0.5, 0.5], atol=1e-12)
+        assert np.allclose(tr[1]["Lr"][0, 0], L2, atol=1e-12), (relax, tr[1]["Lr"][0, 0])
+        assert np.allclose(tr[1]["Ur"][0, 0], U2, atol=1e-12), (relax, tr[1]["Ur"][0, 0])
+        assert abs(g_lo[0, 0] - lo_exp) < 1e-12 and abs(g_hi[0, 0] - 0.75) < 1e-12
+    # With z = h + b, b = fl32(-0.6), the lower equation x/2 + b of z stays below zero (its
+    # max is 0.5 + b) while the neuron crosses (l = b - 0.5, u = 1 + b).  Two ratios give
+    # L' = 0 and, from U = x/2 + 1/2 + b with range [b, 1 + b], U' = (1 + b)(U - b);
+    # one ratio lam = u / (u - l) gives L' = lam (x/2 + b) and U' = lam (U - l) = lam (x/2 + 1).
+    net[1] = (_f32([[1.0]]), _f32([-0.6]))
+    b6 = float(np.float32(-0.6))
+    l, u, lU, uL = b6 - 0.5, 1.0 + b6, b6, 0.5 + b6
+    assert uL < 0.0 < u and l < lU < 0.0
+    for relax in ("one", "two"):
+        g_lo, g_hi, tr = slr.propagate(net, [[1.0]], [0.0], [[-1.0]], [[1.0]], keep=True,
+                                       relax=relax)
+        if relax == "one":
+            lam = u / (u - l)
+            L2, U2 = [lam * b6, lam * 0.5], [lam, lam * 0.5]
+        else:
+            lam = u / (u - lU)
+            L2, U2 = [0.0, 0.0], [lam * 0.5, lam * 0.5]
+        assert np.allclose(tr[1]["Lr"][0, 0], L2, atol=1e-12), (relax, tr[1]["Lr"][0, 0])
+        assert np.allclose(tr[1]["Ur"][0, 0], U2, atol=1e-12), (relax, tr[1]["Ur"][0, 0])
+        assert abs(g_lo[0, 0] - (L2[0] - L2[1])) < 1e-12
+        assert abs(g_hi[0, 0] - (U2[0] + U2[1])) < 1e-12
+
+
+def pin_two_ratio_soundness_and_grid():
+    """Two ratios: sampled soundness of every bound on random networks (as pin_soundness), and
+    the dense-grid check of the exact count on tiny2d."""
+    rng = np.random.default_rng(5)
+    for si, sizes in enumerate(([2, 16, 16, 1], [3, 8, 8, 8, 2], [4, 10, 10, 10, 3])):
+        net = synth.make_net(sizes, 70 + si)
+        n_out = sizes[-1]
+        C = rng.normal(size=(min(2, n_out), n_out)).astype(np.float32)
+        dv = rng.normal(scale=0.1, size=C.shape[0]).astype(np.float32)
+        blo, bhi = synth.uniform_boxes(-np.ones(sizes[0]), np.ones(sizes[0]), 5, 80 + si, 0.6)
+        g_lo, g_hi, tr = slr.propagate(net, C, dv, blo, bhi, keep=True, relax="two")
+        for b in range(5):
+            x = slr.sample_points(blo[b], bhi[b], 2000, rng)
+            for li, z in enumerate(slr.preactivations(net, x)):
+                t = tr[li]
+                a = np.maximum(z, 0.0)
+                Lr = t["Lr"][b, :, 0] + x @ t["Lr"][b, :, 1:].T
+                Ur = t["Ur"][b, :, 0] + x @ t["Ur"][b, :, 1:].T
+                assert np.all(Lr <= a + 1e-12 * (1 + a)) and np.all(a <= Ur + 1e-12 * (1 + a))
+            gv = slr.property_values(net, C, dv, x)
+            assert np.all(g_lo[b] <= gv.min(axis=0)) and np.all(gv.max(axis=0) <= g_hi[b])
+    inst = synth.tiny2d(4)
+    r = count.count_exact(inst.net, inst.C, inst.dvec, inst.lo, inst.hi, 14, 1 << 20,
+                          trace=True, relax="two")
+    assert r["unsafe_exact"] + r["safe_exact"] + r["undecided_exact"] == 1
+    cells = 512
+    h = 2.0 / cells
+    centers = -1.0 + h * (np.arange(cells) + 0.5)
+    X, Y = np.meshgrid(centers, centers, indexing="ij")
+    G = (slr.property_values(inst.net, inst.C, inst.dvec,
+                             np.stack([X.ravel(), Y.ravel()], axis=1))[:, 0] > 0).reshape(cells, cells)
+    for lev in r["levels"]:
+        for i, c in enumerate(lev["cls"]):
+            if c == 0:
+                continue
+            i0, i1 = (int(round((lev["lo"][i, 0] + 1) / h)), int(round((lev["hi"][i, 0] + 1) / h)))
+            j0, j1 = (int(round((lev["lo"][i, 1] + 1) / h)), int(round((lev["hi"][i, 1] + 1) / h)))
+            block = G[i0:i1, j0:j1]
+            assert block.size > 0 and (block.all() if c == 1 else not block.any())
+
+
 ALL_PINS = [pin_eq1_single_relu, pin_two_neurons, pin_linear_regime, pin_soundness,
             pin_irwin_hall, pin_abs_closed_form, pin_dense_grid, pin_accounting,
             pin_alpha_adam_closed_form, pin_alpha_objective_row,
             pin_act_single_neuron_bruteforce, pin_act_soundness, pin_act_dense_grid,
-            pin_split_rule_hand, pin_split_rule_grid]
+            pin_split_rule_hand, pin_split_rule_grid, pin_two_ratio_hand,
+            pin_two_ratio_soundness_and_grid]

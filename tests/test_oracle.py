@@ -283,8 +283,30 @@ def _split_sides_no_aspect_guard(lo, hi, tr, layers):
     return np.where(s.max(axis=1) > 0, np.argmax(s, axis=1), j), robust
 
 
+def _two_ratio_shares_the_range(L, U, lo_b, hi_b, lU, uL, xmag):
+    """Both equations take the neuron's range [l, u] (the one-ratio form)."""
+    return ORIG_RELU_TWO(L, U, lo_b, hi_b, lo_b, hi_b, xmag)
+
+
+def _two_ratio_upper_shift_by_l(L, U, lo_b, hi_b, lU, uL, xmag):
+    """Upper chord through (l, 0) while its slope is taken from [lU, u]."""
+    Ln, Un = ORIG_RELU_TWO(L, U, lo_b, hi_b, lU, uL, xmag)
+    up = (lo_b < 0.0) & (hi_b > 0.0) & (lU < 0.0)
+    lam = np.where(up, hi_b / np.where(up, hi_b - lU, 1.0), 0.0)
+    Un[..., 0] += np.where(up, lam * (lU - lo_b), 0.0)
+    return Ln, Un
+
+
+def _two_ratio_lower_keeps_negative(L, U, lo_b, hi_b, lU, uL, xmag):
+    """Lower line keeps L when uL <= 0 instead of dropping to 0."""
+    Ln, Un = ORIG_RELU_TWO(L, U, lo_b, hi_b, lU, uL, xmag)
+    keep = (lo_b < 0.0) & (hi_b > 0.0) & (uL <= 0.0)
+    return np.where(keep[..., None], L, Ln), Un
+
+
 ORIG_AFFINE = slr.affine
 ORIG_RELU = slr.relu_relax
+ORIG_RELU_TWO = slr.relu_relax_two
 ORIG_CLASSIFY = slr.classify
 ORIG_BISECT = count.bisect
 ORIG_ACT_CRITICAL = slr.act_critical
@@ -307,6 +329,9 @@ MUTANTS = [
     ("smooth activation: offsets from the interval ends only", slr, "act_relax", _act_relax_endpoints_only),
     ("crossing-score split takes the smallest score", count, "split_sides", _split_sides_argmin),
     ("crossing-score split without the aspect guard", count, "split_sides", _split_sides_no_aspect_guard),
+    ("two ratios: both from the neuron's range", slr, "relu_relax_two", _two_ratio_shares_the_range),
+    ("two ratios: upper chord shifted by l", slr, "relu_relax_two", _two_ratio_upper_shift_by_l),
+    ("two ratios: lower keeps L below zero", slr, "relu_relax_two", _two_ratio_lower_keeps_negative),
 ]
 
 
