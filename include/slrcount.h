@@ -172,7 +172,20 @@ typedef struct {
        to disable): the side for undecided boxes (-2 when the widest side was taken by
        split_layers = 0), -1 for decided ones */
     int8_t* trace_dim;
+    /* ReLU relaxation: SLR_RELAX_ONE (Eq. 1: the upper chord's ratio u / (u - l) scales both
+       equations) or SLR_RELAX_TWO (one ratio per equation, from that equation's own range:
+       the upper one becomes the chord of ReLU over [min U, u], or stays U when min U >= 0; the
+       lower one gets slope max L / (max L - l), or 0 when max L <= 0).  SLR_RELAX_TWO bounds
+       every level with the tape-state kernel and keeps its widened float32 classes: boxes
+       within the float32 rounding margin of a decision are not re-decided in FP64 and stay
+       undecided (the bracket stays sound and can be slightly wider than an FP64 evaluation's).
+       It needs a ReLU network with d <= 32 and no alpha or split_layers (SLR_EUNSUPPORTED
+       otherwise); the workspace grows by the tape of 4096 boxes (workspace_size_exact). */
+    int32_t relax;
 } slr_exact_opts;
+
+/* Values of slr_exact_opts.relax and bound_boxes_relax's relax. */
+enum { SLR_RELAX_ONE = 0, SLR_RELAX_TWO = 1 };
 
 typedef struct {
     double unsafe, safe, undecided;   /* volume fractions of the input box; they sum to 1   */
@@ -202,6 +215,14 @@ typedef struct {
  */
 int workspace_size(const slr_net* net, const slr_property* prop, int64_t max_leaves,
                    int32_t samples, int32_t alpha_chunk, size_t* bytes);
+
+/*
+ * workspace_size_exact: bytes of device workspace count_exact needs for `opts` (its
+ * max_leaves, alpha_chunk when alpha_steps > 0, and relax; the workspace fields are ignored).
+ * workspace_size gives the same figure for SLR_RELAX_ONE.
+ */
+int workspace_size_exact(const slr_net* net, const slr_property* prop, const slr_exact_opts* opts,
+                         size_t* bytes);
 
 /*
  * count_exact: Alg. 1 level by level on the device.
@@ -371,6 +392,25 @@ int alpha_tape_size(const slr_net* net, const slr_property* prop, int64_t n, siz
 int bound_boxes_alpha(const slr_net* net, const slr_property* prop, int64_t n, const float* lo,
                       const float* hi, float* alpha, int32_t init, float* g_lo, float* g_hi,
                       int8_t* cls, int32_t raw, void* tape, size_t tape_bytes, void* stream);
+
+/*
+ * bound_boxes_relax: bounds of n boxes with the plain slopes of a ReLU relaxation, from the
+ * tape-state kernel (full lower and upper equations per neuron), on `stream`, asynchronous.
+ *   relax        SLR_RELAX_ONE (Eq. 1, the same bounds as bound_boxes up to float32 rounding)
+ *                or SLR_RELAX_TWO (one ratio per equation, slr_exact_opts.relax)
+ *   lo, hi       device float32 [n, d];  g_lo, g_hi  device float32 [n, rows]
+ *   cls          device int8 [n] (optional): 1 unsafe, 2 safe, 0 undecided, from g_lo / g_hi
+ *                (no FP64 re-decision: count_exact with relax does that)
+ *   raw          1 = no rounding margins (for comparison with an FP64 reference), 0 = sound
+ *   tape         device scratch of at least bound_tape_size(n) bytes
+ * ReLU networks with d <= 32 (SLR_EUNSUPPORTED otherwise).
+ */
+int bound_boxes_relax(const slr_net* net, const slr_property* prop, int64_t n, const float* lo,
+                      const float* hi, int32_t relax, float* g_lo, float* g_hi, int8_t* cls,
+                      int32_t raw, void* tape, size_t tape_bytes, void* stream);
+
+/* bound_tape_size: bytes of the scratch tape bound_boxes_relax needs for n boxes. */
+int bound_tape_size(const slr_net* net, const slr_property* prop, int64_t n, size_t* bytes);
 
 /*
  * bound_boxes_backward: the hand-written adjoint of bound_boxes_alpha.  Given seeds

@@ -6,7 +6,8 @@ The engine is the C-ABI library ``libslrcount.so`` (hand-written HIP for gfx950,
 """
 from .slrcount import (EXPORTS, SAFE, SLR_BUDGET, SLR_OK, UNDECIDED, UNSAFE, Net, Property,  # noqa: F401
                        Batch, SlrError, alpha_kernel_variant, alpha_optimize, alpha_size, alpha_state_variant, alpha_tape_size, alpha_workspace_size,
-                       bound_boxes, bound_boxes_alpha, bound_boxes_backward, bound_kernel_variant, bound_tile_shape,
+                       bound_boxes, bound_boxes_alpha, bound_boxes_backward, bound_boxes_relax, bound_kernel_variant,
+                       bound_tape_size, bound_tile_shape,
                        count_approx, count_exact, count_exact_batch, count_exact_noalloc,
                        count_exact_noalloc_max_bytes, count_exact_stack, stack_workspace_size, last_error, lib, load_net, load_property,
                        sample_violations, workspace_size)

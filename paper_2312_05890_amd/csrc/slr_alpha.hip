@@ -257,13 +257,15 @@ __device__ __forceinline__ void contract_unit(const float* __restrict__ frag, in
 
 struct EpiK {
     float kconc, krelu, lamfac;
+    int two;   // forward passes: one ratio per equation instead of Eq. 1's shared one
 };
 
-__device__ __forceinline__ EpiK epi_k(const NetDev& net, int raw) {
+__device__ __forceinline__ EpiK epi_k(const NetDev& net, int raw, int two = 0) {
     EpiK k;
     k.kconc = raw ? 0.f : net.kconc;
     k.krelu = raw ? 0.f : net.krelu;
     k.lamfac = raw ? 1.f : 1.f + 0x1p-20f;   // keeps hi * rcp(hi - lo) >= the chord slope
+    k.two = two;
     return k;
 }
 
@@ -284,8 +286,8 @@ __device__ __forceinline__ Phase phase_of(float lo, float hi, bool valid, float 
 }
 
 // Forward epilogue of one hidden tile (4 neurons per lane): widen the radius constant by the
-// affine rounding margin eps, concretize, apply the alpha relaxation and write the
-// post-activation state.  get(c) yields pre-activation column c (from the tape slot, or from the
+// affine rounding margin eps, concretize, apply the alpha relaxation (or, with k.two, the
+// relaxation with one ratio per equation) and write the post-activation state.  get(c) yields pre-activation column c (from the tape slot, or from the
 // contraction's registers); the tape receives the widened radius constant and l, u (and, with
 // cols, every pre-activation column).  Returns a bound on sum_c |C_c| + |R_c| over the lane's
 // neurons (for the next layer's rounding margin).
@@ -324,7 +326,7 @@ __device__ __forceinline__ float fwd_relu_core(Get get, PT tape, bool cols, PS p
         }
     }
     f32x4 LO, HI;
-    float al[4], au[4];
+    float al[4], au[4], sh[4];
     bool act[4], cross[4];
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
@@ -335,6 +337,7 @@ __device__ __forceinline__ float fwd_relu_core(Get get, PT tape, bool cols, PS p
         act[v] = p.act;
         cross[v] = p.cross;
         au[v] = p.lam;
+        sh[v] = p.cross ? LO[v] : 0.f;
         const int nrn = rowmap[16 * mt + 4 * g + v];
         float a = p.lam;
         if (arow && nrn >= 0) {
@@ -344,6 +347,17 @@ __device__ __forceinline__ float fwd_relu_core(Get get, PT tape, bool cols, PS p
                 a = fminf(fmaxf(arow[nrn], 0.f), 1.f);
         }
         al[v] = p.cross ? a : p.lam;
+        if (k.two && p.cross) {
+            // upper: chord of ReLU over U's own range [lu, u] (U itself once lu >= 0); lower:
+            // slope uL / (uL - l) from L's range [l, uL] (0 once uL <= 0); any lower slope in
+            // [0, 1] is sound, the upper one is rounded up
+            const float lu = ((C0[v] + R0[v]) - SU[v]) - delta;
+            const float ul = ((C0[v] - R0[v]) + SL[v]) + delta;
+            const bool chord = lu < 0.f;
+            au[v] = chord ? fminf(1.f, HI[v] * __builtin_amdgcn_rcpf(HI[v] - lu) * k.lamfac) : 1.f;
+            sh[v] = chord ? lu : 0.f;
+            al[v] = ul > 0.f ? fminf(1.f, fmaxf(0.f, ul * __builtin_amdgcn_rcpf(ul - LO[v]))) : 0.f;
+        }
     }
     if (tape) {
         tape[at(2 * NC)] = LO;
@@ -371,7 +385,7 @@ __device__ __forceinline__ float fwd_relu_core(Get get, PT tape, bool cols, PS p
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
         const float Lp = al[v] * (C0[v] - R0[v]);
-        const float Up = au[v] * ((C0[v] + R0[v]) - (cross[v] ? LO[v] : 0.f));
+        const float Up = au[v] * ((C0[v] + R0[v]) - sh[v]);
         const float er = cross[v] ? k.krelu * (E[v] + fabsf(Lp) + fabsf(Up)) : 0.f;
         Cn[v] = act[v] ? C0[v] : 0.5f * (Lp + Up);
         Rn[v] = act[v] ? R0[v] : 0.5f * (Up - Lp) + er;
@@ -531,7 +545,9 @@ __device__ __forceinline__ int hidden_rem(const NetDev& net, int h) {
 // RP: every layer's columns fit one contraction unit and its tiles one unit per wavefront, so
 // contraction results stay in registers across the barrier and the epilogue reads no tape.
 // The forward pass of 16-box tile `tile` (one workgroup of kNW wavefronts).
-template <int NC, bool GS, bool RP>
+// TWO: honour A.two_ratio (the standalone forward kernel; the fused optimizer's forward passes
+// always take alpha slopes)
+template <int NC, bool GS, bool RP, bool TWO = false>
 __device__ __forceinline__ void alpha_fwd_tile(const NetDev& net, const PropDev& prop,
                                                const AlphaArgs& A, int slots, int64_t tile,
                                                int init) {
@@ -547,7 +563,7 @@ __device__ __forceinline__ void alpha_fwd_tile(const NetDev& net, const PropDev&
     const int H = net.n_affine - 1;
     const int d = net.d;
     f32x4* tape = reinterpret_cast<f32x4*>(A.tape) + (size_t)tile * slots * slot;
-    const EpiK k = epi_k(net, A.raw);
+    const EpiK k = epi_k(net, A.raw, TWO ? A.two_ratio : 0);
     float* part;
     f32x4* S;
     if constexpr (GS) {
@@ -880,7 +896,7 @@ __device__ __forceinline__ void alpha_bwd_tile(const NetDev& net, const PropDev&
 template <int NC, bool GS, bool RP>
 __global__ __launch_bounds__(kNW * 64, 2) void alpha_fwd_kernel(NetDev net, PropDev prop,
                                                              AlphaArgs A, int slots) {
-    alpha_fwd_tile<NC, GS, RP>(net, prop, A, slots, blockIdx.x, A.init);
+    alpha_fwd_tile<NC, GS, RP, true>(net, prop, A, slots, blockIdx.x, A.init);
 }
 
 template <int NC, bool GS, bool RP>

@@ -582,8 +582,10 @@ AlphaWs layout_alpha(char* base, const NetDev& nd, const PropDev& pd, int64_t n)
     return w;
 }
 
+// tape_state: plain bounds from the tape-state kernel whatever the shape (the relaxation with one
+// ratio per equation needs its full per-neuron equations)
 Workspace layout_ws(char* base, const NetDev& nd, const PropDev& pd, int64_t cap, int samples,
-                    int64_t achunk) {
+                    int64_t achunk, bool tape_state = false) {
     const int d = nd.d;
     Workspace w{};
     size_t o = 0;
@@ -610,7 +612,7 @@ Workspace layout_ws(char* base, const NetDev& nd, const PropDev& pd, int64_t cap
     w.samples = (float*)take(sizeof(float) * (size_t)d * std::max(samples, 0));
     w.viol = (int8_t*)take(std::max(samples, 0));
     w.wchunk = 0;
-    if (!bound_f32_supported(nd, pd) && pd.rows > 0) {
+    if ((tape_state || !bound_f32_supported(nd, pd)) && pd.rows > 0) {
         w.wchunk = std::min<int64_t>(cap, 4096);
         w.wtape = (float*)take(alpha_tape_bytes(nd, pd, w.wchunk, 1));
         w.wlo = (float*)take(sizeof(float) * pd.rows * w.wchunk);
@@ -672,6 +674,21 @@ extern "C" int workspace_size(const slr_net* net, const slr_property* prop, int6
     PropDev pd{};
     if (prop) pd = prop->dev;
     *bytes = layout_ws(nullptr, net->dev, pd, max_leaves, samples, alpha_chunk).bytes;
+    return SLR_OK;
+}
+
+extern "C" int workspace_size_exact(const slr_net* net, const slr_property* prop,
+                                    const slr_exact_opts* opts, size_t* bytes) {
+    g_err.clear();
+    if (!bytes || !opts) return fail(SLR_EINVAL, "workspace_size_exact: NULL argument");
+    int rc = check_pair(net, prop, "workspace_size_exact");
+    if (rc) return rc;
+    if (opts->max_leaves < 1) return fail(SLR_EINVAL, "workspace_size_exact: max_leaves must be >= 1");
+    if (opts->alpha_steps > 0 && opts->alpha_chunk < 1)
+        return fail(SLR_EINVAL, "workspace_size_exact: alpha mode needs alpha_chunk >= 1");
+    const int64_t achunk = opts->alpha_steps > 0 ? opts->alpha_chunk : 0;
+    *bytes = layout_ws(nullptr, net->dev, prop->dev, opts->max_leaves, 0, achunk,
+                       opts->relax == SLR_RELAX_TWO).bytes;
     return SLR_OK;
 }
 
@@ -872,6 +889,49 @@ extern "C" int bound_boxes_alpha(const slr_net* net, const slr_property* prop, i
     return SLR_OK;
 }
 
+extern "C" int bound_boxes_relax(const slr_net* net, const slr_property* prop, int64_t n,
+                                 const float* lo, const float* hi, int32_t relax, float* g_lo,
+                                 float* g_hi, int8_t* cls, int32_t raw, void* tape,
+                                 size_t tape_bytes, void* stream) {
+    g_err.clear();
+    int rc = check_alpha_pair(net, prop, "bound_boxes_relax");
+    if (rc) return rc;
+    if (n < 0) return fail(SLR_EINVAL, "bound_boxes_relax: n < 0");
+    if (raw != 0 && raw != 1) return fail(SLR_EINVAL, "bound_boxes_relax: raw must be 0 or 1");
+    if (relax != SLR_RELAX_ONE && relax != SLR_RELAX_TWO)
+        return fail(SLR_EINVAL, "bound_boxes_relax: relax must be SLR_RELAX_ONE or SLR_RELAX_TWO");
+    if (n == 0) return SLR_OK;
+    if (!is_device_ptr(lo) || !is_device_ptr(hi) || !is_device_ptr(g_lo) || !is_device_ptr(g_hi))
+        return fail(SLR_EINVAL, "bound_boxes_relax: lo, hi, g_lo and g_hi must be device memory");
+    if (cls && !is_device_ptr(cls)) return fail(SLR_EINVAL, "bound_boxes_relax: cls must be device memory");
+    const size_t need = alpha_tape_bytes(net->dev, prop->dev, n, 1);
+    if (!tape || tape_bytes < need)
+        return fail(SLR_ENOMEM, "bound_boxes_relax: tape of %zu bytes is smaller than the %zu required", tape_bytes, need);
+    if (!is_device_ptr(tape)) return fail(SLR_EINVAL, "bound_boxes_relax: tape must be device memory");
+    AlphaArgs a{};
+    a.n = n;
+    a.lo = lo;
+    a.hi = hi;
+    a.g_lo = g_lo;
+    a.g_hi = g_hi;
+    a.cls = cls;
+    a.raw = raw;
+    a.tape = (float*)tape;
+    a.fwd_only = 1;
+    a.two_ratio = relax == SLR_RELAX_TWO;
+    HIP_TRY(launch_alpha_forward(net->dev, prop->dev, a, (hipStream_t)stream), "bound_boxes_relax: kernel");
+    return SLR_OK;
+}
+
+extern "C" int bound_tape_size(const slr_net* net, const slr_property* prop, int64_t n, size_t* bytes) {
+    g_err.clear();
+    int rc = check_alpha_pair(net, prop, "bound_tape_size");
+    if (rc) return rc;
+    if (!bytes || n < 0) return fail(SLR_EINVAL, "bound_tape_size: bytes is NULL or n < 0");
+    *bytes = alpha_tape_bytes(net->dev, prop->dev, n, 1);
+    return SLR_OK;
+}
+
 extern "C" int bound_boxes_backward(const slr_net* net, const slr_property* prop, int64_t n,
                                     const float* alpha, const void* tape, size_t tape_bytes,
                                     const float* dg_lo, const float* dg_hi, float* dalpha,
@@ -1056,10 +1116,14 @@ int count_exact_impl(const slr_net* net, const slr_property* prop, const double*
                 a.hi = w.hi[cur] + off * d;
                 a.tape = w.wtape;
                 a.fwd_only = 1;
+                a.two_ratio = o->relax == SLR_RELAX_TWO;
                 a.g_lo = w.wlo;
                 a.g_hi = w.whi;
                 a.cls = w.cls + off;
                 HIP_TRY(launch_alpha_forward(net->dev, prop->dev, a, s), "count_exact: bound kernel");
+                ++launches;
+                // two ratios: the widened float32 classes stand (no FP64 re-decision)
+                if (a.two_ratio) continue;
                 if (o->alpha_steps > 0 && t >= o->alpha_min_depth && o->alpha_select > 0.f) {
                     // an alpha level that selects its candidates keeps the plain bounds
                     const size_t gb = sizeof(float) * prop->dev.rows * m;
@@ -1076,7 +1140,7 @@ int count_exact_impl(const slr_net* net, const slr_property* prop, const double*
                 HIP_TRY(launch_ambiguity(m, prop->dev.rows, w.wlo, w.whi, w.rlo, w.rhi, w.cls + off,
                                          w.amb_list, w.amb_count, (unsigned)off, s),
                         "count_exact: ambiguity kernel");
-                launches += 2;
+                ++launches;
             }
         } else {
             // an alpha level that selects its candidates keeps the plain bounds
@@ -1103,9 +1167,10 @@ int count_exact_impl(const slr_net* net, const slr_property* prop, const double*
                 bound_ms += ms;
             }
         }
-        HIP_TRY(launch_recheck64(net->dev, prop->dev, n, w.lo[cur], w.hi[cur], nullptr, nullptr,
-                                 w.cls, w.rechecks, w.amb_list, w.amb_count, s),
-                "count_exact: recheck kernel");
+        if (o->relax != SLR_RELAX_TWO)
+            HIP_TRY(launch_recheck64(net->dev, prop->dev, n, w.lo[cur], w.hi[cur], nullptr, nullptr,
+                                     w.cls, w.rechecks, w.amb_list, w.amb_count, s),
+                    "count_exact: recheck kernel");
         if (o->alpha_steps > 0 && t >= o->alpha_min_depth) {
             if (ev0) HIP_TRY(hipEventRecord(ev0, s), "count_exact: event");
             HIP_TRY(hipMemsetAsync(w.amb_count, 0, 2 * sizeof(unsigned), s), "count_exact: clear");
@@ -1298,6 +1363,17 @@ int check_exact_opts(const slr_net* net, const slr_property* prop, const slr_exa
                                 bound_variant_for(net->dev, prop->dev) < 0 || net->dev.d + 3 > 14))
         return fail(SLR_EUNSUPPORTED, "%s: the crossing-score split needs a ReLU network on the LDS bound "
                     "kernel with at most 11 inputs", who);
+    if (o->relax != SLR_RELAX_ONE && o->relax != SLR_RELAX_TWO)
+        return fail(SLR_EINVAL, "%s: relax must be SLR_RELAX_ONE or SLR_RELAX_TWO", who);
+    if (o->relax == SLR_RELAX_TWO) {
+        if (net->dev.act != SLR_ACT_RELU)
+            return fail(SLR_EUNSUPPORTED, "%s: the two-ratio relaxation is defined for ReLU networks only", who);
+        if (o->alpha_steps > 0 || o->split_layers > 0)
+            return fail(SLR_EUNSUPPORTED, "%s: the two-ratio relaxation takes neither alpha slopes nor the "
+                        "crossing-score split", who);
+        if (alpha_shape(net->dev, prop->dev).nc < 0)
+            return fail(SLR_EUNSUPPORTED, "%s: input dimension too large for the tape-state kernel", who);
+    }
     if (net->dev.act != SLR_ACT_RELU) {
         if (o->alpha_steps > 0)
             return fail(SLR_EUNSUPPORTED, "%s: alpha slopes are defined for ReLU networks only", who);
@@ -1305,12 +1381,13 @@ int check_exact_opts(const slr_net* net, const slr_property* prop, const slr_exa
             return fail(SLR_EUNSUPPORTED, "%s: tanh and sigmoid networks need the LDS or register bound kernel", who);
     }
     const int64_t achunk = o->alpha_steps > 0 ? o->alpha_chunk : 0;
-    const size_t need = layout_ws(nullptr, net->dev, prop->dev, o->max_leaves, samples, achunk).bytes;
+    const bool two = o->relax == SLR_RELAX_TWO;
+    const size_t need = layout_ws(nullptr, net->dev, prop->dev, o->max_leaves, samples, achunk, two).bytes;
     if (!o->workspace || o->workspace_bytes < need)
         return fail(SLR_ENOMEM, "%s: workspace of %zu bytes is smaller than the %zu required", who,
                     o->workspace_bytes, need);
     if (check_device && !is_device_ptr(o->workspace)) return fail(SLR_EINVAL, "%s: workspace must be device memory", who);
-    *w = layout_ws((char*)o->workspace, net->dev, prop->dev, o->max_leaves, samples, achunk);
+    *w = layout_ws((char*)o->workspace, net->dev, prop->dev, o->max_leaves, samples, achunk, two);
     return SLR_OK;
 }
 
@@ -1382,7 +1459,8 @@ extern "C" int count_exact_noalloc(const slr_net* net, const slr_property* prop,
         return fail(SLR_EINVAL, "count_exact_noalloc: traces and timing are not available (they need host buffers and events)");
     const int64_t achunk = opts->alpha_steps > 0 ? opts->alpha_chunk : 0;
     if (opts->max_leaves >= 1 && achunk >= 0) {
-        const size_t need = layout_ws(nullptr, net->dev, prop->dev, opts->max_leaves, 0, achunk).bytes;
+        const size_t need = layout_ws(nullptr, net->dev, prop->dev, opts->max_leaves, 0, achunk,
+                                      opts->relax == SLR_RELAX_TWO).bytes;
         if (need > kScratchBytes)
             return fail(SLR_ENOMEM, "count_exact_noalloc: this count needs %zu bytes of workspace, more than the "
                         "%zu-byte static scratch (lower max_leaves or alpha_chunk, or use count_exact)", need, kScratchBytes);

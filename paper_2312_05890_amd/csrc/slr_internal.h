@@ -184,6 +184,7 @@ struct AlphaArgs {
     float* adam_m;         // optional fused projected Adam state [n][nh]
     float* adam_v;
     float lr, beta1, beta2, eps, c1, c2;
+    int two_ratio;         // forward passes: one ratio per equation (plain slopes, no alpha)
 };
 
 struct AlphaShape {

@@ -26,7 +26,8 @@ EXPORTS = ("load_net", "free_net", "load_property", "free_property", "bound_boxe
            "batch_run", "batch_free", "count_exact_batch", "bound_tile_shape",
            "alpha_state_variant", "count_exact_noalloc", "count_exact_noalloc_max_bytes",
            "stack_workspace_size", "count_exact_stack", "alpha_kernel_variant",
-           "batch_create_opts", "load_net_act")
+           "batch_create_opts", "load_net_act", "workspace_size_exact", "bound_boxes_relax",
+           "bound_tape_size")
 
 
 class SlrError(RuntimeError):
@@ -44,7 +45,16 @@ class ExactOpts(C.Structure):
                 ("alpha_steps", C.c_int32), ("alpha_lr", C.c_float),
                 ("alpha_min_depth", C.c_int32), ("alpha_chunk", C.c_int32),
                 ("alpha_select", C.c_float), ("split_layers", C.c_int32),
-                ("trace_dim", C.POINTER(C.c_int8))]
+                ("trace_dim", C.POINTER(C.c_int8)), ("relax", C.c_int32)]
+
+
+RELAX = {"one": 0, "two": 1}
+
+
+def _relax(relax) -> int:
+    if relax not in RELAX:
+        raise ValueError(f"relax must be one of {sorted(RELAX)}, not {relax!r}")
+    return RELAX[relax]
 
 
 class CountResult(C.Structure):
@@ -122,6 +132,8 @@ def lib() -> C.CDLL:
         L.bound_boxes.restype = C.c_int
         L.workspace_size.argtypes = [vp, vp, i64, i32, i32, C.POINTER(C.c_size_t)]
         L.workspace_size.restype = C.c_int
+        L.workspace_size_exact.argtypes = [vp, vp, C.POINTER(ExactOpts), C.POINTER(C.c_size_t)]
+        L.workspace_size_exact.restype = C.c_int
         L.count_exact.argtypes = [vp, vp, C.POINTER(C.c_double), C.POINTER(C.c_double),
                                   C.POINTER(ExactOpts), C.POINTER(CountResult)]
         L.count_exact.restype = C.c_int
@@ -152,6 +164,11 @@ def lib() -> C.CDLL:
         L.bound_boxes_alpha.argtypes = [vp, vp, i64, vp, vp, vp, i32, vp, vp, vp, i32, vp,
                                         C.c_size_t, vp]
         L.bound_boxes_alpha.restype = C.c_int
+        L.bound_boxes_relax.argtypes = [vp, vp, i64, vp, vp, i32, vp, vp, vp, i32, vp,
+                                        C.c_size_t, vp]
+        L.bound_boxes_relax.restype = C.c_int
+        L.bound_tape_size.argtypes = [vp, vp, i64, sz]
+        L.bound_tape_size.restype = C.c_int
         L.bound_boxes_backward.argtypes = [vp, vp, i64, vp, vp, C.c_size_t, vp, vp, vp, i32, vp]
         L.bound_boxes_backward.restype = C.c_int
         L.alpha_optimize.argtypes = [vp, vp, i64, vp, vp, C.POINTER(AlphaOpts), vp, vp, vp, vp,
@@ -326,18 +343,25 @@ def workspace_size(net: Net, prop: Property, max_leaves: int, samples: int = 0,
 
 def _exact_opts(net, prop, max_depth, max_leaves, chunk, workspace, stream, samples,
                 trace_capacity=0, timing=False, alpha_steps=0, alpha_lr=0.0, alpha_min_depth=0,
-                alpha_chunk=0, alpha_select=0.0, split_layers=0):
+                alpha_chunk=0, alpha_select=0.0, split_layers=0, relax="one"):
     import torch
     if alpha_steps > 0 and alpha_chunk <= 0:
         alpha_chunk = 16384
-    need = workspace_size(net, prop, max_leaves, samples, alpha_chunk if alpha_steps > 0 else 0)
-    if workspace is None:
-        workspace = torch.empty(need, dtype=torch.uint8, device="cuda")
-    assert workspace.is_cuda
     o = ExactOpts()
     o.max_depth = int(max_depth)
     o.max_leaves = int(max_leaves)
     o.chunk = int(chunk)
+    o.alpha_steps = int(alpha_steps)
+    o.alpha_chunk = int(alpha_chunk)
+    o.relax = _relax(relax)
+    need = workspace_size(net, prop, max_leaves, samples, alpha_chunk if alpha_steps > 0 else 0)
+    if o.relax:
+        out = C.c_size_t()
+        _check(lib().workspace_size_exact(net.handle, prop.handle, C.byref(o), C.byref(out)))
+        need = max(need, out.value)
+    if workspace is None:
+        workspace = torch.empty(need, dtype=torch.uint8, device="cuda")
+    assert workspace.is_cuda
     o.workspace = workspace.data_ptr()
     o.workspace_bytes = workspace.numel() * workspace.element_size()
     o.stream = _stream(stream)
@@ -356,9 +380,11 @@ def count_exact(net: Net, prop: Property, lo, hi, max_depth: int, max_leaves: in
                 chunk: int = 0, workspace=None, stream=None, trace: bool = False,
                 trace_capacity: Optional[int] = None, timing: int = 0,
                 alpha_steps: int = 0, alpha_lr: float = 0.1, alpha_min_depth: int = 0,
-                alpha_chunk: int = 0, alpha_select: float = 0.0, split_layers: int = 0) -> dict:
+                alpha_chunk: int = 0, alpha_select: float = 0.0, split_layers: int = 0,
+                relax: str = "one") -> dict:
     """Alg. 1 on the device; returns the bracket, counts and (optionally) a per-box trace
-    (with the side bisected per box in ``trace_dim``).
+    (with the side bisected per box in ``trace_dim``).  ``relax``: "one" (Eq. 1) or "two" (one
+    ratio per equation, ``slr_exact_opts.relax``).
 
     ``timing``: bit 0 times the bound-kernel launches (``bound_ms``), bit 1 the split launches
     (``split_ms``, with their algorithmic ``split_bytes``); True means 1.
@@ -373,7 +399,7 @@ def count_exact(net: Net, prop: Property, lo, hi, max_depth: int, max_leaves: in
         cap = int(trace_capacity if trace_capacity is not None else 4 * max_leaves + 64)
     o, ws = _exact_opts(net, prop, max_depth, max_leaves, chunk, workspace, stream, 0, cap, timing,
                         alpha_steps, alpha_lr, alpha_min_depth, alpha_chunk, alpha_select,
-                        split_layers)
+                        split_layers, relax)
     if trace:
         t_depth = np.zeros(cap, np.int32)
         t_path = np.zeros(cap, np.uint64)
@@ -402,7 +428,7 @@ def count_exact(net: Net, prop: Property, lo, hi, max_depth: int, max_leaves: in
 def count_exact_noalloc(net: Net, prop: Property, lo, hi, max_depth: int, max_leaves: int,
                         chunk: int = 0, stream=None, alpha_steps: int = 0, alpha_lr: float = 0.1,
                         alpha_min_depth: int = 0, alpha_chunk: int = 0,
-                        alpha_select: float = 0.0) -> dict:
+                        alpha_select: float = 0.0, relax: str = "one") -> dict:
     """``count_exact`` on the library's static workspace (no allocation by the library or here:
     only the host option and result structs)."""
     lo = np.ascontiguousarray(lo, np.float64)
@@ -419,6 +445,7 @@ def count_exact_noalloc(net: Net, prop: Property, lo, hi, max_depth: int, max_le
     o.alpha_min_depth = int(alpha_min_depth)
     o.alpha_chunk = int(alpha_chunk)
     o.alpha_select = float(alpha_select)
+    o.relax = _relax(relax)
     r = CountResult()
     rc = _check(lib().count_exact_noalloc(net.handle, prop.handle,
                                           lo.ctypes.data_as(C.POINTER(C.c_double)),
@@ -596,6 +623,31 @@ def bound_boxes_alpha(net: Net, prop: Property, lo, hi, alpha=None, init: bool =
                                    _ptr(cls), int(bool(raw)), tape.data_ptr(),
                                    tape.numel() * tape.element_size(), _stream(stream)))
     return g_lo, g_hi, cls, tape
+
+
+def bound_tape_size(net: Net, prop: Property, n: int) -> int:
+    out = C.c_size_t()
+    _check(lib().bound_tape_size(net.handle, prop.handle, int(n), C.byref(out)))
+    return out.value
+
+
+def bound_boxes_relax(net: Net, prop: Property, lo, hi, relax: str = "two", raw: bool = False,
+                      tape=None, want_cls: bool = False, stream=None):
+    """Bounds from the tape-state kernel with the plain slopes of ``relax`` ("one": Eq. 1,
+    "two": one ratio per equation); returns (g_lo, g_hi, cls)."""
+    import torch
+    n = _check_boxes(net, lo, hi)
+    need = bound_tape_size(net, prop, n)
+    if tape is None:
+        tape = torch.empty(max(need, 1), dtype=torch.uint8, device=lo.device)
+    g_lo = torch.empty((n, prop.rows), dtype=torch.float32, device=lo.device)
+    g_hi = torch.empty((n, prop.rows), dtype=torch.float32, device=lo.device)
+    cls = torch.empty((n,), dtype=torch.int8, device=lo.device) if want_cls else None
+    _check(lib().bound_boxes_relax(net.handle, prop.handle, n, lo.data_ptr(), hi.data_ptr(),
+                                   _relax(relax), g_lo.data_ptr(), g_hi.data_ptr(), _ptr(cls),
+                                   int(bool(raw)), tape.data_ptr(),
+                                   tape.numel() * tape.element_size(), _stream(stream)))
+    return g_lo, g_hi, cls
 
 
 def bound_boxes_backward(net: Net, prop: Property, tape, alpha, dg_lo=None, dg_hi=None,

@@ -1,7 +1,9 @@
 """Write the oracle's full-size exact count of the 5-input 6x50 network (seed 0) as a fixture.
 
 Workload: He-normal 5-50x6-5 ReLU network from seed 0, domain [0, 1]^5, unsafe iff
-y0 - y1 > 0, maximum depth 40, leaf budget 2^20 (Alg. 1 with the level-boundary budget rule).
+y0 - y1 > 0, maximum depth 40, leaf budget 2^20 (Alg. 1 with the level-boundary budget rule),
+with the relaxation of Eq. 1 (one ratio, the default) or with one ratio per equation
+(argument ``two``).
 Calls only ``oracle/`` and the seeded input generator; nothing here comes from the HIP path.
 
 Per level the fixture keeps the number of boxes, the class histogram, a SHA-256 digest of
@@ -9,7 +11,7 @@ the boxes' path ids and of their classes in canonical (path) order, and every bo
 decision margin is at most 1e-5 (depth, path, class, margin): a GPU count that differs from
 the oracle anywhere can then be checked box by box against that list.
 
-Usage: python tests/golden/make_acas_full.py   (about 5 minutes on 8 cores)
+Usage: python tests/golden/make_acas_full.py [two]   (about 5 minutes on 8 cores)
 """
 from __future__ import annotations
 
@@ -27,7 +29,7 @@ sys.path.insert(0, ROOT)
 import synth                                    # noqa: E402
 from oracle import count, slr                   # noqa: E402
 
-OUT = os.path.join(os.path.dirname(os.path.abspath(__file__)), "acas0_d40_leaves2p20.json")
+HERE = os.path.dirname(os.path.abspath(__file__))
 SMALL = 1e-5
 
 
@@ -45,14 +47,17 @@ def level_record(lev):
                 small_margin=[[int(path[i]), int(cls[i]), float(mg[i])] for i in small])
 
 
-def main():
+def main(relax="one"):
+    out_path = os.path.join(HERE, "acas0_d40_leaves2p20%s.json" % ("" if relax == "one" else "_two"))
     inst = synth.acas(0)
     t0 = time.time()
     r = count.count_exact(inst.net, inst.C, inst.dvec, inst.lo, inst.hi, 40, 1 << 20,
-                          trace=True, chunk=16384)
+                          trace=True, chunk=16384, relax=relax)
     secs = time.time() - t0
     out = dict(
-        workload="acas seed 0: 5-50x6-5 ReLU (He-normal), [0,1]^5, y0 - y1 > 0, D 40, 2^20 leaves",
+        workload="acas seed 0: 5-50x6-5 ReLU (He-normal), [0,1]^5, y0 - y1 > 0, D 40, 2^20 leaves"
+                 + ("" if relax == "one" else ", two-ratio relaxation"),
+        relax=relax,
         status=int(r["status"]), depth_reached=int(r["depth_reached"]),
         n_boxes_bounded=int(r["n_boxes_bounded"]), n_unsafe=int(r["n_unsafe"]),
         n_safe=int(r["n_safe"]), n_undecided=int(r["n_undecided"]),
@@ -64,11 +69,11 @@ def main():
         small_margin_threshold=SMALL,
         levels=[level_record(lev) for lev in r["levels"]],
         oracle_seconds=round(secs, 1))
-    with open(OUT, "w") as f:
+    with open(out_path, "w") as f:
         json.dump(out, f, indent=1)
-    print(f"wrote {OUT}: {out['n_boxes_bounded']} boxes, depth {out['depth_reached']}, "
+    print(f"wrote {out_path}: {out['n_boxes_bounded']} boxes, depth {out['depth_reached']}, "
           f"{sum(len(l['small_margin']) for l in out['levels'])} small-margin boxes, {secs:.0f} s")
 
 
 if __name__ == "__main__":
-    main()
+    main(*sys.argv[1:2])
