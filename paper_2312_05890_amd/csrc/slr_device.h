@@ -222,15 +222,26 @@ __device__ __forceinline__ float relu_epilogue(float (&a)[NCOL][4], const float 
     return emax;
 }
 
+// XOR swizzle of a lane's 16-byte state slots (quads of K-steps) in the LDS state buffer.  A
+// lane's slots are a row of SP = 4 mq floats; without the swizzle the b128 reads of the 16
+// lanes j of one group land on gcd(mq, 16)-way shared bank groups (for mq = 4, lanes j, j + 4,
+// j + 8, j + 12); XOR-ing the slot index with (j / (16 / m)) mod m, m = gcd(mq, 16), spreads
+// them over distinct groups, and keeps every slot index below mq (m divides mq).
+__device__ __forceinline__ int quad_swizzle(int mq, int j) {
+    const int low = mq & -mq;
+    const int m = low < 16 ? low : 16;
+    return (j / (16 / m)) & (m - 1);
+}
+
 // The full K-quads of one unit (weights fragments wf/qf from global memory, the layer input's
-// state sb from LDS), software-pipelined one quad ahead.  NQ > 0: exactly NQ quads as
+// state sb from LDS, slot swizzle xs), software-pipelined one quad ahead.  NQ > 0: exactly NQ quads as
 // straight-line code (a loop carries the accumulators and the prefetched operands across its back
 // edge, where the compiler shuffles accumulator registers and folds the prefetch back into the
 // iteration); NQ == 0: a loop over nq quads.
 template <int NCOL, int NQ>
 __device__ __forceinline__ void k_quads(f32x4 (&acc)[NCOL], const float* __restrict__ wf,
                                         const uint64_t* __restrict__ qf, const float* sb,
-                                        int colstride, int nq, int nqa) {
+                                        int colstride, int nq, int nqa, int xs) {
     float af[4];
     uint64_t aq = qf[0];
     f32x4 bq[NCOL];
@@ -238,9 +249,11 @@ __device__ __forceinline__ void k_quads(f32x4 (&acc)[NCOL], const float* __restr
     for (int ss = 0; ss < 4; ++ss) af[ss] = wf[ss * 64];
 #pragma unroll
     for (int c = 0; c < NCOL; ++c)
-        bq[c] = *reinterpret_cast<const f32x4*>(sb + c * colstride);
+        bq[c] = *reinterpret_cast<const f32x4*>(sb + c * colstride + 4 * xs);
     auto quad = [&](int qi) {
-        const int nx = min(qi + 1, nqa - 1) * 4;
+        const int qn = min(qi + 1, nqa - 1);
+        const int nx = qn * 4;
+        const float* sn = sb + 4 * (qn ^ xs);
         float an[4];
         const uint64_t aqn = qf[nx * 16];
         f32x4 bn[NCOL];
@@ -248,7 +261,7 @@ __device__ __forceinline__ void k_quads(f32x4 (&acc)[NCOL], const float* __restr
         for (int ss = 0; ss < 4; ++ss) an[ss] = wf[(nx + ss) * 64];
 #pragma unroll
         for (int c = 0; c < NCOL; ++c)
-            bn[c] = *reinterpret_cast<const f32x4*>(sb + c * colstride + nx);
+            bn[c] = *reinterpret_cast<const f32x4*>(sn + c * colstride);
 #pragma unroll
         for (int ss = 0; ss < 4; ++ss) {
             const float aw = af[ss];
@@ -277,39 +290,39 @@ __device__ __forceinline__ void k_quads(f32x4 (&acc)[NCOL], const float* __restr
 template <int NCOL, int MAXQ>
 __device__ __forceinline__ void k_quads_any(f32x4 (&acc)[NCOL], const float* __restrict__ wf,
                                             const uint64_t* __restrict__ qf, const float* sb,
-                                            int colstride, int nq, int nqa) {
+                                            int colstride, int nq, int nqa, int xs) {
     switch (nq) {
-        case 1: k_quads<NCOL, 1>(acc, wf, qf, sb, colstride, nq, nqa); return;
-        case 2: k_quads<NCOL, 2>(acc, wf, qf, sb, colstride, nq, nqa); return;
-        case 3: k_quads<NCOL, 3>(acc, wf, qf, sb, colstride, nq, nqa); return;
-        case 4: k_quads<NCOL, 4>(acc, wf, qf, sb, colstride, nq, nqa); return;
+        case 1: k_quads<NCOL, 1>(acc, wf, qf, sb, colstride, nq, nqa, xs); return;
+        case 2: k_quads<NCOL, 2>(acc, wf, qf, sb, colstride, nq, nqa, xs); return;
+        case 3: k_quads<NCOL, 3>(acc, wf, qf, sb, colstride, nq, nqa, xs); return;
+        case 4: k_quads<NCOL, 4>(acc, wf, qf, sb, colstride, nq, nqa, xs); return;
         case 5:
             if constexpr (MAXQ >= 5) {
-                k_quads<NCOL, 5>(acc, wf, qf, sb, colstride, nq, nqa);
+                k_quads<NCOL, 5>(acc, wf, qf, sb, colstride, nq, nqa, xs);
                 return;
             }
             break;
         case 6:
             if constexpr (MAXQ >= 6) {
-                k_quads<NCOL, 6>(acc, wf, qf, sb, colstride, nq, nqa);
+                k_quads<NCOL, 6>(acc, wf, qf, sb, colstride, nq, nqa, xs);
                 return;
             }
             break;
         case 7:
             if constexpr (MAXQ >= 7) {
-                k_quads<NCOL, 7>(acc, wf, qf, sb, colstride, nq, nqa);
+                k_quads<NCOL, 7>(acc, wf, qf, sb, colstride, nq, nqa, xs);
                 return;
             }
             break;
         case 8:
             if constexpr (MAXQ >= 8) {
-                k_quads<NCOL, 8>(acc, wf, qf, sb, colstride, nq, nqa);
+                k_quads<NCOL, 8>(acc, wf, qf, sb, colstride, nq, nqa, xs);
                 return;
             }
             break;
         default: break;
     }
-    k_quads<NCOL, 0>(acc, wf, qf, sb, colstride, nq, nqa);
+    k_quads<NCOL, 0>(acc, wf, qf, sb, colstride, nq, nqa, xs);
 }
 
 template <int NCOL, int NT, int UW, int NW, bool SMOOTH = false, bool SCORE = false>
@@ -333,9 +346,10 @@ __device__ __forceinline__ void bound_tile(
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6, g = lane >> 4, j = lane & 15;
     const int d = net.d;
+    const int xs = quad_swizzle(SP >> 2, j);          // this lane's slot swizzle
 
     const EpiConst ek = epi_const(net, raw);
-    float* S = lds;                                   // [NT][NCOL][4][16][SP]
+    float* S = lds;                                   // [NT][NCOL][4][16][SP], slots swizzled
     float* part = S + NT * NCOL * 64 * SP;            // [2 parity][mt_max][T] bound on |value|
     float* OUT = part + 2 * net.mt_max * T;           // [rows][T][NCOL]
     const int colstride = 64 * SP;
@@ -394,7 +408,7 @@ __device__ __forceinline__ void bound_tile(
                 }
                 float emax = relu_epilogue<NCOL, SMOOTH, SCORE>(a, eps, valid, ek, scv[i],
                                                                 split_layers >= 1);
-                float* sb = S + ((nt * NCOL * 4 + g) * 16 + j) * SP + 4 * mt;
+                float* sb = S + ((nt * NCOL * 4 + g) * 16 + j) * SP + 4 * (mt ^ xs);
 #pragma unroll
                 for (int c = 0; c < NCOL; ++c) {
                     f32x4 o = {a[c][0], a[c][1], a[c][2], a[c][3]};
@@ -432,21 +446,22 @@ __device__ __forceinline__ void bound_tile(
                 const int nqa = L->ks_alloc >> 2;
                 const uint64_t* qf = L->qfrag + (size_t)mt * nqa * 64 + lane;
                 constexpr int kMaxQ = (UW * NW) / NT >= 8 ? 8 : 4;
-                k_quads_any<NCOL, kMaxQ>(acc, wf, qf, sb, colstride, nq, nqa);
+                k_quads_any<NCOL, kMaxQ>(acc, wf, qf, sb, colstride, nq, nqa, xs);
                 // the last K-steps (ks % 4 of them) one at a time, B read as scalars: a plain
                 // loop keeps the accumulators in place (no per-step selects of the whole set);
                 // the margin column takes the whole partial quad in one bf16 MFMA (its A is
                 // zero beyond ks)
                 if (4 * nq < ks)
                     acc[NCOL - 1] = mfma_bf16_quad(
-                        qf[nq * 64], *reinterpret_cast<const f32x4*>(sb + (NCOL - 1) * colstride + 4 * nq),
+                        qf[nq * 64], *reinterpret_cast<const f32x4*>(sb + (NCOL - 1) * colstride + 4 * (nq ^ xs)),
                         acc[NCOL - 1]);
                 for (int st = 4 * nq; st < ks; ++st) {
                     const float aw = wf[st * 64];
                     const float aa = fabsf(aw);
                     float bs[NCOL - 1];
 #pragma unroll
-                    for (int c = 0; c < NCOL - 1; ++c) bs[c] = sb[c * colstride + st];
+                    for (int c = 0; c < NCOL - 1; ++c)
+                        bs[c] = sb[c * colstride + 4 * ((st >> 2) ^ xs) + (st & 3)];
 #pragma unroll
                     for (int c = 0; c < NCOL - 2; ++c) acc[c] = mfma16(aw, bs[c], acc[c]);
                     acc[NCOL - 2] = mfma16(aa, bs[NCOL - 2], acc[NCOL - 2]);
@@ -479,7 +494,7 @@ __device__ __forceinline__ void bound_tile(
                 }
                 float emax = relu_epilogue<NCOL, SMOOTH, SCORE>(a, eps, valid, ek, scv[i],
                                                                 l + 2 <= split_layers);
-                float* sb = S + ((nt * NCOL * 4 + g) * 16 + j) * SP + 4 * mt;
+                float* sb = S + ((nt * NCOL * 4 + g) * 16 + j) * SP + 4 * (mt ^ xs);
 #pragma unroll
                 for (int c = 0; c < NCOL; ++c) {
                     f32x4 o = {a[c][0], a[c][1], a[c][2], a[c][3]};
@@ -512,7 +527,7 @@ __device__ __forceinline__ void bound_tile(
                 f32x4 bq[NCOL];
 #pragma unroll
                 for (int c = 0; c < NCOL; ++c)
-                    bq[c] = *reinterpret_cast<const f32x4*>(sb + c * colstride + 4 * q);
+                    bq[c] = *reinterpret_cast<const f32x4*>(sb + c * colstride + 4 * (q ^ xs));
 #pragma unroll
                 for (int ss = 0; ss < 4; ++ss) {
                     if (4 * q + ss < prop.ks_out) {
@@ -546,10 +561,11 @@ __device__ __forceinline__ void bound_tile(
             const int nt = bj >> 4, jj = bj & 15;
             const float* wr = prop.wgp + r * K;
             const float* col = S + (nt * NCOL + c) * colstride + jj * SP;
+            const int xj = quad_swizzle(SP >> 2, jj);
             float sacc = 0.f;
             for (int k = 0; k < K; ++k) {
                 const int gg = (k >> 2) & 3;
-                const int sidx = 4 * (k >> 4) + (k & 3);
+                const int sidx = 4 * ((k >> 4) ^ xj) + (k & 3);
                 float w = wr[k];
                 if (c >= NCOL - 2) w = fabsf(w);
                 sacc = fmaf(w, col[gg * 16 * SP + sidx], sacc);

@@ -2208,7 +2208,7 @@ extern "C" int batch_create_opts(int32_t n_inst, const slr_net* const* nets,
         I.max_depth = max_depth[i];
         I.max_leaves = max_leaves[i];
         I.cls_id = cls_of[p];
-        I.sp = 4 * I.net.mt_max + ((I.net.mt_max & 1) ? 0 : 4);
+        I.sp = state_stride(I.net.mt_max);
         I.acls_id = -1;
         if (use_alpha) {
             const AlphaShape sh = alpha_shape(I.net, I.prop);

@@ -116,6 +116,7 @@ hipError_t launch_bound_f32(const NetDev& net, const PropDev& prop, int64_t n, c
                             unsigned* amb_count, unsigned list_base, int8_t* dimsel = nullptr,
                             int split_layers = 0);
 // FP64 re-decision of the boxes list[0 .. *list_count), or of every class-3 box if list is NULL.
+int state_stride(int mt_max);   // floats per lane row of the bound kernel's LDS state
 hipError_t launch_recheck64(const NetDev& net, const PropDev& prop, int64_t n, const float* lo,
                             const float* hi, float* g_lo, float* g_hi, int8_t* cls,
                             unsigned long long* counter, const unsigned* list,

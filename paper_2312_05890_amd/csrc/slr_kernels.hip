@@ -459,7 +459,6 @@ int ncol_class(int d) {
     return 35;
 }
 
-int state_stride(int mt_max) { return 4 * mt_max + ((mt_max & 1) ? 0 : 4); }
 
 template <int NCOL, int NT, int UW, int NW, bool SMOOTH = false, bool SCORE = false>
 hipError_t launch_inst(const NetDev& net, const PropDev& prop, int64_t n, const float* lo,
@@ -627,6 +626,10 @@ TileShape default_shape(int mt_max) {
 }  // namespace
 
 int ncol_class_of(int d) { return ncol_class(d); }
+
+// Floats per lane row of the LDS state: one 16-byte slot per input tile (quad of K-steps); the
+// slots are XOR-swizzled per lane (quad_swizzle) instead of padded against bank conflicts.
+int state_stride(int mt_max) { return 4 * mt_max; }
 
 size_t bound_lds_bytes(int NCOL, TileShape t, int mt_max, int rows) {
     const int T = t.nt * 16;
