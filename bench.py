@@ -314,6 +314,27 @@ def split_section(E, torch, inst, reps=3):
     return out
 
 
+def relax_section(E, torch, inst, reps=3):
+    """The headline count with the two-ratio relaxation (tape-state kernel, widened float32
+    classes) beside Eq. 1: same leaf budget, brackets and time."""
+    net = E.Net(inst.net)
+    prop = E.Property(net, inst.C, inst.dvec)
+    out = {}
+    for relax in ("one", "two"):
+        kw = dict(chunk=65536, relax=relax)
+        E.count_exact(net, prop, inst.lo, inst.hi, inst.max_depth, inst.max_leaves, **kw)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            r = E.count_exact(net, prop, inst.lo, inst.hi, inst.max_depth, inst.max_leaves, **kw)
+        dt = (time.perf_counter() - t0) / reps
+        out["relax_" + relax] = {"time_to_bracket_ms": dt * 1e3,
+                                 "bracket": [r["unsafe"], r["unsafe"] + r["undecided"]],
+                                 "boxes_bounded": r["n_boxes_bounded"],
+                                 "depth_reached": r["depth_reached"]}
+    return out
+
+
 def stack_section(E, torch, seed, depth=24, reps=2):
     """count_exact_stack (depth-first chunks, no leaf budget) on the same network past the
     2^20-leaf budget of the headline count."""
@@ -511,6 +532,7 @@ def main():
     if not args.no_stack:
         line["stack"] = stack_section(E, torch, args.seed)
         line["split_rule"] = split_section(E, torch, inst)
+        line["relaxation"] = relax_section(E, torch, inst)
     if not args.no_approx:
         line["approx"] = approx_section(E, torch, args.seed, not args.no_cpu_baseline)
     if not args.no_alpha:
