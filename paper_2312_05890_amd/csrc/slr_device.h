@@ -223,14 +223,18 @@ __device__ __forceinline__ float relu_epilogue(float (&a)[NCOL][4], const float 
 }
 
 // XOR swizzle of a lane's 16-byte state slots (quads of K-steps) in the LDS state buffer.  A
-// lane's slots are a row of SP = 4 mq floats; without the swizzle the b128 reads of the 16
-// lanes j of one group land on gcd(mq, 16)-way shared bank groups (for mq = 4, lanes j, j + 4,
-// j + 8, j + 12); XOR-ing the slot index with (j / (16 / m)) mod m, m = gcd(mq, 16), spreads
-// them over distinct groups, and keeps every slot index below mq (m divides mq).
+// lane's slots are a row of SP = 4 mq floats, so lanes j of one group sharing j mod (16 / m),
+// m = gcd(mq, 16), would put the same slot on the same bank group.  XOR-ing the slot index with
+// a lane pattern below m (m divides mq, so the index stays below mq) makes the 16-byte slots of
+// every 8 consecutive lanes fall on 8 distinct groups of a 32-bank file and those of all 16 lanes
+// on 16 distinct groups of a 64-bank one.
 __device__ __forceinline__ int quad_swizzle(int mq, int j) {
     const int low = mq & -mq;
-    const int m = low < 16 ? low : 16;
-    return (j / (16 / m)) & (m - 1);
+    if (low == 1) return 0;
+    if (low == 2) return ((j >> 2) ^ (j >> 3)) & 1;
+    if (low == 4) return ((j >> 1) ^ (j >> 3)) & 3;
+    if (low == 8) return (j ^ (j >> 3)) & 7;
+    return j & 15;
 }
 
 // The full K-quads of one unit (weights fragments wf/qf from global memory, the layer input's

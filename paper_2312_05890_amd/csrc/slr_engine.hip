@@ -1048,6 +1048,18 @@ hipEvent_t* timing_events() {
     return te.ev;
 }
 
+// Depth of the one-pass top of the tree (0: none).  Taken where the level loop bisects the widest
+// side with the plain kernel and no per-level extras (alpha passes, split timing), for
+// K >= 4 levels whose complete subtree (2^(K+1) - 1 boxes, at most 65535) fits the frontier.
+int prefix_depth(const slr_net* net, const slr_exact_opts* o, const Workspace& w) {
+    if (o->split_layers > 0 || o->alpha_steps > 0 || o->relax != SLR_RELAX_ONE || w.wchunk > 0 ||
+        (o->timing & 2) || net->dev.d > SLR_MAX_D)
+        return 0;
+    int K = std::min(15, o->max_depth);
+    while (K > 0 && ((int64_t)2 << K) - 1 > o->max_leaves) --K;
+    return K >= 4 ? K : 0;
+}
+
 // no_alloc: the call makes no allocation of any kind (no pinned staging buffer, no event, no
 // host heap): level counts are read back into stack memory and the split waits for them.
 int count_exact_impl(const slr_net* net, const slr_property* prop, const double* lo,
@@ -1101,7 +1113,106 @@ int count_exact_impl(const slr_net* net, const slr_property* prop, const double*
     int cur = 0, levels = 0, stop_level = 0, stopped = 0, status = SLR_OK;
     std::vector<unsigned long long> hpath;
     std::vector<int8_t> hcls, hdim;
-    for (int t = 0; t <= D; ++t) {
+    int t_begin = 0;
+    bool finished = false;
+    const int K = prefix_depth(net, o, w);
+    if (K > 0) {
+        // Depths 0 .. K in one pass: the complete subtree is built, bounded and re-decided in
+        // large launches instead of K + 1 latency-bound levels; the replay keeps exactly the
+        // boxes the level loop would bound (results, counts and traces are identical).
+        const int64_t N = ((int64_t)2 << K) - 1;
+        const int64_t sl = ((int64_t)1 << K) - 1;   // first box of depth K
+        const int64_t nK = (int64_t)1 << K;
+        RootBox rb{};
+        for (int k = 0; k < d; ++k) {
+            rb.lo[k] = root[k];
+            rb.hi[k] = root[d + k];
+        }
+        HIP_TRY(launch_prefix_boxes(N, d, rb, w.lo[0], w.hi[0], w.path[0], w.err, s), "count_exact: prefix kernel");
+        HIP_TRY(hipMemsetAsync(w.amb_count, 0, sizeof(unsigned), s), "count_exact: clear");
+        if (ev0) HIP_TRY(hipEventRecord(ev0, s), "count_exact: event");
+        for (int64_t off = 0; off < N; off += chunk) {
+            const int64_t m = std::min(chunk, N - off);
+            int unsup = 0;
+            HIP_TRY(launch_bound_f32(net->dev, prop->dev, m, w.lo[0] + off * d, w.hi[0] + off * d, nullptr,
+                                     nullptr, w.cls + off, 0, s, &unsup, w.amb_list, w.amb_count,
+                                     (unsigned)off),
+                    "count_exact: bound kernel");
+            if (unsup) return fail(SLR_EUNSUPPORTED, "count_exact: shape not supported");
+            ++launches;
+        }
+        if (ev1) HIP_TRY(hipEventRecord(ev1, s), "count_exact: event");
+        HIP_TRY(launch_recheck64(net->dev, prop->dev, N, w.lo[0], w.hi[0], nullptr, nullptr, w.cls,
+                                 w.rechecks, w.amb_list, w.amb_count, s),
+                "count_exact: recheck kernel");
+        HIP_TRY(launch_prefix_replay(N, K, w.cls, w.stats, s), "count_exact: prefix replay kernel");
+        HIP_TRY(launch_level_count(nK, w.cls + sl, w.tile_und, w.stats + K, s), "count_exact: count kernel");
+        LevelStats hst[16];
+        HIP_TRY(hipMemcpyAsync(hst, w.stats, sizeof(LevelStats) * (K + 1), hipMemcpyDeviceToHost, s),
+                "count_exact: readback");
+        const bool tr = o->trace_capacity > 0 && o->trace_path && o->trace_cls && o->trace_depth;
+        if (tr) {
+            hpath.resize(N);
+            hcls.resize(N);
+            HIP_TRY(hipMemcpyAsync(hpath.data(), w.path[0], N * sizeof(unsigned long long), hipMemcpyDeviceToHost, s), "count_exact: trace");
+            HIP_TRY(hipMemcpyAsync(hcls.data(), w.cls, N, hipMemcpyDeviceToHost, s), "count_exact: trace");
+        }
+        HIP_TRY(hipStreamSynchronize(s), "count_exact: sync");
+        if (ev0) {
+            float ms = 0.f;
+            HIP_TRY(hipEventElapsedTime(&ms, ev0, ev1), "count_exact: event");
+            bound_ms += ms;
+        }
+        // the level loop's decisions, level by level
+        for (int t = 0; t <= K; ++t) {
+            const LevelStats& h = hst[t];
+            const int64_t und = (int64_t)h.undecided_cnt;
+            const int64_t nt = (int64_t)(h.unsafe_cnt + h.safe_cnt) + und;
+            if (tr) {
+                const int64_t b0 = ((int64_t)1 << t) - 1, b1 = ((int64_t)2 << t) - 1;
+                int64_t seen = 0;
+                for (int64_t i = b0; i < b1; ++i) {
+                    if (hcls[i] == 4) continue;
+                    ++seen;
+                    if (tcount < o->trace_capacity) {
+                        o->trace_depth[tcount] = t;
+                        o->trace_path[tcount] = hpath[i];
+                        o->trace_cls[tcount] = hcls[i];
+                        if (o->trace_dim) o->trace_dim[tcount] = hcls[i] == 0 ? (int8_t)-2 : (int8_t)-1;
+                        ++tcount;
+                    }
+                }
+                if (seen != nt)
+                    return fail(SLR_EINTERNAL, "count_exact: prefix level %d lists %lld boxes, counts %lld", t,
+                                (long long)seen, (long long)nt);
+            }
+            bounded += nt;
+            levels = t + 1;
+            resolved += (int64_t)(h.unsafe_cnt + h.safe_cnt);
+            if (und == 0) {
+                finished = true;
+                break;
+            }
+            if (t == D || resolved + 2 * und > M) {
+                stopped = 1;
+                stop_level = t;
+                status = SLR_BUDGET;
+                finished = true;
+                break;
+            }
+            if (t == K) {
+                HIP_TRY(launch_split(nK, d, w.cls + sl, w.tile_und, w.lo[0] + sl * d, w.hi[0] + sl * d,
+                                     w.path[0] + sl, w.lo[1], w.hi[1], w.path[1], w.err + K, M, s),
+                        "count_exact: split kernel");
+                split_bytes += nK + und * (int64_t)(2 * d * sizeof(float) + 8) * 3 +
+                               (int64_t)level_tiles(nK) * 4;
+                n = 2 * und;
+                cur = 1;
+                t_begin = K + 1;
+            }
+        }
+    }
+    for (int t = t_begin; !finished && t <= D; ++t) {
         int unsup = 0;
         HIP_TRY(hipMemsetAsync(w.amb_count, 0, sizeof(unsigned), s), "count_exact: clear");
         if (ev0) HIP_TRY(hipEventRecord(ev0, s), "count_exact: event");

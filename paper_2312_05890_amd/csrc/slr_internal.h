@@ -123,6 +123,16 @@ hipError_t launch_recheck64(const NetDev& net, const PropDev& prop, int64_t n, c
                             const unsigned* list_count, hipStream_t stream);
 hipError_t launch_level_count(int64_t n, const int8_t* cls, unsigned int* tile_und,
                               LevelStats* stats, hipStream_t stream);
+// Top of the search tree in one pass (depths 0 .. K, K <= 15): the 2^(K+1) - 1 boxes of the complete
+// subtree in heap order (path id = index + 1) built by the widest-side split rule, and after
+// they are bounded, the replay that marks the boxes the level-by-level search would not visit
+// (class 4) and counts the visited ones of depths 0 .. K - 1 into stats.
+struct RootBox {
+    float lo[SLR_MAX_D], hi[SLR_MAX_D];
+};
+hipError_t launch_prefix_boxes(int64_t N, int d, const RootBox& rb, float* lo, float* hi,
+                               unsigned long long* path, unsigned* err, hipStream_t stream);
+hipError_t launch_prefix_replay(int64_t N, int K, int8_t* cls, LevelStats* stats, hipStream_t stream);
 // dimsel: the side of each parent chosen by the bound kernel (NULL: the widest side).
 hipError_t launch_split(int64_t n, int d, const int8_t* cls, const unsigned int* tile_und,
                         const float* lo, const float* hi, const unsigned long long* path,
