@@ -314,6 +314,50 @@ def split_section(E, torch, inst, reps=3):
     return out
 
 
+def resolve_section(E, torch, count=256, depth=16, leaves=1 << 16, reps=3):
+    """Time to the exact count where the search resolves: ``count`` instances of the 2-16-16-1
+    network (seeds 0..count-1, [-1,1]^2, y > 0, depth 16) counted one at a time with
+    count_exact, as one batch, and as one batch with the near-decision alpha pass; total time,
+    boxes bounded and the summed undecided volume (what is left between the bracket's ends)."""
+    import synth
+    items = []
+    for seed in range(count):
+        inst = synth.tiny2d(seed)
+        net = E.Net(inst.net)
+        items.append((net, E.Property(net, inst.C, inst.dvec), inst.lo, inst.hi, depth, leaves))
+    ws = torch.empty(max(E.workspace_size(it[0], it[1], it[5]) for it in items), dtype=torch.uint8,
+                     device="cuda")
+
+    def summary(res, dt):
+        return {"ms": dt * 1e3, "boxes_bounded": sum(r["n_boxes_bounded"] for r in res),
+                "undecided_volume_sum": sum(r["undecided"] for r in res),
+                "unsafe_volume_sum": sum(r["unsafe"] for r in res)}
+
+    E.count_exact(*items[0][:4], depth, leaves, workspace=ws)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    seq = [E.count_exact(*it[:4], depth, leaves, workspace=ws) for it in items]
+    out = {"workload": "%d x 2-16-16-1 ReLU (seeds 0..%d), [-1,1]^2, y > 0, depth %d, 2^%d leaves"
+                       % (count, count - 1, depth, leaves.bit_length() - 1),
+           "sequential_count_exact": summary(seq, time.perf_counter() - t0)}
+    for name, kw in (("batch", {}),
+                     ("batch_alpha", dict(alpha_steps=5, alpha_min_depth=6, alpha_select=ALPHA_SELECT,
+                                          alpha_chunk=1 << 16)),
+                     ("batch_alpha_late", dict(alpha_steps=2, alpha_min_depth=12,
+                                               alpha_select=ALPHA_SELECT, alpha_chunk=1 << 16))):
+        b = E.Batch(items, use_graph=True, **kw)
+        res = b.run()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            res = b.run()
+        out[name] = summary(res, (time.perf_counter() - t0) / reps)
+        out[name]["brackets_inside_plain"] = all(
+            r["unsafe"] >= q["unsafe"] and r["unsafe"] + r["undecided"] <= q["unsafe"] + q["undecided"]
+            for r, q in zip(res, seq))
+    return out
+
+
 def relax_section(E, torch, inst, reps=3):
     """The headline count with the two-ratio relaxation (tape-state kernel, widened float32
     classes) beside Eq. 1: same leaf budget, brackets and time."""
@@ -529,6 +573,7 @@ def main():
     }
     if not args.no_batch:
         line["batch"] = batch_section(E, torch, args.seed)
+        line["resolving"] = resolve_section(E, torch)
     if not args.no_stack:
         line["stack"] = stack_section(E, torch, args.seed)
         line["split_rule"] = split_section(E, torch, inst)

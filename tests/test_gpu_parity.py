@@ -361,6 +361,29 @@ def test_count_exact_deterministic_and_budget():
     assert z["n_boxes_bounded"] == 1 and z["depth_reached"] == 0
 
 
+@pytest.mark.parametrize("name,seed,D,M,chunk", [
+    ("tiny2d", 1, 12, 1 << 12, 0),      # decisions inside the one-pass top (depths 0..11)
+    ("tiny2d", 2, 5, 100, 7),           # the depth limit inside it, launches of 7 boxes
+    ("tiny2d", 4, 14, 40, 0),           # the leaf budget stops the search inside it
+    ("acas", 1, 30, 1 << 12, 1000),     # top of depth 11, then levels in 1000-box launches
+    ("batch", 14, 20, 1 << 11, 0),      # 96-wide instance, top of depth 10
+])
+def test_count_exact_one_pass_top_equals_level_loop(name, seed, D, M, chunk):
+    """The one-pass top of the tree (complete subtree bounded at once, replayed to the boxes the
+    level loop visits) gives the oracle's boxes and classes, and the level loop's exact result:
+    timing bit 1 (split timing) keeps the level loop, so both are compared bit for bit."""
+    inst = make(name, seed)
+    g, o, diverge = compare_counts(inst, D, M, chunk=chunk)
+    net, prop = load(inst)
+    ref = E().count_exact(net, prop, inst.lo, inst.hi, D, M, chunk=chunk, trace=True, timing=2)
+    for k in ("unsafe", "safe", "undecided", "n_unsafe", "n_safe", "n_undecided",
+              "n_boxes_bounded", "n_recheck64", "depth_reached", "status"):
+        assert g[k] == ref[k], (k, g[k], ref[k])
+    for k in ("trace_depth", "trace_path", "trace_cls", "trace_dim"):
+        assert np.array_equal(g[k], ref[k]), k
+    assert ref["bound_launches"] >= g["bound_launches"]
+
+
 def test_count_exact_timing_flags():
     """Timing changes no result; bit 0 times the bound launches, bit 1 the split launches, whose
     algorithmic bytes follow from the per-level counts (from the trace): every class byte, the
