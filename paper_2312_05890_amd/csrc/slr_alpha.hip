@@ -551,7 +551,7 @@ template <int NC, bool GS, bool RP, bool TWO = false>
 __device__ __forceinline__ void alpha_fwd_tile(const NetDev& net, const PropDev& prop,
                                                const AlphaArgs& A, int slots, int64_t tile,
                                                int init) {
-    extern __shared__ float lds[];
+    extern __shared__ __attribute__((aligned(16))) float lds[];   // 16-byte aligned after any static LDS
     using G = Groups<NC>;
     constexpr int NC2 = 2 * NC;
     constexpr int NCT = 2 * NC + 2;
@@ -762,7 +762,7 @@ template <int NC, bool GS, bool RP>
 __device__ __forceinline__ void alpha_bwd_tile(const NetDev& net, const PropDev& prop,
                                                const AlphaArgs& A, int slots, int64_t tile,
                                                const AdamK& ak) {
-    extern __shared__ float lds[];
+    extern __shared__ __attribute__((aligned(16))) float lds[];   // 16-byte aligned after any static LDS
     using G = Groups<NC>;
     constexpr int NC2 = 2 * NC;
     constexpr int NCT = 2 * NC + 2;

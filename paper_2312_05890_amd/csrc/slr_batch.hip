@@ -46,14 +46,24 @@ __global__ __launch_bounds__(256) void batch_init_kernel(BatchInst* insts, int n
         I.lo[0][k] = I.root[k];
         I.hi[0][k] = I.root[I.d + k];
     }
+    if (threadIdx.x < 16) I.perr[threadIdx.x] = 0;
     if (threadIdx.x == 0) {
         I.path[0][0] = 1ull;
         I.n = 1;
+        I.coff = 0;
+        I.cn = 1;
+        I.prefix_pending = 0;
+        if (I.pk > 0) {   // first level: the top of the tree (boxes from batch_prefix_kernel)
+            I.n = ((long long)2 << I.pk) - 1;
+            I.coff = ((long long)1 << I.pk) - 1;
+            I.cn = (long long)1 << I.pk;
+            I.prefix_pending = 1;
+        }
         I.n_next = 0;
         I.resolved = 0;
         I.bounded = 0;
         I.cur = 0;
-        I.level = 0;
+        I.level = I.pk;
         I.active = 1;
         I.split_pending = 0;
         I.status = 0;
@@ -69,6 +79,32 @@ __global__ __launch_bounds__(256) void batch_init_kernel(BatchInst* insts, int n
         I.n_alpha_boxes = 0;
         I.n_alpha_decided = 0;
     }
+}
+
+// The complete subtree of depth pk (heap order, split rule of the level loop) of every instance
+// that has one; grid: boxes x instances.
+__global__ __launch_bounds__(256) void batch_prefix_kernel(BatchInst* insts, int n_inst) {
+    const int i = blockIdx.y;
+    if (i >= n_inst) return;
+    BatchInst& I = insts[i];
+    if (I.pk <= 0) return;
+    const int64_t N = ((int64_t)2 << I.pk) - 1;
+    const int64_t b = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (b >= N) return;
+    const int d = I.d;
+    prefix_box(b, d, I.root, I.root + d, I.lo[0] + b * d, I.hi[0] + b * d, I.path[0] + b, I.perr, 1);
+}
+
+// Replay of the top's level once its classes are final: boxes the level loop would not visit get
+// class 4, the visited ones of depths 0 .. pk - 1 are counted; grid: boxes x instances.
+__global__ __launch_bounds__(256) void batch_prefix_replay_kernel(BatchInst* insts, int n_inst) {
+    const int i = blockIdx.y;
+    if (i >= n_inst) return;
+    BatchInst& I = insts[i];
+    if (!I.prefix_pending) return;
+    const int64_t N = ((int64_t)2 << I.pk) - 1;
+    if ((int64_t)blockIdx.x * 256 >= N) return;
+    prefix_replay_block(N, I.pk, I.cls, I.stats, (int64_t)blockIdx.x * 256);
 }
 
 // One workgroup of 1024 threads, thread i = instance i (instances are sorted by kernel class,
@@ -109,15 +145,18 @@ __global__ __launch_bounds__(1024) void batch_plan_kernel(BatchInst* insts, int 
         BatchInst& I = insts[i];
         if (I.split_pending) {
             I.n = I.n_next;
+            I.coff = 0;
+            I.cn = I.n;
             I.cur ^= 1;
             I.level += 1;
             I.split_pending = 0;
         }
         const long long n = I.active ? I.n : 0;
+        const long long cn = I.active ? I.cn : 0;
         cid = I.cls_id;
         const int T = ctl->tbox[cid];
         tb = (unsigned)((n + T - 1) / T);
-        tc = (unsigned)((n + kTile - 1) / kTile);
+        tc = (unsigned)((cn + kTile - 1) / kTile);
     }
     unsigned tot_b, tot_c;
     const unsigned pb = block_exclusive_scan1024(tb, wtot, &tot_b);
@@ -189,7 +228,7 @@ __global__ __launch_bounds__(256) void batch_count_kernel(BatchInst* insts, int 
     for (unsigned t = blockIdx.x; t < total; t += gridDim.x) {
         const int i = find_owner(cpre, 0, n_inst, t);
         BatchInst& I = insts[i];
-        count_tile(I.n, I.cls, I.tile_und, I.stats + I.level, (int64_t)(t - cpre[i]));
+        count_tile(I.cn, I.cls + I.coff, I.tile_und, I.stats + I.level, (int64_t)(t - cpre[i]));
         __syncthreads();
     }
 }
@@ -199,6 +238,35 @@ __global__ __launch_bounds__(256) void batch_advance_kernel(BatchInst* insts, in
     if (i >= n_inst) return;
     BatchInst& I = insts[i];
     if (!I.active) return;
+    if (I.prefix_pending) {   // the level loop's decisions at depths 0 .. pk, depth by depth
+        I.prefix_pending = 0;
+        for (int t = 0; t <= I.pk; ++t) {
+            const LevelStats h = I.stats[t];
+            const long long und = (long long)h.undecided_cnt;
+            I.bounded += (long long)(h.unsafe_cnt + h.safe_cnt) + und;
+            I.levels = t + 1;
+            I.resolved += (long long)(h.unsafe_cnt + h.safe_cnt);
+            if (und == 0) {
+                I.active = 0;
+                I.status = 0;
+                return;
+            }
+            if (t == I.max_depth || I.resolved + 2 * und > I.max_leaves) {
+                I.active = 0;
+                I.stopped = 1;
+                I.stop_level = t;
+                I.status = 1;
+                return;
+            }
+            if (t < I.pk) {
+                if (I.perr[t]) I.err |= 1u;   // a split the level loop makes
+            } else {
+                I.split_pending = 1;
+                I.n_next = 2 * und;
+            }
+        }
+        return;
+    }
     const LevelStats h = I.stats[I.level];
     I.bounded += I.n;
     I.levels = I.level + 1;
@@ -229,9 +297,10 @@ __global__ __launch_bounds__(256) void batch_split_kernel(BatchInst* insts, int 
         BatchInst& I = insts[i];
         if (!I.split_pending) continue;
         const int c = I.cur;
-        split_tile(I.n, I.d, I.cls, I.tile_und, I.lo[c], I.hi[c], I.path[c], I.lo[c ^ 1],
-                   I.hi[c ^ 1], I.path[c ^ 1], &I.err, I.max_leaves, (int64_t)(t - cpre[i]),
-                   split_stage);
+        const long long o = I.coff;   // the depth-pk slice of the top's level, else 0
+        split_tile(I.cn, I.d, I.cls + o, I.tile_und, I.lo[c] + o * I.d, I.hi[c] + o * I.d,
+                   I.path[c] + o, I.lo[c ^ 1], I.hi[c ^ 1], I.path[c ^ 1], &I.err, I.max_leaves,
+                   (int64_t)(t - cpre[i]), split_stage);
         __syncthreads();
     }
 }
@@ -482,6 +551,24 @@ hipError_t batch_prepare_class(int ncol, TileShape t, size_t lds, int* blocks) {
 hipError_t launch_batch_init(BatchInst* insts, int n_inst, hipStream_t stream) {
     (void)hipGetLastError();
     hipLaunchKernelGGL(batch_init_kernel, dim3(n_inst), dim3(64), 0, stream, insts, n_inst);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_prefix(BatchInst* insts, int n_inst, int pk_max, hipStream_t stream) {
+    if (pk_max <= 0) return hipSuccess;
+    if (pk_max > 15) return hipErrorInvalidValue;
+    const unsigned bx = (unsigned)((((int64_t)2 << pk_max) - 1 + 255) / 256);
+    (void)hipGetLastError();
+    hipLaunchKernelGGL(batch_prefix_kernel, dim3(bx, n_inst), dim3(256), 0, stream, insts, n_inst);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_prefix_replay(BatchInst* insts, int n_inst, int pk_max, hipStream_t stream) {
+    if (pk_max <= 0) return hipSuccess;
+    if (pk_max > 15) return hipErrorInvalidValue;
+    const unsigned bx = (unsigned)((((int64_t)2 << pk_max) - 1 + 255) / 256);
+    (void)hipGetLastError();
+    hipLaunchKernelGGL(batch_prefix_replay_kernel, dim3(bx, n_inst), dim3(256), 0, stream, insts, n_inst);
     return hipGetLastError();
 }
 

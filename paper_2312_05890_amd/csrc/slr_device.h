@@ -336,7 +336,7 @@ __device__ __forceinline__ void bound_tile(
     float* __restrict__ g_hi, int8_t* __restrict__ cls, int raw, int SP,
     unsigned* __restrict__ amb_list, unsigned* __restrict__ amb_count, unsigned list_base,
     int8_t* __restrict__ dimsel = nullptr, int split_layers = 0) {
-    extern __shared__ float lds[];
+    extern __shared__ __attribute__((aligned(16))) float lds[];   // 16-byte aligned after any static LDS
     constexpr int T = NT * 16;
     constexpr int D = NCOL - 3;
     // SCORE: per-lane crossing scores of each unit's box (a unit keeps its 16-box column)
@@ -979,6 +979,81 @@ __device__ __forceinline__ unsigned block_sum256(unsigned v, unsigned* red) {
 }
 
 // Class histogram of one 1024-box tile and its undecided count.
+// Top of the search tree in one pass.  Box i of the complete subtree of depth K (heap order,
+// path id i + 1, depth = position of the id's leading bit), built from the root corners rlo, rhi
+// by the split rule of `split_tile` (widest side, lowest index on ties, float32 midpoint): the
+// same operations on the same values, so its corners are those the level-by-level search makes.
+// A midpoint that is not exact sets bit 0 of err[parent depth] (err_stride 1) or of *err
+// (err_stride 0).
+__device__ __forceinline__ void prefix_box(int64_t i, int d, const float* rlo, const float* rhi,
+                                           float* __restrict__ L, float* __restrict__ H,
+                                           unsigned long long* __restrict__ path, unsigned* err,
+                                           int err_stride) {
+    const unsigned long long P = (unsigned long long)i + 1ull;
+    const int t = 63 - __clzll((long long)P);
+    for (int k = 0; k < d; ++k) {
+        L[k] = rlo[k];
+        H[k] = rhi[k];
+    }
+    for (int s = t - 1; s >= 0; --s) {
+        int js = 0;
+        float wbest = H[0] - L[0];
+        for (int k = 1; k < d; ++k) {
+            const float w = H[k] - L[k];
+            if (w > wbest) {
+                wbest = w;
+                js = k;
+            }
+        }
+        const float m = 0.5f * (L[js] + H[js]);
+        if (!(m - L[js] == H[js] - m && L[js] < m && m < H[js])) atomicOr(err + err_stride * (t - 1 - s), 1u);
+        if ((P >> s) & 1ull)
+            L[js] = m;
+        else
+            H[js] = m;
+    }
+    *path = P;
+}
+
+// Which subtree boxes the level-by-level search visits: box i is bounded there iff none of its
+// ancestors was decided (class 1 or 2).  Unvisited boxes get class 4 (no count, no split); the
+// visited ones of depths 0 .. K - 1 are counted into stats[depth] (one block of 256 boxes, LDS
+// histogram, then 64-bit atomics).  (A box's own class is final here; overwriting an unvisited
+// ancestor's 0 with 4 while a descendant reads it cannot change the descendant's verdict: that
+// ancestor has a decided ancestor of its own, which the descendant reads as well.)
+__device__ __forceinline__ void prefix_replay_block(int64_t N, int K, int8_t* cls, LevelStats* stats,
+                                                    int64_t i0) {
+    __shared__ unsigned hist[16 * 3];
+    for (int e = threadIdx.x; e < 16 * 3; e += blockDim.x) hist[e] = 0;
+    __syncthreads();
+    const int64_t i = i0 + threadIdx.x;
+    if (i < N) {
+        const unsigned long long P = (unsigned long long)i + 1ull;
+        const int t = 63 - __clzll((long long)P);
+        bool visited = true;
+        for (unsigned long long a = P >> 1; a >= 1ull; a >>= 1) {
+            const int8_t c = cls[a - 1];
+            if (c == 1 || c == 2) {
+                visited = false;
+                break;
+            }
+        }
+        const int8_t c = cls[i];
+        if (!visited)
+            cls[i] = 4;
+        else if (t < K)
+            atomicAdd(&hist[t * 3 + (c == 1 ? 0 : (c == 2 ? 1 : 2))], 1u);
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < K * 3; e += blockDim.x) {
+        const unsigned v = hist[e];
+        if (!v) continue;
+        LevelStats* st = stats + e / 3;
+        unsigned long long* dst = e % 3 == 0 ? &st->unsafe_cnt : (e % 3 == 1 ? &st->safe_cnt : &st->undecided_cnt);
+        atomicAdd(dst, (unsigned long long)v);
+    }
+}
+
 __device__ __forceinline__ void count_tile(int64_t n, const int8_t* __restrict__ cls,
                                            unsigned* __restrict__ tile_und, LevelStats* stats,
                                            int64_t tile) {

@@ -1979,6 +1979,7 @@ extern "C" int count_approx(const slr_net* net, const slr_property* prop, const 
 // ------------------------------------------------------------------------------------------
 struct slr_batch {
     int n_inst = 0, levels = 0;
+    int pk_max = 0;                   // deepest one-pass top of the tree among the instances
     std::vector<int> order;           // device position -> caller index
     void* mem = nullptr;
     BatchInst* insts = nullptr;
@@ -2014,6 +2015,7 @@ namespace {
 // The whole batch count: init, then every level's fixed launch sequence, then the volumes.
 int batch_enqueue(const slr_batch* b, hipStream_t s) {
     HIP_TRY(launch_batch_init(b->insts, b->n_inst, s), "batch: init kernel");
+    HIP_TRY(launch_batch_prefix(b->insts, b->n_inst, b->pk_max, s), "batch: prefix kernel");
     for (int t = 0; t < b->levels; ++t) {
         HIP_TRY(launch_batch_plan(b->insts, b->n_inst, b->ctl, b->bpre, b->cpre, (int)b->cls.size(), s),
                 "batch: plan kernel");
@@ -2024,6 +2026,8 @@ int batch_enqueue(const slr_batch* b, hipStream_t s) {
                     "batch: bound kernel");
         }
         HIP_TRY(launch_batch_recheck(b->insts, b->ctl, b->amb, b->nrow, b->ncol_max, s), "batch: recheck kernel");
+        if (t == 0)
+            HIP_TRY(launch_batch_prefix_replay(b->insts, b->n_inst, b->pk_max, s), "batch: prefix replay kernel");
         if (!b->acls.empty()) {
             HIP_TRY(launch_batch_alpha_cand(b->insts, b->n_inst, b->ctl, b->cpre, b->tile_cand,
                                             b->alpha_select, s), "batch: alpha candidate kernel");
@@ -2330,7 +2334,14 @@ extern "C" int batch_create_opts(int32_t n_inst, const slr_net* const* nets,
             I.aslots = sh.slots;
             I.atile_floats = (unsigned long long)sh.slots * sh.slot_floats;
         }
-        levels = std::max(levels, max_depth[i] + 1);
+        // depths 0 .. pk in the first level (complete subtree within the leaf budget, below the
+        // first alpha depth)
+        int pk = std::min(15, max_depth[i]);
+        while (pk > 0 && ((int64_t)2 << pk) - 1 > max_leaves[i]) --pk;
+        if (use_alpha) pk = std::min(pk, opts->alpha_min_depth - 1);
+        I.pk = pk >= 4 ? pk : 0;
+        b->pk_max = std::max(b->pk_max, I.pk);
+        levels = std::max(levels, max_depth[i] - I.pk + 1);
         std::vector<float> root(2 * I.d);
         for (int k = 0; k < I.d; ++k) {
             root[k] = (float)lo[i][k];

@@ -264,8 +264,12 @@ struct BatchInst {
     const float* root;           // [2 d]: lower corner, then upper corner
     int d, max_depth, cls_id, sp;
     long long max_leaves;
+    int pk;                      // depth of the one-pass top of the tree (0: none)
+    int prefix_pending;          // the top's level has not been replayed yet
     // dynamic state, reset by the init kernel
     long long n, n_next, resolved, bounded;
+    long long coff, cn;          // boxes [coff, coff + cn) of the level are counted and split
+    unsigned perr[16];           // inexact midpoints in the top's splits, by parent depth
     int cur, level, active, split_pending;
     int status, stop_level, stopped, levels;
     unsigned long long rechecks;
@@ -332,6 +336,10 @@ int batch_class_of(const NetDev& net, const PropDev& prop, int* ncol, TileShape*
 size_t batch_bound_lds(int ncol, TileShape t, int mt_max, int rows);
 hipError_t batch_prepare_class(int ncol, TileShape t, size_t lds, int* blocks);
 hipError_t launch_batch_init(BatchInst* insts, int n_inst, hipStream_t stream);
+// The one-pass top of the tree of the instances with pk > 0 (pk_max: the largest pk): its boxes,
+// and the replay of its level after the re-decision.
+hipError_t launch_batch_prefix(BatchInst* insts, int n_inst, int pk_max, hipStream_t stream);
+hipError_t launch_batch_prefix_replay(BatchInst* insts, int n_inst, int pk_max, hipStream_t stream);
 hipError_t launch_batch_plan(BatchInst* insts, int n_inst, BatchCtl* ctl, unsigned* bpre,
                              unsigned* cpre, int n_classes, hipStream_t stream);
 hipError_t launch_batch_bound(int ncol, TileShape t, int blocks, size_t lds, BatchInst* insts,

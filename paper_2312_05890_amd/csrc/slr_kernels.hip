@@ -250,7 +250,7 @@ __global__ __launch_bounds__(256) void bound_reg_kernel(
     unsigned* __restrict__ amb_count, unsigned list_base) {
     constexpr int D = NCOL - 3;
     constexpr int KS = 4 * MT;
-    extern __shared__ float lds[];
+    extern __shared__ __attribute__((aligned(16))) float lds[];   // 16-byte aligned after any static LDS
     const int nmid = net.n_affine - 2;
     const int d = net.d;
     // [mid fragments nmid][MT][KS][64] | output fragments [KS][64] | bias, |W| row sums
@@ -596,11 +596,9 @@ bool reg_fits(const NetDev& net, const PropDev& prop) {
            reg_lds_bytes(net, prop, net.d + 3) <= 160 * 1024;
 }
 
-// Top of the search tree in one pass: every box of the complete binary subtree of depth K
-// (heap order: box i has path id i + 1, depth = position of that id's leading bit), each built
-// from the root by the split rule of `split_tile` (widest side, lowest index on ties, float32
-// midpoint; the same operations on the same values, so the corners are those the level-by-level
-// search produces).  A midpoint that is not exact flags the parent depth's error slot.
+// Top of the search tree in one pass: every box of the complete subtree of depth K
+// (`prefix_box`), and after bounding, the replay to the boxes the level loop visits
+// (`prefix_replay_block`).
 __global__ __launch_bounds__(256) void prefix_boxes_kernel(int64_t N, int d, RootBox rb,
                                                            float* __restrict__ lo,
                                                            float* __restrict__ hi,
@@ -608,71 +606,12 @@ __global__ __launch_bounds__(256) void prefix_boxes_kernel(int64_t N, int d, Roo
                                                            unsigned* err) {
     const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (i >= N) return;
-    const unsigned long long P = (unsigned long long)i + 1ull;
-    const int t = 63 - __clzll((long long)P);
-    float* L = lo + i * d;
-    float* H = hi + i * d;
-    for (int k = 0; k < d; ++k) {
-        L[k] = rb.lo[k];
-        H[k] = rb.hi[k];
-    }
-    for (int s = t - 1; s >= 0; --s) {
-        int js = 0;
-        float wbest = H[0] - L[0];
-        for (int k = 1; k < d; ++k) {
-            const float w = H[k] - L[k];
-            if (w > wbest) {
-                wbest = w;
-                js = k;
-            }
-        }
-        const float m = 0.5f * (L[js] + H[js]);
-        if (!(m - L[js] == H[js] - m && L[js] < m && m < H[js])) atomicOr(err + (t - 1 - s), 1u);
-        if ((P >> s) & 1ull)
-            L[js] = m;
-        else
-            H[js] = m;
-    }
-    path[i] = P;
+    prefix_box(i, d, rb.lo, rb.hi, lo + i * d, hi + i * d, path + i, err, 1);
 }
 
-// Which prefix boxes the level-by-level search visits: a box is bounded there iff none of its
-// ancestors was decided (class 1 or 2).  Unvisited boxes get class 4 (no count, no split); the
-// visited ones of depths 0 .. K - 1 are counted into their depth's level statistics.  (A box's
-// own class is final before this kernel; overwriting an unvisited ancestor's 0 with 4 while a
-// descendant reads it cannot change the descendant's verdict: that ancestor has a decided
-// ancestor of its own, which the descendant reads as well.)
 __global__ __launch_bounds__(256) void prefix_replay_kernel(int64_t N, int K, int8_t* cls,
                                                             LevelStats* stats) {
-    __shared__ unsigned hist[16 * 3];
-    for (int e = threadIdx.x; e < 16 * 3; e += 256) hist[e] = 0;
-    __syncthreads();
-    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (i < N) {
-        const unsigned long long P = (unsigned long long)i + 1ull;
-        const int t = 63 - __clzll((long long)P);
-        bool visited = true;
-        for (unsigned long long a = P >> 1; a >= 1ull; a >>= 1) {
-            const int8_t c = cls[a - 1];
-            if (c == 1 || c == 2) {
-                visited = false;
-                break;
-            }
-        }
-        const int8_t c = cls[i];
-        if (!visited)
-            cls[i] = 4;
-        else if (t < K)
-            atomicAdd(&hist[t * 3 + (c == 1 ? 0 : (c == 2 ? 1 : 2))], 1u);
-    }
-    __syncthreads();
-    for (int e = threadIdx.x; e < K * 3; e += 256) {
-        const unsigned v = hist[e];
-        if (!v) continue;
-        LevelStats* st = stats + e / 3;
-        unsigned long long* dst = e % 3 == 0 ? &st->unsafe_cnt : (e % 3 == 1 ? &st->safe_cnt : &st->undecided_cnt);
-        atomicAdd(dst, (unsigned long long)v);
-    }
+    prefix_replay_block(N, K, cls, stats, (int64_t)blockIdx.x * 256);
 }
 
 }  // namespace
