@@ -84,15 +84,16 @@ __global__ __launch_bounds__(256) void batch_init_kernel(BatchInst* insts, int n
 // The complete subtree of depth pk (heap order, split rule of the level loop) of every instance
 // that has one; grid: boxes x instances.
 __global__ __launch_bounds__(256) void batch_prefix_kernel(BatchInst* insts, int n_inst) {
+    extern __shared__ float prefix_stage[];   // 2 * 256 * (largest d) floats
     const int i = blockIdx.y;
     if (i >= n_inst) return;
     BatchInst& I = insts[i];
     if (I.pk <= 0) return;
     const int64_t N = ((int64_t)2 << I.pk) - 1;
-    const int64_t b = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (b >= N) return;
+    const int64_t i0 = (int64_t)blockIdx.x * 256;
+    if (i0 >= N) return;   // uniform over the workgroup
     const int d = I.d;
-    prefix_box(b, d, I.root, I.root + d, I.lo[0] + b * d, I.hi[0] + b * d, I.path[0] + b, I.perr, 1);
+    prefix_block(N, i0, d, I.root, I.root + d, I.lo[0], I.hi[0], I.path[0], I.perr, 1, prefix_stage);
 }
 
 // Replay of the top's level once its classes are final: boxes the level loop would not visit get
@@ -554,12 +555,13 @@ hipError_t launch_batch_init(BatchInst* insts, int n_inst, hipStream_t stream) {
     return hipGetLastError();
 }
 
-hipError_t launch_batch_prefix(BatchInst* insts, int n_inst, int pk_max, hipStream_t stream) {
+hipError_t launch_batch_prefix(BatchInst* insts, int n_inst, int pk_max, int d_max, hipStream_t stream) {
     if (pk_max <= 0) return hipSuccess;
-    if (pk_max > 15) return hipErrorInvalidValue;
+    if (pk_max > 15 || d_max < 1 || d_max > SLR_MAX_D) return hipErrorInvalidValue;
     const unsigned bx = (unsigned)((((int64_t)2 << pk_max) - 1 + 255) / 256);
     (void)hipGetLastError();
-    hipLaunchKernelGGL(batch_prefix_kernel, dim3(bx, n_inst), dim3(256), 0, stream, insts, n_inst);
+    hipLaunchKernelGGL(batch_prefix_kernel, dim3(bx, n_inst), dim3(256), sizeof(float) * 2 * 256 * d_max,
+                       stream, insts, n_inst);
     return hipGetLastError();
 }
 

@@ -190,7 +190,7 @@ __device__ __forceinline__ float relu_epilogue(float (&a)[NCOL][4], const float 
             a[0][v] = c0n;
             a[R][v] = rn;
             a[Q][v] = valid[v] ? fmaf(1.f + lam, q, delta + er) : 0.f;
-            emax = fmaxf(emax, (fabsf(c0n) + lam * S + rn) * (1.f + 4.f * kU32));
+            emax = fmaxf(emax, fabsf(c0n) + lam * S + rn);
             continue;
         }
         const bool dead = !valid[v] || !(hi > 0.f);
@@ -217,9 +217,10 @@ __device__ __forceinline__ float relu_epilogue(float (&a)[NCOL][4], const float 
         a[0][v] = c0n;
         a[R][v] = rn;
         a[Q][v] = fmaf(qf, q, qa);
-        emax = fmaxf(emax, (fabsf(c0n) + lam * S + rn) * (1.f + 4.f * kU32));
+        emax = fmaxf(emax, fabsf(c0n) + lam * S + rn);
     }
-    return emax;
+    // rounding is monotone, so scaling the maximum equals the maximum of the scaled values
+    return emax * (1.f + 4.f * kU32);
 }
 
 // XOR swizzle of a lane's 16-byte state slots (quads of K-steps) in the LDS state buffer.  A
@@ -1013,6 +1014,27 @@ __device__ __forceinline__ void prefix_box(int64_t i, int d, const float* rlo, c
             H[js] = m;
     }
     *path = P;
+}
+
+// Boxes [i0, i0 + 256) of the complete subtree (heap order), one per thread: made in the LDS
+// stage (2 x 256 x d floats, each box's corners a contiguous row), then written out by the
+// workgroup with consecutive threads on consecutive floats (coalesced; a box per thread would
+// store with a stride of d floats).
+__device__ __forceinline__ void prefix_block(int64_t N, int64_t i0, int d, const float* rlo,
+                                             const float* rhi, float* __restrict__ lo,
+                                             float* __restrict__ hi,
+                                             unsigned long long* __restrict__ path, unsigned* err,
+                                             int err_stride, float* stage) {
+    const int64_t i = i0 + threadIdx.x;
+    float* L = stage + threadIdx.x * d;
+    float* H = stage + (256 + threadIdx.x) * d;
+    if (i < N) prefix_box(i, d, rlo, rhi, L, H, path + i, err, err_stride);
+    __syncthreads();
+    const int nf = (int)min((int64_t)256, N - i0) * d;
+    for (int e = threadIdx.x; e < nf; e += blockDim.x) {
+        lo[i0 * d + e] = stage[e];
+        hi[i0 * d + e] = stage[256 * d + e];
+    }
 }
 
 // Which subtree boxes the level-by-level search visits: box i is bounded there iff none of its

@@ -1980,6 +1980,7 @@ extern "C" int count_approx(const slr_net* net, const slr_property* prop, const 
 struct slr_batch {
     int n_inst = 0, levels = 0;
     int pk_max = 0;                   // deepest one-pass top of the tree among the instances
+    int d_max = 0;                    // largest input dimension among the instances
     std::vector<int> order;           // device position -> caller index
     void* mem = nullptr;
     BatchInst* insts = nullptr;
@@ -2015,7 +2016,7 @@ namespace {
 // The whole batch count: init, then every level's fixed launch sequence, then the volumes.
 int batch_enqueue(const slr_batch* b, hipStream_t s) {
     HIP_TRY(launch_batch_init(b->insts, b->n_inst, s), "batch: init kernel");
-    HIP_TRY(launch_batch_prefix(b->insts, b->n_inst, b->pk_max, s), "batch: prefix kernel");
+    HIP_TRY(launch_batch_prefix(b->insts, b->n_inst, b->pk_max, b->d_max, s), "batch: prefix kernel");
     for (int t = 0; t < b->levels; ++t) {
         HIP_TRY(launch_batch_plan(b->insts, b->n_inst, b->ctl, b->bpre, b->cpre, (int)b->cls.size(), s),
                 "batch: plan kernel");
@@ -2341,6 +2342,7 @@ extern "C" int batch_create_opts(int32_t n_inst, const slr_net* const* nets,
         if (use_alpha) pk = std::min(pk, opts->alpha_min_depth - 1);
         I.pk = pk >= 4 ? pk : 0;
         b->pk_max = std::max(b->pk_max, I.pk);
+        b->d_max = std::max(b->d_max, I.d);
         levels = std::max(levels, max_depth[i] - I.pk + 1);
         std::vector<float> root(2 * I.d);
         for (int k = 0; k < I.d; ++k) {

@@ -336,9 +336,9 @@ int batch_class_of(const NetDev& net, const PropDev& prop, int* ncol, TileShape*
 size_t batch_bound_lds(int ncol, TileShape t, int mt_max, int rows);
 hipError_t batch_prepare_class(int ncol, TileShape t, size_t lds, int* blocks);
 hipError_t launch_batch_init(BatchInst* insts, int n_inst, hipStream_t stream);
-// The one-pass top of the tree of the instances with pk > 0 (pk_max: the largest pk): its boxes,
-// and the replay of its level after the re-decision.
-hipError_t launch_batch_prefix(BatchInst* insts, int n_inst, int pk_max, hipStream_t stream);
+// The one-pass top of the tree of the instances with pk > 0 (pk_max: the largest pk, d_max: the
+// largest input dimension): its boxes, and the replay of its level after the re-decision.
+hipError_t launch_batch_prefix(BatchInst* insts, int n_inst, int pk_max, int d_max, hipStream_t stream);
 hipError_t launch_batch_prefix_replay(BatchInst* insts, int n_inst, int pk_max, hipStream_t stream);
 hipError_t launch_batch_plan(BatchInst* insts, int n_inst, BatchCtl* ctl, unsigned* bpre,
                              unsigned* cpre, int n_classes, hipStream_t stream);

@@ -604,9 +604,8 @@ __global__ __launch_bounds__(256) void prefix_boxes_kernel(int64_t N, int d, Roo
                                                            float* __restrict__ hi,
                                                            unsigned long long* __restrict__ path,
                                                            unsigned* err) {
-    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (i >= N) return;
-    prefix_box(i, d, rb.lo, rb.hi, lo + i * d, hi + i * d, path + i, err, 1);
+    extern __shared__ float prefix_stage[];   // 2 * 256 * d floats
+    prefix_block(N, (int64_t)blockIdx.x * 256, d, rb.lo, rb.hi, lo, hi, path, err, 1, prefix_stage);
 }
 
 __global__ __launch_bounds__(256) void prefix_replay_kernel(int64_t N, int K, int8_t* cls,
@@ -769,8 +768,9 @@ hipError_t launch_prefix_boxes(int64_t N, int d, const RootBox& rb, float* lo, f
                                unsigned long long* path, unsigned* err, hipStream_t stream) {
     if (N <= 0) return hipSuccess;
     (void)hipGetLastError();
-    hipLaunchKernelGGL(prefix_boxes_kernel, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, stream,
-                       N, d, rb, lo, hi, path, err);
+    if (d < 1 || d > SLR_MAX_D) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(prefix_boxes_kernel, dim3((unsigned)((N + 255) / 256)), dim3(256),
+                       sizeof(float) * 2 * 256 * d, stream, N, d, rb, lo, hi, path, err);
     return hipGetLastError();
 }
 
