@@ -108,6 +108,18 @@ __global__ __launch_bounds__(256) void batch_prefix_replay_kernel(BatchInst* ins
     prefix_replay_block(N, I.pk, I.cls, I.stats, (int64_t)blockIdx.x * 256);
 }
 
+// The FP64 re-decisions of top boxes that the level loop does not visit (class 4 after the
+// replay) are not the loop's: each such listed box takes one off its instance's counter.
+__global__ __launch_bounds__(256) void batch_prefix_recheck_uncount_kernel(BatchInst* insts, const BatchCtl* ctl,
+                                                                           const unsigned* __restrict__ amb_list) {
+    const unsigned n = ctl->amb_count;
+    for (unsigned k = blockIdx.x * 256 + threadIdx.x; k < n; k += gridDim.x * 256) {
+        const unsigned e = amb_list[k];
+        BatchInst& I = insts[e >> 22];
+        if (I.cls[e & 0x3FFFFFu] == 4) atomicAdd(&I.rechecks, ~0ull);   // minus one
+    }
+}
+
 // One workgroup of 1024 threads, thread i = instance i (instances are sorted by kernel class,
 // so each class is a contiguous run): applies the pending split, then two exclusive scans over
 // the instances, of their bound tiles (bpre: offset inside the instance's class) and of their
@@ -565,12 +577,15 @@ hipError_t launch_batch_prefix(BatchInst* insts, int n_inst, int pk_max, int d_m
     return hipGetLastError();
 }
 
-hipError_t launch_batch_prefix_replay(BatchInst* insts, int n_inst, int pk_max, hipStream_t stream) {
+hipError_t launch_batch_prefix_replay(BatchInst* insts, int n_inst, int pk_max, BatchCtl* ctl,
+                                      const unsigned* amb_list, hipStream_t stream) {
     if (pk_max <= 0) return hipSuccess;
     if (pk_max > 15) return hipErrorInvalidValue;
     const unsigned bx = (unsigned)((((int64_t)2 << pk_max) - 1 + 255) / 256);
     (void)hipGetLastError();
     hipLaunchKernelGGL(batch_prefix_replay_kernel, dim3(bx, n_inst), dim3(256), 0, stream, insts, n_inst);
+    hipLaunchKernelGGL(batch_prefix_recheck_uncount_kernel, dim3(64), dim3(256), 0, stream, insts,
+                       (const BatchCtl*)ctl, amb_list);
     return hipGetLastError();
 }
 

@@ -1146,6 +1146,8 @@ int count_exact_impl(const slr_net* net, const slr_property* prop, const double*
                                  w.rechecks, w.amb_list, w.amb_count, s),
                 "count_exact: recheck kernel");
         HIP_TRY(launch_prefix_replay(N, K, w.cls, w.stats, s), "count_exact: prefix replay kernel");
+        HIP_TRY(launch_prefix_recheck_uncount(N, w.amb_list, w.amb_count, w.cls, w.rechecks, s),
+                "count_exact: prefix replay kernel");
         HIP_TRY(launch_level_count(nK, w.cls + sl, w.tile_und, w.stats + K, s), "count_exact: count kernel");
         LevelStats hst[16];
         HIP_TRY(hipMemcpyAsync(hst, w.stats, sizeof(LevelStats) * (K + 1), hipMemcpyDeviceToHost, s),
@@ -2028,7 +2030,8 @@ int batch_enqueue(const slr_batch* b, hipStream_t s) {
         }
         HIP_TRY(launch_batch_recheck(b->insts, b->ctl, b->amb, b->nrow, b->ncol_max, s), "batch: recheck kernel");
         if (t == 0)
-            HIP_TRY(launch_batch_prefix_replay(b->insts, b->n_inst, b->pk_max, s), "batch: prefix replay kernel");
+            HIP_TRY(launch_batch_prefix_replay(b->insts, b->n_inst, b->pk_max, b->ctl, b->amb, s),
+                    "batch: prefix replay kernel");
         if (!b->acls.empty()) {
             HIP_TRY(launch_batch_alpha_cand(b->insts, b->n_inst, b->ctl, b->cpre, b->tile_cand,
                                             b->alpha_select, s), "batch: alpha candidate kernel");

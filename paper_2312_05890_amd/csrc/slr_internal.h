@@ -133,6 +133,11 @@ struct RootBox {
 hipError_t launch_prefix_boxes(int64_t N, int d, const RootBox& rb, float* lo, float* hi,
                                unsigned long long* path, unsigned* err, hipStream_t stream);
 hipError_t launch_prefix_replay(int64_t N, int K, int8_t* cls, LevelStats* stats, hipStream_t stream);
+// After the replay: one off `counter` per listed box (list[0 .. *count)) of the N top boxes that
+// the level loop does not visit.
+hipError_t launch_prefix_recheck_uncount(int64_t N, const unsigned* list, const unsigned* count,
+                                         const int8_t* cls, unsigned long long* counter,
+                                         hipStream_t stream);
 // dimsel: the side of each parent chosen by the bound kernel (NULL: the widest side).
 hipError_t launch_split(int64_t n, int d, const int8_t* cls, const unsigned int* tile_und,
                         const float* lo, const float* hi, const unsigned long long* path,
@@ -339,7 +344,8 @@ hipError_t launch_batch_init(BatchInst* insts, int n_inst, hipStream_t stream);
 // The one-pass top of the tree of the instances with pk > 0 (pk_max: the largest pk, d_max: the
 // largest input dimension): its boxes, and the replay of its level after the re-decision.
 hipError_t launch_batch_prefix(BatchInst* insts, int n_inst, int pk_max, int d_max, hipStream_t stream);
-hipError_t launch_batch_prefix_replay(BatchInst* insts, int n_inst, int pk_max, hipStream_t stream);
+hipError_t launch_batch_prefix_replay(BatchInst* insts, int n_inst, int pk_max, BatchCtl* ctl,
+                                      const unsigned* amb_list, hipStream_t stream);
 hipError_t launch_batch_plan(BatchInst* insts, int n_inst, BatchCtl* ctl, unsigned* bpre,
                              unsigned* cpre, int n_classes, hipStream_t stream);
 hipError_t launch_batch_bound(int ncol, TileShape t, int blocks, size_t lds, BatchInst* insts,

@@ -613,6 +613,17 @@ __global__ __launch_bounds__(256) void prefix_replay_kernel(int64_t N, int K, in
     prefix_replay_block(N, K, cls, stats, (int64_t)blockIdx.x * 256);
 }
 
+// The FP64 re-decisions of the top's boxes that the level loop does not visit (class 4 after
+// the replay) are not the loop's: each such listed box takes one off the re-decision counter.
+__global__ __launch_bounds__(256) void prefix_recheck_uncount_kernel(const unsigned* __restrict__ list,
+                                                                     const unsigned* __restrict__ count,
+                                                                     const int8_t* __restrict__ cls,
+                                                                     unsigned long long* counter) {
+    const unsigned n = *count;
+    for (unsigned k = blockIdx.x * 256 + threadIdx.x; k < n; k += gridDim.x * 256)
+        if (cls[list[k]] == 4) atomicAdd(counter, ~0ull);   // minus one
+}
+
 }  // namespace
 
 int set_bound_variant(int v) {
@@ -779,6 +790,16 @@ hipError_t launch_prefix_replay(int64_t N, int K, int8_t* cls, LevelStats* stats
     (void)hipGetLastError();
     hipLaunchKernelGGL(prefix_replay_kernel, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, stream,
                        N, K, cls, stats);
+    return hipGetLastError();
+}
+
+hipError_t launch_prefix_recheck_uncount(int64_t N, const unsigned* list, const unsigned* count,
+                                         const int8_t* cls, unsigned long long* counter,
+                                         hipStream_t stream) {
+    if (N <= 0) return hipSuccess;
+    (void)hipGetLastError();
+    hipLaunchKernelGGL(prefix_recheck_uncount_kernel, dim3((unsigned)((N + 255) / 256 < 64 ? (N + 255) / 256 : 64)),
+                       dim3(256), 0, stream, list, count, cls, counter);
     return hipGetLastError();
 }
 

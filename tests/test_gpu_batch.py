@@ -144,6 +144,54 @@ def test_batch_mixed_shapes_and_budgets_against_oracle():
             assert abs(r["unsafe"] - o["unsafe"]) <= sum(2.0 ** -k[0] for k in diverge)
 
 
+def _level_loop(it):
+    """``count_exact`` with split timing, which keeps the level-by-level driver (no one-pass top
+    of the tree)."""
+    net, prop, lo, hi, D, M = it
+    return E().count_exact(net, prop, lo, hi, D, M, timing=2)
+
+
+def test_batch_top_of_tree_equals_level_loop():
+    """Instances whose counts end inside the batch's first level (the complete subtree of depth
+    pk, replayed depth by depth) or right after it, and instances without one: nothing left
+    undecided (2-input sub-boxes), the depth limit at pk (depth 5, 4), the leaf budget at pk
+    (63 = 2^6 - 1 leaves), no top at all (depth 3, 30 leaves), and ordinary counts past it;
+    every result, including the number of FP64 re-decisions, equals the level-by-level
+    driver's, and the resolved sub-boxes' volumes are the oracle's."""
+    eng = E()
+    sub = _one_per_shape(4)[:4]
+    def quarter(seed, cx, cy):   # a quarter-side sub-box of a 2-input net's domain
+        inst = synth.tiny2d(seed)
+        lo = inst.lo + (inst.hi - inst.lo) * np.array([cx, cy]) / 4.0
+        return dataclasses.replace(inst, name=f"tiny2d{seed}q{cx}{cy}", lo=lo,
+                                   hi=lo + (inst.hi - inst.lo) / 4.0)
+    # sub-boxes that the oracle resolves completely at depths 9, 9 and 8
+    cases = [(quarter(1, 2, 1), 16, 1 << 16), (quarter(1, 3, 0), 16, 1 << 16),
+             (quarter(0, 0, 1), 16, 1 << 16)]
+    cases += [(synth.tiny2d(s), 16, 1 << 16) for s in (0, 3)]
+    cases += [(synth.acas(0), 5, 1 << 12), (synth.acas(1), 4, 1 << 12), (synth.acas(2), 20, 63),
+              (synth.acas(0), 3, 1 << 12), (synth.acas(1), 12, 30), (synth.acas(2), 10, 1 << 10)]
+    cases += [(inst, 4 * inst.sizes[0], 1 << 11) for inst in sub]
+    items = []
+    for inst, D, M in cases:
+        net = eng.Net(inst.net)
+        items.append((net, eng.Property(net, inst.C, inst.dvec), inst.lo, inst.hi, D, M))
+    for use_graph in (True, False):
+        res = eng.Batch(items, use_graph=use_graph).run()
+        for (inst, D, M), it, r in zip(cases, items, res):
+            ref = _level_loop(it)
+            assert same(r, ref), (inst.name, D, M, r, ref)
+            assert same(single(it), ref), (inst.name, D, M)
+    for (inst, D, M), r in list(zip(cases, res))[:3]:
+        o = count.count_exact(inst.net, inst.C, inst.dvec, inst.lo, inst.hi, D, M)
+        assert o["status"] == 0 and o["undecided"] == 0.0
+        for k in ("unsafe", "safe", "undecided", "n_boxes_bounded", "depth_reached", "status"):
+            assert r[k] == o[k], (inst.name, k, r[k], o[k])
+    statuses = {r["status"] for r in res}
+    assert len(statuses) == 2   # finished and stopped counts both occur
+    assert any(r["n_recheck64"] > 0 for r in res)
+
+
 def test_batch_full_config_counts():
     """256 instances: d 5..10, 3..6 hidden layers of 32..128, 2..5 outputs, depth 4 d, 2^16
     leaves each; spot-check 8 instances against single-instance counts."""
