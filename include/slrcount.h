@@ -146,7 +146,9 @@ typedef struct {
     int8_t* trace_cls;
     int32_t timing;         /* bit 0: time the bound-kernel launches with HIP events on
                                `stream`; bit 1: time the split launches (each timed launch is
-                               bracketed by two events, which cost a few microseconds each) */
+                               bracketed by two events, which cost a few microseconds each);
+                               bit 2: run every depth with the level-by-level driver (no
+                               one-pass top of the tree; results are the same either way) */
     /* alpha mode: boxes that the plain bounds leave undecided at depth >= alpha_min_depth get
        alpha_steps projected-Adam steps of optimized lower slopes (0 = plain only), in batches
        of alpha_chunk boxes (the workspace must be sized for it) */

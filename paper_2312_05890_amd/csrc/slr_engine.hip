@@ -1053,7 +1053,7 @@ hipEvent_t* timing_events() {
 // K >= 4 levels whose complete subtree (2^(K+1) - 1 boxes, at most 65535) fits the frontier.
 int prefix_depth(const slr_net* net, const slr_exact_opts* o, const Workspace& w) {
     if (o->split_layers > 0 || o->alpha_steps > 0 || o->relax != SLR_RELAX_ONE || w.wchunk > 0 ||
-        (o->timing & 2) || net->dev.d > SLR_MAX_D)
+        (o->timing & 4) || net->dev.d > SLR_MAX_D)
         return 0;
     int K = std::min(15, o->max_depth);
     while (K > 0 && ((int64_t)2 << K) - 1 > o->max_leaves) --K;
@@ -1203,9 +1203,14 @@ int count_exact_impl(const slr_net* net, const slr_property* prop, const double*
                 break;
             }
             if (t == K) {
+                if (time_split) HIP_TRY(hipEventRecord(sev(K, 0), s), "count_exact: event");
                 HIP_TRY(launch_split(nK, d, w.cls + sl, w.tile_und, w.lo[0] + sl * d, w.hi[0] + sl * d,
                                      w.path[0] + sl, w.lo[1], w.hi[1], w.path[1], w.err + K, M, s),
                         "count_exact: split kernel");
+                if (time_split) {
+                    HIP_TRY(hipEventRecord(sev(K, 1), s), "count_exact: event");
+                    split_pending = K;   // read after the next level's sync
+                }
                 split_bytes += nK + und * (int64_t)(2 * d * sizeof(float) + 8) * 3 +
                                (int64_t)level_tiles(nK) * 4;
                 n = 2 * und;

@@ -387,7 +387,8 @@ def count_exact(net: Net, prop: Property, lo, hi, max_depth: int, max_leaves: in
     ratio per equation, ``slr_exact_opts.relax``).
 
     ``timing``: bit 0 times the bound-kernel launches (``bound_ms``), bit 1 the split launches
-    (``split_ms``, with their algorithmic ``split_bytes``); True means 1.
+    (``split_ms``, with their algorithmic ``split_bytes``); bit 2 keeps the level-by-level driver
+    for the top of the tree as well (same results); True means 1.
     With ``alpha_steps`` > 0 the boxes the plain bounds leave undecided (from depth
     ``alpha_min_depth`` on) are re-bounded with optimized lower slopes before they are split;
     ``alpha_select`` > 0 limits that to boxes whose plain bounds are within that fraction of

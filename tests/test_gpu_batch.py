@@ -145,10 +145,10 @@ def test_batch_mixed_shapes_and_budgets_against_oracle():
 
 
 def _level_loop(it):
-    """``count_exact`` with split timing, which keeps the level-by-level driver (no one-pass top
-    of the tree)."""
+    """``count_exact`` with the level-by-level driver for every depth (timing bit 2: no one-pass
+    top of the tree)."""
     net, prop, lo, hi, D, M = it
-    return E().count_exact(net, prop, lo, hi, D, M, timing=2)
+    return E().count_exact(net, prop, lo, hi, D, M, timing=4)
 
 
 def test_batch_top_of_tree_equals_level_loop():

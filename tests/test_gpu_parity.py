@@ -371,11 +371,11 @@ def test_count_exact_deterministic_and_budget():
 def test_count_exact_one_pass_top_equals_level_loop(name, seed, D, M, chunk):
     """The one-pass top of the tree (complete subtree bounded at once, replayed to the boxes the
     level loop visits) gives the oracle's boxes and classes, and the level loop's exact result:
-    timing bit 1 (split timing) keeps the level loop, so both are compared bit for bit."""
+    timing bit 2 keeps the level loop, so both are compared bit for bit."""
     inst = make(name, seed)
     g, o, diverge = compare_counts(inst, D, M, chunk=chunk)
     net, prop = load(inst)
-    ref = E().count_exact(net, prop, inst.lo, inst.hi, D, M, chunk=chunk, trace=True, timing=2)
+    ref = E().count_exact(net, prop, inst.lo, inst.hi, D, M, chunk=chunk, trace=True, timing=4)
     for k in ("unsafe", "safe", "undecided", "n_unsafe", "n_safe", "n_undecided",
               "n_boxes_bounded", "n_recheck64", "depth_reached", "status"):
         assert g[k] == ref[k], (k, g[k], ref[k])
@@ -388,26 +388,35 @@ def test_count_exact_timing_flags():
     """Timing changes no result; bit 0 times the bound launches, bit 1 the split launches, whose
     algorithmic bytes follow from the per-level counts (from the trace): every class byte, the
     undecided parents' corners and paths and two children each, and one 4-byte count per
-    1024-box tile, for each level the search continued from."""
+    1024-box tile, for each level the split kernel continued from: every level with bit 2 (the
+    level loop throughout), the levels from the top's depth K on without it (the top's boxes
+    are made by the subtree kernel; K = 11 here, the deepest whose 2^(K+1) - 1 boxes fit the
+    4096-leaf budget)."""
     inst = synth.tiny2d(3)
     net, prop = load(inst)
     D, M = 14, 1 << 12
     base = E().count_exact(net, prop, inst.lo, inst.hi, D, M, trace=True)
     keys = ("unsafe", "safe", "undecided", "n_unsafe", "n_safe", "n_undecided", "n_boxes_bounded",
             "n_recheck64", "depth_reached", "status")
-    for flag in (0, 1, 2, 3):
+    split_bytes = {}
+    for flag in range(8):
         r = E().count_exact(net, prop, inst.lo, inst.hi, D, M, timing=flag)
         assert all(r[k] == base[k] for k in keys)
         assert (r["bound_ms"] > 0) == bool(flag & 1)
         assert (r["split_ms"] > 0) == bool(flag & 2)
+        split_bytes[flag] = r["split_bytes"]
     d = inst.lo.shape[0]
     depth, cls = base["trace_depth"], base["trace_cls"]
-    expect = 0
+    def level_bytes(n_t, und):
+        return n_t + und * (2 * d * 4 + 8) * 3 + -(-n_t // 1024) * 4
+    per_level, und_at = [], []
     for t in range(int(depth.max())):          # levels with a next level
-        n_t = int((depth == t).sum())
-        und = int(((depth == t) & (cls == 0)).sum())
-        expect += n_t + und * (2 * d * 4 + 8) * 3 + -(-n_t // 1024) * 4
-    assert r["split_bytes"] == expect
+        und_at.append(int(((depth == t) & (cls == 0)).sum()))
+        per_level.append(level_bytes(int((depth == t).sum()), und_at[-1]))
+    assert int(depth.max()) > 11
+    assert split_bytes[6] == sum(per_level)
+    # the split of depth 11 reads the whole depth-11 slice of the top (2^11 class bytes)
+    assert split_bytes[2] == level_bytes(1 << 11, und_at[11]) + sum(per_level[12:])
 
 
 def test_count_exact_rejects_bad_input():
