@@ -1049,13 +1049,15 @@ hipEvent_t* timing_events() {
 }
 
 // Depth of the one-pass top of the tree (0: none).  Taken where the level loop bisects the widest
-// side with the plain kernel and no per-level extras (alpha passes, split timing), for
-// K >= 4 levels whose complete subtree (2^(K+1) - 1 boxes, at most 65535) fits the frontier.
+// side with the plain kernel, above the first alpha depth (levels with an alpha pass run level by
+// level), for K >= 4 levels whose complete subtree (2^(K+1) - 1 boxes, at most 65535) fits the
+// frontier.
 int prefix_depth(const slr_net* net, const slr_exact_opts* o, const Workspace& w) {
-    if (o->split_layers > 0 || o->alpha_steps > 0 || o->relax != SLR_RELAX_ONE || w.wchunk > 0 ||
-        (o->timing & 4) || net->dev.d > SLR_MAX_D)
+    if (o->split_layers > 0 || o->relax != SLR_RELAX_ONE || w.wchunk > 0 || (o->timing & 4) ||
+        net->dev.d > SLR_MAX_D)
         return 0;
     int K = std::min(15, o->max_depth);
+    if (o->alpha_steps > 0) K = std::min(K, o->alpha_min_depth - 1);
     while (K > 0 && ((int64_t)2 << K) - 1 > o->max_leaves) --K;
     return K >= 4 ? K : 0;
 }
@@ -1160,7 +1162,7 @@ int count_exact_impl(const slr_net* net, const slr_property* prop, const double*
             HIP_TRY(hipMemcpyAsync(hcls.data(), w.cls, N, hipMemcpyDeviceToHost, s), "count_exact: trace");
         }
         HIP_TRY(hipStreamSynchronize(s), "count_exact: sync");
-        if (ev0) {
+        if (ev0 && o->alpha_steps <= 0) {   // as in the level loop: no bound time with alpha
             float ms = 0.f;
             HIP_TRY(hipEventElapsedTime(&ms, ev0, ev1), "count_exact: event");
             bound_ms += ms;
