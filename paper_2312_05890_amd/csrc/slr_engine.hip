@@ -1162,7 +1162,7 @@ int count_exact_impl(const slr_net* net, const slr_property* prop, const double*
             HIP_TRY(hipMemcpyAsync(hcls.data(), w.cls, N, hipMemcpyDeviceToHost, s), "count_exact: trace");
         }
         HIP_TRY(hipStreamSynchronize(s), "count_exact: sync");
-        if (ev0 && o->alpha_steps <= 0) {   // as in the level loop: no bound time with alpha
+        if (ev0) {
             float ms = 0.f;
             HIP_TRY(hipEventElapsedTime(&ms, ev0, ev1), "count_exact: event");
             bound_ms += ms;
