@@ -584,8 +584,19 @@ AlphaWs layout_alpha(char* base, const NetDev& nd, const PropDev& pd, int64_t n)
 
 // tape_state: plain bounds from the tape-state kernel whatever the shape (the relaxation with one
 // ratio per equation needs its full per-neuron equations)
+// Boxes per launch of the tape-state kernel: as many as keep its tape within 128 MiB (at least
+// 4096, at most 65536, a multiple of 4096; small_tape: 4096, for the static scratch of the
+// allocation-free count).  Larger launches fill the GPU where one 4096-box launch is a single
+// wave of tiles.
+int64_t tape_chunk(const NetDev& nd, const PropDev& pd, bool small_tape) {
+    if (small_tape) return 4096;
+    const size_t per_tile = alpha_tape_bytes(nd, pd, 16, 1);
+    const int64_t fit = per_tile > 0 ? (int64_t)((size_t)(128 << 20) / per_tile) * 16 : 65536;
+    return std::max<int64_t>(4096, std::min<int64_t>(65536, fit / 4096 * 4096));
+}
+
 Workspace layout_ws(char* base, const NetDev& nd, const PropDev& pd, int64_t cap, int samples,
-                    int64_t achunk, bool tape_state = false) {
+                    int64_t achunk, bool tape_state = false, bool small_tape = false) {
     const int d = nd.d;
     Workspace w{};
     size_t o = 0;
@@ -613,7 +624,7 @@ Workspace layout_ws(char* base, const NetDev& nd, const PropDev& pd, int64_t cap
     w.viol = (int8_t*)take(std::max(samples, 0));
     w.wchunk = 0;
     if ((tape_state || !bound_f32_supported(nd, pd)) && pd.rows > 0) {
-        w.wchunk = std::min<int64_t>(cap, 4096);
+        w.wchunk = std::min<int64_t>(cap, tape_chunk(nd, pd, small_tape));
         w.wtape = (float*)take(alpha_tape_bytes(nd, pd, w.wchunk, 1));
         w.wlo = (float*)take(sizeof(float) * pd.rows * w.wchunk);
         w.whi = (float*)take(sizeof(float) * pd.rows * w.wchunk);
@@ -1462,7 +1473,8 @@ int count_exact_impl(const slr_net* net, const slr_property* prop, const double*
 }
 
 int check_exact_opts(const slr_net* net, const slr_property* prop, const slr_exact_opts* o,
-                     int samples, Workspace* w, const char* who, bool check_device = true) {
+                     int samples, Workspace* w, const char* who, bool check_device = true,
+                     bool small_tape = false) {
     if (!o) return fail(SLR_EINVAL, "%s: opts is NULL", who);
     if (o->max_depth < 0 || o->max_depth > kMaxLevels - 1)
         return fail(SLR_EINVAL, "%s: max_depth must be in [0, %d]", who, kMaxLevels - 1);
@@ -1502,12 +1514,14 @@ int check_exact_opts(const slr_net* net, const slr_property* prop, const slr_exa
     }
     const int64_t achunk = o->alpha_steps > 0 ? o->alpha_chunk : 0;
     const bool two = o->relax == SLR_RELAX_TWO;
-    const size_t need = layout_ws(nullptr, net->dev, prop->dev, o->max_leaves, samples, achunk, two).bytes;
+    const size_t need = layout_ws(nullptr, net->dev, prop->dev, o->max_leaves, samples, achunk, two,
+                                  small_tape).bytes;
     if (!o->workspace || o->workspace_bytes < need)
         return fail(SLR_ENOMEM, "%s: workspace of %zu bytes is smaller than the %zu required", who,
                     o->workspace_bytes, need);
     if (check_device && !is_device_ptr(o->workspace)) return fail(SLR_EINVAL, "%s: workspace must be device memory", who);
-    *w = layout_ws((char*)o->workspace, net->dev, prop->dev, o->max_leaves, samples, achunk, two);
+    *w = layout_ws((char*)o->workspace, net->dev, prop->dev, o->max_leaves, samples, achunk, two,
+                   small_tape);
     return SLR_OK;
 }
 
@@ -1580,7 +1594,7 @@ extern "C" int count_exact_noalloc(const slr_net* net, const slr_property* prop,
     const int64_t achunk = opts->alpha_steps > 0 ? opts->alpha_chunk : 0;
     if (opts->max_leaves >= 1 && achunk >= 0) {
         const size_t need = layout_ws(nullptr, net->dev, prop->dev, opts->max_leaves, 0, achunk,
-                                      opts->relax == SLR_RELAX_TWO).bytes;
+                                      opts->relax == SLR_RELAX_TWO, /*small_tape=*/true).bytes;
         if (need > kScratchBytes)
             return fail(SLR_ENOMEM, "count_exact_noalloc: this count needs %zu bytes of workspace, more than the "
                         "%zu-byte static scratch (lower max_leaves or alpha_chunk, or use count_exact)", need, kScratchBytes);
@@ -1591,7 +1605,9 @@ extern "C" int count_exact_noalloc(const slr_net* net, const slr_property* prop,
     o.workspace = base;
     o.workspace_bytes = kScratchBytes;
     Workspace w;
-    if ((rc = check_exact_opts(net, prop, &o, 0, &w, "count_exact_noalloc", /*check_device=*/false))) return rc;
+    if ((rc = check_exact_opts(net, prop, &o, 0, &w, "count_exact_noalloc", /*check_device=*/false,
+                               /*small_tape=*/true)))
+        return rc;
     memset(out, 0, sizeof *out);
     return count_exact_impl(net, prop, lo, hi, &o, w, out, /*no_alloc=*/true);
 }
