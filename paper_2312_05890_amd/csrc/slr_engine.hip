@@ -1060,13 +1060,12 @@ hipEvent_t* timing_events() {
 }
 
 // Depth of the one-pass top of the tree (0: none).  Taken where the level loop bisects the widest
-// side with the plain kernel, above the first alpha depth (levels with an alpha pass run level by
-// level), for K >= 4 levels whose complete subtree (2^(K+1) - 1 boxes, at most 65535) fits the
-// frontier.
+// side (with the LDS or the tape-state kernel, either relaxation), above the first alpha depth
+// (levels with an alpha pass run level by level), for K >= 4 levels whose complete subtree
+// (2^(K+1) - 1 boxes, at most 65535) fits the frontier.
 int prefix_depth(const slr_net* net, const slr_exact_opts* o, const Workspace& w) {
-    if (o->split_layers > 0 || o->relax != SLR_RELAX_ONE || w.wchunk > 0 || (o->timing & 4) ||
-        net->dev.d > SLR_MAX_D)
-        return 0;
+    (void)w;
+    if (o->split_layers > 0 || (o->timing & 4) || net->dev.d > SLR_MAX_D) return 0;
     int K = std::min(15, o->max_depth);
     if (o->alpha_steps > 0) K = std::min(K, o->alpha_min_depth - 1);
     while (K > 0 && ((int64_t)2 << K) - 1 > o->max_leaves) --K;
@@ -1144,20 +1143,51 @@ int count_exact_impl(const slr_net* net, const slr_property* prop, const double*
         HIP_TRY(launch_prefix_boxes(N, d, rb, w.lo[0], w.hi[0], w.path[0], w.err, s), "count_exact: prefix kernel");
         HIP_TRY(hipMemsetAsync(w.amb_count, 0, sizeof(unsigned), s), "count_exact: clear");
         if (ev0) HIP_TRY(hipEventRecord(ev0, s), "count_exact: event");
-        for (int64_t off = 0; off < N; off += chunk) {
-            const int64_t m = std::min(chunk, N - off);
-            int unsup = 0;
-            HIP_TRY(launch_bound_f32(net->dev, prop->dev, m, w.lo[0] + off * d, w.hi[0] + off * d, nullptr,
-                                     nullptr, w.cls + off, 0, s, &unsup, w.amb_list, w.amb_count,
-                                     (unsigned)off),
-                    "count_exact: bound kernel");
-            if (unsup) return fail(SLR_EUNSUPPORTED, "count_exact: shape not supported");
-            ++launches;
+        if (w.wchunk > 0) {
+            // tape-state kernel, as in the level loop below: widened classes, then (one ratio)
+            // raw bounds that list the boxes near a decision for the FP64 re-decision
+            for (int64_t off = 0; off < N; off += w.wchunk) {
+                const int64_t m = std::min(w.wchunk, N - off);
+                AlphaArgs a{};
+                a.n = m;
+                a.lo = w.lo[0] + off * d;
+                a.hi = w.hi[0] + off * d;
+                a.tape = w.wtape;
+                a.fwd_only = 1;
+                a.two_ratio = o->relax == SLR_RELAX_TWO;
+                a.g_lo = w.wlo;
+                a.g_hi = w.whi;
+                a.cls = w.cls + off;
+                HIP_TRY(launch_alpha_forward(net->dev, prop->dev, a, s), "count_exact: bound kernel");
+                ++launches;
+                if (a.two_ratio) continue;
+                a.raw = 1;
+                a.g_lo = w.rlo;
+                a.g_hi = w.rhi;
+                a.cls = nullptr;
+                HIP_TRY(launch_alpha_forward(net->dev, prop->dev, a, s), "count_exact: bound kernel");
+                HIP_TRY(launch_ambiguity(m, prop->dev.rows, w.wlo, w.whi, w.rlo, w.rhi, w.cls + off,
+                                         w.amb_list, w.amb_count, (unsigned)off, s),
+                        "count_exact: ambiguity kernel");
+                ++launches;
+            }
+        } else {
+            for (int64_t off = 0; off < N; off += chunk) {
+                const int64_t m = std::min(chunk, N - off);
+                int unsup = 0;
+                HIP_TRY(launch_bound_f32(net->dev, prop->dev, m, w.lo[0] + off * d, w.hi[0] + off * d,
+                                         nullptr, nullptr, w.cls + off, 0, s, &unsup, w.amb_list,
+                                         w.amb_count, (unsigned)off),
+                        "count_exact: bound kernel");
+                if (unsup) return fail(SLR_EUNSUPPORTED, "count_exact: shape not supported");
+                ++launches;
+            }
         }
         if (ev1) HIP_TRY(hipEventRecord(ev1, s), "count_exact: event");
-        HIP_TRY(launch_recheck64(net->dev, prop->dev, N, w.lo[0], w.hi[0], nullptr, nullptr, w.cls,
-                                 w.rechecks, w.amb_list, w.amb_count, s),
-                "count_exact: recheck kernel");
+        if (o->relax != SLR_RELAX_TWO)
+            HIP_TRY(launch_recheck64(net->dev, prop->dev, N, w.lo[0], w.hi[0], nullptr, nullptr, w.cls,
+                                     w.rechecks, w.amb_list, w.amb_count, s),
+                    "count_exact: recheck kernel");
         HIP_TRY(launch_prefix_replay(N, K, w.cls, w.stats, s), "count_exact: prefix replay kernel");
         HIP_TRY(launch_prefix_recheck_uncount(N, w.amb_list, w.amb_count, w.cls, w.rechecks, s),
                 "count_exact: prefix replay kernel");

@@ -242,6 +242,36 @@ def test_noalloc_equals_count_exact():
         assert a[k] == b[k], k
 
 
+KEYS = ("unsafe", "safe", "undecided", "n_unsafe", "n_safe", "n_undecided", "n_boxes_bounded",
+        "n_recheck64", "depth_reached", "status")
+
+
+@pytest.mark.parametrize("relax,variant,name,seed,D,M", [
+    ("two", 0, "acas", 0, 30, 1 << 14),     # top of depth 12, then levels
+    ("two", 0, "tiny2d", 3, 16, 1 << 16),   # top of depth 15, then the last level
+    ("two", 0, "acas", 2, 9, 1 << 12),      # the depth limit inside the top
+    ("one", 3, "acas", 1, 20, 1 << 13),     # tape-state kernel with one ratio (FP64 re-decision)
+    ("one", 3, "nav22", 0, 24, 1 << 12),
+])
+def test_one_pass_top_on_the_tape_state_kernel(relax, variant, name, seed, D, M):
+    """The one-pass top of the tree with the tape-state kernel (two ratios, or the plain slopes
+    under bound_kernel_variant 3) gives the level-by-level driver's exact result (timing bit 2
+    keeps the level loop), traces included."""
+    inst = make(name, seed)
+    net, prop = load(inst)
+    E().bound_kernel_variant(variant)
+    try:
+        a = E().count_exact(net, prop, inst.lo, inst.hi, D, M, relax=relax, trace=True)
+        b = E().count_exact(net, prop, inst.lo, inst.hi, D, M, relax=relax, trace=True, timing=4)
+    finally:
+        E().bound_kernel_variant(0)
+    for k in KEYS:
+        assert a[k] == b[k], (k, a[k], b[k])
+    for k in ("trace_depth", "trace_path", "trace_cls"):
+        assert np.array_equal(a[k], b[k]), k
+    assert b["bound_launches"] >= a["bound_launches"]
+
+
 def test_relax_rejects_bad_options():
     eng = E()
     inst = synth.acas(1)
